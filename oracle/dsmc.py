@@ -1,0 +1,249 @@
+"""dSMC (de-Sequentialized Monte Carlo) smoother, plain fp64 CPU version.
+
+TEST INFRASTRUCTURE: part of the fp64 CPU oracle; see oracle/__init__.py.
+
+Steps, in the paper's order:
+
+* ``sample_leaves``   Algorithm 2 (smoother initialisation) with the t = 0
+                      reweighting of Proposition 2.2.
+* ``combine``         Algorithm 1 (block combination): the product-form weights
+                      W_c^{mn} (Section 2.2, normalised-weights equation), the
+                      normalising-constant increment (equation for L_{a:b}),
+                      multinomial resampling of N index pairs, and the gather.
+* ``schedule``        Algorithm 5 (parallel combination by array reshaping):
+                      the balanced tree actually executed.
+* ``smooth``          leaves, then the tree, then the output.
+
+Readings of the paper this file takes (each also listed in the design doc):
+
+* Time points are t = 0..K-1.
+* Weights are carried normalised, with a separate log L per block (Algorithm 2
+  returns both; Algorithm 1's return value is consistent with it).  A merged
+  block carries uniform weights -log N.
+* Algorithm 1 writes the pair measure with the roles of x_{c-1} and x_c
+  swapped and the increment equation writes omega_c(X_{c-1}, X_{c-1}); here
+  m indexes the left block (time c-1) and n the right block (time c), as in
+  the normalised-weights equation.
+* weighting "leaf_obs": nu_t proportional to h_t q_t, so the leaf log-weight
+  is log h_t (t >= 1) and log omega_c = log p_c - log q_c up to the constant
+  that the leaf L_t estimates; "boundary_obs": nu_t = q_t, leaf weight 1 for
+  t >= 1 and log omega_c = log p_c + log h_c - log q_c.  At t = 0 both use
+  log h_0 + log p_0 - log q_0 (Proposition 2.2 and Algorithm 2).
+* Multinomial resampling (the scheme Proposition 2.4 assumes) realised in two
+  stages: the row index from the row marginal with u1, then the column from the
+  chosen row with u2; both by inverse CDF with the strict rule
+  "first index whose cumulative sum exceeds u * total", on unnormalised fp64
+  cumulative sums, so zero-weight entries are never drawn.
+* If every pair weight of a combine is zero the increment is -inf, the status
+  is "degenerate" and indices are drawn uniformly: l = floor(u1 N), r = floor(u2 N).
+"""
+from __future__ import annotations
+
+from dataclasses import dataclass, field
+
+import numpy as np
+
+from . import philox
+from .ssm import log_potential, log_prior, log_proposal, log_transition_pairs, proposal_draw
+
+
+def logsumexp(v: np.ndarray, axis=None) -> np.ndarray:
+    v = np.asarray(v, dtype=np.float64)
+    m = np.max(v, axis=axis, keepdims=True)
+    m_safe = np.where(np.isfinite(m), m, 0.0)
+    with np.errstate(divide="ignore"):
+        s = np.log(np.sum(np.exp(v - m_safe), axis=axis, keepdims=True)) + m_safe
+    if axis is None:
+        return s.reshape(())[()]
+    return np.squeeze(s, axis=axis)
+
+
+# --------------------------------------------------------------------------
+# Leaves: Algorithm 2 and Proposition 2.2
+# --------------------------------------------------------------------------
+
+@dataclass
+class Leaves:
+    x: np.ndarray        # (K, N, d_x) particles X_t^n ~ q_t
+    logw: np.ndarray     # (K, N) normalised log-weights
+    logL: np.ndarray     # (K,) log L_t = log (1/N sum_n w_t^n)
+    raw: np.ndarray      # (K, N) unnormalised log-weights
+
+
+def leaf_logweights(spec, t: int, x: np.ndarray) -> np.ndarray:
+    """Unnormalised leaf log-weights log w_t^n of Algorithm 2 for particles x (N, d_x)."""
+    if t == 0:
+        # nu_0 proportional to h_0 P_0 (Proposition 2.2): w = h_0 dP_0/dq_0
+        return log_potential(spec, 0, x) + log_prior(spec, x) - log_proposal(spec, 0, x)
+    if spec.weighting == "leaf_obs":
+        return log_potential(spec, t, x)       # d nu_t / d q_t  with nu_t ~ h_t q_t
+    if spec.weighting == "boundary_obs":
+        return np.zeros(x.shape[0])            # nu_t = q_t
+    raise ValueError(spec.weighting)
+
+
+def normalise(raw: np.ndarray):
+    """(normalised log-weights, log L) with L = mean of the weights (Algorithm 2)."""
+    lse = logsumexp(raw)
+    return raw - lse, lse - np.log(raw.shape[0])
+
+
+def sample_leaves(spec, N: int, seed: int, x: np.ndarray | None = None) -> Leaves:
+    """Algorithm 2.  If ``x`` (K, N, d_x) is given those particles are weighted
+    instead of drawing new ones (used to feed the oracle another path's inputs)."""
+    K, d = spec.K, spec.d_x
+    if x is None:
+        x = np.empty((K, N, d))
+        for t in range(K):
+            x[t] = proposal_draw(spec, t, philox.leaf_normals(seed, t, N, d))
+    x = np.asarray(x, dtype=np.float64)
+    raw = np.empty((K, N))
+    logw = np.empty((K, N))
+    logL = np.empty(K)
+    for t in range(K):
+        raw[t] = leaf_logweights(spec, t, x[t])
+        logw[t], logL[t] = normalise(raw[t])
+    return Leaves(x=x, logw=logw, logL=logL, raw=raw)
+
+
+# --------------------------------------------------------------------------
+# Combine: Algorithm 1
+# --------------------------------------------------------------------------
+
+@dataclass
+class CombineResult:
+    l: np.ndarray            # (N,) left indices l_n
+    r: np.ndarray            # (N,) right indices r_n
+    row_lse: np.ndarray      # (N,) r_m = log sum_n exp S[m, n]
+    Z: float                 # log of the normalising-constant increment
+    degenerate: bool
+    S: np.ndarray | None = None
+
+
+def pair_logweights(spec, c: int, xL, xR, lwL, lwR) -> np.ndarray:
+    """S[m, n] = log( w_{c-1}^m w_c^n omega_c(X_{c-1}^m, X_c^n) ), the log of the
+    unnormalised product-form weight (normalised-weights equation, Section 2.2)
+    with omega_c of Proposition 2.3 for the chosen nu_c."""
+    b = lwR - log_proposal(spec, c, xR)
+    if spec.weighting == "boundary_obs":
+        b = b + log_potential(spec, c, xR)
+    return lwL[:, None] + b[None, :] + log_transition_pairs(spec, xL, xR)
+
+
+def inverse_cdf(weights: np.ndarray, u: float) -> int:
+    """First index i with u * total < cumsum(weights)[i] (fp64, sequential sums)."""
+    cum = np.cumsum(weights)
+    i = int(np.searchsorted(cum, u * cum[-1], side="right"))
+    if i >= len(weights):                       # u * total rounded up to total
+        i = int(np.flatnonzero(weights > 0)[-1])
+    return i
+
+
+def combine(spec, c: int, xL, xR, lwL, lwR, u1, u2, keep_S: bool = False) -> CombineResult:
+    """Algorithm 1 at boundary c on the left block's particles at time c-1 (xL)
+    and the right block's particles at time c (xR), with block log-weights
+    lwL, lwR.  Returns the N index pairs and the log increment Z_c."""
+    N = xL.shape[0]
+    S = pair_logweights(spec, c, np.asarray(xL, np.float64), np.asarray(xR, np.float64),
+                        np.asarray(lwL, np.float64), np.asarray(lwR, np.float64))
+    if np.isnan(S).any():
+        raise FloatingPointError(f"NaN pair weight at boundary {c}")
+    row_lse = logsumexp(S, axis=1)
+    Z = float(logsumexp(row_lse))
+    l = np.empty(N, dtype=np.int64)
+    r = np.empty(N, dtype=np.int64)
+    if not np.isfinite(Z):
+        l[:] = np.minimum((u1 * N).astype(np.int64), N - 1)
+        r[:] = np.minimum((u2 * N).astype(np.int64), N - 1)
+        return CombineResult(l, r, row_lse, Z, True, S if keep_S else None)
+    row_w = np.exp(row_lse - np.max(row_lse))
+    for n in range(N):
+        m = inverse_cdf(row_w, u1[n])
+        row = S[m]
+        j = inverse_cdf(np.exp(row - np.max(row)), u2[n])
+        l[n], r[n] = m, j
+    return CombineResult(l, r, row_lse, Z, False, S if keep_S else None)
+
+
+# --------------------------------------------------------------------------
+# Tree: Algorithm 5
+# --------------------------------------------------------------------------
+
+def schedule(K: int):
+    """Algorithm 5 as a list of levels; each level is a list of
+    (a, c, b) = left block [a, c), right block [c, b) to combine at boundary c.
+    Blocks are padded to 2^L with null blocks; a block whose right neighbour is
+    padding is left unchanged."""
+    L = 0
+    while (1 << L) < K:
+        L += 1
+    blocks = [(t, t + 1) for t in range(K)] + [None] * ((1 << L) - K)
+    levels = []
+    for _ in range(L):
+        nodes, nxt = [], []
+        for k in range(0, len(blocks), 2):
+            left, right = blocks[k], blocks[k + 1]
+            if right is None:
+                nxt.append(left)
+            else:
+                nodes.append((left[0], left[1], right[1]))
+                nxt.append((left[0], right[1]))
+        levels.append(nodes)
+        blocks = nxt
+    return levels
+
+
+@dataclass
+class Block:
+    a: int
+    b: int
+    x: np.ndarray            # (b - a, N, d_x)
+    logw: np.ndarray         # (N,)
+    logL: float
+    idx: np.ndarray          # (b - a, N) leaf particle index of each trajectory entry
+
+
+@dataclass
+class SmoothResult:
+    x: np.ndarray            # (K, N, d_x) output trajectories
+    logw: np.ndarray         # (N,) their log-weights (uniform for K >= 2)
+    logZ: float              # log L^N_{0:K-1}
+    leaves: Leaves
+    ancestry: np.ndarray     # (K-1, 2, N): (l_n, r_n) of the combine at boundary c = 1..K-1
+    Zc: np.ndarray           # (K-1,) log increments
+    row_lse: np.ndarray      # (K-1, N)
+    idx: np.ndarray          # (K, N) leaf index of every output entry
+    degenerate: bool = False
+    levels: list = field(default_factory=list)
+
+
+def run_tree(spec, leaves: Leaves, seed: int) -> SmoothResult:
+    K, N = leaves.x.shape[0], leaves.x.shape[1]
+    blocks = {t: Block(t, t + 1, leaves.x[t:t + 1], leaves.logw[t].copy(), float(leaves.logL[t]),
+                       np.arange(N)[None, :].copy()) for t in range(K)}
+    anc = np.zeros((max(K - 1, 0), 2, N), dtype=np.int64)
+    Zc = np.zeros(max(K - 1, 0))
+    rows = np.zeros((max(K - 1, 0), N))
+    degenerate = False
+    levels = schedule(K)
+    for nodes in levels:
+        for (a, c, b) in nodes:
+            L, R = blocks.pop(a), blocks.pop(c)
+            u1, u2 = philox.combine_uniforms(seed, c, N)
+            res = combine(spec, c, L.x[-1], R.x[0], L.logw, R.logw, u1, u2)
+            degenerate |= res.degenerate
+            anc[c - 1, 0], anc[c - 1, 1] = res.l, res.r
+            Zc[c - 1] = res.Z
+            rows[c - 1] = res.row_lse
+            x = np.concatenate([L.x[:, res.l], R.x[:, res.r]], axis=0)
+            idx = np.concatenate([L.idx[:, res.l], R.idx[:, res.r]], axis=0)
+            blocks[a] = Block(a, b, x, np.full(N, -np.log(N)), L.logL + R.logL + res.Z, idx)
+    top = blocks[0]
+    return SmoothResult(x=top.x, logw=top.logw, logZ=top.logL, leaves=leaves, ancestry=anc,
+                        Zc=Zc, row_lse=rows, idx=top.idx, degenerate=degenerate, levels=levels)
+
+
+def smooth(spec, N: int, seed: int) -> SmoothResult:
+    """Leaves (Algorithm 2), then the tree of Algorithm 5 with Algorithm 1 at
+    every node; log Z = sum_t log L_t + sum_c Z_c."""
+    return run_tree(spec, sample_leaves(spec, N, seed), seed)
