@@ -1,0 +1,212 @@
+/*
+ * dsmc.h - C ABI of an MI355X (gfx950) implementation of dSMC, the
+ * de-Sequentialized Monte Carlo particle smoother of Corenflos, Chopin and
+ * Sarkka (2022).
+ *
+ * What the library computes (paper, Section 2):
+ *   leaves   Algorithm 2: for every time t, N particles X_t^n ~ q_t with
+ *            normalised log-weights and log L_t = log mean_n w_t^n; the t = 0
+ *            weight is h_0 dP_0/dq_0 (Proposition 2.2).
+ *   tree     Algorithm 5 (appendix, parallel combination by array reshaping):
+ *            ceil(log2 K) levels; at level l, adjacent blocks of 2^l time
+ *            points are merged at boundary c = (2k+1) 2^l, and a block whose
+ *            right neighbour is padding is left as it is.
+ *   combine  Algorithm 1 at each boundary c: the N x N product-form weights
+ *            W_c^{mn} (normalised-weights equation, Section 2.2) with the
+ *            stitching weight omega_c of Proposition 2.3, their log-sum
+ *            (the normalising-constant increment, equation for L_{a:b}),
+ *            N multinomial draws of index pairs (l_n, r_n) (the resampling of
+ *            Proposition 2.4), and the gather of the chosen trajectories.
+ *   output   equally weighted trajectories approximating Q_{0:K-1} and
+ *            log L^N = sum_t log L_t + sum_c Z_c.
+ *
+ * Time points are t = 0..K-1 (the paper's t = 0..T with K = T + 1).
+ *
+ * Randomness: the library owns it.  Every draw comes from Philox4x64-10
+ * (Salmon et al., SC'11) with key (seed, 0x64534D43) and counter
+ * (n, t or c, purpose, j): purpose 2 = leaf normals (Box-Muller in fp64),
+ * purpose 3 = the two uniforms (u1, u2) of draw n of the combine at c.  Results
+ * therefore depend only on (model, N, seed), not on batching or launch order.
+ *
+ * Multinomial draws are taken in two stages: the left index from the row
+ * marginal with u1, then the right index from that row with u2, each by the
+ * inverse CDF "first index whose cumulative weight exceeds u * total" on fp64
+ * cumulative sums (zero-weight entries are never drawn).
+ *
+ * Conventions
+ *   - Every function returns a dsmc_status (0 = success, < 0 = error) unless
+ *     stated otherwise; dsmc_last_error() returns a thread-local message.
+ *   - Pointers in dsmc_model_desc are HOST pointers, read during
+ *     dsmc_model_create only.  Pointers in dsmc_output are DEVICE pointers
+ *     owned by the caller.
+ *   - Matrices are row-major, fp64.  Cholesky factors are lower triangular
+ *     with positive diagonal.
+ *   - dsmc_smooth / dsmc_smooth_batch validate their arguments, enqueue all
+ *     work on the plan's stream and return without synchronising.  Numerical
+ *     conditions found on the device are reported in dsmc_output.status.
+ */
+#ifndef DSMC_H
+#define DSMC_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef enum dsmc_status {
+  DSMC_OK = 0,
+  DSMC_EINVAL = -1,       /* invalid argument */
+  DSMC_ENOMEM = -2,       /* device or host allocation failed, or plan too small */
+  DSMC_EUNSUPPORTED = -3, /* size or option this build does not support */
+  DSMC_EAGAIN = -4,       /* dsmc_poll: the job has not finished */
+  DSMC_EDEGENERATE = -5,  /* a combine had zero total weight */
+  DSMC_ENUMERIC = -6,     /* a weight was NaN */
+  DSMC_EDEVICE = -8,      /* HIP runtime error */
+  DSMC_ECANCELLED = -9    /* server shut down before the job ran */
+} dsmc_status;
+
+/* Bits written to dsmc_output.status by the device (0 = clean run). */
+#define DSMC_FLAG_DEGENERATE 1 /* some combine (or leaf) had total weight 0; log_Z = -inf */
+#define DSMC_FLAG_NUMERIC 2    /* a NaN weight was met; outputs are undefined */
+
+/* Largest state dimension and particle count this build accepts. */
+#define DSMC_MAX_DX 32
+#define DSMC_MAX_N 4096
+
+/* ---------------------------------------------------------------- model */
+
+enum { DSMC_OBS_LINEAR_GAUSSIAN = 0, /* y_t ~ N(H x_t + h, R)                  */
+       DSMC_OBS_STOCH_VOL = 1 };     /* y_t ~ N(0, exp(x_t)), needs d_x = d_y = 1 */
+
+/* Choice of the auxiliary measures nu_t of Definition 2.1 (Section 2.1):
+ *   LEAF_OBS      nu_t proportional to h_t q_t: leaf log-weight log h_t (t >= 1),
+ *                 log omega_c = log p_c - log q_c (+ a constant estimated by L_t);
+ *   BOUNDARY_OBS  nu_t = q_t as in the paper's experiments: leaf weight 1
+ *                 (t >= 1), log omega_c = log p_c + log h_c - log q_c.
+ * Both target the same smoothing distribution. */
+enum { DSMC_WEIGHT_LEAF_OBS = 0, DSMC_WEIGHT_BOUNDARY_OBS = 1 };
+
+/* The Feynman-Kac model of the paper's introduction: prior P_0, transitions
+ * P_t with density p_t, potentials h_t, and the independent proposals q_t of
+ * Algorithm 2.  The four components are given as parametric families (the
+ * device cannot call host code); all are read in fp64. */
+typedef struct dsmc_model_desc {
+  int K;   /* time points t = 0..K-1, K >= 1 */
+  int d_x; /* state dimension, 1..DSMC_MAX_DX */
+  int d_y; /* observation dimension, >= 1 */
+  /* prior P_0 = N(m0, P0 = P0_chol P0_chol^T) */
+  const double *m0;      /* [d_x] */
+  const double *P0_chol; /* [d_x][d_x] */
+  /* transition P_t(x_t | x_{t-1}) = N(F x_{t-1} + f, Q = Q_chol Q_chol^T), t >= 1 */
+  const double *F;      /* [d_x][d_x] */
+  const double *f;      /* [d_x] */
+  const double *Q_chol; /* [d_x][d_x] */
+  /* potential h_t(x_t) = density of the observation y_t given x_t */
+  int obs_kind;         /* DSMC_OBS_* */
+  const double *H;      /* [d_y][d_x] (LINEAR_GAUSSIAN only) */
+  const double *h;      /* [d_y]      (LINEAR_GAUSSIAN only) */
+  const double *R_chol; /* [d_y][d_y] (LINEAR_GAUSSIAN only) */
+  const double *y;      /* [K][d_y] */
+  /* proposal q_t = N(q_mean[t], q_chol[t] q_chol[t]^T), independent over t */
+  const double *q_mean; /* [K][d_x] */
+  const double *q_chol; /* [K][d_x][d_x] */
+  int weighting;        /* DSMC_WEIGHT_* */
+} dsmc_model_desc;
+
+typedef struct dsmc_model dsmc_model_t;
+
+/* Validate the description, derive inverse Cholesky factors and log
+ * normalisers on the host in fp64, and copy everything to device memory of
+ * the current device (synchronously).  Errors: DSMC_EINVAL (bad sizes,
+ * non-positive Cholesky diagonal, unknown kind, STOCH_VOL with d_x != 1),
+ * DSMC_ENOMEM, DSMC_EDEVICE.  The model may be shared by many calls. */
+int dsmc_model_create(const dsmc_model_desc *desc, dsmc_model_t **out);
+void dsmc_model_destroy(dsmc_model_t *model);
+int dsmc_model_K(const dsmc_model_t *model);
+
+/* ----------------------------------------------------------------- plan */
+
+enum { DSMC_FP32 = 0, /* particles and pair weights in fp32, sums and CDFs in fp64 */
+       DSMC_FP64 = 1  /* everything in fp64 */ };
+
+#define DSMC_PLAN_PROFILE 1 /* record HIP events around every kernel launch */
+
+typedef struct dsmc_plan_desc {
+  int N;           /* particles per time point, 1..DSMC_MAX_N */
+  int d_x;         /* state dimension of the models run with this plan */
+  int max_K;       /* largest K of one series */
+  int max_total_K; /* largest sum of K over one dsmc_smooth_batch call (0 = max_K) */
+  int precision;   /* DSMC_FP32 or DSMC_FP64 */
+  int flags;       /* DSMC_PLAN_* */
+  void *stream;    /* hipStream_t all work is enqueued on; NULL = null stream */
+} dsmc_plan_desc;
+
+typedef struct dsmc_plan_impl dsmc_plan_t;
+
+/* Allocate the plan's device workspace (about
+ * max_total_K * N * (d_x*s + 12) bytes plus N*N*s/8 per node of the widest
+ * level, s = sizeof the real type).  Errors: DSMC_EINVAL, DSMC_EUNSUPPORTED,
+ * DSMC_ENOMEM. */
+int dsmc_plan(const dsmc_plan_desc *desc, dsmc_plan_t **out);
+void dsmc_plan_destroy(dsmc_plan_t *plan);
+
+/* ---------------------------------------------------------------- output */
+
+/* Caller-owned DEVICE buffers for one series of K time points.  `real` is
+ * float for DSMC_FP32 plans and double for DSMC_FP64 plans. */
+typedef struct dsmc_output {
+  void *traj;      /* real [d_x][K][N]: trajectory n is traj[.][0..K-1][n] (required) */
+  void *logw;      /* real [N]: log-weights of the trajectories; -log N when K >= 2,
+                      the normalised leaf weights when K == 1 (optional) */
+  double *log_Z;   /* [1]: log L^N (required) */
+  int32_t *status; /* [1]: DSMC_FLAG_* bits, 0 on a clean run (required) */
+  /* diagnostics, NULL = not written */
+  void *leaf_x;      /* real [d_x][K][N]: leaf particles X_t^n */
+  void *leaf_logw;   /* real [K][N]: normalised leaf log-weights */
+  double *leaf_logL; /* [K]: log L_t */
+  int32_t *ancestry; /* [K-1][2][N]: (l_n, r_n) of the combine at boundary c, row c-1 */
+  double *logZ_inc;  /* [K-1]: Z_c = log sum_{m,n} exp S_c[m,n], row c-1 */
+  double *row_lse;   /* [K-1][N]: r_m = log sum_n exp S_c[m,n], row c-1 */
+  int32_t *index;    /* [K][N]: leaf particle index of traj[.][t][n] */
+} dsmc_output;
+
+/* ------------------------------------------------------------- smoothing */
+
+/* One smoother run: leaves, the combine tree, output.  model->K <= max_K,
+ * model d_x == plan d_x.  Enqueued on the plan's stream; `out` buffers must
+ * stay valid until the stream reaches this work.  Calls on one plan must not
+ * overlap (they share its workspace).  Errors: DSMC_EINVAL, DSMC_EDEVICE. */
+int dsmc_smooth(dsmc_plan_t *plan, const dsmc_model_t *model, uint64_t seed,
+                const dsmc_output *out);
+
+/* B independent series (each with its own model, K and seed) in packed
+ * launches: every level's combines of all series run in the same kernels.
+ * The results equal B separate dsmc_smooth calls bit for bit.
+ * sum of K <= max_total_K.  Errors as dsmc_smooth. */
+int dsmc_smooth_batch(dsmc_plan_t *plan, int B, const dsmc_model_t *const *models,
+                      const uint64_t *seeds, const dsmc_output *outs);
+
+/* Kernel timings of a plan created with DSMC_PLAN_PROFILE, accumulated over
+ * every dsmc_smooth / dsmc_smooth_batch since the previous dsmc_plan_profile
+ * call: synchronises the stream, fills per-kernel-class totals (HIP events
+ * recorded around each launch on the plan's stream) and restarts the
+ * accumulation.  Classes: 0 leaves, 1 node preparation, 2 pair rows,
+ * 3 sampling, 4 gather, 5 output. */
+#define DSMC_NUM_KERNEL_CLASSES 6
+typedef struct dsmc_profile {
+  int launches[DSMC_NUM_KERNEL_CLASSES];
+  double ms[DSMC_NUM_KERNEL_CLASSES];
+  double pairs; /* algorithmic pair evaluations: (K-1) N^2 summed over series */
+} dsmc_profile;
+int dsmc_plan_profile(dsmc_plan_t *plan, dsmc_profile *out);
+
+/* Message describing the last error on this thread ("" if none). */
+const char *dsmc_last_error(void);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* DSMC_H */

@@ -1,0 +1,552 @@
+// Host side of the C ABI declared in include/dsmc.h: model upload, plans and
+// their device workspace, the Algorithm-5 schedule, and the launch sequence.
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <cmath>
+#include <cstdarg>
+#include <cstdio>
+#include <cstring>
+#include <string>
+#include <vector>
+
+#include "dsmc.h"
+#include "dsmc_internal.h"
+#include "dsmc_launch.h"
+
+using namespace dsmc;
+
+// ------------------------------------------------------------------ errors
+static thread_local std::string g_err;
+
+static int fail(int code, const char* fmt, ...) {
+  char buf[512];
+  va_list ap;
+  va_start(ap, fmt);
+  vsnprintf(buf, sizeof buf, fmt, ap);
+  va_end(ap);
+  g_err = buf;
+  return code;
+}
+
+#define HIP_TRY(expr)                                                              \
+  do {                                                                             \
+    hipError_t e_ = (expr);                                                        \
+    if (e_ != hipSuccess)                                                          \
+      return fail(e_ == hipErrorOutOfMemory ? DSMC_ENOMEM : DSMC_EDEVICE, "%s: %s", \
+                  #expr, hipGetErrorString(e_));                                   \
+  } while (0)
+
+extern "C" const char* dsmc_last_error(void) { return g_err.c_str(); }
+
+// ------------------------------------------------------------------- model
+struct dsmc_model {
+  void* dmem = nullptr;  // DevModel header followed by its arrays
+  DevModel* dev = nullptr;
+  int K = 0, dx = 0;
+};
+
+// Inverse of a lower-triangular matrix (forward substitution), fp64.
+static bool tri_inverse(const double* L, int d, double* out) {
+  std::fill(out, out + d * d, 0.0);
+  for (int j = 0; j < d; ++j) {
+    if (!(L[j * d + j] > 0.0) || !std::isfinite(L[j * d + j])) return false;
+    out[j * d + j] = 1.0 / L[j * d + j];
+    for (int i = j + 1; i < d; ++i) {
+      double s = 0.0;
+      for (int k = j; k < i; ++k) s += L[i * d + k] * out[k * d + j];
+      out[i * d + j] = -s / L[i * d + i];
+    }
+  }
+  return true;
+}
+
+static double log_norm(const double* L, int d) {
+  double s = 0.0;
+  for (int i = 0; i < d; ++i) s += std::log(L[i * d + i]);
+  return -s - 0.5 * d * std::log(2.0 * M_PI);
+}
+
+static bool all_finite(const double* p, size_t n) {
+  for (size_t i = 0; i < n; ++i)
+    if (!std::isfinite(p[i])) return false;
+  return true;
+}
+
+extern "C" int dsmc_model_create(const dsmc_model_desc* d, dsmc_model_t** out) {
+  if (!d || !out) return fail(DSMC_EINVAL, "null argument");
+  *out = nullptr;
+  const int K = d->K, dx = d->d_x, dy = d->d_y;
+  if (K < 1) return fail(DSMC_EINVAL, "K must be >= 1 (got %d)", K);
+  if (dx < 1 || dx > DSMC_MAX_DX) return fail(DSMC_EINVAL, "d_x must be in 1..%d", DSMC_MAX_DX);
+  if (dy < 1) return fail(DSMC_EINVAL, "d_y must be >= 1");
+  if (!d->m0 || !d->P0_chol || !d->F || !d->f || !d->Q_chol || !d->y || !d->q_mean || !d->q_chol)
+    return fail(DSMC_EINVAL, "missing model array");
+  if (d->obs_kind == DSMC_OBS_STOCH_VOL) {
+    if (dx != 1 || dy != 1) return fail(DSMC_EINVAL, "stochastic volatility needs d_x = d_y = 1");
+  } else if (d->obs_kind == DSMC_OBS_LINEAR_GAUSSIAN) {
+    if (!d->H || !d->h || !d->R_chol) return fail(DSMC_EINVAL, "missing observation array");
+  } else {
+    return fail(DSMC_EINVAL, "unknown obs_kind %d", d->obs_kind);
+  }
+  if (d->weighting != DSMC_WEIGHT_LEAF_OBS && d->weighting != DSMC_WEIGHT_BOUNDARY_OBS)
+    return fail(DSMC_EINVAL, "unknown weighting %d", d->weighting);
+  const size_t dd = (size_t)dx * dx;
+  if (!all_finite(d->m0, dx) || !all_finite(d->P0_chol, dd) || !all_finite(d->F, dd) ||
+      !all_finite(d->f, dx) || !all_finite(d->Q_chol, dd) ||
+      !all_finite(d->q_mean, (size_t)K * dx) || !all_finite(d->q_chol, (size_t)K * dd))
+    return fail(DSMC_EINVAL, "non-finite model parameter");
+
+  // host copies of every array the device needs
+  std::vector<double> m0(d->m0, d->m0 + dx), P0i(dd), F(d->F, d->F + dd), f(d->f, d->f + dx),
+      Qi(dd), H, y, qm(d->q_mean, d->q_mean + (size_t)K * dx),
+      qc(d->q_chol, d->q_chol + (size_t)K * dd), qi((size_t)K * dd), qln(K), Wcol(dd), Wrow(dd),
+      woff(dx);
+  if (!tri_inverse(d->P0_chol, dx, P0i.data())) return fail(DSMC_EINVAL, "bad P0_chol");
+  if (!tri_inverse(d->Q_chol, dx, Qi.data())) return fail(DSMC_EINVAL, "bad Q_chol");
+  for (int t = 0; t < K; ++t) {
+    if (!tri_inverse(d->q_chol + (size_t)t * dd, dx, qi.data() + (size_t)t * dd))
+      return fail(DSMC_EINVAL, "bad q_chol at t=%d", t);
+    qln[t] = log_norm(d->q_chol + (size_t)t * dd, dx);
+  }
+  double obs_ln = 0.0;
+  if (d->obs_kind == DSMC_OBS_LINEAR_GAUSSIAN) {
+    std::vector<double> Ri((size_t)dy * dy);
+    if (!tri_inverse(d->R_chol, dy, Ri.data())) return fail(DSMC_EINVAL, "bad R_chol");
+    obs_ln = log_norm(d->R_chol, dy);
+    H.assign((size_t)dy * dx, 0.0);  // R^{-1/2} H
+    for (int i = 0; i < dy; ++i)
+      for (int k = 0; k < dx; ++k) {
+        double s = 0.0;
+        for (int j = 0; j <= i; ++j) s += Ri[i * dy + j] * d->H[j * dx + k];
+        H[i * dx + k] = s;
+      }
+    y.assign((size_t)K * dy, 0.0);  // R^{-1/2} (y_t - h)
+    for (int t = 0; t < K; ++t)
+      for (int i = 0; i < dy; ++i) {
+        double s = 0.0;
+        for (int j = 0; j <= i; ++j) s += Ri[i * dy + j] * (d->y[(size_t)t * dy + j] - d->h[j]);
+        y[(size_t)t * dy + i] = s;
+      }
+  } else {
+    H.assign(1, 0.0);
+    y.assign(d->y, d->y + K);
+  }
+  // whitening: ||kappa Q^{-1/2} (x_R - F x_L - f)||^2 = (log2 e / 2) * quadratic form
+  const double kappa = std::sqrt(0.5 / std::log(2.0));
+  for (int i = 0; i < dx; ++i) {
+    double so = 0.0;
+    for (int j = 0; j < dx; ++j) {
+      Wcol[i * dx + j] = kappa * Qi[i * dx + j];
+      double s = 0.0;
+      for (int k = 0; k < dx; ++k) s += Qi[i * dx + k] * F[k * dx + j];
+      Wrow[i * dx + j] = kappa * s;
+      so += Qi[i * dx + j] * f[j];
+    }
+    woff[i] = kappa * so;
+  }
+
+  // pack: header, then arrays (each 256-byte aligned)
+  std::vector<const std::vector<double>*> arrs = {&m0, &P0i, &F,  &f,  &Qi,  &H,    &y,
+                                                  &qm, &qc,  &qi, &qln, &Wcol, &Wrow, &woff};
+  size_t off = (sizeof(DevModel) + 255) & ~size_t(255);
+  std::vector<size_t> offs;
+  for (auto* a : arrs) {
+    offs.push_back(off);
+    off += (a->size() * sizeof(double) + 255) & ~size_t(255);
+  }
+  std::vector<char> blob(off, 0);
+  auto* m = new dsmc_model;
+  m->K = K;
+  m->dx = dx;
+  hipError_t e = hipMalloc(&m->dmem, off);
+  if (e != hipSuccess) {
+    delete m;
+    return fail(DSMC_ENOMEM, "hipMalloc(model): %s", hipGetErrorString(e));
+  }
+  char* base = (char*)m->dmem;
+  for (size_t i = 0; i < arrs.size(); ++i)
+    std::memcpy(blob.data() + offs[i], arrs[i]->data(), arrs[i]->size() * sizeof(double));
+  DevModel hdr{};
+  hdr.K = K;
+  hdr.dx = dx;
+  hdr.dy = dy;
+  hdr.obs_kind = d->obs_kind;
+  hdr.weighting = d->weighting;
+  auto P = [&](int i) { return (const double*)(base + offs[i]); };
+  hdr.m0 = P(0);
+  hdr.P0_inv = P(1);
+  hdr.prior_lognorm = log_norm(d->P0_chol, dx);
+  hdr.F = P(2);
+  hdr.f = P(3);
+  hdr.Q_inv = P(4);
+  hdr.trans_lognorm = log_norm(d->Q_chol, dx);
+  hdr.H = P(5);
+  hdr.y = P(6);
+  hdr.obs_lognorm = obs_ln;
+  hdr.q_mean = P(7);
+  hdr.q_chol = P(8);
+  hdr.q_inv = P(9);
+  hdr.q_lognorm = P(10);
+  hdr.Wcol = P(11);
+  hdr.Wrow = P(12);
+  hdr.wcol_off = P(13);
+  std::memcpy(blob.data(), &hdr, sizeof hdr);
+  e = hipMemcpy(m->dmem, blob.data(), off, hipMemcpyHostToDevice);
+  if (e != hipSuccess) {
+    hipFree(m->dmem);
+    delete m;
+    return fail(DSMC_EDEVICE, "hipMemcpy(model): %s", hipGetErrorString(e));
+  }
+  m->dev = (DevModel*)m->dmem;
+  *out = m;
+  return DSMC_OK;
+}
+
+extern "C" void dsmc_model_destroy(dsmc_model_t* m) {
+  if (!m) return;
+  hipFree(m->dmem);
+  delete m;
+}
+
+extern "C" int dsmc_model_K(const dsmc_model_t* m) { return m ? m->K : -1; }
+
+// -------------------------------------------------------------------- plan
+struct dsmc_plan_impl {
+  dsmc_plan_desc d{};
+  int DX = 1;
+  bool fp64 = false;
+  size_t rsz = 4;
+  hipStream_t stream = nullptr;
+  int Npad = 0, Nc = 0;
+  int node_cap = 0;  // combines per launch slice
+  // device workspace
+  void* leafX = nullptr;
+  void* leafW = nullptr;
+  double* leafL = nullptr;
+  int32_t* sigma = nullptr;
+  int32_t* anc = nullptr;
+  double* zinc = nullptr;
+  void* col = nullptr;
+  void* row = nullptr;
+  double* nscal = nullptr;
+  void* P = nullptr;
+  NodeDesc* d_nodes = nullptr;
+  int32_t* d_series_of_t = nullptr;
+  SeriesDesc* d_series = nullptr;
+  int series_cap = 0;
+  // pinned staging
+  NodeDesc* h_nodes = nullptr;
+  int32_t* h_series_of_t = nullptr;
+  SeriesDesc* h_series = nullptr;
+  hipEvent_t staged = nullptr;
+  bool staged_pending = false;
+  // schedule of the last call (host copy) and the K list it was built for
+  std::vector<int> sched_K;
+  std::vector<int> level_off, level_cnt;
+  int total_nodes = 0;
+  // profiling
+  Timer timer;
+  double last_pairs = 0.0;
+};
+
+static void plan_free(dsmc_plan_t* p) {
+  hipFree(p->leafX);
+  hipFree(p->leafW);
+  hipFree(p->leafL);
+  hipFree(p->sigma);
+  hipFree(p->anc);
+  hipFree(p->zinc);
+  hipFree(p->col);
+  hipFree(p->row);
+  hipFree(p->nscal);
+  hipFree(p->P);
+  hipFree(p->d_nodes);
+  hipFree(p->d_series_of_t);
+  hipFree(p->d_series);
+  hipHostFree(p->h_nodes);
+  hipHostFree(p->h_series_of_t);
+  hipHostFree(p->h_series);
+  if (p->staged) hipEventDestroy(p->staged);
+}
+
+static int padded_dx(int dx) {
+  int p = 1;
+  while (p < dx) p <<= 1;
+  return p;
+}
+
+extern "C" int dsmc_plan(const dsmc_plan_desc* d, dsmc_plan_t** out) {
+  if (!d || !out) return fail(DSMC_EINVAL, "null argument");
+  *out = nullptr;
+  if (d->N < 1 || d->N > DSMC_MAX_N) return fail(DSMC_EUNSUPPORTED, "N must be in 1..%d", DSMC_MAX_N);
+  if (d->d_x < 1 || d->d_x > DSMC_MAX_DX) return fail(DSMC_EUNSUPPORTED, "d_x must be in 1..%d", DSMC_MAX_DX);
+  if (d->max_K < 1) return fail(DSMC_EINVAL, "max_K must be >= 1");
+  if (d->precision != DSMC_FP32 && d->precision != DSMC_FP64)
+    return fail(DSMC_EUNSUPPORTED, "precision %d not supported", d->precision);
+  auto* p = new dsmc_plan_t;
+  p->d = *d;
+  if (p->d.max_total_K < p->d.max_K) p->d.max_total_K = p->d.max_K;
+  p->DX = padded_dx(d->d_x);
+  p->fp64 = d->precision == DSMC_FP64;
+  p->rsz = p->fp64 ? 8 : 4;
+  p->stream = (hipStream_t)d->stream;
+  p->timer.on = (d->flags & DSMC_PLAN_PROFILE) != 0;
+  const int N = d->N;
+  p->Npad = (N + kChunk - 1) / kChunk * kChunk;
+  p->Nc = p->Npad / kChunk;
+  const size_t TK = (size_t)p->d.max_total_K;
+  const size_t max_nodes = std::max<size_t>(1, TK / 2);
+  const size_t per_node_P = (size_t)N * p->Nc * p->rsz;
+  const size_t cap_by_mem = std::max<size_t>(1, ((size_t)1 << 30) / per_node_P);
+  p->node_cap = (int)std::min(max_nodes, cap_by_mem);
+  const size_t nc = (size_t)p->node_cap;
+  int rc = DSMC_OK;
+#define ALLOC(ptr, bytes)                                                   \
+  do {                                                                      \
+    hipError_t e_ = hipMalloc((void**)&(ptr), (bytes));                      \
+    if (e_ != hipSuccess) {                                                 \
+      rc = fail(DSMC_ENOMEM, "hipMalloc(%s, %zu B): %s", #ptr, (size_t)(bytes), \
+                hipGetErrorString(e_));                                     \
+      goto bad;                                                             \
+    }                                                                       \
+  } while (0)
+  ALLOC(p->leafX, (size_t)d->d_x * TK * N * p->rsz);
+  ALLOC(p->leafW, TK * N * p->rsz);
+  ALLOC(p->leafL, TK * sizeof(double));
+  ALLOC(p->sigma, TK * N * sizeof(int32_t));
+  ALLOC(p->anc, TK * 2 * N * sizeof(int32_t));
+  ALLOC(p->zinc, TK * sizeof(double));
+  ALLOC(p->col, nc * p->Npad * (p->DX + 1) * p->rsz);
+  ALLOC(p->row, nc * p->Npad * p->DX * p->rsz);
+  ALLOC(p->nscal, nc * 4 * sizeof(double));
+  ALLOC(p->P, nc * per_node_P);
+  ALLOC(p->d_nodes, TK * sizeof(NodeDesc));
+  ALLOC(p->d_series_of_t, TK * sizeof(int32_t));
+#undef ALLOC
+  if (hipHostMalloc((void**)&p->h_nodes, TK * sizeof(NodeDesc), hipHostMallocDefault) != hipSuccess ||
+      hipHostMalloc((void**)&p->h_series_of_t, TK * sizeof(int32_t), hipHostMallocDefault) != hipSuccess) {
+    rc = fail(DSMC_ENOMEM, "hipHostMalloc(schedule staging)");
+    goto bad;
+  }
+  if (hipEventCreateWithFlags(&p->staged, hipEventDisableTiming) != hipSuccess) {
+    rc = fail(DSMC_EDEVICE, "hipEventCreate");
+    goto bad;
+  }
+  *out = p;
+  return DSMC_OK;
+bad:
+  plan_free(p);
+  delete p;
+  return rc;
+}
+
+extern "C" void dsmc_plan_destroy(dsmc_plan_t* p) {
+  if (!p) return;
+  hipStreamSynchronize(p->stream);
+  plan_free(p);
+  delete p;
+}
+
+static int ensure_series_cap(dsmc_plan_t* p, int B) {
+  if (B <= p->series_cap) return DSMC_OK;
+  if (p->staged_pending) HIP_TRY(hipEventSynchronize(p->staged));
+  HIP_TRY(hipStreamSynchronize(p->stream));
+  hipFree(p->d_series);
+  hipHostFree(p->h_series);
+  p->d_series = nullptr;
+  p->h_series = nullptr;
+  int cap = std::max(B, 2 * p->series_cap);
+  HIP_TRY(hipMalloc((void**)&p->d_series, (size_t)cap * sizeof(SeriesDesc)));
+  HIP_TRY(hipHostMalloc((void**)&p->h_series, (size_t)cap * sizeof(SeriesDesc), hipHostMallocDefault));
+  p->series_cap = cap;
+  return DSMC_OK;
+}
+
+// Algorithm 5 for every series: level l combines blocks [2k 2^l, (2k+1) 2^l)
+// and [(2k+1) 2^l, min((2k+2) 2^l, K)) when (2k+1) 2^l < K.  Nodes of all
+// series are grouped by level.
+static void build_schedule(dsmc_plan_t* p, const std::vector<int>& Ks, const std::vector<int>& bases) {
+  int maxL = 0;
+  for (int K : Ks) {
+    int L = 0;
+    while ((1 << L) < K) ++L;
+    maxL = std::max(maxL, L);
+  }
+  p->level_off.assign(maxL, 0);
+  p->level_cnt.assign(maxL, 0);
+  int n = 0;
+  for (int l = 0; l < maxL; ++l) {
+    p->level_off[l] = n;
+    const int h = 1 << l;
+    for (size_t s = 0; s < Ks.size(); ++s) {
+      const int K = Ks[s];
+      for (int a = 0; a + h < K; a += 2 * h) {
+        NodeDesc nd;
+        nd.series = (int32_t)s;
+        nd.a = a;
+        nd.c = a + h;
+        nd.b = std::min(a + 2 * h, K);
+        p->h_nodes[n++] = nd;
+      }
+    }
+    p->level_cnt[l] = n - p->level_off[l];
+  }
+  p->total_nodes = n;
+  for (size_t s = 0; s < Ks.size(); ++s)
+    for (int t = 0; t < Ks[s]; ++t) p->h_series_of_t[bases[s] + t] = (int32_t)s;
+}
+
+static int check_output(const dsmc_output* o) {
+  if (!o) return fail(DSMC_EINVAL, "null output");
+  if (!o->traj || !o->log_Z || !o->status)
+    return fail(DSMC_EINVAL, "output traj, log_Z and status are required");
+  return DSMC_OK;
+}
+
+extern "C" int dsmc_smooth_batch(dsmc_plan_t* p, int B, const dsmc_model_t* const* models,
+                                 const uint64_t* seeds, const dsmc_output* outs) {
+  if (!p || B < 1 || !models || !seeds || !outs) return fail(DSMC_EINVAL, "bad argument");
+  const int N = p->d.N;
+  std::vector<int> Ks(B), bases(B);
+  long total = 0;
+  for (int s = 0; s < B; ++s) {
+    const dsmc_model_t* m = models[s];
+    if (!m) return fail(DSMC_EINVAL, "null model %d", s);
+    if (m->dx != p->d.d_x) return fail(DSMC_EINVAL, "model %d has d_x %d, plan %d", s, m->dx, p->d.d_x);
+    if (m->K > p->d.max_K) return fail(DSMC_EINVAL, "model %d has K %d > max_K %d", s, m->K, p->d.max_K);
+    int rc = check_output(&outs[s]);
+    if (rc) return rc;
+    Ks[s] = m->K;
+    bases[s] = (int)total;
+    total += m->K;
+  }
+  if (total > p->d.max_total_K)
+    return fail(DSMC_EINVAL, "sum of K %ld > max_total_K %d", total, p->d.max_total_K);
+  const int totalK = (int)total;
+  int rc = ensure_series_cap(p, B);
+  if (rc) return rc;
+  // the staging buffers of the previous call must have been consumed
+  if (p->staged_pending) HIP_TRY(hipEventSynchronize(p->staged));
+  const bool new_sched = (Ks != p->sched_K);
+  if (new_sched) {
+    build_schedule(p, Ks, bases);
+    p->sched_K = Ks;
+  }
+  double pairs = 0.0;
+  for (int s = 0; s < B; ++s) {
+    const dsmc_output& o = outs[s];
+    SeriesDesc sd{};
+    sd.model = models[s]->dev;
+    sd.seed = seeds[s];
+    sd.K = Ks[s];
+    sd.base = bases[s];
+    sd.anc = o.ancestry ? o.ancestry : p->anc + (size_t)bases[s] * 2 * N;
+    sd.zinc = o.logZ_inc ? o.logZ_inc : p->zinc + bases[s];
+    sd.row_lse = o.row_lse;
+    sd.status = o.status;
+    sd.traj = o.traj;
+    sd.logw = o.logw;
+    sd.log_Z = o.log_Z;
+    sd.leaf_x = o.leaf_x;
+    sd.leaf_logw = o.leaf_logw;
+    sd.leaf_logL = o.leaf_logL;
+    sd.index = o.index;
+    p->h_series[s] = sd;
+    pairs += (double)(Ks[s] - 1) * N * (double)N;
+  }
+  p->last_pairs += pairs;
+  hipStream_t st = p->stream;
+  HIP_TRY(hipMemcpyAsync(p->d_series, p->h_series, (size_t)B * sizeof(SeriesDesc),
+                         hipMemcpyHostToDevice, st));
+  if (new_sched) {
+    if (p->total_nodes)
+      HIP_TRY(hipMemcpyAsync(p->d_nodes, p->h_nodes, (size_t)p->total_nodes * sizeof(NodeDesc),
+                             hipMemcpyHostToDevice, st));
+    HIP_TRY(hipMemcpyAsync(p->d_series_of_t, p->h_series_of_t, (size_t)totalK * sizeof(int32_t),
+                           hipMemcpyHostToDevice, st));
+  }
+  HIP_TRY(hipEventRecord(p->staged, st));
+  p->staged_pending = true;
+
+  launch_clear_status(p->d_series, B, st);
+  LeafLaunch LL{};
+  LL.fp64 = p->fp64;
+  LL.DX = p->DX;
+  LL.N = N;
+  LL.totalK = totalK;
+  LL.d_series = p->d_series;
+  LL.d_series_of_t = p->d_series_of_t;
+  LL.leafX = p->leafX;
+  LL.leafW = p->leafW;
+  LL.leafL = p->leafL;
+  LL.sigma = p->sigma;
+  if (launch_leaves(LL, st, &p->timer)) return fail(DSMC_EUNSUPPORTED, "no leaf kernel for d_x");
+  HIP_TRY(hipGetLastError());
+
+  const int RB = (N + kBlock - 1) / kBlock;
+  for (size_t l = 0; l < p->level_cnt.size(); ++l) {
+    const int cnt = p->level_cnt[l];
+    for (int s0 = 0; s0 < cnt; s0 += p->node_cap) {
+      const int nodes = std::min(p->node_cap, cnt - s0);
+      LevelLaunch L{};
+      L.fp64 = p->fp64;
+      L.DX = p->DX;
+      L.nodes = nodes;
+      L.N = N;
+      L.Npad = p->Npad;
+      L.Nc = p->Nc;
+      L.RB = RB;
+      // enough workgroups to fill the chip: split the columns of a node
+      const long want = 4096;
+      int CS = (int)std::min<long>(p->Nc, std::max<long>(1, (want + (long)nodes * RB - 1) / ((long)nodes * RB)));
+      const int KC = (p->Nc + CS - 1) / CS;
+      CS = (p->Nc + KC - 1) / KC;
+      L.CS = CS;
+      L.KC = KC;
+      L.totalK = totalK;
+      L.d_nodes = p->d_nodes + p->level_off[l] + s0;
+      L.d_series = p->d_series;
+      L.leafX = p->leafX;
+      L.leafW = p->leafW;
+      L.sigma = p->sigma;
+      L.col = p->col;
+      L.row = p->row;
+      L.nscal = p->nscal;
+      L.P = p->P;
+      if (launch_level(L, st, &p->timer)) return fail(DSMC_EUNSUPPORTED, "no combine kernel for d_x");
+      HIP_TRY(hipGetLastError());
+    }
+    launch_gather(p->d_nodes + p->level_off[l], p->d_series, cnt, 2 << l, N, p->sigma, st,
+                  &p->timer);
+    HIP_TRY(hipGetLastError());
+  }
+  launch_output(LL, B, p->d.d_x, st, &p->timer);
+  HIP_TRY(hipGetLastError());
+  return DSMC_OK;
+}
+
+extern "C" int dsmc_smooth(dsmc_plan_t* p, const dsmc_model_t* model, uint64_t seed,
+                           const dsmc_output* out) {
+  const dsmc_model_t* ms[1] = {model};
+  return dsmc_smooth_batch(p, 1, ms, &seed, out);
+}
+
+extern "C" int dsmc_plan_profile(dsmc_plan_t* p, dsmc_profile* out) {
+  if (!p || !out) return fail(DSMC_EINVAL, "null argument");
+  std::memset(out, 0, sizeof *out);
+  if (!p->timer.on) return fail(DSMC_EINVAL, "plan was created without DSMC_PLAN_PROFILE");
+  HIP_TRY(hipStreamSynchronize(p->stream));
+  for (size_t i = 0; i < p->timer.cls.size(); ++i) {
+    float ms = 0.0f;
+    if (p->timer.beg[i] && p->timer.fin[i])
+      HIP_TRY(hipEventElapsedTime(&ms, p->timer.beg[i], p->timer.fin[i]));
+    const int c = p->timer.cls[i];
+    out->launches[c] += 1;
+    out->ms[c] += ms;
+  }
+  out->pairs = p->last_pairs;
+  p->timer.reset();
+  p->last_pairs = 0.0;
+  return DSMC_OK;
+}

@@ -1,0 +1,224 @@
+// Device helpers: Philox4x64-10, Box-Muller, model log densities (fp64),
+// real-type traits and workgroup reductions.
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+#include "dsmc_internal.h"
+
+namespace dsmc {
+
+// ------------------------------------------------------------------ Philox
+// Philox4x64-10 (Salmon, Moraes, Dror, Shaw, SC'11): ten rounds of two
+// 64x64->128 multiplications with the round constants below and a Weyl key
+// schedule between rounds.
+constexpr uint64_t kPhiloxM0 = 0xD2E7470EE14C6C93ull;
+constexpr uint64_t kPhiloxM1 = 0xCA5A826395121157ull;
+constexpr uint64_t kPhiloxW0 = 0x9E3779B97F4A7C15ull;
+constexpr uint64_t kPhiloxW1 = 0xBB67AE8584CAA73Bull;
+constexpr uint64_t kKey1 = 0x64534D43ull;  // second key word of every stream
+constexpr uint64_t kPurposeLeaf = 2;
+constexpr uint64_t kPurposeCombine = 3;
+
+struct Words4 {
+  uint64_t w0, w1, w2, w3;
+};
+
+__device__ __forceinline__ Words4 philox4x64_10(uint64_t c0, uint64_t c1, uint64_t c2,
+                                                uint64_t c3, uint64_t k0, uint64_t k1) {
+#pragma unroll
+  for (int r = 0; r < 10; ++r) {
+    if (r) {
+      k0 += kPhiloxW0;
+      k1 += kPhiloxW1;
+    }
+    const uint64_t hi0 = __umul64hi(kPhiloxM0, c0), lo0 = kPhiloxM0 * c0;
+    const uint64_t hi1 = __umul64hi(kPhiloxM1, c2), lo1 = kPhiloxM1 * c2;
+    const uint64_t n0 = hi1 ^ c1 ^ k0, n2 = hi0 ^ c3 ^ k1;
+    c0 = n0;
+    c1 = lo1;
+    c2 = n2;
+    c3 = lo0;
+  }
+  return {c0, c1, c2, c3};
+}
+
+// [0, 1) with 53 random bits
+__device__ __forceinline__ double unif53(uint64_t w) { return (double)(w >> 11) * 0x1p-53; }
+// (0, 1] with 53 random bits
+__device__ __forceinline__ double unif53_open0(uint64_t w) {
+  return (double)((w >> 11) + 1ull) * 0x1p-53;
+}
+
+// Two standard normals from two words (Box-Muller, fp64).
+__device__ __forceinline__ void box_muller(uint64_t wa, uint64_t wb, double& z0, double& z1) {
+  const double ua = unif53_open0(wa);
+  const double ub = unif53(wb);
+  const double rad = sqrt(-2.0 * log(ua));
+  const double th = 2.0 * 3.141592653589793 * ub;
+  z0 = rad * cos(th);
+  z1 = rad * sin(th);
+}
+
+// ------------------------------------------------------------- real traits
+template <typename R>
+struct Real;
+
+template <>
+struct Real<float> {
+  static __device__ __forceinline__ float exp2(float x) { return __builtin_amdgcn_exp2f(x); }
+  static __device__ __forceinline__ float fma(float a, float b, float c) {
+    return __builtin_fmaf(a, b, c);
+  }
+  static constexpr double kTiny = 0x1p-80;  // row sums below this are recomputed shifted
+};
+
+template <>
+struct Real<double> {
+  static __device__ __forceinline__ double exp2(double x) { return ::exp2(x); }
+  static __device__ __forceinline__ double fma(double a, double b, double c) {
+    return __builtin_fma(a, b, c);
+  }
+  static constexpr double kTiny = 0x1p-900;
+};
+
+// log2 of one pair weight, relative to the node's column maximum:
+//   beta_n - || u_n - v_m ||^2
+// with whitened, pre-scaled coordinates (so exp2 of it is the natural-scale
+// weight).  Written with explicit fma so every call site rounds identically.
+template <typename R, int DX>
+__device__ __forceinline__ R pair_log2w(const R* u, R beta, const R* v) {
+  R s = beta;
+#pragma unroll
+  for (int d = 0; d < DX; ++d) {
+    const R del = u[d] - v[d];
+    s = Real<R>::fma(-del, del, s);
+  }
+  return s;
+}
+
+// ------------------------------------------------------------ model terms
+constexpr double kLog2e = 1.4426950408889634;
+constexpr double kLn2 = 0.6931471805599453;
+
+// -1/2 || Linv (x - mean) ||^2 with Linv lower triangular [dx][dx].
+template <int DX>
+__device__ __forceinline__ double neg_half_quad(const double* Linv, const double* mean,
+                                                const double (&x)[DX], int dx) {
+  double q = 0.0;
+#pragma unroll
+  for (int i = 0; i < DX; ++i) {
+    if (i < dx) {
+      double z = 0.0;
+#pragma unroll
+      for (int j = 0; j <= i; ++j) z += Linv[i * dx + j] * (x[j] - mean[j]);
+      q += z * z;
+    }
+  }
+  return -0.5 * q;
+}
+
+template <int DX>
+__device__ __forceinline__ double log_prior(const DevModel& M, const double (&x)[DX]) {
+  return neg_half_quad<DX>(M.P0_inv, M.m0, x, M.dx) + M.prior_lognorm;
+}
+
+template <int DX>
+__device__ __forceinline__ double log_proposal(const DevModel& M, int t, const double (&x)[DX]) {
+  const int dx = M.dx;
+  return neg_half_quad<DX>(M.q_inv + (size_t)t * dx * dx, M.q_mean + (size_t)t * dx, x, dx) +
+         M.q_lognorm[t];
+}
+
+// log h_t(x).  Linear-Gaussian: H and y are pre-whitened on the host
+// (H <- R_inv H, y <- R_inv (y - h)), so the quadratic needs no temporaries.
+template <int DX>
+__device__ __forceinline__ double log_potential(const DevModel& M, int t, const double (&x)[DX]) {
+  if (M.obs_kind == 1) {  // stochastic volatility: y ~ N(0, exp(x))
+    const double y = M.y[t];
+    return -0.9189385332046728 - 0.5 * x[0] - 0.5 * y * y * exp(-x[0]);
+  }
+  const int dx = M.dx, dy = M.dy;
+  const double* yt = M.y + (size_t)t * dy;
+  double q = 0.0;
+  for (int i = 0; i < dy; ++i) {
+    double r = yt[i];
+#pragma unroll
+    for (int k = 0; k < DX; ++k)
+      if (k < dx) r -= M.H[i * dx + k] * x[k];
+    q += r * r;
+  }
+  return -0.5 * q + M.obs_lognorm;
+}
+
+// ------------------------------------------------------------- reductions
+__device__ __forceinline__ double wave_max(double v) {
+#pragma unroll
+  for (int o = 32; o > 0; o >>= 1) v = fmax(v, __shfl_xor(v, o, 64));
+  return v;
+}
+__device__ __forceinline__ double wave_sum(double v) {
+#pragma unroll
+  for (int o = 32; o > 0; o >>= 1) v += __shfl_xor(v, o, 64);
+  return v;
+}
+__device__ __forceinline__ int wave_max_i(int v) {
+#pragma unroll
+  for (int o = 32; o > 0; o >>= 1) v = max(v, __shfl_xor(v, o, 64));
+  return v;
+}
+__device__ __forceinline__ int wave_or_i(int v) {
+#pragma unroll
+  for (int o = 32; o > 0; o >>= 1) v |= __shfl_xor(v, o, 64);
+  return v;
+}
+
+// Workgroup-wide reductions (kBlock threads); `red` holds kBlock/64 values.
+// The combination order is fixed, so results are deterministic.
+__device__ __forceinline__ double block_max(double v, double* red) {
+  v = wave_max(v);
+  const int w = threadIdx.x >> 6;
+  __syncthreads();
+  if ((threadIdx.x & 63) == 0) red[w] = v;
+  __syncthreads();
+  double r = red[0];
+#pragma unroll
+  for (int i = 1; i < kBlock / 64; ++i) r = fmax(r, red[i]);
+  return r;
+}
+__device__ __forceinline__ double block_sum(double v, double* red) {
+  v = wave_sum(v);
+  const int w = threadIdx.x >> 6;
+  __syncthreads();
+  if ((threadIdx.x & 63) == 0) red[w] = v;
+  __syncthreads();
+  double r = red[0];
+#pragma unroll
+  for (int i = 1; i < kBlock / 64; ++i) r += red[i];
+  return r;
+}
+__device__ __forceinline__ int block_max_i(int v, int* red) {
+  v = wave_max_i(v);
+  const int w = threadIdx.x >> 6;
+  __syncthreads();
+  if ((threadIdx.x & 63) == 0) red[w] = v;
+  __syncthreads();
+  int r = red[0];
+#pragma unroll
+  for (int i = 1; i < kBlock / 64; ++i) r = max(r, red[i]);
+  return r;
+}
+__device__ __forceinline__ int block_or_i(int v, int* red) {
+  v = wave_or_i(v);
+  const int w = threadIdx.x >> 6;
+  __syncthreads();
+  if ((threadIdx.x & 63) == 0) red[w] = v;
+  __syncthreads();
+  int r = red[0];
+#pragma unroll
+  for (int i = 1; i < kBlock / 64; ++i) r |= red[i];
+  return r;
+}
+
+}  // namespace dsmc

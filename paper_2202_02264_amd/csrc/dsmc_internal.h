@@ -1,0 +1,67 @@
+// Internal data structures shared by the host code and the HIP kernels.
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+namespace dsmc {
+
+constexpr int kBlock = 256;  // threads per workgroup (4 wave64)
+constexpr int kChunk = 32;   // columns per chunk of the pair matrix
+
+// Device-resident model (one allocation: this header, then the arrays).
+// Inverse Cholesky factors and log normalisers are derived on the host in fp64.
+struct DevModel {
+  int K, dx, dy, obs_kind, weighting;
+  int pad_;
+  const double* m0;       // [dx]
+  const double* P0_inv;   // [dx][dx] inverse of the prior Cholesky factor
+  double prior_lognorm;   // -sum log diag(P0_chol) - dx/2 log(2 pi)
+  const double* F;        // [dx][dx]
+  const double* f;        // [dx]
+  const double* Q_inv;    // [dx][dx] inverse of the transition Cholesky factor
+  double trans_lognorm;   // -sum log diag(Q_chol) - dx/2 log(2 pi)
+  const double* H;        // [dy][dx]
+  const double* h;        // [dy]
+  const double* R_inv;    // [dy][dy]
+  double obs_lognorm;
+  const double* y;        // [K][dy]
+  const double* q_mean;   // [K][dx]
+  const double* q_chol;   // [K][dx][dx]
+  const double* q_inv;    // [K][dx][dx]
+  const double* q_lognorm;  // [K]
+  const double* Wcol;     // [dx][dx] = kappa Q_inv          (column whitening)
+  const double* Wrow;     // [dx][dx] = kappa Q_inv F        (row whitening)
+  const double* wcol_off; // [dx]     = kappa Q_inv f
+};
+
+// One series of a (batched) run.
+struct SeriesDesc {
+  const DevModel* model;  // device pointer
+  uint64_t seed;
+  int K;
+  int base;               // offset of its time 0 on the packed time axis
+  int32_t* anc;           // [K-1][2][N]
+  double* zinc;           // [K-1]
+  double* row_lse;        // [K-1][N] or null
+  int32_t* status;        // [1]
+  void* traj;             // [dx][K][N]
+  void* logw;             // [N] or null
+  double* log_Z;          // [1]
+  void* leaf_x;           // [dx][K][N] or null
+  void* leaf_logw;        // [K][N] or null
+  double* leaf_logL;      // [K] or null
+  int32_t* index;         // [K][N] or null
+};
+
+// One combine of a level: boundary c of series `series`.
+struct NodeDesc {
+  int32_t series;
+  int32_t c;
+  int32_t a;      // first time of the left block
+  int32_t b;      // one past the last time of the right block
+};
+
+enum : int32_t { kFlagDegenerate = 1, kFlagNumeric = 2 };
+
+}  // namespace dsmc

@@ -1,0 +1,259 @@
+"""Thin ctypes binding of libdsmc.so (include/dsmc.h).
+
+Functions carry the C names and only marshal arguments: models are uploaded
+from numpy fp64 arrays, outputs are torch tensors on the GPU whose device
+pointers are passed through.  Every step of the smoother runs in the HIP
+kernels of libdsmc.so; there is no CPU fallback.  If the library is missing
+the import fails.
+"""
+from __future__ import annotations
+
+import ctypes as C
+import os
+from dataclasses import dataclass
+from typing import Optional, Sequence
+
+import numpy as np
+
+_PKG = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(_PKG, "libdsmc.so")
+
+DSMC_OK, DSMC_EINVAL, DSMC_ENOMEM, DSMC_EUNSUPPORTED = 0, -1, -2, -3
+DSMC_EAGAIN, DSMC_EDEGENERATE, DSMC_ENUMERIC, DSMC_EDEVICE, DSMC_ECANCELLED = -4, -5, -6, -8, -9
+DSMC_FLAG_DEGENERATE, DSMC_FLAG_NUMERIC = 1, 2
+DSMC_OBS_LINEAR_GAUSSIAN, DSMC_OBS_STOCH_VOL = 0, 1
+DSMC_WEIGHT_LEAF_OBS, DSMC_WEIGHT_BOUNDARY_OBS = 0, 1
+DSMC_FP32, DSMC_FP64 = 0, 1
+DSMC_PLAN_PROFILE = 1
+DSMC_MAX_DX, DSMC_MAX_N = 32, 4096
+DSMC_NUM_KERNEL_CLASSES = 6
+KERNEL_CLASSES = ("leaves", "prep", "rows", "sample", "gather", "output")
+
+_dp = C.POINTER(C.c_double)
+
+
+class dsmc_model_desc(C.Structure):
+    _fields_ = [("K", C.c_int), ("d_x", C.c_int), ("d_y", C.c_int),
+                ("m0", _dp), ("P0_chol", _dp), ("F", _dp), ("f", _dp), ("Q_chol", _dp),
+                ("obs_kind", C.c_int), ("H", _dp), ("h", _dp), ("R_chol", _dp), ("y", _dp),
+                ("q_mean", _dp), ("q_chol", _dp), ("weighting", C.c_int)]
+
+
+class dsmc_plan_desc(C.Structure):
+    _fields_ = [("N", C.c_int), ("d_x", C.c_int), ("max_K", C.c_int), ("max_total_K", C.c_int),
+                ("precision", C.c_int), ("flags", C.c_int), ("stream", C.c_void_p)]
+
+
+class dsmc_output(C.Structure):
+    _fields_ = [("traj", C.c_void_p), ("logw", C.c_void_p), ("log_Z", C.c_void_p),
+                ("status", C.c_void_p), ("leaf_x", C.c_void_p), ("leaf_logw", C.c_void_p),
+                ("leaf_logL", C.c_void_p), ("ancestry", C.c_void_p), ("logZ_inc", C.c_void_p),
+                ("row_lse", C.c_void_p), ("index", C.c_void_p)]
+
+
+class dsmc_profile(C.Structure):
+    _fields_ = [("launches", C.c_int * DSMC_NUM_KERNEL_CLASSES),
+                ("ms", C.c_double * DSMC_NUM_KERNEL_CLASSES), ("pairs", C.c_double)]
+
+
+def _load() -> C.CDLL:
+    if not os.path.exists(LIB_PATH):
+        raise ImportError(f"{LIB_PATH} is not built; run __graft_entry__.build()")
+    lib = C.CDLL(LIB_PATH)
+    vp, i, u64 = C.c_void_p, C.c_int, C.c_uint64
+    sig = {
+        "dsmc_model_create": (i, [C.POINTER(dsmc_model_desc), C.POINTER(vp)]),
+        "dsmc_model_destroy": (None, [vp]),
+        "dsmc_model_K": (i, [vp]),
+        "dsmc_plan": (i, [C.POINTER(dsmc_plan_desc), C.POINTER(vp)]),
+        "dsmc_plan_destroy": (None, [vp]),
+        "dsmc_smooth": (i, [vp, vp, u64, C.POINTER(dsmc_output)]),
+        "dsmc_smooth_batch": (i, [vp, i, C.POINTER(vp), C.POINTER(u64), C.POINTER(dsmc_output)]),
+        "dsmc_plan_profile": (i, [vp, C.POINTER(dsmc_profile)]),
+        "dsmc_last_error": (C.c_char_p, []),
+    }
+    for name, (res, args) in sig.items():
+        fn = getattr(lib, name)
+        fn.restype = res
+        fn.argtypes = args
+    return lib
+
+
+_lib = _load()
+
+
+class DsmcError(RuntimeError):
+    def __init__(self, code: int, where: str):
+        msg = _lib.dsmc_last_error().decode()
+        super().__init__(f"{where} failed with {code}: {msg}")
+        self.code = code
+
+
+def _check(code: int, where: str) -> None:
+    if code != DSMC_OK:
+        raise DsmcError(code, where)
+
+
+def _ptr(a: Optional[np.ndarray]):
+    if a is None:
+        return None
+    return a.ctypes.data_as(_dp)
+
+
+def _f64(a) -> np.ndarray:
+    return np.ascontiguousarray(np.asarray(a, dtype=np.float64))
+
+
+class Model:
+    """Device-resident model (dsmc_model_create)."""
+
+    def __init__(self, spec):
+        K, dx, dy = spec.K, spec.d_x, spec.d_y
+        keep = {
+            "m0": _f64(spec.m0).reshape(dx), "P0_chol": _f64(spec.P0_chol).reshape(dx, dx),
+            "F": _f64(spec.F).reshape(dx, dx), "f": _f64(spec.f).reshape(dx),
+            "Q_chol": _f64(spec.Q_chol).reshape(dx, dx), "y": _f64(spec.y).reshape(K, dy),
+            "q_mean": _f64(spec.q_mean).reshape(K, dx), "q_chol": _f64(spec.q_chol).reshape(K, dx, dx),
+        }
+        sv = spec.obs == "sv"
+        if not sv:
+            keep["H"] = _f64(spec.H).reshape(dy, dx)
+            keep["h"] = _f64(spec.h).reshape(dy)
+            keep["R_chol"] = _f64(spec.R_chol).reshape(dy, dy)
+        d = dsmc_model_desc()
+        d.K, d.d_x, d.d_y = K, dx, dy
+        for k, v in keep.items():
+            setattr(d, k, _ptr(v))
+        d.obs_kind = DSMC_OBS_STOCH_VOL if sv else DSMC_OBS_LINEAR_GAUSSIAN
+        d.weighting = {"leaf_obs": DSMC_WEIGHT_LEAF_OBS,
+                       "boundary_obs": DSMC_WEIGHT_BOUNDARY_OBS}[spec.weighting]
+        h = C.c_void_p()
+        _check(_lib.dsmc_model_create(C.byref(d), C.byref(h)), "dsmc_model_create")
+        self.handle = h
+        self.K, self.d_x = K, dx
+
+    def __del__(self):
+        if getattr(self, "handle", None):
+            _lib.dsmc_model_destroy(self.handle)
+            self.handle = None
+
+
+def dsmc_model_create(spec) -> Model:
+    return Model(spec)
+
+
+class Plan:
+    """dsmc_plan: workspace for series of up to max_K points (sum max_total_K)."""
+
+    def __init__(self, N: int, d_x: int, max_K: int, max_total_K: int = 0,
+                 precision: int = DSMC_FP32, profile: bool = False, stream=None):
+        import torch
+        if stream is None:
+            stream = torch.cuda.current_stream()
+        d = dsmc_plan_desc()
+        d.N, d.d_x, d.max_K, d.max_total_K = N, d_x, max_K, max_total_K
+        d.precision = precision
+        d.flags = DSMC_PLAN_PROFILE if profile else 0
+        d.stream = C.c_void_p(stream.cuda_stream)
+        h = C.c_void_p()
+        _check(_lib.dsmc_plan(C.byref(d), C.byref(h)), "dsmc_plan")
+        self.handle = h
+        self.N, self.d_x, self.precision = N, d_x, precision
+        self.max_K = max_K
+        self.max_total_K = max(max_total_K, max_K)
+        self.stream = stream
+        self.dtype = torch.float64 if precision == DSMC_FP64 else torch.float32
+
+    def __del__(self):
+        if getattr(self, "handle", None):
+            _lib.dsmc_plan_destroy(self.handle)
+            self.handle = None
+
+
+def dsmc_plan(N: int, d_x: int, max_K: int, **kw) -> Plan:
+    return Plan(N, d_x, max_K, **kw)
+
+
+@dataclass
+class Output:
+    """Caller-owned device buffers of one series (torch tensors)."""
+    traj: "object"
+    logw: "object"
+    log_Z: "object"
+    status: "object"
+    leaf_x: "object" = None
+    leaf_logw: "object" = None
+    leaf_logL: "object" = None
+    ancestry: "object" = None
+    logZ_inc: "object" = None
+    row_lse: "object" = None
+    index: "object" = None
+
+    def c_struct(self) -> dsmc_output:
+        o = dsmc_output()
+        for f in dsmc_output._fields_:
+            t = getattr(self, f[0])
+            setattr(o, f[0], None if t is None else t.data_ptr())
+        return o
+
+
+def alloc_output(plan: Plan, K: int, diagnostics: bool = False, device="cuda") -> Output:
+    import torch
+    N, dx, dt = plan.N, plan.d_x, plan.dtype
+    kw = dict(device=device)
+    o = Output(traj=torch.empty((dx, K, N), dtype=dt, **kw), logw=torch.empty(N, dtype=dt, **kw),
+               log_Z=torch.empty(1, dtype=torch.float64, **kw),
+               status=torch.zeros(1, dtype=torch.int32, **kw))
+    if diagnostics:
+        o.leaf_x = torch.empty((dx, K, N), dtype=dt, **kw)
+        o.leaf_logw = torch.empty((K, N), dtype=dt, **kw)
+        o.leaf_logL = torch.empty(K, dtype=torch.float64, **kw)
+        o.ancestry = torch.empty((max(K - 1, 0), 2, N), dtype=torch.int32, **kw)
+        o.logZ_inc = torch.empty(max(K - 1, 0), dtype=torch.float64, **kw)
+        o.row_lse = torch.empty((max(K - 1, 0), N), dtype=torch.float64, **kw)
+        o.index = torch.empty((K, N), dtype=torch.int32, **kw)
+    return o
+
+
+def dsmc_smooth(plan: Plan, model: Model, seed: int, out: Output) -> None:
+    o = out.c_struct()
+    _check(_lib.dsmc_smooth(plan.handle, model.handle, C.c_uint64(seed & (2**64 - 1)),
+                            C.byref(o)), "dsmc_smooth")
+
+
+def dsmc_smooth_batch(plan: Plan, models: Sequence[Model], seeds: Sequence[int],
+                      outs: Sequence[Output]) -> None:
+    B = len(models)
+    hs = (C.c_void_p * B)(*[m.handle.value for m in models])
+    ss = (C.c_uint64 * B)(*[int(s) & (2**64 - 1) for s in seeds])
+    os_ = (dsmc_output * B)(*[o.c_struct() for o in outs])
+    _check(_lib.dsmc_smooth_batch(plan.handle, B, hs, ss, os_), "dsmc_smooth_batch")
+
+
+def dsmc_plan_profile(plan: Plan) -> dict:
+    p = dsmc_profile()
+    _check(_lib.dsmc_plan_profile(plan.handle, C.byref(p)), "dsmc_plan_profile")
+    return {"launches": dict(zip(KERNEL_CLASSES, list(p.launches))),
+            "ms": dict(zip(KERNEL_CLASSES, list(p.ms))), "pairs": p.pairs}
+
+
+def check_status(out: Output) -> int:
+    """Synchronise and return the device status bits of an output."""
+    import torch
+    torch.cuda.synchronize()
+    return int(out.status.item())
+
+
+def smooth(spec, N: int, seed: int, precision: int = DSMC_FP32, diagnostics: bool = False,
+           plan: Optional[Plan] = None, model: Optional[Model] = None) -> Output:
+    """Convenience wrapper: upload, plan, run, synchronise, raise on device flags."""
+    import torch
+    model = model or Model(spec)
+    plan = plan or Plan(N, spec.d_x, spec.K, precision=precision)
+    out = alloc_output(plan, spec.K, diagnostics)
+    dsmc_smooth(plan, model, seed, out)
+    torch.cuda.synchronize()
+    st = int(out.status.item())
+    if st & DSMC_FLAG_NUMERIC:
+        raise DsmcError(DSMC_ENUMERIC, "dsmc_smooth (device)")
+    return out

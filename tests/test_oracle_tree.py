@@ -149,3 +149,15 @@ def test_nan_raises():
     spec.y[2, 0] = np.nan
     with pytest.raises(FloatingPointError):
         D.smooth(spec, 8, seed=1)
+
+
+def test_zero_leaf_weights_degenerate():
+    """A time point where every leaf weight is zero: L_t = 0, uniform weights,
+    log L = -inf and the run is flagged degenerate."""
+    spec = W.sv(5, seed=1)
+    spec.y = spec.y.copy()
+    spec.y[3, 0] = np.inf
+    out = D.smooth(spec, 8, seed=2)
+    assert out.degenerate and out.logZ == -np.inf
+    assert out.leaves.logL[3] == -np.inf
+    np.testing.assert_allclose(out.leaves.logw[3], -np.log(8))
