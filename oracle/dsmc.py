@@ -69,6 +69,10 @@ class Leaves:
     logL: np.ndarray     # (K,) log L_t = log (1/N sum_n w_t^n)
     raw: np.ndarray      # (K, N) unnormalised log-weights
 
+    @property
+    def degenerate(self) -> bool:
+        return bool(np.any(self.logL == -np.inf))
+
 
 def leaf_logweights(spec, t: int, x: np.ndarray) -> np.ndarray:
     """Unnormalised leaf log-weights log w_t^n of Algorithm 2 for particles x (N, d_x)."""
@@ -83,8 +87,12 @@ def leaf_logweights(spec, t: int, x: np.ndarray) -> np.ndarray:
 
 
 def normalise(raw: np.ndarray):
-    """(normalised log-weights, log L) with L = mean of the weights (Algorithm 2)."""
+    """(normalised log-weights, log L) with L = mean of the weights (Algorithm 2).
+    If every weight is zero, L = 0 and the weights are taken uniform (the run
+    is then flagged degenerate)."""
     lse = logsumexp(raw)
+    if lse == -np.inf:
+        return np.full(raw.shape[0], -np.log(raw.shape[0])), -np.inf
     return raw - lse, lse - np.log(raw.shape[0])
 
 
@@ -224,7 +232,9 @@ def run_tree(spec, leaves: Leaves, seed: int) -> SmoothResult:
     anc = np.zeros((max(K - 1, 0), 2, N), dtype=np.int64)
     Zc = np.zeros(max(K - 1, 0))
     rows = np.zeros((max(K - 1, 0), N))
-    degenerate = False
+    if np.isnan(leaves.raw).any():
+        raise FloatingPointError("NaN leaf weight")
+    degenerate = leaves.degenerate
     levels = schedule(K)
     for nodes in levels:
         for (a, c, b) in nodes:
