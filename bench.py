@@ -27,8 +27,10 @@ sys.path.insert(0, ROOT)
 # for single-rate VALU work (fp32 add/sub/fma without packed math).
 LANE_OPS_PER_S = 256 * 4 * 16 * 2.4e9
 # VALU issue slots per pair evaluation in the pair-row kernel (d_x = 1):
-# v_sub, v_fma, v_add at one slot each, plus v_exp_f32 at TRANS_SLOTS slots.
-TRANS_SLOTS = 4.0
+# v_sub, v_fma, v_add at one slot each, plus v_exp_f32 at TRANS_SLOTS slots
+# (v_exp_f32 issues at half the rate of v_fma_f32 on gfx950 and does not
+# co-issue with it: measured 1.85e13 vs 3.5e13 lane-instructions/s).
+TRANS_SLOTS = 2.0
 SLOTS_PER_PAIR = 3.0 + TRANS_SLOTS
 
 
@@ -136,7 +138,7 @@ def main():
         ms_rows = prof["ms"]["rows"]
         achieved = prof["pairs"] / (ms_rows * 1e-3)
         peak = LANE_OPS_PER_S / SLOTS_PER_PAIR
-        res["roofline"] = {"bound": "alu", "kernel": "k_rows<float,1>",
+        res["roofline"] = {"bound": "alu", "kernel": "k_rows<float,1,RPL>",
                            "achieved": achieved / 1e9, "peak": peak / 1e9, "unit": "Gpair/s",
                            "frac": achieved / peak, "traffic": None,
                            "avg_launch_ms": ms_rows / max(1, n_rows),

@@ -131,7 +131,9 @@ int dsmc_model_K(const dsmc_model_t *model);
 enum { DSMC_FP32 = 0, /* particles and pair weights in fp32, sums and CDFs in fp64 */
        DSMC_FP64 = 1  /* everything in fp64 */ };
 
-#define DSMC_PLAN_PROFILE 1 /* record HIP events around every kernel launch */
+#define DSMC_PLAN_PROFILE 1  /* record HIP events around every kernel launch */
+#define DSMC_PLAN_AUTOTUNE 2 /* time the pair-row kernel's tile shapes on first use of each
+                                level size and keep the fastest (results do not depend on it) */
 
 typedef struct dsmc_plan_desc {
   int N;           /* particles per time point, 1..DSMC_MAX_N */
@@ -145,10 +147,11 @@ typedef struct dsmc_plan_desc {
 
 typedef struct dsmc_plan_impl dsmc_plan_t;
 
-/* Allocate the plan's device workspace (about
- * max_total_K * N * (d_x*s + 12) bytes plus N*N*s/8 per node of the widest
- * level, s = sizeof the real type).  Errors: DSMC_EINVAL, DSMC_EUNSUPPORTED,
- * DSMC_ENOMEM. */
+/* Allocate the plan's device workspace: about
+ * max_total_K * N * ((3 d_x + 2) s + 28) bytes for particles, weights, ancestry
+ * and per-combine data, plus at most 1 GiB of per-level chunk sums
+ * (N * N * s / 32 per combine of a launch), s = sizeof the real type.
+ * Errors: DSMC_EINVAL, DSMC_EUNSUPPORTED, DSMC_ENOMEM. */
 int dsmc_plan(const dsmc_plan_desc *desc, dsmc_plan_t **out);
 void dsmc_plan_destroy(dsmc_plan_t *plan);
 
@@ -192,9 +195,8 @@ int dsmc_smooth_batch(dsmc_plan_t *plan, int B, const dsmc_model_t *const *model
  * every dsmc_smooth / dsmc_smooth_batch since the previous dsmc_plan_profile
  * call: synchronises the stream, fills per-kernel-class totals (HIP events
  * recorded around each launch on the plan's stream) and restarts the
- * accumulation.  Classes: 0 leaves, 1 node preparation, 2 pair rows,
- * 3 sampling, 4 gather, 5 output. */
-#define DSMC_NUM_KERNEL_CLASSES 6
+ * accumulation.  Classes: 0 leaves, 1 pair rows, 2 sampling, 3 output. */
+#define DSMC_NUM_KERNEL_CLASSES 4
 typedef struct dsmc_profile {
   int launches[DSMC_NUM_KERNEL_CLASSES];
   double ms[DSMC_NUM_KERNEL_CLASSES];

@@ -7,6 +7,7 @@
 #include <cstdarg>
 #include <cstdio>
 #include <cstring>
+#include <map>
 #include <string>
 #include <vector>
 
@@ -212,6 +213,10 @@ extern "C" void dsmc_model_destroy(dsmc_model_t* m) {
 extern "C" int dsmc_model_K(const dsmc_model_t* m) { return m ? m->K : -1; }
 
 // -------------------------------------------------------------------- plan
+struct TileChoice {
+  int RPL, W, CS;
+};
+
 struct dsmc_plan_impl {
   dsmc_plan_desc d{};
   int DX = 1;
@@ -220,60 +225,58 @@ struct dsmc_plan_impl {
   hipStream_t stream = nullptr;
   int Npad = 0, Nc = 0;
   int node_cap = 0;  // combines per launch slice
-  // device workspace
+  bool autotune = false;
+  // device workspace: per time row
   void* leafX = nullptr;
   void* leafW = nullptr;
   double* leafL = nullptr;
-  int32_t* sigma = nullptr;
+  double* bmerged = nullptr;
   int32_t* anc = nullptr;
   double* zinc = nullptr;
-  void* col = nullptr;
-  void* row = nullptr;
-  double* nscal = nullptr;
+  // per combine
+  NodeBufs nb{};
+  // per launch slice
   void* P = nullptr;
+  double* Rsum = nullptr;
+  // schedule
   NodeDesc* d_nodes = nullptr;
   int32_t* d_series_of_t = nullptr;
+  int32_t* d_leaf_cons = nullptr;
   SeriesDesc* d_series = nullptr;
   int series_cap = 0;
   // pinned staging
   NodeDesc* h_nodes = nullptr;
   int32_t* h_series_of_t = nullptr;
+  int32_t* h_leaf_cons = nullptr;
   SeriesDesc* h_series = nullptr;
   hipEvent_t staged = nullptr;
   bool staged_pending = false;
-  // schedule of the last call (host copy) and the K list it was built for
+  // schedule of the last call and the K list it was built for
   std::vector<int> sched_K;
+  std::vector<int> roots;
   std::vector<int> level_off, level_cnt;
   int total_nodes = 0;
+  // rows-kernel tile per launch size (autotuned or heuristic)
+  std::map<int, TileChoice> tiles;
   // profiling
   Timer timer;
   double last_pairs = 0.0;
 };
 
 static void plan_free(dsmc_plan_t* p) {
-  hipFree(p->leafX);
-  hipFree(p->leafW);
-  hipFree(p->leafL);
-  hipFree(p->sigma);
-  hipFree(p->anc);
-  hipFree(p->zinc);
-  hipFree(p->col);
-  hipFree(p->row);
-  hipFree(p->nscal);
-  hipFree(p->P);
-  hipFree(p->d_nodes);
-  hipFree(p->d_series_of_t);
-  hipFree(p->d_series);
-  hipHostFree(p->h_nodes);
-  hipHostFree(p->h_series_of_t);
-  hipHostFree(p->h_series);
-  if (p->staged) hipEventDestroy(p->staged);
+  void* dev[] = {p->leafX, p->leafW, p->leafL, p->bmerged, p->anc, p->zinc, p->nb.col, p->nb.row,
+                 p->nb.alpha, p->nb.bcol, p->nb.sfirst, p->nb.slast, p->P, p->Rsum, p->d_nodes,
+                 p->d_series_of_t, p->d_leaf_cons, p->d_series};
+  for (void* q : dev) (void)hipFree(q);
+  void* host[] = {p->h_nodes, p->h_series_of_t, p->h_leaf_cons, p->h_series};
+  for (void* q : host) (void)hipHostFree(q);
+  if (p->staged) (void)hipEventDestroy(p->staged);
 }
 
 static int padded_dx(int dx) {
-  int p = 1;
-  while (p < dx) p <<= 1;
-  return p;
+  int q = 1;
+  while (q < dx) q <<= 1;
+  return q;
 }
 
 extern "C" int dsmc_plan(const dsmc_plan_desc* d, dsmc_plan_t** out) {
@@ -292,58 +295,65 @@ extern "C" int dsmc_plan(const dsmc_plan_desc* d, dsmc_plan_t** out) {
   p->rsz = p->fp64 ? 8 : 4;
   p->stream = (hipStream_t)d->stream;
   p->timer.on = (d->flags & DSMC_PLAN_PROFILE) != 0;
+  p->autotune = (d->flags & DSMC_PLAN_AUTOTUNE) != 0;
   const int N = d->N;
   p->Npad = (N + kChunk - 1) / kChunk * kChunk;
   p->Nc = p->Npad / kChunk;
   const size_t TK = (size_t)p->d.max_total_K;
   const size_t max_nodes = std::max<size_t>(1, TK / 2);
-  const size_t per_node_P = (size_t)N * p->Nc * p->rsz;
+  const size_t per_node_P = (size_t)N * p->Nc * p->rsz + (size_t)N * sizeof(double);
   const size_t cap_by_mem = std::max<size_t>(1, ((size_t)1 << 30) / per_node_P);
   p->node_cap = (int)std::min(max_nodes, cap_by_mem);
   const size_t nc = (size_t)p->node_cap;
+  const size_t R = p->rsz, DXp = (size_t)p->DX;
   int rc = DSMC_OK;
-#define ALLOC(ptr, bytes)                                                   \
-  do {                                                                      \
-    hipError_t e_ = hipMalloc((void**)&(ptr), (bytes));                      \
-    if (e_ != hipSuccess) {                                                 \
-      rc = fail(DSMC_ENOMEM, "hipMalloc(%s, %zu B): %s", #ptr, (size_t)(bytes), \
-                hipGetErrorString(e_));                                     \
-      goto bad;                                                             \
-    }                                                                       \
-  } while (0)
-  ALLOC(p->leafX, (size_t)d->d_x * TK * N * p->rsz);
-  ALLOC(p->leafW, TK * N * p->rsz);
-  ALLOC(p->leafL, TK * sizeof(double));
-  ALLOC(p->sigma, TK * N * sizeof(int32_t));
-  ALLOC(p->anc, TK * 2 * N * sizeof(int32_t));
-  ALLOC(p->zinc, TK * sizeof(double));
-  ALLOC(p->col, nc * p->Npad * (p->DX + 1) * p->rsz);
-  ALLOC(p->row, nc * p->Npad * p->DX * p->rsz);
-  ALLOC(p->nscal, nc * 4 * sizeof(double));
-  ALLOC(p->P, nc * per_node_P);
-  ALLOC(p->d_nodes, TK * sizeof(NodeDesc));
-  ALLOC(p->d_series_of_t, TK * sizeof(int32_t));
-#undef ALLOC
-  if (hipHostMalloc((void**)&p->h_nodes, TK * sizeof(NodeDesc), hipHostMallocDefault) != hipSuccess ||
-      hipHostMalloc((void**)&p->h_series_of_t, TK * sizeof(int32_t), hipHostMallocDefault) != hipSuccess) {
-    rc = fail(DSMC_ENOMEM, "hipHostMalloc(schedule staging)");
-    goto bad;
+  struct A {
+    void** ptr;
+    size_t bytes;
+    const char* what;
+  } allocs[] = {
+      {&p->leafX, (size_t)d->d_x * TK * N * R, "leaf particles"},
+      {&p->leafW, TK * N * R, "leaf weights"},
+      {(void**)&p->leafL, TK * sizeof(double), "leaf log L"},
+      {(void**)&p->bmerged, TK * sizeof(double), "column bounds"},
+      {(void**)&p->anc, TK * 2 * N * sizeof(int32_t), "ancestry"},
+      {(void**)&p->zinc, TK * sizeof(double), "increments"},
+      {&p->nb.col, TK * p->Npad * (DXp + 1) * R, "column data"},
+      {&p->nb.row, TK * p->Npad * DXp * R, "row data"},
+      {&p->nb.alpha, TK * N * R, "row weights"},
+      {(void**)&p->nb.bcol, TK * sizeof(double), "column shifts"},
+      {(void**)&p->nb.sfirst, TK * N * sizeof(int32_t), "first-time ancestry"},
+      {(void**)&p->nb.slast, TK * N * sizeof(int32_t), "last-time ancestry"},
+      {&p->P, nc * N * p->Nc * R, "chunk sums"},
+      {(void**)&p->Rsum, nc * N * sizeof(double), "row sums"},
+      {(void**)&p->d_nodes, TK * sizeof(NodeDesc), "schedule"},
+      {(void**)&p->d_series_of_t, TK * sizeof(int32_t), "series map"},
+      {(void**)&p->d_leaf_cons, TK * sizeof(int32_t), "leaf consumers"},
+  };
+  for (auto& a : allocs) {
+    hipError_t e = hipMalloc(a.ptr, std::max<size_t>(a.bytes, 256));
+    if (e != hipSuccess) {
+      rc = fail(DSMC_ENOMEM, "hipMalloc(%s, %zu B): %s", a.what, a.bytes, hipGetErrorString(e));
+      plan_free(p);
+      delete p;
+      return rc;
+    }
   }
-  if (hipEventCreateWithFlags(&p->staged, hipEventDisableTiming) != hipSuccess) {
-    rc = fail(DSMC_EDEVICE, "hipEventCreate");
-    goto bad;
+  if (hipHostMalloc((void**)&p->h_nodes, TK * sizeof(NodeDesc), hipHostMallocDefault) != hipSuccess ||
+      hipHostMalloc((void**)&p->h_series_of_t, TK * sizeof(int32_t), hipHostMallocDefault) != hipSuccess ||
+      hipHostMalloc((void**)&p->h_leaf_cons, TK * sizeof(int32_t), hipHostMallocDefault) != hipSuccess ||
+      hipEventCreateWithFlags(&p->staged, hipEventDisableTiming) != hipSuccess) {
+    plan_free(p);
+    delete p;
+    return fail(DSMC_ENOMEM, "host staging allocation failed");
   }
   *out = p;
   return DSMC_OK;
-bad:
-  plan_free(p);
-  delete p;
-  return rc;
 }
 
 extern "C" void dsmc_plan_destroy(dsmc_plan_t* p) {
   if (!p) return;
-  hipStreamSynchronize(p->stream);
+  (void)hipStreamSynchronize(p->stream);
   plan_free(p);
   delete p;
 }
@@ -352,8 +362,8 @@ static int ensure_series_cap(dsmc_plan_t* p, int B) {
   if (B <= p->series_cap) return DSMC_OK;
   if (p->staged_pending) HIP_TRY(hipEventSynchronize(p->staged));
   HIP_TRY(hipStreamSynchronize(p->stream));
-  hipFree(p->d_series);
-  hipHostFree(p->h_series);
+  (void)hipFree(p->d_series);
+  (void)hipHostFree(p->h_series);
   p->d_series = nullptr;
   p->h_series = nullptr;
   int cap = std::max(B, 2 * p->series_cap);
@@ -363,38 +373,78 @@ static int ensure_series_cap(dsmc_plan_t* p, int B) {
   return DSMC_OK;
 }
 
-// Algorithm 5 for every series: level l combines blocks [2k 2^l, (2k+1) 2^l)
-// and [(2k+1) 2^l, min((2k+2) 2^l, K)) when (2k+1) 2^l < K.  Nodes of all
-// series are grouped by level.
+// Algorithm 5 for every series.  Blocks start as single time points; at each
+// level adjacent blocks (2k, 2k+1) are merged by one combine and a trailing
+// block without a right neighbour is kept as it is.  Combines get ids level
+// by level (all series of a level contiguous), and each records the combine
+// that formed its left and right blocks and the combine that consumes the
+// block it forms.
 static void build_schedule(dsmc_plan_t* p, const std::vector<int>& Ks, const std::vector<int>& bases) {
-  int maxL = 0;
-  for (int K : Ks) {
-    int L = 0;
-    while ((1 << L) < K) ++L;
-    maxL = std::max(maxL, L);
-  }
-  p->level_off.assign(maxL, 0);
-  p->level_cnt.assign(maxL, 0);
-  int n = 0;
-  for (int l = 0; l < maxL; ++l) {
-    p->level_off[l] = n;
-    const int h = 1 << l;
-    for (size_t s = 0; s < Ks.size(); ++s) {
-      const int K = Ks[s];
-      for (int a = 0; a + h < K; a += 2 * h) {
-        NodeDesc nd;
-        nd.series = (int32_t)s;
-        nd.a = a;
-        nd.c = a + h;
-        nd.b = std::min(a + 2 * h, K);
-        p->h_nodes[n++] = nd;
-      }
+  struct Blk {
+    int a, b, former;
+  };
+  const int B = (int)Ks.size();
+  std::vector<std::vector<Blk>> blocks(B);
+  for (int s = 0; s < B; ++s) {
+    blocks[s].reserve(Ks[s]);
+    for (int t = 0; t < Ks[s]; ++t) {
+      blocks[s].push_back({t, t + 1, -1});
+      p->h_series_of_t[bases[s] + t] = s;
+      p->h_leaf_cons[bases[s] + t] = -1;
     }
-    p->level_cnt[l] = n - p->level_off[l];
+  }
+  p->level_off.clear();
+  p->level_cnt.clear();
+  int n = 0;
+  for (;;) {
+    bool any = false;
+    for (int s = 0; s < B; ++s) any |= blocks[s].size() > 1;
+    if (!any) break;
+    p->level_off.push_back(n);
+    for (int s = 0; s < B; ++s) {
+      auto& bl = blocks[s];
+      if (bl.size() <= 1) continue;
+      std::vector<Blk> nxt;
+      nxt.reserve((bl.size() + 1) / 2);
+      for (size_t k = 0; k < bl.size(); k += 2) {
+        if (k + 1 == bl.size()) {
+          nxt.push_back(bl[k]);
+          continue;
+        }
+        const Blk& L = bl[k];
+        const Blk& R = bl[k + 1];
+        const int id = n++;
+        NodeDesc nd;
+        nd.series = s;
+        nd.a = L.a;
+        nd.c = R.a;
+        nd.b = R.b;
+        nd.lchild = L.former;
+        nd.rchild = R.former;
+        nd.consumer = -1;
+        nd.role = 0;
+        p->h_nodes[id] = nd;
+        if (L.former >= 0) {
+          p->h_nodes[L.former].consumer = id;
+          p->h_nodes[L.former].role = 0;
+        } else {
+          p->h_leaf_cons[bases[s] + L.a] = 2 * id;
+        }
+        if (R.former >= 0) {
+          p->h_nodes[R.former].consumer = id;
+          p->h_nodes[R.former].role = 1;
+        } else {
+          p->h_leaf_cons[bases[s] + R.a] = 2 * id + 1;
+        }
+        nxt.push_back({L.a, R.b, id});
+      }
+      bl.swap(nxt);
+    }
+    p->level_cnt.push_back(n - p->level_off.back());
   }
   p->total_nodes = n;
-  for (size_t s = 0; s < Ks.size(); ++s)
-    for (int t = 0; t < Ks[s]; ++t) p->h_series_of_t[bases[s] + t] = (int32_t)s;
+  p->roots.assign(B, -1);
+  for (int s = 0; s < B; ++s) p->roots[s] = blocks[s][0].former;
 }
 
 static int check_output(const dsmc_output* o) {
@@ -402,6 +452,75 @@ static int check_output(const dsmc_output* o) {
   if (!o->traj || !o->log_Z || !o->status)
     return fail(DSMC_EINVAL, "output traj, log_Z and status are required");
   return DSMC_OK;
+}
+
+// Column splits that bring a launch to about `want` waves (8 waves per SIMD).
+static int pick_cs(int nodes, int N, int Nc, int rpl, int W) {
+  const long rb = (N + 64L * rpl * W - 1) / (64L * rpl * W);
+  const long waves = (long)nodes * rb * W;
+  const long want = 8192;
+  const long cs = (want + waves - 1) / waves;
+  return (int)std::max<long>(1, std::min<long>(cs, Nc));
+}
+
+// Heuristic rows-kernel tile: most rows per lane that still gives 16 waves
+// per CU without column splits, else one row per lane and column splits.
+static TileChoice heuristic_tile(int nodes, int N, int Nc) {
+  const int rpls[3] = {4, 2, 1};
+  for (int rpl : rpls) {
+    const long waves = (long)nodes * ((N + 64 * rpl - 1) / (64 * rpl));
+    if (waves >= 4096 || rpl == 1) {
+      int W = 4;
+      while (W > 1 && 64 * rpl * W > N) W >>= 1;
+      return {rpl, W, pick_cs(nodes, N, Nc, rpl, W)};
+    }
+  }
+  return {1, 1, 1};
+}
+
+static void set_tile(LevelLaunch& L, TileChoice tc) {
+  L.RPL = tc.RPL;
+  L.W = tc.W;
+  L.RB = (L.N + 64 * tc.RPL * tc.W - 1) / (64 * tc.RPL * tc.W);
+  L.KC = (L.Nc + tc.CS - 1) / tc.CS;
+  L.CS = (L.Nc + L.KC - 1) / L.KC;
+}
+
+// Time every (rows per lane, waves per workgroup) candidate, each with the
+// column splits that fill the chip, on this launch's real inputs (the rows
+// kernel only writes its own outputs) and keep the fastest.  The tile does
+// not change any result.
+static TileChoice autotune_tile(dsmc_plan_t* p, LevelLaunch L) {
+  TileChoice best = heuristic_tile(L.nodes, L.N, L.Nc);
+  hipEvent_t e0, e1;
+  if (hipEventCreate(&e0) != hipSuccess) return best;
+  if (hipEventCreate(&e1) != hipSuccess) {
+    (void)hipEventDestroy(e0);
+    return best;
+  }
+  float best_ms = 1e30f;
+  const int rpls[3] = {1, 2, 4};
+  const int ws[3] = {1, 2, 4};
+  for (int rpl : rpls)
+    for (int w : ws) {
+      if (64 * rpl * w > 2 * L.N && !(rpl == 1 && w == 1)) continue;
+      const TileChoice tc{rpl, w, pick_cs(L.nodes, L.N, L.Nc, rpl, w)};
+      set_tile(L, tc);
+      float ms = 0.0f;
+      bool ok = true;
+      for (int rep = 0; rep < 2 && ok; ++rep) {
+        ok = hipEventRecord(e0, p->stream) == hipSuccess && launch_rows_only(L, p->stream) == 0 &&
+             hipEventRecord(e1, p->stream) == hipSuccess && hipEventSynchronize(e1) == hipSuccess &&
+             hipEventElapsedTime(&ms, e0, e1) == hipSuccess;
+      }
+      if (ok && ms < best_ms) {
+        best_ms = ms;
+        best = tc;
+      }
+    }
+  (void)hipEventDestroy(e0);
+  (void)hipEventDestroy(e1);
+  return best;
 }
 
 extern "C" int dsmc_smooth_batch(dsmc_plan_t* p, int B, const dsmc_model_t* const* models,
@@ -441,6 +560,7 @@ extern "C" int dsmc_smooth_batch(dsmc_plan_t* p, int B, const dsmc_model_t* cons
     sd.seed = seeds[s];
     sd.K = Ks[s];
     sd.base = bases[s];
+    sd.root = p->roots[s];
     sd.anc = o.ancestry ? o.ancestry : p->anc + (size_t)bases[s] * 2 * N;
     sd.zinc = o.logZ_inc ? o.logZ_inc : p->zinc + bases[s];
     sd.row_lse = o.row_lse;
@@ -465,6 +585,8 @@ extern "C" int dsmc_smooth_batch(dsmc_plan_t* p, int B, const dsmc_model_t* cons
                              hipMemcpyHostToDevice, st));
     HIP_TRY(hipMemcpyAsync(p->d_series_of_t, p->h_series_of_t, (size_t)totalK * sizeof(int32_t),
                            hipMemcpyHostToDevice, st));
+    HIP_TRY(hipMemcpyAsync(p->d_leaf_cons, p->h_leaf_cons, (size_t)totalK * sizeof(int32_t),
+                           hipMemcpyHostToDevice, st));
   }
   HIP_TRY(hipEventRecord(p->staged, st));
   p->staged_pending = true;
@@ -474,17 +596,20 @@ extern "C" int dsmc_smooth_batch(dsmc_plan_t* p, int B, const dsmc_model_t* cons
   LL.fp64 = p->fp64;
   LL.DX = p->DX;
   LL.N = N;
+  LL.Npad = p->Npad;
   LL.totalK = totalK;
   LL.d_series = p->d_series;
   LL.d_series_of_t = p->d_series_of_t;
+  LL.d_leaf_cons = p->d_leaf_cons;
+  LL.d_nodes = p->d_nodes;
   LL.leafX = p->leafX;
   LL.leafW = p->leafW;
   LL.leafL = p->leafL;
-  LL.sigma = p->sigma;
+  LL.bmerged = p->bmerged;
+  LL.nb = p->nb;
   if (launch_leaves(LL, st, &p->timer)) return fail(DSMC_EUNSUPPORTED, "no leaf kernel for d_x");
   HIP_TRY(hipGetLastError());
 
-  const int RB = (N + kBlock - 1) / kBlock;
   for (size_t l = 0; l < p->level_cnt.size(); ++l) {
     const int cnt = p->level_cnt[l];
     for (int s0 = 0; s0 < cnt; s0 += p->node_cap) {
@@ -492,34 +617,34 @@ extern "C" int dsmc_smooth_batch(dsmc_plan_t* p, int B, const dsmc_model_t* cons
       LevelLaunch L{};
       L.fp64 = p->fp64;
       L.DX = p->DX;
+      L.node0 = p->level_off[l] + s0;
       L.nodes = nodes;
       L.N = N;
       L.Npad = p->Npad;
       L.Nc = p->Nc;
-      L.RB = RB;
-      // enough workgroups to fill the chip: split the columns of a node
-      const long want = 4096;
-      int CS = (int)std::min<long>(p->Nc, std::max<long>(1, (want + (long)nodes * RB - 1) / ((long)nodes * RB)));
-      const int KC = (p->Nc + CS - 1) / CS;
-      CS = (p->Nc + KC - 1) / KC;
-      L.CS = CS;
-      L.KC = KC;
       L.totalK = totalK;
-      L.d_nodes = p->d_nodes + p->level_off[l] + s0;
+      L.d_nodes = p->d_nodes;
       L.d_series = p->d_series;
       L.leafX = p->leafX;
-      L.leafW = p->leafW;
-      L.sigma = p->sigma;
-      L.col = p->col;
-      L.row = p->row;
-      L.nscal = p->nscal;
+      L.bmerged = p->bmerged;
       L.P = p->P;
+      L.Rsum = p->Rsum;
+      L.nb = p->nb;
+      auto it = p->tiles.find(nodes);
+      TileChoice tc;
+      if (it != p->tiles.end()) {
+        tc = it->second;
+      } else {
+        tc = p->autotune ? autotune_tile(p, L) : heuristic_tile(nodes, N, p->Nc);
+        p->tiles[nodes] = tc;
+      }
+      set_tile(L, tc);
+      // sampling: enough workgroups to cover the chip when a level has few combines
+      const int ds_max = std::max(1, (N + 127) / 128);
+      L.DS = (int)std::min<long>(ds_max, std::max<long>(1, (2048 + nodes - 1) / nodes));
       if (launch_level(L, st, &p->timer)) return fail(DSMC_EUNSUPPORTED, "no combine kernel for d_x");
       HIP_TRY(hipGetLastError());
     }
-    launch_gather(p->d_nodes + p->level_off[l], p->d_series, cnt, 2 << l, N, p->sigma, st,
-                  &p->timer);
-    HIP_TRY(hipGetLastError());
   }
   launch_output(LL, B, p->d.d_x, st, &p->timer);
   HIP_TRY(hipGetLastError());

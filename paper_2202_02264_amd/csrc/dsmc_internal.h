@@ -6,7 +6,7 @@
 
 namespace dsmc {
 
-constexpr int kBlock = 256;  // threads per workgroup (4 wave64)
+constexpr int kBlock = 256;  // threads per workgroup of the leaf / sample / output kernels
 constexpr int kChunk = 32;   // columns per chunk of the pair matrix
 
 // Device-resident model (one allocation: this header, then the arrays).
@@ -21,11 +21,9 @@ struct DevModel {
   const double* f;        // [dx]
   const double* Q_inv;    // [dx][dx] inverse of the transition Cholesky factor
   double trans_lognorm;   // -sum log diag(Q_chol) - dx/2 log(2 pi)
-  const double* H;        // [dy][dx]
-  const double* h;        // [dy]
-  const double* R_inv;    // [dy][dy]
+  const double* H;        // [dy][dx] R^{-1/2} H (linear-Gaussian potential)
+  const double* y;        // [K][dy]  R^{-1/2} (y_t - h), or raw y_t (stochastic volatility)
   double obs_lognorm;
-  const double* y;        // [K][dy]
   const double* q_mean;   // [K][dx]
   const double* q_chol;   // [K][dx][dx]
   const double* q_inv;    // [K][dx][dx]
@@ -41,6 +39,8 @@ struct SeriesDesc {
   uint64_t seed;
   int K;
   int base;               // offset of its time 0 on the packed time axis
+  int root;               // node id of its last combine (-1 if K == 1)
+  int pad_;
   int32_t* anc;           // [K-1][2][N]
   double* zinc;           // [K-1]
   double* row_lse;        // [K-1][N] or null
@@ -54,12 +54,29 @@ struct SeriesDesc {
   int32_t* index;         // [K][N] or null
 };
 
-// One combine of a level: boundary c of series `series`.
+// One combine at boundary c of series `series`: left block [a, c), right
+// block [c, b).  lchild / rchild: node that formed the left / right block
+// (-1: the block is a single leaf).  consumer: the node that will combine the
+// block formed here (-1: root); role 0 = it is that node's left block, 1 = right.
 struct NodeDesc {
   int32_t series;
   int32_t c;
-  int32_t a;      // first time of the left block
-  int32_t b;      // one past the last time of the right block
+  int32_t a;
+  int32_t b;
+  int32_t lchild;
+  int32_t rchild;
+  int32_t consumer;
+  int32_t role;
+};
+
+// Per-node buffers, indexed by node id (position in the schedule).
+struct NodeBufs {
+  void* col;        // [nodes][Npad][DX+1]  (u_n, beta_n) of the node's right block
+  void* row;        // [nodes][Npad][DX]    v_m of the node's left block
+  void* alpha;      // [nodes][N]           left block log-weights a_m (real type)
+  double* bcol;     // [nodes]              B: shift of the node's beta (log2 units: beta = log2e (b - B))
+  int32_t* sfirst;  // [nodes][N]           leaf index, at the block's first time, of trajectory n
+  int32_t* slast;   // [nodes][N]           same at the block's last time
 };
 
 enum : int32_t { kFlagDegenerate = 1, kFlagNumeric = 2 };

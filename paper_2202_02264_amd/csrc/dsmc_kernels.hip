@@ -1,20 +1,20 @@
 // HIP kernels of the dSMC combine tree for gfx950 (wave64, fp32/fp64 VALU).
 //
-// Per level of the tree (Algorithm 5) four kernels run over all combine
-// nodes of the level (of every series in the launch):
-//   k_prep    per node: whitened coordinates and log-weights of the two
-//             boundary particle sets (O(N d_x^2)).
-//   k_rows    the N x N pair-weight matrix of every node, never stored: one
-//             lane per row, columns streamed through scalar registers, the
-//             exp2 of each entry summed per chunk of 32 columns.  Output: the
-//             chunk sums P[node][m][k].
-//   k_sample  per node: row sums -> row marginal CDF (fp64 scan) -> left index
-//             by binary search; right index by a scan over that row's chunk
-//             sums and a recomputation of one 32-column chunk (Algorithm 1's
-//             multinomial resampling, in two stages).
-//   k_gather  in-place gather of the composed ancestry sigma[t][n] (leaf index
-//             of trajectory n at time t) for every time row of the merged blocks.
-// Leaves (Algorithm 2) and the output pass run once per call.
+//   k_leaves   once per call, one workgroup per time point: Algorithm 2 (draw,
+//              weight, normalise), plus the data the time point's consumer
+//              combine needs (whitened coordinates and log-weights).
+//   k_rows     per level: the N x N pair-weight matrix of every combine, never
+//              stored.  Each lane owns RPL rows; all lanes walk the same
+//              columns, whose (u, beta) are wave-uniform and come through
+//              scalar registers.  Per pair: DX x (sub, fma) + exp2 + add.
+//              Output: 32-column chunk sums and fp64 row sums.
+//   k_sample   per level: per combine, the fp64 row-marginal CDF, N two-stage
+//              multinomial draws (Algorithm 1), the ancestry of the merged
+//              block's first and last times, and the data its consumer combine
+//              needs.  Several workgroups may share one combine's draws.
+//   k_output   once per call: each output entry follows the ancestry from the
+//              root combine down to its leaf (the gather of Algorithm 1, done
+//              once instead of per level).
 #include <hip/hip_runtime.h>
 
 #include <cmath>
@@ -24,18 +24,60 @@
 
 namespace dsmc {
 
-// ================================================================ leaves
-// One workgroup per time row g of the packed time axis: draw X_g^n ~ q_t from
-// the Philox normals, store it (rounded to R), weight the rounded particle
-// (Algorithm 2 with the t = 0 weight of Proposition 2.2), normalise.
+// Whitened column coordinates of a right-block particle x at boundary c:
+// u = Wcol (x - q_mean[c]).
+template <int DX>
+__device__ __forceinline__ void col_coords(const DevModel& M, int c, const double (&x)[DX],
+                                           double (&u)[DX]) {
+  const int dx = M.dx;
+  const double* qm = M.q_mean + (size_t)c * dx;
+#pragma unroll
+  for (int i = 0; i < DX; ++i) {
+    double s = 0.0;
+    if (i < dx)
+      for (int j = 0; j < dx; ++j) s += M.Wcol[i * dx + j] * (x[j] - qm[j]);
+    u[i] = s;
+  }
+}
+
+// Whitened row coordinates of a left-block particle x at boundary c:
+// v = Wrow x + wcol_off - Wcol q_mean[c], so that
+// ||u - v||^2 = (log2 e / 2) ||Q^{-1/2} (x_R - F x_L - f)||^2.
+template <int DX>
+__device__ __forceinline__ void row_coords(const DevModel& M, int c, const double (&x)[DX],
+                                           double (&v)[DX]) {
+  const int dx = M.dx;
+  const double* qm = M.q_mean + (size_t)c * dx;
+#pragma unroll
+  for (int i = 0; i < DX; ++i) {
+    double s = 0.0;
+    if (i < dx) {
+      s = M.wcol_off[i];
+      for (int j = 0; j < dx; ++j) s += M.Wrow[i * dx + j] * x[j] - M.Wcol[i * dx + j] * qm[j];
+    }
+    v[i] = s;
+  }
+}
+
 template <typename R, int DX>
-__global__ __launch_bounds__(kBlock) void k_leaves(const SeriesDesc* __restrict__ series,
-                                                   const int32_t* __restrict__ series_of_t,
-                                                   int totalK, int N, R* __restrict__ leafX,
-                                                   R* __restrict__ leafW,
-                                                   double* __restrict__ leafL,
-                                                   int32_t* __restrict__ sigma) {
-  extern __shared__ double ell[];  // [N]
+__device__ __forceinline__ void load_particle(const R* __restrict__ leafX, int totalK, int N, int g,
+                                              int src, int dx, double (&x)[DX]) {
+#pragma unroll
+  for (int i = 0; i < DX; ++i)
+    x[i] = (i < dx) ? (double)leafX[((size_t)i * totalK + g) * N + src] : 0.0;
+}
+
+// ================================================================ leaves
+// One workgroup per time row g of the packed time axis.
+template <typename R, int DX>
+__global__ __launch_bounds__(kBlock) void k_leaves(
+    const SeriesDesc* __restrict__ series, const int32_t* __restrict__ series_of_t,
+    const int32_t* __restrict__ leaf_cons, const NodeDesc* __restrict__ nodes, int totalK, int N,
+    int Npad, R* __restrict__ leafX, R* __restrict__ leafW, double* __restrict__ leafL,
+    double* __restrict__ bmerged, NodeBufs nb) {
+  extern __shared__ double sh[];
+  double* ell = sh;      // [N] unnormalised leaf log-weights
+  double* gq = sh + N;   // [N] -log q_t(x) (+ log h_t(x) under boundary weighting)
   __shared__ double red[kBlock / 64];
   __shared__ int redi[kBlock / 64];
   const int g = blockIdx.x;
@@ -43,6 +85,7 @@ __global__ __launch_bounds__(kBlock) void k_leaves(const SeriesDesc* __restrict_
   const DevModel& M = *sd.model;
   const int t = g - sd.base;
   const int dx = M.dx;
+  const double logN = log((double)N);
   int bad = 0;
   for (int n = threadIdx.x; n < N; n += kBlock) {
     double z[DX + 3];
@@ -69,225 +112,203 @@ __global__ __launch_bounds__(kBlock) void k_leaves(const SeriesDesc* __restrict_
       }
       x[i] = xi;
     }
-    double l;
+    const double lq = log_proposal<DX>(M, t, x);
+    double l, gg = -lq;
     if (t == 0) {
-      l = log_potential<DX>(M, 0, x) + log_prior<DX>(M, x) - log_proposal<DX>(M, 0, x);
+      l = log_potential<DX>(M, 0, x) + log_prior<DX>(M, x) - lq;
+      if (M.weighting == 1) gg += log_potential<DX>(M, 0, x);
     } else if (M.weighting == 0) {
       l = log_potential<DX>(M, t, x);
     } else {
       l = 0.0;
+      gg += log_potential<DX>(M, t, x);
     }
-    if (isnan(l)) bad = kFlagNumeric;
+    if (isnan(l) || isnan(gg)) bad = kFlagNumeric;
     ell[n] = l;
-    sigma[(size_t)g * N + n] = n;
+    gq[n] = gg;
   }
   __syncthreads();
-  double mx = -INFINITY;
-  for (int n = threadIdx.x; n < N; n += kBlock) mx = fmax(mx, ell[n]);
+  double mx = -INFINITY, gmx = -INFINITY;
+  for (int n = threadIdx.x; n < N; n += kBlock) {
+    mx = fmax(mx, ell[n]);
+    gmx = fmax(gmx, gq[n]);
+  }
   mx = block_max(mx, red);
+  gmx = block_max(gmx, red);
   double s = 0.0;
   if (mx > -INFINITY)
     for (int n = threadIdx.x; n < N; n += kBlock) s += exp(ell[n] - mx);
   s = block_sum(s, red);
-  const double lse = mx + log(s);
   const bool degenerate = !(mx > -INFINITY);
-  for (int n = threadIdx.x; n < N; n += kBlock)
-    leafW[(size_t)g * N + n] = degenerate ? (R)(-log((double)N)) : (R)(ell[n] - lse);
+  const double lse = mx + log(s);
+  double bmax = -INFINITY;  // max_n (lbar_n + gq_n): shift of a leaf right block
+  for (int n = threadIdx.x; n < N; n += kBlock) {
+    const double lbar = degenerate ? -logN : ell[n] - lse;
+    const R lr = (R)lbar;
+    leafW[(size_t)g * N + n] = lr;
+    ell[n] = (double)lr;  // the stored (rounded) weight is what every consumer sees
+    bmax = fmax(bmax, (double)lr + gq[n]);
+  }
+  bmax = block_max(bmax, red);
   bad = block_or_i(bad, redi);
   if (threadIdx.x == 0) {
-    leafL[g] = degenerate ? -INFINITY : lse - log((double)N);
+    leafL[g] = degenerate ? -INFINITY : lse - logN;
+    bmerged[g] = -logN + gmx;
     const int flags = bad | (degenerate ? kFlagDegenerate : 0);
     if (flags) atomicOr(sd.status, flags);
   }
-}
-
-// ================================================================= prep
-// One workgroup per node.  Column data (right block, time c):
-//   u_n   = Wcol (x_R[n] - q_mean[c])                        (DX values)
-//   beta_n = log2e (b_n - B*),  b_n = w_R[n] - log q_c(x_R[n]) [+ log h_c(x_R[n])]
-// Row data (left block, time c-1):
-//   v_m   = Wrow x_L[m] + wcol_off - Wcol q_mean[c]
-// so that ||u_n - v_m||^2 = (log2 e / 2) ||Q^{-1/2}(x_R - F x_L - f)||^2 and
-// exp2(beta_n - ||u_n - v_m||^2) = exp(b_n - B* + log p(x_R|x_L) - trans_lognorm).
-// Centering both sets on the proposal mean keeps the fp32 coordinates small.
-// Scalars: nscal[node] = {A* = max_m a_m, B*, trans_lognorm, 0}.
-template <typename R, int DX>
-__global__ __launch_bounds__(kBlock) void k_prep(const NodeDesc* __restrict__ nodes,
-                                                 const SeriesDesc* __restrict__ series,
-                                                 int totalK, int N, int Npad,
-                                                 const R* __restrict__ leafX,
-                                                 const R* __restrict__ leafW,
-                                                 const int32_t* __restrict__ sigma,
-                                                 R* __restrict__ col, R* __restrict__ row,
-                                                 double* __restrict__ nscal) {
-  extern __shared__ double bsh[];  // [N]
-  __shared__ double red[kBlock / 64];
-  __shared__ int redi[kBlock / 64];
-  const NodeDesc nd = nodes[blockIdx.x];
-  const SeriesDesc& sd = series[nd.series];
-  const DevModel& M = *sd.model;
-  const int c = nd.c, dx = M.dx;
-  const bool left_leaf = (c - nd.a) == 1, right_leaf = (nd.b - c) == 1;
-  const int gL = sd.base + c - 1, gR = sd.base + c;
-  const double logN = log((double)N);
-  R* colp = col + (size_t)blockIdx.x * Npad * (DX + 1);
-  R* rowp = row + (size_t)blockIdx.x * Npad * DX;
-  const double* qmc = M.q_mean + (size_t)c * dx;
-  int bad = 0;
-  // centre: Wcol q_mean[c] (each side subtracts it)
-  double cen[DX];
+  // data of the combine that consumes this single-point block
+  const int cons = leaf_cons[g];
+  if (cons < 0) return;
+  const int P = cons >> 1, role = cons & 1;
+  const int c = nodes[P].c;
+  if (role == 1) {  // right block of combine P (c == t)
+    R* colp = (R*)nb.col + (size_t)P * Npad * (DX + 1);
+    for (int n = threadIdx.x; n < Npad; n += kBlock) {
+      if (n < N) {
+        double x[DX], u[DX];
+        load_particle<R, DX>(leafX, totalK, N, g, n, dx, x);
+        col_coords<DX>(M, c, x, u);
 #pragma unroll
-  for (int i = 0; i < DX; ++i) {
-    double s = 0.0;
-    if (i < dx)
-      for (int j = 0; j < dx; ++j) s += M.Wcol[i * dx + j] * qmc[j];
-    cen[i] = s;
-  }
-  double bmax = -INFINITY;
-  for (int n = threadIdx.x; n < N; n += kBlock) {
-    const int src = sigma[(size_t)gR * N + n];
-    double x[DX];
+        for (int i = 0; i < DX; ++i) colp[(size_t)n * (DX + 1) + i] = (R)u[i];
+        const double beta =
+            (bmax > -INFINITY) ? (ell[n] + gq[n] - bmax) * kLog2e : -INFINITY;
+        colp[(size_t)n * (DX + 1) + DX] = (R)beta;
+      } else {
 #pragma unroll
-    for (int i = 0; i < DX; ++i)
-      x[i] = (i < dx) ? (double)leafX[((size_t)i * totalK + gR) * N + src] : 0.0;
-    double b = (right_leaf ? (double)leafW[(size_t)gR * N + src] : -logN) -
-               log_proposal<DX>(M, c, x);
-    if (M.weighting == 1) b += log_potential<DX>(M, c, x);
-    if (isnan(b)) bad = kFlagNumeric;
-    bsh[n] = b;
-    bmax = fmax(bmax, b);
-#pragma unroll
-    for (int i = 0; i < DX; ++i) {
-      double u = 0.0;
-      if (i < dx) {
-        for (int j = 0; j < dx; ++j) u += M.Wcol[i * dx + j] * (x[j] - qmc[j]);
+        for (int i = 0; i < DX; ++i) colp[(size_t)n * (DX + 1) + i] = (R)0;
+        colp[(size_t)n * (DX + 1) + DX] = (R)(-INFINITY);
       }
-      colp[(size_t)n * (DX + 1) + i] = (R)u;
     }
-  }
-  for (int n = N + threadIdx.x; n < Npad; n += kBlock) {
+    if (threadIdx.x == 0) nb.bcol[P] = bmax;
+  } else {  // left block of combine P (c == t + 1)
+    R* rowp = (R*)nb.row + (size_t)P * Npad * DX;
+    for (int n = threadIdx.x; n < N; n += kBlock) {
+      double x[DX], v[DX];
+      load_particle<R, DX>(leafX, totalK, N, g, n, dx, x);
+      row_coords<DX>(M, c, x, v);
 #pragma unroll
-    for (int i = 0; i < DX; ++i) colp[(size_t)n * (DX + 1) + i] = (R)0;
-    colp[(size_t)n * (DX + 1) + DX] = (R)(-INFINITY);
-  }
-  double amax = -INFINITY;
-  for (int m = threadIdx.x; m < N; m += kBlock) {
-    const int src = sigma[(size_t)gL * N + m];
-    double x[DX];
-#pragma unroll
-    for (int i = 0; i < DX; ++i)
-      x[i] = (i < dx) ? (double)leafX[((size_t)i * totalK + gL) * N + src] : 0.0;
-    const double a = left_leaf ? (double)leafW[(size_t)gL * N + src] : -logN;
-    amax = fmax(amax, a);
-#pragma unroll
-    for (int i = 0; i < DX; ++i) {
-      double v = 0.0;
-      if (i < dx) {
-        v = M.wcol_off[i] - cen[i];
-        for (int j = 0; j < dx; ++j) v += M.Wrow[i * dx + j] * x[j];
-      }
-      rowp[(size_t)m * DX + i] = (R)v;
+      for (int i = 0; i < DX; ++i) rowp[(size_t)n * DX + i] = (R)v[i];
+      ((R*)nb.alpha)[(size_t)P * N + n] = (R)ell[n];
     }
-  }
-  bmax = block_max(bmax, red);  // contains a __syncthreads: bsh is complete
-  amax = block_max(amax, red);
-  for (int n = threadIdx.x; n < N; n += kBlock) {
-    const double beta = (bmax > -INFINITY) ? (bsh[n] - bmax) * kLog2e : -INFINITY;
-    colp[(size_t)n * (DX + 1) + DX] = (R)beta;
-  }
-  bad = block_or_i(bad, redi);
-  if (threadIdx.x == 0) {
-    double* ns = nscal + (size_t)blockIdx.x * 4;
-    ns[0] = amax;
-    ns[1] = bmax;
-    ns[2] = M.trans_lognorm;
-    ns[3] = 0.0;
-    if (bad) atomicOr(sd.status, bad);
   }
 }
 
 // ================================================================= rows
-// Tile = (node, 256-row block, range of KC column chunks).  Lane m of the
-// workgroup owns row m; all lanes walk the same columns, whose (u, beta) are
-// wave-uniform and so are read into scalar registers.  Per pair:
-// DX x (sub, fma) + exp2 + add.
-template <typename R, int DX>
+// Tile = (combine, row block of RPL*64*W rows, column split of KC chunks).
+// Lane owns rows base + lane + 64 r, r < RPL; lanes past N recompute row N-1
+// and store the same values (no per-row branches).  Chunk sums go to
+// P[node][k][m] (coalesced over m).  With one column split the tile also
+// stores the row sum sum_k P[k][m] (fp64, k ascending); otherwise the
+// sampling kernel forms that same sum from P.
+template <typename R, int DX, int RPL>
 __global__ __launch_bounds__(kBlock) void k_rows(const R* __restrict__ col,
                                                  const R* __restrict__ row,
-                                                 R* __restrict__ P, int N, int Npad, int Nc,
-                                                 int RB, int CS, int KC) {
+                                                 R* __restrict__ P, double* __restrict__ Rsum,
+                                                 int node0, int N, int Npad, int Nc, int RB,
+                                                 int CS, int KC) {
+  const int W = blockDim.x >> 6;
   const int tiles = RB * CS;
-  const int node = blockIdx.x / tiles;
-  const int tile = blockIdx.x - node * tiles;
+  const int node_local = blockIdx.x / tiles;
+  const int tile = blockIdx.x - node_local * tiles;
   const int rb = tile / CS, cs = tile - rb * CS;
-  const int m = rb * kBlock + threadIdx.x;
-  const R* __restrict__ colp = col + (size_t)node * Npad * (DX + 1);
-  R v[DX];
-  const int mm = m < N ? m : N - 1;
+  const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
+  const int base = (rb * W + wave) * 64 * RPL;
+  if (base >= N) return;  // wave-uniform
+  const size_t nodeid = (size_t)node0 + node_local;
+  const R* __restrict__ colp = col + nodeid * Npad * (DX + 1);
+  R v[RPL][DX];
+  int mrow[RPL];
 #pragma unroll
-  for (int i = 0; i < DX; ++i) v[i] = row[((size_t)node * Npad + mm) * DX + i];
-  const int k0 = cs * KC;
-  const int k1 = min(Nc, k0 + KC);
-  R* __restrict__ Pm = P + ((size_t)node * N + mm) * Nc;
+  for (int r = 0; r < RPL; ++r) {
+    const int m = base + lane + 64 * r;
+    mrow[r] = m < N ? m : N - 1;
+#pragma unroll
+    for (int i = 0; i < DX; ++i) v[r][i] = row[(nodeid * Npad + mrow[r]) * DX + i];
+  }
+  double Rm[RPL];
+#pragma unroll
+  for (int r = 0; r < RPL; ++r) Rm[r] = 0.0;
+  R* __restrict__ Pn = P + (size_t)node_local * Nc * N;
+  const int k0 = cs * KC, k1 = min(Nc, k0 + KC);
   for (int k = k0; k < k1; ++k) {
     const R* __restrict__ cp = colp + (size_t)k * kChunk * (DX + 1);
-    R acc = (R)0;
+    R acc[RPL];
+#pragma unroll
+    for (int r = 0; r < RPL; ++r) acc[r] = (R)0;
 #pragma unroll
     for (int jj = 0; jj < kChunk; ++jj) {
       R u[DX];
 #pragma unroll
       for (int i = 0; i < DX; ++i) u[i] = cp[jj * (DX + 1) + i];
-      acc += Real<R>::exp2(pair_log2w<R, DX>(u, cp[jj * (DX + 1) + DX], v));
+      const R beta = cp[jj * (DX + 1) + DX];
+#pragma unroll
+      for (int r = 0; r < RPL; ++r) acc[r] += Real<R>::exp2(pair_log2w<R, DX>(u, beta, v[r]));
     }
-    if (m < N) Pm[k] = acc;
+#pragma unroll
+    for (int r = 0; r < RPL; ++r) {
+      Pn[(size_t)k * N + mrow[r]] = acc[r];
+      Rm[r] += (double)acc[r];
+    }
+  }
+  if (CS == 1) {
+#pragma unroll
+    for (int r = 0; r < RPL; ++r) Rsum[(size_t)node_local * N + mrow[r]] = Rm[r];
   }
 }
 
 // =============================================================== sample
-// One workgroup per node (Algorithm 1: normalise, draw N index pairs).
-//   R_m  = sum_k P[m][k]                         (fp64, k ascending)
-//   w_m  = exp(a_m - A*) R_m,   C_m = sum_{i<=m} w_i   (fp64 scan)
-//   Z_c  = A* + B* + trans_lognorm + log C_{N-1}
-//   l_n  = first m with C_m > u1 C_{N-1}
-//   r_n  = first j with  cumulative row-l weight > u2 R_l, found by a scan
-//          over the chunk sums of row l and one recomputed chunk.
-// Rows whose R_m underflows fp32 range (< kTiny) are recomputed with their
-// exact maximum as shift and drawn from by a full-row scan.
+// Workgroup (combine, ds) of DS workgroups per combine; each builds the row
+// CDF of its combine and takes the draws n in [ds per, (ds+1) per).
+//   w_m = exp(rho_m - G),  rho_m = a_m - A* + ln R_m (+ shift_m ln 2),  G = max rho
+//   C_m = sum_{i<=m} w_i (fp64);  Z_c = A* + B + trans_lognorm + G + ln C_{N-1}
+//   l_n = first m with C_m > u1 C_{N-1}
+//   r_n = first j with (chunk prefix + within-chunk prefix) > u2 R_l
+// Rows whose R_m underflows fp32 range are recomputed with their exact
+// maximum as shift and drawn from by a full-row scan.
 template <typename R, int DX>
 __global__ __launch_bounds__(kBlock) void k_sample(
-    const NodeDesc* __restrict__ nodes, const SeriesDesc* __restrict__ series, int totalK,
-    int N, int Npad, int Nc, const R* __restrict__ leafW, const int32_t* __restrict__ sigma,
-    const R* __restrict__ col, const R* __restrict__ row, const R* __restrict__ P,
-    const double* __restrict__ nscal) {
+    const NodeDesc* __restrict__ nodes, const SeriesDesc* __restrict__ series, int node0, int DS,
+    int totalK, int N, int Npad, int Nc, int rows_summed, const R* __restrict__ leafX,
+    const double* __restrict__ bmerged, const R* __restrict__ P,
+    const double* __restrict__ Rsum, NodeBufs nb) {
   extern __shared__ double smem[];
-  double* cdf = smem;                          // [Npad]
-  double* rs = smem + Npad;                    // [Npad]
-  float* shift = (float*)(smem + 2 * Npad);    // [Npad]
+  double* cdf = smem;                        // [Npad]
+  double* rs = smem + Npad;                  // [Npad]
+  float* shift = (float*)(smem + 2 * Npad);  // [Npad]
   __shared__ double red[kBlock / 64];
   __shared__ int redi[kBlock / 64];
-  const int node = blockIdx.x;
-  const NodeDesc nd = nodes[node];
+  const int node_local = blockIdx.x / DS;
+  const int ds = blockIdx.x - node_local * DS;
+  const int nodeid = node0 + node_local;
+  const NodeDesc nd = nodes[nodeid];
   const SeriesDesc& sd = series[nd.series];
-  const int c = nd.c;
-  const bool left_leaf = (c - nd.a) == 1;
-  const int gL = sd.base + c - 1;
+  const DevModel& M = *sd.model;
+  const int c = nd.c, dx = M.dx;
+  const bool left_leaf = nd.lchild < 0;
   const double logN = log((double)N);
-  const double* ns = nscal + (size_t)node * 4;
-  const double Astar = ns[0], Bstar = ns[1], c0 = ns[2];
-  const R* __restrict__ colp = col + (size_t)node * Npad * (DX + 1);
-  const R* __restrict__ rowp = row + (size_t)node * Npad * DX;
-  const R* __restrict__ Pn = P + (size_t)node * N * Nc;
+  const R* __restrict__ colp = (const R*)nb.col + (size_t)nodeid * Npad * (DX + 1);
+  const R* __restrict__ rowp = (const R*)nb.row + (size_t)nodeid * Npad * DX;
+  const R* __restrict__ Pn = P + (size_t)node_local * Nc * N;
+  const double* __restrict__ Rn = Rsum + (size_t)node_local * N;
+  const R* __restrict__ alp = (const R*)nb.alpha + (size_t)nodeid * N;
 
-  // ---- row sums and log row weights (thread owns a contiguous segment of rows)
-  //   rho_m = a_m - A* + shift_m ln 2 + ln R_m;  w_m = exp(rho_m - G), G = max rho
+  // ---- log row weights (thread owns a contiguous segment of rows)
   const int per = (N + kBlock - 1) / kBlock;
   const int m0 = threadIdx.x * per, m1 = min(N, m0 + per);
+  double amax = -INFINITY;
+  for (int m = m0; m < m1; ++m) amax = fmax(amax, left_leaf ? (double)alp[m] : -logN);
+  const double Astar = block_max(amax, red);
   double gmax = -INFINITY;
   bool row_nan = false;
   for (int m = m0; m < m1; ++m) {
-    double Rm = 0.0;
-    const R* Pm = Pn + (size_t)m * Nc;
-    for (int k = 0; k < Nc; ++k) Rm += (double)Pm[k];
+    double Rm;
+    if (rows_summed) {
+      Rm = Rn[m];
+    } else {  // the same sequential chunk-order sum the rows kernel forms
+      Rm = 0.0;
+      for (int k = 0; k < Nc; ++k) Rm += (double)Pn[(size_t)k * N + m];
+    }
     float sh = 0.0f;
     if (!(Rm >= Real<R>::kTiny) && !isnan(Rm)) {
       // underflow rescue: exact row maximum as shift, full-row fp64 sum
@@ -301,8 +322,8 @@ __global__ __launch_bounds__(kBlock) void k_sample(
         for (int i = 0; i < DX; ++i) u[i] = colp[(size_t)j * (DX + 1) + i];
         smax = fmax(smax, pair_log2w<R, DX>(u, colp[(size_t)j * (DX + 1) + DX], v));
       }
+      Rm = 0.0;
       if (smax > (R)(-INFINITY)) {
-        Rm = 0.0;
         for (int j = 0; j < N; ++j) {
           R u[DX];
 #pragma unroll
@@ -311,17 +332,15 @@ __global__ __launch_bounds__(kBlock) void k_sample(
                                       smax);
         }
         sh = (float)smax;  // < 0 since the row sum was tiny
-      } else {
-        Rm = 0.0;
       }
     }
     rs[m] = Rm;
     shift[m] = sh;
-    const double a = left_leaf ? (double)leafW[(size_t)gL * N + sigma[(size_t)gL * N + m]] : -logN;
+    const double a = left_leaf ? (double)alp[m] : -logN;
     double rho = -INFINITY;
     if (Astar > -INFINITY && Rm > 0.0) rho = a - Astar + (double)sh * kLn2 + log(Rm);
     if (isnan(Rm) || isnan(a)) row_nan = true;
-    cdf[m] = rho;  // log row weight for now
+    cdf[m] = rho;
     gmax = fmax(gmax, rho);
   }
   gmax = block_max(gmax, red);
@@ -333,8 +352,7 @@ __global__ __launch_bounds__(kBlock) void k_sample(
     seg += w;
     cdf[m] = seg;  // segment-local inclusive prefix for now
   }
-  // ---- workgroup exclusive scan of the segment totals
-  {
+  {  // workgroup scan of the segment totals
     const int lane = threadIdx.x & 63, wid = threadIdx.x >> 6;
     double incl = seg;
 #pragma unroll
@@ -349,28 +367,46 @@ __global__ __launch_bounds__(kBlock) void k_sample(
     for (int i = 0; i < wid; ++i) off += red[i];
     for (int m = m0; m < m1; ++m) cdf[m] += off;
   }
-  lastpos = block_max_i(lastpos, redi);  // also orders the cdf writes
-  __syncthreads();
+  lastpos = block_max_i(lastpos, redi);
   const int any_nan = block_or_i(row_nan ? 1 : 0, redi);
+  __syncthreads();
   const double T = cdf[N - 1];
-  const bool nan_total = isnan(T) || any_nan;
   const bool degenerate = !(T > 0.0);
-  if (threadIdx.x == 0) {
-    sd.zinc[c - 1] = degenerate ? -INFINITY : Astar + Bstar + c0 + gmax + log(T);
-    const int flags = (degenerate ? kFlagDegenerate : 0) | (nan_total ? kFlagNumeric : 0);
-    if (flags) atomicOr(sd.status, flags);
-  }
-  if (sd.row_lse) {
-    double* rl = sd.row_lse + (size_t)(c - 1) * N;
-    for (int m = threadIdx.x; m < N; m += kBlock) {
-      const double a = left_leaf ? (double)leafW[(size_t)gL * N + sigma[(size_t)gL * N + m]] : -logN;
-      rl[m] = a + Bstar + c0 + log(rs[m]) + (double)shift[m] * kLn2;
+  const double Bc = nb.bcol[nodeid];
+  if (ds == 0) {
+    if (threadIdx.x == 0) {
+      sd.zinc[c - 1] = degenerate ? -INFINITY : Astar + Bc + M.trans_lognorm + gmax + log(T);
+      const int flags = (degenerate ? kFlagDegenerate : 0) | ((isnan(T) || any_nan) ? kFlagNumeric : 0);
+      if (flags) atomicOr(sd.status, flags);
+    }
+    if (sd.row_lse) {
+      double* rl = sd.row_lse + (size_t)(c - 1) * N;
+      for (int m = threadIdx.x; m < N; m += kBlock) {
+        const double a = left_leaf ? (double)alp[m] : -logN;
+        rl[m] = a + Bc + M.trans_lognorm + log(rs[m]) + (double)shift[m] * kLn2;
+      }
     }
   }
-  // ---- N draws
+  // consumer of the merged block [a, b)
+  const int cons = nd.consumer;
+  const int crole = nd.role;
+  const int ca = nd.a, cb = nd.b;
+  const int gA = sd.base + ca, gB = sd.base + cb - 1;
+  if (cons >= 0 && crole == 1 && ds == 0) {
+    R* ccol = (R*)nb.col + (size_t)cons * Npad * (DX + 1);
+    for (int n = N + threadIdx.x; n < Npad; n += kBlock) {
+#pragma unroll
+      for (int i = 0; i < DX; ++i) ccol[(size_t)n * (DX + 1) + i] = (R)0;
+      ccol[(size_t)n * (DX + 1) + DX] = (R)(-INFINITY);
+    }
+    if (threadIdx.x == 0) nb.bcol[cons] = bmerged[gA];
+  }
+  // ---- draws
+  const int dper = (N + DS - 1) / DS;
+  const int n0 = ds * dper, n1 = min(N, n0 + dper);
   int32_t* ancL = sd.anc + (size_t)(c - 1) * 2 * N;
   int32_t* ancR = ancL + N;
-  for (int n = threadIdx.x; n < N; n += kBlock) {
+  for (int n = n0 + threadIdx.x; n < n1; n += kBlock) {
     const Words4 w = philox4x64_10((uint64_t)n, (uint64_t)c, kPurposeCombine, 0ull, sd.seed, kKey1);
     const double u1 = unif53(w.w0), u2 = unif53(w.w1);
     int l, r;
@@ -407,17 +443,27 @@ __global__ __launch_bounds__(kBlock) void k_sample(
         }
         if (r < 0) r = lastj;
       } else {
-        const R* Pl = Pn + (size_t)l * Nc;
+        // chunk: first k with prefix_k > target2 (chunk sums read 16 at a time)
+        const R* Pl = Pn + l;
         double pref = 0.0, pref_last = 0.0;
         int k = -1, klast = 0;
-        for (int kk = 0; kk < Nc; ++kk) {
-          const double p = (double)Pl[kk];
-          if (p > 0.0) { klast = kk; pref_last = pref; }
-          if (target2 < pref + p) { k = kk; break; }
-          pref += p;
+        for (int kb = 0; kb < Nc && k < 0; kb += 16) {
+          R q[16];
+#pragma unroll
+          for (int i = 0; i < 16; ++i) q[i] = (kb + i < Nc) ? Pl[(size_t)(kb + i) * N] : (R)0;
+#pragma unroll
+          for (int i = 0; i < 16; ++i) {
+            const int kk = kb + i;
+            if (k < 0 && kk < Nc) {
+              const double p = (double)q[i];
+              if (p > 0.0) { klast = kk; pref_last = pref; }
+              if (target2 < pref + p) k = kk; else pref += p;
+            }
+          }
         }
         if (k < 0) { k = klast; pref = pref_last; }
         const double rem = target2 - pref;
+        // recompute chunk k of row l in the rows kernel's order
         const R* cp = colp + (size_t)k * kChunk * (DX + 1);
         R acc = (R)0;
         int lastj = 0;
@@ -438,50 +484,43 @@ __global__ __launch_bounds__(kBlock) void k_sample(
     }
     ancL[n] = l;
     ancR[n] = r;
-  }
-}
-
-// =============================================================== gather
-// In place: sigma[t][n] <- sigma[t][l_n] (t in the left block) or
-// sigma[t][r_n] (right block).  One workgroup per time row; the whole row is
-// read before any of it is written.
-constexpr int kGatherPer = 4096 / kBlock;
-__global__ __launch_bounds__(kBlock) void k_gather(const NodeDesc* __restrict__ nodes,
-                                                   const SeriesDesc* __restrict__ series, int N,
-                                                   int rows_per_node, int32_t* __restrict__ sigma) {
-  const int node = blockIdx.x / rows_per_node;
-  const int rr = blockIdx.x - node * rows_per_node;
-  const NodeDesc nd = nodes[node];
-  const int t = nd.a + rr;
-  if (t >= nd.b) return;  // uniform over the workgroup
-  const SeriesDesc& sd = series[nd.series];
-  const int32_t* __restrict__ idx = sd.anc + (size_t)(nd.c - 1) * 2 * N + (t < nd.c ? 0 : N);
-  int32_t* srow = sigma + (size_t)(sd.base + t) * N;
-  int32_t vals[kGatherPer];
+    // ancestry of the merged block at its first and last times
+    const int sf = left_leaf ? l : nb.sfirst[(size_t)nd.lchild * N + l];
+    const int sl = (nd.rchild < 0) ? r : nb.slast[(size_t)nd.rchild * N + r];
+    nb.sfirst[(size_t)nodeid * N + n] = sf;
+    nb.slast[(size_t)nodeid * N + n] = sl;
+    if (cons >= 0) {
+      if (crole == 1) {  // merged block is the right block of `cons` (boundary ca)
+        double x[DX], u[DX];
+        load_particle<R, DX>(leafX, totalK, N, gA, sf, dx, x);
+        col_coords<DX>(M, ca, x, u);
+        double b = -logN - log_proposal<DX>(M, ca, x);
+        if (M.weighting == 1) b += log_potential<DX>(M, ca, x);
+        R* ccol = (R*)nb.col + (size_t)cons * Npad * (DX + 1);
 #pragma unroll
-  for (int i = 0; i < kGatherPer; ++i) {
-    const int n = threadIdx.x + i * kBlock;
-    if (n < N) vals[i] = srow[idx[n]];
-  }
-  __syncthreads();
+        for (int i = 0; i < DX; ++i) ccol[(size_t)n * (DX + 1) + i] = (R)u[i];
+        ccol[(size_t)n * (DX + 1) + DX] = (R)((b - bmerged[gA]) * kLog2e);
+      } else {  // merged block is the left block of `cons` (boundary cb)
+        double x[DX], v2[DX];
+        load_particle<R, DX>(leafX, totalK, N, gB, sl, dx, x);
+        row_coords<DX>(M, cb, x, v2);
+        R* crow = (R*)nb.row + (size_t)cons * Npad * DX;
 #pragma unroll
-  for (int i = 0; i < kGatherPer; ++i) {
-    const int n = threadIdx.x + i * kBlock;
-    if (n < N) srow[n] = vals[i];
+        for (int i = 0; i < DX; ++i) crow[(size_t)n * DX + i] = (R)v2[i];
+        ((R*)nb.alpha)[(size_t)cons * N + n] = (R)(-logN);
+      }
+    }
   }
 }
 
 // =============================================================== output
-// One workgroup per time row: traj[d][t][n] = leafX[d][g][sigma[g][n]] and the
-// optional diagnostic copies.
+// One workgroup per time row: the leaf index of output entry (t, n) is found
+// by following the ancestry from the root combine down to t's leaf.
 template <typename R>
-__global__ __launch_bounds__(kBlock) void k_output_rows(const SeriesDesc* __restrict__ series,
-                                                        const int32_t* __restrict__ series_of_t,
-                                                        int totalK, int N, int dx,
-                                                        const R* __restrict__ leafX,
-                                                        const R* __restrict__ leafW,
-                                                        const double* __restrict__ leafL,
-                                                        const int32_t* __restrict__ sigma) {
+__global__ __launch_bounds__(kBlock) void k_output_rows(
+    const SeriesDesc* __restrict__ series, const int32_t* __restrict__ series_of_t,
+    const NodeDesc* __restrict__ nodes, int totalK, int N, int dx, const R* __restrict__ leafX,
+    const R* __restrict__ leafW, const double* __restrict__ leafL) {
   const int g = blockIdx.x;
   const SeriesDesc& sd = series[series_of_t[g]];
   const int t = g - sd.base, K = sd.K;
@@ -489,13 +528,21 @@ __global__ __launch_bounds__(kBlock) void k_output_rows(const SeriesDesc* __rest
   R* lx = (R*)sd.leaf_x;
   R* lw = (R*)sd.leaf_logw;
   for (int n = threadIdx.x; n < N; n += kBlock) {
-    const int src = sigma[(size_t)g * N + n];
+    int idx = n;
+    int cur = sd.root;
+    // a tree over K <= 2^31 points has at most 31 levels
+    for (int depth = 0; cur >= 0 && depth < 32; ++depth) {
+      const NodeDesc nd = nodes[cur];
+      const bool right = t >= nd.c;
+      idx = sd.anc[(size_t)(nd.c - 1) * 2 * N + (right ? N : 0) + idx];
+      cur = right ? nd.rchild : nd.lchild;
+    }
     for (int i = 0; i < dx; ++i) {
-      traj[((size_t)i * K + t) * N + n] = leafX[((size_t)i * totalK + g) * N + src];
+      traj[((size_t)i * K + t) * N + n] = leafX[((size_t)i * totalK + g) * N + idx];
       if (lx) lx[((size_t)i * K + t) * N + n] = leafX[((size_t)i * totalK + g) * N + n];
     }
     if (lw) lw[(size_t)t * N + n] = leafW[(size_t)g * N + n];
-    if (sd.index) sd.index[(size_t)t * N + n] = src;
+    if (sd.index) sd.index[(size_t)t * N + n] = idx;
   }
   if (threadIdx.x == 0 && sd.leaf_logL) sd.leaf_logL[t] = leafL[g];
 }
@@ -516,8 +563,9 @@ __global__ __launch_bounds__(kBlock) void k_output_series(const SeriesDesc* __re
   if (threadIdx.x == 0) *sd.log_Z = s;
   if (sd.logw) {
     R* lw = (R*)sd.logw;
+    const R uni = (R)(-log((double)N));
     for (int n = threadIdx.x; n < N; n += kBlock)
-      lw[n] = (K == 1) ? leafW[(size_t)sd.base * N + n] : (R)(-log((double)N));
+      lw[n] = (K == 1) ? leafW[(size_t)sd.base * N + n] : uni;
   }
 }
 
@@ -528,34 +576,49 @@ __global__ void k_clear_status(const SeriesDesc* __restrict__ series, int B) {
 
 // ============================================================ launchers
 template <typename R, int DX>
-static void launch_level_t(const LevelLaunch& L, hipStream_t st, Timer* tm) {
-  const size_t lds_prep = (size_t)L.N * sizeof(double);
+static int launch_rows_t(const LevelLaunch& L, hipStream_t st) {
+  const unsigned grid = (unsigned)L.nodes * L.RB * L.CS;
+  const unsigned block = 64u * L.W;
+  switch (L.RPL) {
+    case 1:
+      k_rows<R, DX, 1><<<grid, block, 0, st>>>((const R*)L.nb.col, (const R*)L.nb.row, (R*)L.P,
+                                               L.Rsum, L.node0, L.N, L.Npad, L.Nc, L.RB, L.CS, L.KC);
+      return 0;
+    case 2:
+      k_rows<R, DX, 2><<<grid, block, 0, st>>>((const R*)L.nb.col, (const R*)L.nb.row, (R*)L.P,
+                                               L.Rsum, L.node0, L.N, L.Npad, L.Nc, L.RB, L.CS, L.KC);
+      return 0;
+    case 4:
+      k_rows<R, DX, 4><<<grid, block, 0, st>>>((const R*)L.nb.col, (const R*)L.nb.row, (R*)L.P,
+                                               L.Rsum, L.node0, L.N, L.Npad, L.Nc, L.RB, L.CS, L.KC);
+      return 0;
+  }
+  return -1;
+}
+
+template <typename R, int DX>
+static int launch_level_t(const LevelLaunch& L, hipStream_t st, Timer* tm) {
   tm->begin(1, st);
-  k_prep<R, DX><<<L.nodes, kBlock, lds_prep, st>>>(
-      L.d_nodes, L.d_series, L.totalK, L.N, L.Npad, (const R*)L.leafX, (const R*)L.leafW,
-      L.sigma, (R*)L.col, (R*)L.row, L.nscal);
+  if (launch_rows_t<R, DX>(L, st)) return -1;
   tm->end(1, st);
-  tm->begin(2, st);
-  k_rows<R, DX><<<(unsigned)L.nodes * L.RB * L.CS, kBlock, 0, st>>>(
-      (const R*)L.col, (const R*)L.row, (R*)L.P, L.N, L.Npad, L.Nc, L.RB, L.CS, L.KC);
-  tm->end(2, st);
   const size_t lds_samp = (size_t)L.Npad * (2 * sizeof(double) + sizeof(float));
-  tm->begin(3, st);
-  k_sample<R, DX><<<L.nodes, kBlock, lds_samp, st>>>(
-      L.d_nodes, L.d_series, L.totalK, L.N, L.Npad, L.Nc, (const R*)L.leafW, L.sigma,
-      (const R*)L.col, (const R*)L.row, (const R*)L.P, L.nscal);
-  tm->end(3, st);
+  tm->begin(2, st);
+  k_sample<R, DX><<<(unsigned)L.nodes * L.DS, kBlock, lds_samp, st>>>(
+      L.d_nodes, L.d_series, L.node0, L.DS, L.totalK, L.N, L.Npad, L.Nc, L.CS == 1 ? 1 : 0,
+      (const R*)L.leafX, L.bmerged, (const R*)L.P, L.Rsum, L.nb);
+  tm->end(2, st);
+  return 0;
 }
 
 template <typename R>
 static int launch_level_r(const LevelLaunch& L, hipStream_t st, Timer* tm) {
   switch (L.DX) {
-    case 1: launch_level_t<R, 1>(L, st, tm); return 0;
-    case 2: launch_level_t<R, 2>(L, st, tm); return 0;
-    case 4: launch_level_t<R, 4>(L, st, tm); return 0;
-    case 8: launch_level_t<R, 8>(L, st, tm); return 0;
-    case 16: launch_level_t<R, 16>(L, st, tm); return 0;
-    case 32: launch_level_t<R, 32>(L, st, tm); return 0;
+    case 1: return launch_level_t<R, 1>(L, st, tm);
+    case 2: return launch_level_t<R, 2>(L, st, tm);
+    case 4: return launch_level_t<R, 4>(L, st, tm);
+    case 8: return launch_level_t<R, 8>(L, st, tm);
+    case 16: return launch_level_t<R, 16>(L, st, tm);
+    case 32: return launch_level_t<R, 32>(L, st, tm);
   }
   return -1;
 }
@@ -564,19 +627,35 @@ int launch_level(const LevelLaunch& L, hipStream_t st, Timer* tm) {
   return L.fp64 ? launch_level_r<double>(L, st, tm) : launch_level_r<float>(L, st, tm);
 }
 
-void launch_gather(const NodeDesc* d_nodes, const SeriesDesc* d_series, int nodes,
-                   int rows_per_node, int N, int32_t* sigma, hipStream_t st, Timer* tm) {
-  tm->begin(4, st);
-  k_gather<<<(unsigned)nodes * rows_per_node, kBlock, 0, st>>>(d_nodes, d_series, N,
-                                                               rows_per_node, sigma);
-  tm->end(4, st);
+int launch_rows_only(const LevelLaunch& L, hipStream_t st) {
+  if (L.fp64) {
+    switch (L.DX) {
+      case 1: return launch_rows_t<double, 1>(L, st);
+      case 2: return launch_rows_t<double, 2>(L, st);
+      case 4: return launch_rows_t<double, 4>(L, st);
+      case 8: return launch_rows_t<double, 8>(L, st);
+      case 16: return launch_rows_t<double, 16>(L, st);
+      case 32: return launch_rows_t<double, 32>(L, st);
+    }
+  } else {
+    switch (L.DX) {
+      case 1: return launch_rows_t<float, 1>(L, st);
+      case 2: return launch_rows_t<float, 2>(L, st);
+      case 4: return launch_rows_t<float, 4>(L, st);
+      case 8: return launch_rows_t<float, 8>(L, st);
+      case 16: return launch_rows_t<float, 16>(L, st);
+      case 32: return launch_rows_t<float, 32>(L, st);
+    }
+  }
+  return -1;
 }
 
 template <typename R, int DX>
 static void launch_leaves_t(const LeafLaunch& L, hipStream_t st, Timer* tm) {
   tm->begin(0, st);
-  k_leaves<R, DX><<<L.totalK, kBlock, (size_t)L.N * sizeof(double), st>>>(
-      L.d_series, L.d_series_of_t, L.totalK, L.N, (R*)L.leafX, (R*)L.leafW, L.leafL, L.sigma);
+  k_leaves<R, DX><<<L.totalK, kBlock, 2 * (size_t)L.N * sizeof(double), st>>>(
+      L.d_series, L.d_series_of_t, L.d_leaf_cons, L.d_nodes, L.totalK, L.N, L.Npad, (R*)L.leafX,
+      (R*)L.leafW, L.leafL, L.bmerged, L.nb);
   tm->end(0, st);
 }
 
@@ -603,12 +682,12 @@ void launch_clear_status(const SeriesDesc* d_series, int B, hipStream_t st) {
 
 template <typename R>
 static void launch_output_t(const LeafLaunch& L, int B, int dx, hipStream_t st, Timer* tm) {
-  tm->begin(5, st);
-  k_output_rows<R><<<L.totalK, kBlock, 0, st>>>(L.d_series, L.d_series_of_t, L.totalK, L.N, dx,
-                                                (const R*)L.leafX, (const R*)L.leafW, L.leafL,
-                                                L.sigma);
+  tm->begin(3, st);
+  k_output_rows<R><<<L.totalK, kBlock, 0, st>>>(L.d_series, L.d_series_of_t, L.d_nodes, L.totalK,
+                                                L.N, dx, (const R*)L.leafX, (const R*)L.leafW,
+                                                L.leafL);
   k_output_series<R><<<B, kBlock, 0, st>>>(L.d_series, L.N, (const R*)L.leafW, L.leafL);
-  tm->end(5, st);
+  tm->end(3, st);
 }
 
 void launch_output(const LeafLaunch& L, int B, int dx, hipStream_t st, Timer* tm) {

@@ -10,14 +10,13 @@
 namespace dsmc {
 
 // Optional per-launch HIP-event timing, grouped by kernel class
-// (0 leaves, 1 prep, 2 rows, 3 sample, 4 gather, 5 output).
+// (0 leaves, 1 rows, 2 sample, 3 output).
 struct Timer {
   bool on = false;
   std::vector<hipEvent_t> pool;
   size_t used = 0;
   std::vector<int> cls;               // class of each recorded pair
   std::vector<hipEvent_t> beg, fin;   // recorded pairs
-  hipEvent_t pending = nullptr;
 
   hipEvent_t take() {
     if (used == pool.size()) {
@@ -35,56 +34,59 @@ struct Timer {
   }
   void begin(int c, hipStream_t st) {
     if (!on) return;
-    pending = take();
-    if (pending) hipEventRecord(pending, st);
+    hipEvent_t e = take();
+    if (e) (void)hipEventRecord(e, st);
     cls.push_back(c);
-    beg.push_back(pending);
+    beg.push_back(e);
   }
   void end(int, hipStream_t st) {
     if (!on) return;
     hipEvent_t e = take();
-    if (e) hipEventRecord(e, st);
+    if (e) (void)hipEventRecord(e, st);
     fin.push_back(e);
   }
   ~Timer() {
-    for (auto e : pool) hipEventDestroy(e);
+    for (auto e : pool) (void)hipEventDestroy(e);
   }
 };
 
 struct LevelLaunch {
   bool fp64;
   int DX;
+  int node0;            // id of the first combine of this launch
   int nodes;            // combines in this launch
   int N, Npad, Nc;      // particles, padded columns, chunks per row
-  int RB, CS, KC;       // row blocks, column splits, chunks per split
+  int RPL, W, RB;       // rows kernel: rows per lane, waves per workgroup, row blocks per combine
+  int CS, KC;           // rows kernel: column splits per combine, chunks per split
+  int DS;               // sample kernel: workgroups per combine
   int totalK;
   const NodeDesc* d_nodes;
   const SeriesDesc* d_series;
   const void* leafX;
-  const void* leafW;
-  const int32_t* sigma;
-  void* col;
-  void* row;
-  double* nscal;
+  const double* bmerged;
   void* P;
+  double* Rsum;
+  NodeBufs nb;
 };
 
 struct LeafLaunch {
   bool fp64;
   int DX;
-  int N, totalK;
+  int N, Npad, totalK;
   const SeriesDesc* d_series;
   const int32_t* d_series_of_t;
+  const int32_t* d_leaf_cons;
+  const NodeDesc* d_nodes;
   void* leafX;
   void* leafW;
   double* leafL;
-  int32_t* sigma;
+  double* bmerged;
+  NodeBufs nb;
 };
 
 int launch_leaves(const LeafLaunch& L, hipStream_t st, Timer* tm);
 int launch_level(const LevelLaunch& L, hipStream_t st, Timer* tm);
-void launch_gather(const NodeDesc* d_nodes, const SeriesDesc* d_series, int nodes,
-                   int rows_per_node, int N, int32_t* sigma, hipStream_t st, Timer* tm);
+int launch_rows_only(const LevelLaunch& L, hipStream_t st);
 void launch_output(const LeafLaunch& L, int B, int dx, hipStream_t st, Timer* tm);
 void launch_clear_status(const SeriesDesc* d_series, int B, hipStream_t st);
 

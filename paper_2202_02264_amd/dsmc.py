@@ -25,9 +25,10 @@ DSMC_OBS_LINEAR_GAUSSIAN, DSMC_OBS_STOCH_VOL = 0, 1
 DSMC_WEIGHT_LEAF_OBS, DSMC_WEIGHT_BOUNDARY_OBS = 0, 1
 DSMC_FP32, DSMC_FP64 = 0, 1
 DSMC_PLAN_PROFILE = 1
+DSMC_PLAN_AUTOTUNE = 2
 DSMC_MAX_DX, DSMC_MAX_N = 32, 4096
-DSMC_NUM_KERNEL_CLASSES = 6
-KERNEL_CLASSES = ("leaves", "prep", "rows", "sample", "gather", "output")
+DSMC_NUM_KERNEL_CLASSES = 4
+KERNEL_CLASSES = ("leaves", "rows", "sample", "output")
 
 _dp = C.POINTER(C.c_double)
 
@@ -146,14 +147,15 @@ class Plan:
     """dsmc_plan: workspace for series of up to max_K points (sum max_total_K)."""
 
     def __init__(self, N: int, d_x: int, max_K: int, max_total_K: int = 0,
-                 precision: int = DSMC_FP32, profile: bool = False, stream=None):
+                 precision: int = DSMC_FP32, profile: bool = False, autotune: bool = True,
+                 stream=None):
         import torch
         if stream is None:
             stream = torch.cuda.current_stream()
         d = dsmc_plan_desc()
         d.N, d.d_x, d.max_K, d.max_total_K = N, d_x, max_K, max_total_K
         d.precision = precision
-        d.flags = DSMC_PLAN_PROFILE if profile else 0
+        d.flags = (DSMC_PLAN_PROFILE if profile else 0) | (DSMC_PLAN_AUTOTUNE if autotune else 0)
         d.stream = C.c_void_p(stream.cuda_stream)
         h = C.c_void_p()
         _check(_lib.dsmc_plan(C.byref(d), C.byref(h)), "dsmc_plan")
