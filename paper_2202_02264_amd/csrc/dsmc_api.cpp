@@ -223,7 +223,7 @@ struct dsmc_plan_impl {
   bool fp64 = false;
   size_t rsz = 4;
   hipStream_t stream = nullptr;
-  int Npad = 0, Nc = 0;
+  int Npad = 0, Nc = 0, NcP = 0;
   int node_cap = 0;  // combines per launch slice
   bool autotune = false;
   // device workspace: per time row
@@ -299,9 +299,10 @@ extern "C" int dsmc_plan(const dsmc_plan_desc* d, dsmc_plan_t** out) {
   const int N = d->N;
   p->Npad = (N + kChunk - 1) / kChunk * kChunk;
   p->Nc = p->Npad / kChunk;
+  p->NcP = (p->Nc + 3) / 4 * 4;
   const size_t TK = (size_t)p->d.max_total_K;
   const size_t max_nodes = std::max<size_t>(1, TK / 2);
-  const size_t per_node_P = (size_t)N * p->Nc * p->rsz + (size_t)N * sizeof(double);
+  const size_t per_node_P = (size_t)N * p->NcP * p->rsz + (size_t)N * sizeof(double);
   const size_t cap_by_mem = std::max<size_t>(1, ((size_t)1 << 30) / per_node_P);
   p->node_cap = (int)std::min(max_nodes, cap_by_mem);
   const size_t nc = (size_t)p->node_cap;
@@ -324,7 +325,7 @@ extern "C" int dsmc_plan(const dsmc_plan_desc* d, dsmc_plan_t** out) {
       {(void**)&p->nb.bcol, TK * sizeof(double), "column shifts"},
       {(void**)&p->nb.sfirst, TK * N * sizeof(int32_t), "first-time ancestry"},
       {(void**)&p->nb.slast, TK * N * sizeof(int32_t), "last-time ancestry"},
-      {&p->P, nc * N * p->Nc * R, "chunk sums"},
+      {&p->P, nc * N * p->NcP * R, "chunk sums"},
       {(void**)&p->Rsum, nc * N * sizeof(double), "row sums"},
       {(void**)&p->d_nodes, TK * sizeof(NodeDesc), "schedule"},
       {(void**)&p->d_series_of_t, TK * sizeof(int32_t), "series map"},
@@ -455,6 +456,8 @@ static int check_output(const dsmc_output* o) {
 }
 
 // Column splits that bring a launch to about `want` waves (8 waves per SIMD).
+// With one split the rows kernel also forms the row sums; with more, the
+// sampler re-reads the chunk sums to form them.
 static int pick_cs(int nodes, int N, int Nc, int rpl, int W) {
   const long rb = (N + 64L * rpl * W - 1) / (64L * rpl * W);
   const long waves = (long)nodes * rb * W;
@@ -482,7 +485,7 @@ static void set_tile(LevelLaunch& L, TileChoice tc) {
   L.RPL = tc.RPL;
   L.W = tc.W;
   L.RB = (L.N + 64 * tc.RPL * tc.W - 1) / (64 * tc.RPL * tc.W);
-  L.KC = (L.Nc + tc.CS - 1) / tc.CS;
+  L.KC = ((L.Nc + tc.CS - 1) / tc.CS + 3) / 4 * 4;  // whole groups of four chunks
   L.CS = (L.Nc + L.KC - 1) / L.KC;
 }
 
@@ -502,9 +505,11 @@ static TileChoice autotune_tile(dsmc_plan_t* p, LevelLaunch L) {
   const int rpls[3] = {1, 2, 4};
   const int ws[3] = {1, 2, 4};
   for (int rpl : rpls)
-    for (int w : ws) {
+    for (int w : ws)
+      for (int split = 0; split < 2; ++split) {
       if (64 * rpl * w > 2 * L.N && !(rpl == 1 && w == 1)) continue;
-      const TileChoice tc{rpl, w, pick_cs(L.nodes, L.N, L.Nc, rpl, w)};
+      const TileChoice tc{rpl, w, split ? pick_cs(L.nodes, L.N, L.Nc, rpl, w) : 1};
+      if (split && tc.CS == 1) continue;
       set_tile(L, tc);
       float ms = 0.0f;
       bool ok = true;
@@ -591,13 +596,15 @@ extern "C" int dsmc_smooth_batch(dsmc_plan_t* p, int B, const dsmc_model_t* cons
   HIP_TRY(hipEventRecord(p->staged, st));
   p->staged_pending = true;
 
-  launch_clear_status(p->d_series, B, st);
+  launch_clear_status(p->d_series, 0, B, st);
   LeafLaunch LL{};
   LL.fp64 = p->fp64;
   LL.DX = p->DX;
   LL.N = N;
   LL.Npad = p->Npad;
   LL.totalK = totalK;
+  LL.row0 = 0;
+  LL.rows = totalK;
   LL.d_series = p->d_series;
   LL.d_series_of_t = p->d_series_of_t;
   LL.d_leaf_cons = p->d_leaf_cons;
@@ -617,11 +624,13 @@ extern "C" int dsmc_smooth_batch(dsmc_plan_t* p, int B, const dsmc_model_t* cons
       LevelLaunch L{};
       L.fp64 = p->fp64;
       L.DX = p->DX;
+      L.node_list = nullptr;
       L.node0 = p->level_off[l] + s0;
       L.nodes = nodes;
       L.N = N;
       L.Npad = p->Npad;
       L.Nc = p->Nc;
+      L.NcP = p->NcP;
       L.totalK = totalK;
       L.d_nodes = p->d_nodes;
       L.d_series = p->d_series;
@@ -641,12 +650,12 @@ extern "C" int dsmc_smooth_batch(dsmc_plan_t* p, int B, const dsmc_model_t* cons
       set_tile(L, tc);
       // sampling: enough workgroups to cover the chip when a level has few combines
       const int ds_max = std::max(1, (N + 127) / 128);
-      L.DS = (int)std::min<long>(ds_max, std::max<long>(1, (2048 + nodes - 1) / nodes));
+      L.DS = nodes >= 256 ? 1 : (int)std::min<long>(ds_max, (512 + nodes - 1) / nodes);
       if (launch_level(L, st, &p->timer)) return fail(DSMC_EUNSUPPORTED, "no combine kernel for d_x");
       HIP_TRY(hipGetLastError());
     }
   }
-  launch_output(LL, B, p->d.d_x, st, &p->timer);
+  launch_output(LL, 0, B, p->d.d_x, st, &p->timer);
   HIP_TRY(hipGetLastError());
   return DSMC_OK;
 }

@@ -19,6 +19,7 @@
 
 #include <cmath>
 
+#include "dsmc.h"
 #include "dsmc_device.h"
 #include "dsmc_launch.h"
 
@@ -72,15 +73,15 @@ __device__ __forceinline__ void load_particle(const R* __restrict__ leafX, int t
 template <typename R, int DX>
 __global__ __launch_bounds__(kBlock) void k_leaves(
     const SeriesDesc* __restrict__ series, const int32_t* __restrict__ series_of_t,
-    const int32_t* __restrict__ leaf_cons, const NodeDesc* __restrict__ nodes, int totalK, int N,
-    int Npad, R* __restrict__ leafX, R* __restrict__ leafW, double* __restrict__ leafL,
-    double* __restrict__ bmerged, NodeBufs nb) {
+    const int32_t* __restrict__ leaf_cons, const NodeDesc* __restrict__ nodes, int row0,
+    int totalK, int N, int Npad, R* __restrict__ leafX, R* __restrict__ leafW,
+    double* __restrict__ leafL, double* __restrict__ bmerged, NodeBufs nb) {
   extern __shared__ double sh[];
   double* ell = sh;      // [N] unnormalised leaf log-weights
   double* gq = sh + N;   // [N] -log q_t(x) (+ log h_t(x) under boundary weighting)
   __shared__ double red[kBlock / 64];
   __shared__ int redi[kBlock / 64];
-  const int g = blockIdx.x;
+  const int g = row0 + blockIdx.x;
   const SeriesDesc& sd = series[series_of_t[g]];
   const DevModel& M = *sd.model;
   const int t = g - sd.base;
@@ -195,18 +196,32 @@ __global__ __launch_bounds__(kBlock) void k_leaves(
 }
 
 // ================================================================= rows
-// Tile = (combine, row block of RPL*64*W rows, column split of KC chunks).
-// Lane owns rows base + lane + 64 r, r < RPL; lanes past N recompute row N-1
-// and store the same values (no per-row branches).  Chunk sums go to
-// P[node][k][m] (coalesced over m).  With one column split the tile also
-// stores the row sum sum_k P[k][m] (fp64, k ascending); otherwise the
-// sampling kernel forms that same sum from P.
+// Tile = (combine, row block of RPL*64*W rows, column split of KC chunks, KC a
+// multiple of 4).  Lane owns rows base + lane + 64 r, r < RPL; lanes past N
+// recompute row N-1 and store the same values (no per-row branches).  Chunk
+// sums go to P[node][m][k] (row stride NcP = Nc rounded up to 4), four chunks
+// per vector store, so the sampler reads a row's sums as one contiguous run.
+// With one column split the tile also stores the row sum sum_k P[m][k] (fp64,
+// k ascending); otherwise the sampling kernel forms that same sum from P.
+template <typename R>
+__device__ __forceinline__ void store4(R* p, R a, R b, R c, R d);
+template <>
+__device__ __forceinline__ void store4<float>(float* p, float a, float b, float c, float d) {
+  *(float4*)p = make_float4(a, b, c, d);
+}
+template <>
+__device__ __forceinline__ void store4<double>(double* p, double a, double b, double c, double d) {
+  ((double2*)p)[0] = make_double2(a, b);
+  ((double2*)p)[1] = make_double2(c, d);
+}
+
 template <typename R, int DX, int RPL>
 __global__ __launch_bounds__(kBlock) void k_rows(const R* __restrict__ col,
                                                  const R* __restrict__ row,
                                                  R* __restrict__ P, double* __restrict__ Rsum,
-                                                 int node0, int N, int Npad, int Nc, int RB,
-                                                 int CS, int KC) {
+                                                 const int32_t* __restrict__ node_list,
+                                                 int node0, int N, int Npad, int Nc, int NcP,
+                                                 int RB, int CS, int KC) {
   const int W = blockDim.x >> 6;
   const int tiles = RB * CS;
   const int node_local = blockIdx.x / tiles;
@@ -215,7 +230,7 @@ __global__ __launch_bounds__(kBlock) void k_rows(const R* __restrict__ col,
   const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
   const int base = (rb * W + wave) * 64 * RPL;
   if (base >= N) return;  // wave-uniform
-  const size_t nodeid = (size_t)node0 + node_local;
+  const size_t nodeid = node_list ? (size_t)node_list[node_local] : (size_t)node0 + node_local;
   const R* __restrict__ colp = col + nodeid * Npad * (DX + 1);
   R v[RPL][DX];
   int mrow[RPL];
@@ -229,27 +244,33 @@ __global__ __launch_bounds__(kBlock) void k_rows(const R* __restrict__ col,
   double Rm[RPL];
 #pragma unroll
   for (int r = 0; r < RPL; ++r) Rm[r] = 0.0;
-  R* __restrict__ Pn = P + (size_t)node_local * Nc * N;
+  R* __restrict__ Pn = P + (size_t)node_local * N * NcP;
   const int k0 = cs * KC, k1 = min(Nc, k0 + KC);
-  for (int k = k0; k < k1; ++k) {
-    const R* __restrict__ cp = colp + (size_t)k * kChunk * (DX + 1);
-    R acc[RPL];
+  for (int kg = k0; kg < k1; kg += 4) {
+    R acc[RPL][4];
 #pragma unroll
-    for (int r = 0; r < RPL; ++r) acc[r] = (R)0;
+    for (int q = 0; q < 4; ++q) {
 #pragma unroll
-    for (int jj = 0; jj < kChunk; ++jj) {
-      R u[DX];
+      for (int r = 0; r < RPL; ++r) acc[r][q] = (R)0;
+      if (kg + q < k1) {  // uniform
+        const R* __restrict__ cp = colp + (size_t)(kg + q) * kChunk * (DX + 1);
 #pragma unroll
-      for (int i = 0; i < DX; ++i) u[i] = cp[jj * (DX + 1) + i];
-      const R beta = cp[jj * (DX + 1) + DX];
+        for (int jj = 0; jj < kChunk; ++jj) {
+          R u[DX];
 #pragma unroll
-      for (int r = 0; r < RPL; ++r) acc[r] += Real<R>::exp2(pair_log2w<R, DX>(u, beta, v[r]));
+          for (int i = 0; i < DX; ++i) u[i] = cp[jj * (DX + 1) + i];
+          const R beta = cp[jj * (DX + 1) + DX];
+#pragma unroll
+          for (int r = 0; r < RPL; ++r)
+            acc[r][q] += Real<R>::exp2(pair_log2w<R, DX>(u, beta, v[r]));
+        }
+#pragma unroll
+        for (int r = 0; r < RPL; ++r) Rm[r] += (double)acc[r][q];
+      }
     }
 #pragma unroll
-    for (int r = 0; r < RPL; ++r) {
-      Pn[(size_t)k * N + mrow[r]] = acc[r];
-      Rm[r] += (double)acc[r];
-    }
+    for (int r = 0; r < RPL; ++r)
+      store4<R>(Pn + (size_t)mrow[r] * NcP + kg, acc[r][0], acc[r][1], acc[r][2], acc[r][3]);
   }
   if (CS == 1) {
 #pragma unroll
@@ -260,94 +281,173 @@ __global__ __launch_bounds__(kBlock) void k_rows(const R* __restrict__ col,
 // =============================================================== sample
 // Workgroup (combine, ds) of DS workgroups per combine; each builds the row
 // CDF of its combine and takes the draws n in [ds per, (ds+1) per).
-//   w_m = exp(rho_m - G),  rho_m = a_m - A* + ln R_m (+ shift_m ln 2),  G = max rho
-//   C_m = sum_{i<=m} w_i (fp64);  Z_c = A* + B + trans_lognorm + G + ln C_{N-1}
+//   w_m = exp(a_m - A*) R_m  (fp64),  C_m = sum_{i<=m} w_i,
+//   Z_c = A* + B + trans_lognorm + ln C_{N-1}
 //   l_n = first m with C_m > u1 C_{N-1}
 //   r_n = first j with (chunk prefix + within-chunk prefix) > u2 R_l
 // Rows whose R_m underflows fp32 range are recomputed with their exact
-// maximum as shift and drawn from by a full-row scan.
+// maximum as shift (R_m then carries a factor 2^shift_m, the weights are
+// formed in log space) and drawn from by a full-row scan.
+// The combine's column data is staged in LDS when it fits (col_in_lds).
+template <typename R>
+__device__ __forceinline__ void load4(const R* p, R (&q)[4]);
+template <>
+__device__ __forceinline__ void load4<float>(const float* p, float (&q)[4]) {
+  const float4 v = *(const float4*)p;
+  q[0] = v.x; q[1] = v.y; q[2] = v.z; q[3] = v.w;
+}
+template <>
+__device__ __forceinline__ void load4<double>(const double* p, double (&q)[4]) {
+  const double2 a = ((const double2*)p)[0], b = ((const double2*)p)[1];
+  q[0] = a.x; q[1] = a.y; q[2] = b.x; q[3] = b.y;
+}
+
 template <typename R, int DX>
 __global__ __launch_bounds__(kBlock) void k_sample(
-    const NodeDesc* __restrict__ nodes, const SeriesDesc* __restrict__ series, int node0, int DS,
-    int totalK, int N, int Npad, int Nc, int rows_summed, const R* __restrict__ leafX,
-    const double* __restrict__ bmerged, const R* __restrict__ P,
+    const NodeDesc* __restrict__ nodes, const SeriesDesc* __restrict__ series,
+    const int32_t* __restrict__ node_list, int node0, int DS,
+    int totalK, int N, int Npad, int Nc, int NcP, int rows_summed, int col_in_lds,
+    const R* __restrict__ leafX, const double* __restrict__ bmerged, const R* __restrict__ P,
     const double* __restrict__ Rsum, NodeBufs nb) {
   extern __shared__ double smem[];
   double* cdf = smem;                        // [Npad]
   double* rs = smem + Npad;                  // [Npad]
   float* shift = (float*)(smem + 2 * Npad);  // [Npad]
+  R* lcol = (R*)(shift + Npad);              // [Npad][DX+1] when col_in_lds
   __shared__ double red[kBlock / 64];
   __shared__ int redi[kBlock / 64];
   const int node_local = blockIdx.x / DS;
   const int ds = blockIdx.x - node_local * DS;
-  const int nodeid = node0 + node_local;
+  const int nodeid = node_list ? node_list[node_local] : node0 + node_local;
   const NodeDesc nd = nodes[nodeid];
   const SeriesDesc& sd = series[nd.series];
   const DevModel& M = *sd.model;
   const int c = nd.c, dx = M.dx;
   const bool left_leaf = nd.lchild < 0;
   const double logN = log((double)N);
-  const R* __restrict__ colp = (const R*)nb.col + (size_t)nodeid * Npad * (DX + 1);
+  const R* __restrict__ gcol = (const R*)nb.col + (size_t)nodeid * Npad * (DX + 1);
   const R* __restrict__ rowp = (const R*)nb.row + (size_t)nodeid * Npad * DX;
-  const R* __restrict__ Pn = P + (size_t)node_local * Nc * N;
+  const R* __restrict__ Pn = P + (size_t)node_local * N * NcP;
   const double* __restrict__ Rn = Rsum + (size_t)node_local * N;
   const R* __restrict__ alp = (const R*)nb.alpha + (size_t)nodeid * N;
+  if (col_in_lds)
+    for (int i = threadIdx.x; i < Npad * (DX + 1); i += kBlock) lcol[i] = gcol[i];
+  const R* colp = col_in_lds ? lcol : gcol;
+  __syncthreads();
 
-  // ---- log row weights (thread owns a contiguous segment of rows)
+  // ---- row sums (thread owns a contiguous segment of rows)
+  __shared__ unsigned need[DSMC_MAX_N / 32];  // rows still to rescue
+  __shared__ int rescue_list[kBlock];
+  __shared__ int n_rescue;
+  for (int i = threadIdx.x; i < DSMC_MAX_N / 32; i += kBlock) need[i] = 0u;
+  __syncthreads();
   const int per = (N + kBlock - 1) / kBlock;
   const int m0 = threadIdx.x * per, m1 = min(N, m0 + per);
   double amax = -INFINITY;
-  for (int m = m0; m < m1; ++m) amax = fmax(amax, left_leaf ? (double)alp[m] : -logN);
-  const double Astar = block_max(amax, red);
-  double gmax = -INFINITY;
-  bool row_nan = false;
+  int rescued = 0, row_nan = 0;
   for (int m = m0; m < m1; ++m) {
+    amax = fmax(amax, left_leaf ? (double)alp[m] : -logN);
     double Rm;
     if (rows_summed) {
       Rm = Rn[m];
     } else {  // the same sequential chunk-order sum the rows kernel forms
       Rm = 0.0;
-      for (int k = 0; k < Nc; ++k) Rm += (double)Pn[(size_t)k * N + m];
+      const R* Pm = Pn + (size_t)m * NcP;
+      for (int kb = 0; kb < NcP; kb += 4) {
+        R q[4];
+        load4<R>(Pm + kb, q);
+#pragma unroll
+        for (int i = 0; i < 4; ++i)
+          if (kb + i < Nc) Rm += (double)q[i];
+      }
     }
-    float sh = 0.0f;
     if (!(Rm >= Real<R>::kTiny) && !isnan(Rm)) {
-      // underflow rescue: exact row maximum as shift, full-row fp64 sum
+      atomicOr(&need[m >> 5], 1u << (m & 31));
+      rescued = 1;
+    }
+    if (isnan(Rm)) row_nan = 1;
+    rs[m] = Rm;
+    shift[m] = 0.0f;
+  }
+  rescued = block_or_i(rescued, redi);  // also orders the writes above
+  // Underflow rescue, one row at a time by the whole workgroup: exact row
+  // maximum as shift, then the fp64 sum of exp2(s - shift) over a fixed
+  // partition of the columns in a fixed reduction order.  Rows are taken in
+  // passes of at most kBlock.
+  while (rescued) {
+    if (threadIdx.x == 0) n_rescue = 0;
+    __syncthreads();
+    for (int wd = threadIdx.x; wd < Npad / 32; wd += kBlock) {
+      unsigned bits = need[wd];
+      while (bits) {
+        const int b = __ffs(bits) - 1;
+        bits &= bits - 1;
+        const int slot = atomicAdd(&n_rescue, 1);
+        if (slot < kBlock) {
+          rescue_list[slot] = wd * 32 + b;
+          atomicAnd(&need[wd], ~(1u << b));
+        }
+      }
+    }
+    __syncthreads();
+    const int total = n_rescue;
+    const int cnt = min(total, kBlock);
+    for (int i = 0; i < cnt; ++i) {
+      const int m = rescue_list[i];
       R v[DX];
 #pragma unroll
-      for (int i = 0; i < DX; ++i) v[i] = rowp[(size_t)m * DX + i];
-      R smax = (R)(-INFINITY);
-      for (int j = 0; j < N; ++j) {
+      for (int d = 0; d < DX; ++d) v[d] = rowp[(size_t)m * DX + d];
+      double smax = -INFINITY;
+      for (int j = threadIdx.x; j < N; j += kBlock) {
         R u[DX];
 #pragma unroll
-        for (int i = 0; i < DX; ++i) u[i] = colp[(size_t)j * (DX + 1) + i];
-        smax = fmax(smax, pair_log2w<R, DX>(u, colp[(size_t)j * (DX + 1) + DX], v));
+        for (int d = 0; d < DX; ++d) u[d] = colp[(size_t)j * (DX + 1) + d];
+        smax = fmax(smax, (double)pair_log2w<R, DX>(u, colp[(size_t)j * (DX + 1) + DX], v));
       }
-      Rm = 0.0;
-      if (smax > (R)(-INFINITY)) {
-        for (int j = 0; j < N; ++j) {
+      smax = block_max(smax, red);
+      const R sh = (R)smax;
+      double part = 0.0;
+      if (smax > -INFINITY)
+        for (int j = threadIdx.x; j < N; j += kBlock) {
           R u[DX];
 #pragma unroll
-          for (int i = 0; i < DX; ++i) u[i] = colp[(size_t)j * (DX + 1) + i];
-          Rm += (double)Real<R>::exp2(pair_log2w<R, DX>(u, colp[(size_t)j * (DX + 1) + DX], v) -
-                                      smax);
+          for (int d = 0; d < DX; ++d) u[d] = colp[(size_t)j * (DX + 1) + d];
+          part += (double)Real<R>::exp2(pair_log2w<R, DX>(u, colp[(size_t)j * (DX + 1) + DX], v) - sh);
         }
-        sh = (float)smax;  // < 0 since the row sum was tiny
+      const double tot = block_sum(part, red);
+      if (threadIdx.x == 0) {
+        rs[m] = (smax > -INFINITY) ? tot : 0.0;
+        shift[m] = (smax > -INFINITY) ? (float)sh : 0.0f;  // < 0 since the row sum was tiny
       }
     }
-    rs[m] = Rm;
-    shift[m] = sh;
-    const double a = left_leaf ? (double)alp[m] : -logN;
-    double rho = -INFINITY;
-    if (Astar > -INFINITY && Rm > 0.0) rho = a - Astar + (double)sh * kLn2 + log(Rm);
-    if (isnan(Rm) || isnan(a)) row_nan = true;
-    cdf[m] = rho;
-    gmax = fmax(gmax, rho);
+    __syncthreads();
+    if (total <= kBlock) break;
   }
-  gmax = block_max(gmax, red);
+  const double Astar = block_max(amax, red);
+  // ---- row weights: direct, or in log space when a row carries a shift
+  double G = 0.0;
+  if (rescued) {
+    double gmax = -INFINITY;
+    for (int m = m0; m < m1; ++m) {
+      const double a = left_leaf ? (double)alp[m] : -logN;
+      double rho = -INFINITY;
+      if (Astar > -INFINITY && rs[m] > 0.0) rho = a - Astar + (double)shift[m] * kLn2 + log(rs[m]);
+      cdf[m] = rho;
+      gmax = fmax(gmax, rho);
+    }
+    G = block_max(gmax, red);
+    for (int m = m0; m < m1; ++m) cdf[m] = (G > -INFINITY) ? exp(cdf[m] - G) : 0.0;
+  } else {
+    for (int m = m0; m < m1; ++m) {
+      double w = 0.0;
+      if (Astar > -INFINITY) w = (left_leaf ? exp((double)alp[m] - Astar) : 1.0) * rs[m];
+      cdf[m] = w;
+    }
+  }
   double seg = 0.0;
   int lastpos = -1;
   for (int m = m0; m < m1; ++m) {
-    const double w = (gmax > -INFINITY) ? exp(cdf[m] - gmax) : 0.0;
+    const double w = cdf[m];
     if (w > 0.0) lastpos = m;
     seg += w;
     cdf[m] = seg;  // segment-local inclusive prefix for now
@@ -368,14 +468,14 @@ __global__ __launch_bounds__(kBlock) void k_sample(
     for (int m = m0; m < m1; ++m) cdf[m] += off;
   }
   lastpos = block_max_i(lastpos, redi);
-  const int any_nan = block_or_i(row_nan ? 1 : 0, redi);
+  const int any_nan = block_or_i(row_nan, redi);
   __syncthreads();
   const double T = cdf[N - 1];
   const bool degenerate = !(T > 0.0);
   const double Bc = nb.bcol[nodeid];
   if (ds == 0) {
     if (threadIdx.x == 0) {
-      sd.zinc[c - 1] = degenerate ? -INFINITY : Astar + Bc + M.trans_lognorm + gmax + log(T);
+      sd.zinc[c - 1] = degenerate ? -INFINITY : Astar + Bc + M.trans_lognorm + G + log(T);
       const int flags = (degenerate ? kFlagDegenerate : 0) | ((isnan(T) || any_nan) ? kFlagNumeric : 0);
       if (flags) atomicOr(sd.status, flags);
     }
@@ -444,13 +544,23 @@ __global__ __launch_bounds__(kBlock) void k_sample(
         if (r < 0) r = lastj;
       } else {
         // chunk: first k with prefix_k > target2 (chunk sums read 16 at a time)
-        const R* Pl = Pn + l;
+        const R* Pl = Pn + (size_t)l * NcP;
         double pref = 0.0, pref_last = 0.0;
         int k = -1, klast = 0;
         for (int kb = 0; kb < Nc && k < 0; kb += 16) {
           R q[16];
 #pragma unroll
-          for (int i = 0; i < 16; ++i) q[i] = (kb + i < Nc) ? Pl[(size_t)(kb + i) * N] : (R)0;
+          for (int g4 = 0; g4 < 4; ++g4) {
+            if (kb + 4 * g4 < NcP) {
+              R t4[4];
+              load4<R>(Pl + kb + 4 * g4, t4);
+#pragma unroll
+              for (int i = 0; i < 4; ++i) q[4 * g4 + i] = t4[i];
+            } else {
+#pragma unroll
+              for (int i = 0; i < 4; ++i) q[4 * g4 + i] = (R)0;
+            }
+          }
 #pragma unroll
           for (int i = 0; i < 16; ++i) {
             const int kk = kb + i;
@@ -519,9 +629,9 @@ __global__ __launch_bounds__(kBlock) void k_sample(
 template <typename R>
 __global__ __launch_bounds__(kBlock) void k_output_rows(
     const SeriesDesc* __restrict__ series, const int32_t* __restrict__ series_of_t,
-    const NodeDesc* __restrict__ nodes, int totalK, int N, int dx, const R* __restrict__ leafX,
-    const R* __restrict__ leafW, const double* __restrict__ leafL) {
-  const int g = blockIdx.x;
+    const NodeDesc* __restrict__ nodes, int row0, int totalK, int N, int dx,
+    const R* __restrict__ leafX, const R* __restrict__ leafW, const double* __restrict__ leafL) {
+  const int g = row0 + blockIdx.x;
   const SeriesDesc& sd = series[series_of_t[g]];
   const int t = g - sd.base, K = sd.K;
   R* traj = (R*)sd.traj;
@@ -551,10 +661,11 @@ __global__ __launch_bounds__(kBlock) void k_output_rows(
 // reduction order), and the output log-weights.
 template <typename R>
 __global__ __launch_bounds__(kBlock) void k_output_series(const SeriesDesc* __restrict__ series,
-                                                          int N, const R* __restrict__ leafW,
+                                                          int s0, int N,
+                                                          const R* __restrict__ leafW,
                                                           const double* __restrict__ leafL) {
   __shared__ double red[kBlock / 64];
-  const SeriesDesc& sd = series[blockIdx.x];
+  const SeriesDesc& sd = series[s0 + blockIdx.x];
   const int K = sd.K;
   double s = 0.0;
   for (int t = threadIdx.x; t < K; t += kBlock) s += leafL[sd.base + t];
@@ -569,9 +680,9 @@ __global__ __launch_bounds__(kBlock) void k_output_series(const SeriesDesc* __re
   }
 }
 
-__global__ void k_clear_status(const SeriesDesc* __restrict__ series, int B) {
+__global__ void k_clear_status(const SeriesDesc* __restrict__ series, int s0, int B) {
   const int i = blockIdx.x * blockDim.x + threadIdx.x;
-  if (i < B) *series[i].status = 0;
+  if (i < B) *series[s0 + i].status = 0;
 }
 
 // ============================================================ launchers
@@ -582,15 +693,18 @@ static int launch_rows_t(const LevelLaunch& L, hipStream_t st) {
   switch (L.RPL) {
     case 1:
       k_rows<R, DX, 1><<<grid, block, 0, st>>>((const R*)L.nb.col, (const R*)L.nb.row, (R*)L.P,
-                                               L.Rsum, L.node0, L.N, L.Npad, L.Nc, L.RB, L.CS, L.KC);
+                                               L.Rsum, L.node_list, L.node0, L.N, L.Npad, L.Nc,
+                                               L.NcP, L.RB, L.CS, L.KC);
       return 0;
     case 2:
       k_rows<R, DX, 2><<<grid, block, 0, st>>>((const R*)L.nb.col, (const R*)L.nb.row, (R*)L.P,
-                                               L.Rsum, L.node0, L.N, L.Npad, L.Nc, L.RB, L.CS, L.KC);
+                                               L.Rsum, L.node_list, L.node0, L.N, L.Npad, L.Nc,
+                                               L.NcP, L.RB, L.CS, L.KC);
       return 0;
     case 4:
       k_rows<R, DX, 4><<<grid, block, 0, st>>>((const R*)L.nb.col, (const R*)L.nb.row, (R*)L.P,
-                                               L.Rsum, L.node0, L.N, L.Npad, L.Nc, L.RB, L.CS, L.KC);
+                                               L.Rsum, L.node_list, L.node0, L.N, L.Npad, L.Nc,
+                                               L.NcP, L.RB, L.CS, L.KC);
       return 0;
   }
   return -1;
@@ -601,11 +715,15 @@ static int launch_level_t(const LevelLaunch& L, hipStream_t st, Timer* tm) {
   tm->begin(1, st);
   if (launch_rows_t<R, DX>(L, st)) return -1;
   tm->end(1, st);
-  const size_t lds_samp = (size_t)L.Npad * (2 * sizeof(double) + sizeof(float));
+  size_t lds_samp = (size_t)L.Npad * (2 * sizeof(double) + sizeof(float));
+  const size_t lds_col = (size_t)L.Npad * (DX + 1) * sizeof(R);
+  const int col_in_lds = (lds_samp + lds_col <= 96 * 1024) ? 1 : 0;
+  if (col_in_lds) lds_samp += lds_col;
   tm->begin(2, st);
   k_sample<R, DX><<<(unsigned)L.nodes * L.DS, kBlock, lds_samp, st>>>(
-      L.d_nodes, L.d_series, L.node0, L.DS, L.totalK, L.N, L.Npad, L.Nc, L.CS == 1 ? 1 : 0,
-      (const R*)L.leafX, L.bmerged, (const R*)L.P, L.Rsum, L.nb);
+      L.d_nodes, L.d_series, L.node_list, L.node0, L.DS, L.totalK, L.N, L.Npad, L.Nc, L.NcP,
+      L.CS == 1 ? 1 : 0,
+      col_in_lds, (const R*)L.leafX, L.bmerged, (const R*)L.P, L.Rsum, L.nb);
   tm->end(2, st);
   return 0;
 }
@@ -653,9 +771,9 @@ int launch_rows_only(const LevelLaunch& L, hipStream_t st) {
 template <typename R, int DX>
 static void launch_leaves_t(const LeafLaunch& L, hipStream_t st, Timer* tm) {
   tm->begin(0, st);
-  k_leaves<R, DX><<<L.totalK, kBlock, 2 * (size_t)L.N * sizeof(double), st>>>(
-      L.d_series, L.d_series_of_t, L.d_leaf_cons, L.d_nodes, L.totalK, L.N, L.Npad, (R*)L.leafX,
-      (R*)L.leafW, L.leafL, L.bmerged, L.nb);
+  k_leaves<R, DX><<<L.rows, kBlock, 2 * (size_t)L.N * sizeof(double), st>>>(
+      L.d_series, L.d_series_of_t, L.d_leaf_cons, L.d_nodes, L.row0, L.totalK, L.N, L.Npad,
+      (R*)L.leafX, (R*)L.leafW, L.leafL, L.bmerged, L.nb);
   tm->end(0, st);
 }
 
@@ -676,23 +794,23 @@ int launch_leaves(const LeafLaunch& L, hipStream_t st, Timer* tm) {
   return L.fp64 ? launch_leaves_r<double>(L, st, tm) : launch_leaves_r<float>(L, st, tm);
 }
 
-void launch_clear_status(const SeriesDesc* d_series, int B, hipStream_t st) {
-  k_clear_status<<<(B + kBlock - 1) / kBlock, kBlock, 0, st>>>(d_series, B);
+void launch_clear_status(const SeriesDesc* d_series, int s0, int B, hipStream_t st) {
+  k_clear_status<<<(B + kBlock - 1) / kBlock, kBlock, 0, st>>>(d_series, s0, B);
 }
 
 template <typename R>
-static void launch_output_t(const LeafLaunch& L, int B, int dx, hipStream_t st, Timer* tm) {
+static void launch_output_t(const LeafLaunch& L, int s0, int B, int dx, hipStream_t st, Timer* tm) {
   tm->begin(3, st);
-  k_output_rows<R><<<L.totalK, kBlock, 0, st>>>(L.d_series, L.d_series_of_t, L.d_nodes, L.totalK,
-                                                L.N, dx, (const R*)L.leafX, (const R*)L.leafW,
-                                                L.leafL);
-  k_output_series<R><<<B, kBlock, 0, st>>>(L.d_series, L.N, (const R*)L.leafW, L.leafL);
+  k_output_rows<R><<<L.rows, kBlock, 0, st>>>(L.d_series, L.d_series_of_t, L.d_nodes, L.row0,
+                                              L.totalK, L.N, dx, (const R*)L.leafX,
+                                              (const R*)L.leafW, L.leafL);
+  k_output_series<R><<<B, kBlock, 0, st>>>(L.d_series, s0, L.N, (const R*)L.leafW, L.leafL);
   tm->end(3, st);
 }
 
-void launch_output(const LeafLaunch& L, int B, int dx, hipStream_t st, Timer* tm) {
-  if (L.fp64) launch_output_t<double>(L, B, dx, st, tm);
-  else launch_output_t<float>(L, B, dx, st, tm);
+void launch_output(const LeafLaunch& L, int s0, int B, int dx, hipStream_t st, Timer* tm) {
+  if (L.fp64) launch_output_t<double>(L, s0, B, dx, st, tm);
+  else launch_output_t<float>(L, s0, B, dx, st, tm);
 }
 
 }  // namespace dsmc

@@ -53,9 +53,10 @@ struct Timer {
 struct LevelLaunch {
   bool fp64;
   int DX;
-  int node0;            // id of the first combine of this launch
+  const int32_t* node_list;  // device list of combine ids, or null: ids node0 .. node0+nodes-1
+  int node0;            // id of the first combine of this launch (without a list)
   int nodes;            // combines in this launch
-  int N, Npad, Nc;      // particles, padded columns, chunks per row
+  int N, Npad, Nc, NcP; // particles, padded columns, chunks per row, chunk-row stride
   int RPL, W, RB;       // rows kernel: rows per lane, waves per workgroup, row blocks per combine
   int CS, KC;           // rows kernel: column splits per combine, chunks per split
   int DS;               // sample kernel: workgroups per combine
@@ -72,7 +73,8 @@ struct LevelLaunch {
 struct LeafLaunch {
   bool fp64;
   int DX;
-  int N, Npad, totalK;
+  int N, Npad, totalK; // totalK: length (stride) of the packed time axis
+  int row0, rows;       // time rows [row0, row0 + rows) of this launch
   const SeriesDesc* d_series;
   const int32_t* d_series_of_t;
   const int32_t* d_leaf_cons;
@@ -87,7 +89,7 @@ struct LeafLaunch {
 int launch_leaves(const LeafLaunch& L, hipStream_t st, Timer* tm);
 int launch_level(const LevelLaunch& L, hipStream_t st, Timer* tm);
 int launch_rows_only(const LevelLaunch& L, hipStream_t st);
-void launch_output(const LeafLaunch& L, int B, int dx, hipStream_t st, Timer* tm);
-void launch_clear_status(const SeriesDesc* d_series, int B, hipStream_t st);
+void launch_output(const LeafLaunch& L, int s0, int B, int dx, hipStream_t st, Timer* tm);
+void launch_clear_status(const SeriesDesc* d_series, int s0, int B, hipStream_t st);
 
 }  // namespace dsmc

@@ -80,8 +80,15 @@ def simulate(spec: SSM, K: int, seed: int) -> tuple[np.ndarray, np.ndarray]:
     dx = spec.d_x
     x = np.empty((K, dx))
     x[0] = spec.m0 + spec.P0_chol @ g.standard_normal(dx)
-    for t in range(1, K):
-        x[t] = spec.F @ x[t - 1] + spec.f + spec.Q_chol @ g.standard_normal(dx)
+    if dx == 1:
+        from scipy.signal import lfilter
+        e = spec.f[0] + spec.Q_chol[0, 0] * g.standard_normal(K - 1)
+        a = spec.F[0, 0]
+        if K > 1:
+            x[1:, 0] = lfilter([1.0], [1.0, -a], e, zi=[a * x[0, 0]])[0]
+    else:
+        for t in range(1, K):
+            x[t] = spec.F @ x[t - 1] + spec.f + spec.Q_chol @ g.standard_normal(dx)
     if spec.obs == "sv":
         y = (np.exp(0.5 * x[:, 0]) * g.standard_normal(K))[:, None]
     else:
@@ -106,12 +113,10 @@ def lg1d(K: int, A: float = 0.9, Q: float = 1.0, R: float = 1.0, m0: float = 0.0
     P_t = A^2 P_{t-1} + Q (an independent proposal, the closest independent
     analogue of a bootstrap proposal).
     """
-    means = np.empty(K)
-    var = np.empty(K)
-    means[0], var[0] = m0, P0
-    for t in range(1, K):
-        means[t] = A * means[t - 1]
-        var[t] = A * A * var[t - 1] + Q
+    tt = np.arange(K)
+    means = m0 * A ** tt
+    a2t = (A * A) ** tt
+    var = a2t * P0 + (Q * tt if A * A == 1.0 else Q * (1.0 - a2t) / (1.0 - A * A))
     spec = SSM(d_x=1, d_y=1, m0=np.array([m0]), P0_chol=np.array([[np.sqrt(P0)]]),
                F=np.array([[A]]), f=np.zeros(1), Q_chol=np.array([[np.sqrt(Q)]]),
                obs="lg", H=np.eye(1), h=np.zeros(1), R_chol=np.array([[np.sqrt(R)]]),

@@ -111,18 +111,20 @@ def test_single_time_point():
     check_leaves(spec, 300, 9, g, TOL32)
 
 
-def test_underflow_rescue_rows():
+@pytest.mark.parametrize("N", [64, 512])
+def test_underflow_rescue_rows(N):
     """Consecutive proposal means two units apart with transition sd 0.1: every
     pair weight underflows fp32 (about -290 in log2 units), so every row goes
-    through the rescue path; results still match the oracle."""
-    K = 24
+    through the rescue path (N = 512: more rows than one rescue pass takes);
+    results still match the oracle."""
+    K = 24 if N == 64 else 9
     qm = np.where(np.arange(K) % 2 == 0, 0.0, 2.0)[:, None]
     spec = W.lg1d(K, A=1.0, Q=0.01, R=1.0, seed=21)
     spec.q_mean = qm.astype(float)
     spec.q_chol = np.full((K, 1, 1), 0.05)
-    g = run_gpu(spec, 64, 5)
+    g = run_gpu(spec, N, 5)
     assert g["status"][0] == 0
-    rep = teacher_forced(spec, 64, 5, g, TOL32)
+    rep = teacher_forced(spec, N, 5, g, TOL32)
     log(f"rescue: {rep.summary()}")
     assert rep.mismatches_outside_band == 0, rep.worst[:5]
 
