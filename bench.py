@@ -45,10 +45,14 @@ def parse():
                     help="wall-clock budget of the oracle baseline sample (0 = skip)")
     ap.add_argument("--no-kernel-events", action="store_true",
                     help="time the steps without per-kernel HIP events")
-    ap.add_argument("--workload", choices=("sv", "batch"), default="sv",
+    ap.add_argument("--workload", choices=("sv", "batch", "serve"), default="sv",
                     help="sv: one long stochastic-volatility series (default); batch: "
                          "B linear-Gaussian series of uneven length, packed vs one at a time")
     ap.add_argument("--B", type=int, default=512)
+    ap.add_argument("--jobs", type=int, default=600, help="serving: jobs per arrival run")
+    ap.add_argument("--rates", type=str, default="0.25,0.5,0.75,0.9,1.1",
+                    help="serving: Poisson arrival rates as fractions of the saturated rate")
+    ap.add_argument("--serve-mem-gib", type=int, default=72)
     return ap.parse_args()
 
 
@@ -146,11 +150,122 @@ def bench_batch(args):
     print(json.dumps(res))
 
 
+def _pct(a, q):
+    import numpy as np
+    return float(np.percentile(np.asarray(a), q)) if len(a) else float("nan")
+
+
+def bench_serve(args):
+    """Serving: a seeded stream of jobs (half stochastic-volatility, half 4-D
+    linear-Gaussian, K ~ lognormal(median 512, sigma_log 1) clipped to
+    [2, 16384], N uniform over {256, 1024, 4096}, fp32) through dsmc_submit /
+    dsmc_poll.  First all jobs at once (saturated throughput), then Poisson
+    arrivals at fractions of that rate (p50/p99 latency from submission to
+    completion as the engine observes it).  Models and output buffers are on
+    the device before the clock starts.  Against it: the same jobs through
+    dsmc_smooth one after another (one set of launches per level per job)."""
+    import numpy as np
+    import torch
+
+    from paper_2202_02264_amd import dsmc as G
+    from paper_2202_02264_amd import workloads as W
+    t_gen = time.perf_counter()
+    jobs = W.serving_jobs(args.jobs)
+    models = [G.Model(s) for s, _, _ in jobs]
+    outs = [G.alloc_job_output(N, s.d_x, s.K) for s, N, _ in jobs]
+    torch.cuda.synchronize()
+    print(f"# serve: {len(jobs)} jobs generated and uploaded in "
+          f"{time.perf_counter() - t_gen:.1f} s", file=sys.stderr, flush=True)
+    pairs = sum((s.K - 1) * N * N for s, N, _ in jobs)
+    srv = G.Server(mem_budget=args.serve_mem_gib << 30, max_jobs=1024, max_classes=6)
+
+    def run(order, gaps=None):
+        ids = []
+        t0 = time.monotonic()
+        t_next = t0
+        for k in order:
+            spec, N, seed = jobs[k]
+            if gaps is not None:
+                t_next += gaps[len(ids)]
+                while True:
+                    d = t_next - time.monotonic()
+                    if d <= 0:
+                        break
+                    if d > 1e-3:
+                        time.sleep(d - 5e-4)
+            ids.append(G.dsmc_submit(srv, models[k], N, seed, outs[k]))
+        pending = set(ids)
+        while pending:
+            for i in list(pending):
+                rc, _ = G.dsmc_poll(srv, i)
+                if rc != G.DSMC_EAGAIN:
+                    if rc != 0:
+                        raise RuntimeError(f"serving job {i} failed with code {rc}")
+                    pending.discard(i)
+            time.sleep(2e-4)
+        ts = np.array([G.dsmc_job_times(srv, i) for i in ids])
+        lat = (ts[:, 2] - ts[:, 0]) * 1e3
+        span = ts[:, 2].max() - ts[:, 0].min()
+        return {"jobs_per_sec": len(ids) / span, "p50_ms": _pct(lat, 50), "p99_ms": _pct(lat, 99),
+                "mean_ms": float(lat.mean()), "span_s": float(span),
+                "pair_evals_per_sec": sum((jobs[k][0].K - 1) * jobs[k][1] ** 2 for k in order) / span}
+
+    warm = list(range(min(len(jobs), 48)))
+    run(warm)  # creates the class pools
+    sat = run(range(len(jobs)))
+    print(f"# serve saturated: {sat['jobs_per_sec']:.1f} jobs/s", file=sys.stderr, flush=True)
+    # the same jobs alone through dsmc_smooth, compared with the served results
+    served = {k: outs[k].traj.cpu() for k in range(0, len(jobs), 37)}
+    plans = {}
+    for spec, N, _ in jobs:
+        key = (N, spec.d_x)
+        plans[key] = max(plans.get(key, 0), spec.K)
+    plans = {k: G.Plan(k[0], k[1], K) for k, K in plans.items()}
+    for k in warm[:8]:
+        spec, N, seed = jobs[k]
+        G.dsmc_smooth(plans[(N, spec.d_x)], models[k], seed, outs[k])
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for k, (spec, N, seed) in enumerate(jobs):
+        G.dsmc_smooth(plans[(N, spec.d_x)], models[k], seed, outs[k])
+    torch.cuda.synchronize()
+    dt_plain = time.perf_counter() - t0
+    same = all(torch.equal(served[k], outs[k].traj.cpu()) for k in served)
+    print(f"# serve plain: {len(jobs) / dt_plain:.1f} jobs/s, served == alone: {same}",
+          file=sys.stderr, flush=True)
+    g = np.random.default_rng(7)
+    sweep = []
+    for f in [float(x) for x in args.rates.split(",") if x]:
+        rate = f * sat["jobs_per_sec"]
+        gaps = g.exponential(1.0 / rate, len(jobs))
+        r = run(range(len(jobs)), gaps)
+        r.update({"offered_jobs_per_sec": rate, "fraction_of_saturation": f})
+        sweep.append(r)
+        print(f"# serve rate {rate:.1f}/s: {r['jobs_per_sec']:.1f} jobs/s p50 {r['p50_ms']:.2f} ms "
+              f"p99 {r['p99_ms']:.2f} ms", file=sys.stderr, flush=True)
+    srv.close()
+    Ks = np.array([s.K for s, _, _ in jobs])
+    res = {"metric": "jobs/sec (serving, continuous batching)", "value": sat["jobs_per_sec"],
+           "unit": "jobs/s", "n_gpus": 1, "steps": 1, "warmup": 1,
+           "ms_per_step": sat["span_s"] * 1e3, "higher_is_better": True, "scaling": "weak",
+           "vs_baseline": None, "dtype": "f32", "data": "synthetic",
+           "config": {"workload": f"{len(jobs)} jobs, SV / 4-D LG 50/50, K ~ lognormal(median 512, "
+                                  f"sigma 1) in [2, 16384] (median {int(np.median(Ks))}, max "
+                                  f"{int(Ks.max())}), N in {{256, 1024, 4096}}, fp32",
+                      "jobs": len(jobs), "sum_pairs": pairs},
+           "saturated": sat, "plain_jobs_per_sec": len(jobs) / dt_plain,
+           "speedup_vs_plain": sat["jobs_per_sec"] * dt_plain / len(jobs),
+           "served_equals_alone": same, "sweep": sweep}
+    print(json.dumps(res))
+
+
 def main():
     args = parse()
     if args.gpus != 1:
         print(json.dumps({"error": "this build runs on one GPU only; --gpus must be 1"}))
         sys.exit(2)
+    if args.workload == "serve":
+        return bench_serve(args)
     if args.workload == "batch":
         return bench_batch(args)
     import torch

@@ -191,6 +191,54 @@ int dsmc_smooth(dsmc_plan_t *plan, const dsmc_model_t *model, uint64_t seed,
 int dsmc_smooth_batch(dsmc_plan_t *plan, int B, const dsmc_model_t *const *models,
                       const uint64_t *seeds, const dsmc_output *outs);
 
+/* --------------------------------------------------------------- serving */
+
+/* A serving engine runs smoothing jobs submitted at any time, with continuous
+ * batching: a scheduler thread admits queued jobs as device memory and slots
+ * free up, runs their leaves, and at every step packs the next tree level of
+ * every resident job of the same (N, d_x) class into one shared pair-rows and
+ * one sampling launch.  A job's results equal those of dsmc_smooth alone with
+ * the same model, N and seed, bit for bit. */
+typedef struct dsmc_server_desc {
+  size_t mem_budget; /* device bytes for all job classes together (0 = 16 GiB) */
+  int max_jobs;      /* resident jobs per class (0 = 1024) */
+  int max_classes;   /* distinct (N, d_x) classes; each gets mem_budget / max_classes (0 = 4) */
+  int precision;     /* DSMC_FP32 or DSMC_FP64 */
+  int flags;         /* reserved, 0 */
+} dsmc_server_desc;
+
+typedef struct dsmc_server_impl dsmc_server_t;
+
+/* One smoothing job.  The model and the output buffers must stay valid until
+ * dsmc_poll reports the job DONE or FAILED. */
+typedef struct dsmc_job {
+  const dsmc_model_t *model;
+  int N;          /* particles, 1..DSMC_MAX_N */
+  uint64_t seed;
+  dsmc_output out;
+} dsmc_job;
+
+enum { DSMC_JOB_QUEUED = 0, DSMC_JOB_RUNNING = 1, DSMC_JOB_DONE = 2, DSMC_JOB_FAILED = 3 };
+
+/* Start the scheduler thread.  Device pools are allocated per class on first
+ * use.  Errors: DSMC_EINVAL, DSMC_ENOMEM, DSMC_EDEVICE. */
+int dsmc_server_create(const dsmc_server_desc *desc, dsmc_server_t **out);
+/* Stop: queued jobs become FAILED (DSMC_ECANCELLED); jobs already on the GPU
+ * are finished; device pools are released. */
+void dsmc_server_destroy(dsmc_server_t *server);
+/* Queue a job (its descriptor is copied).  Errors (job not created):
+ * DSMC_EINVAL (bad arguments), DSMC_EUNSUPPORTED (N or d_x out of range). */
+int dsmc_submit(dsmc_server_t *server, const dsmc_job *job, uint64_t *job_id);
+/* State of a job: returns DSMC_OK when DONE (outputs complete on the device),
+ * DSMC_EAGAIN while QUEUED or RUNNING, the job's error code when FAILED
+ * (DSMC_ENOMEM: it can never fit the class pool; DSMC_ECANCELLED).  `state`
+ * may be NULL.  DSMC_EINVAL for an unknown id. */
+int dsmc_poll(dsmc_server_t *server, uint64_t job_id, int *state);
+/* Host steady-clock times in seconds of a job's submission, admission and
+ * observed completion (0 while not reached). */
+int dsmc_job_times(dsmc_server_t *server, uint64_t job_id, double *t_submit, double *t_start,
+                   double *t_done);
+
 /* Kernel timings of a plan created with DSMC_PLAN_PROFILE, accumulated over
  * every dsmc_smooth / dsmc_smooth_batch since the previous dsmc_plan_profile
  * call: synchronises the stream, fills per-kernel-class totals (HIP events

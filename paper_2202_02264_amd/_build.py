@@ -13,7 +13,7 @@ INCLUDE = os.path.join(ROOT, "include")
 LIB = os.path.join(PKG, "libdsmc.so")
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
 
-SOURCES = ["dsmc_kernels.hip", "dsmc_api.cpp"]
+SOURCES = ["dsmc_kernels.hip", "dsmc_api.cpp", "dsmc_server.cpp"]
 
 # Packed-fp32 instructions are disabled for all device code (the compiler
 # would otherwise form v_pk_* from plain float arithmetic).

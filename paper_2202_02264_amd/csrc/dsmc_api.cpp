@@ -12,6 +12,7 @@
 #include <vector>
 
 #include "dsmc.h"
+#include "dsmc_host.h"
 #include "dsmc_internal.h"
 #include "dsmc_launch.h"
 
@@ -20,7 +21,7 @@ using namespace dsmc;
 // ------------------------------------------------------------------ errors
 static thread_local std::string g_err;
 
-static int fail(int code, const char* fmt, ...) {
+int dsmc::fail(int code, const char* fmt, ...) {
   char buf[512];
   va_list ap;
   va_start(ap, fmt);
@@ -30,22 +31,9 @@ static int fail(int code, const char* fmt, ...) {
   return code;
 }
 
-#define HIP_TRY(expr)                                                              \
-  do {                                                                             \
-    hipError_t e_ = (expr);                                                        \
-    if (e_ != hipSuccess)                                                          \
-      return fail(e_ == hipErrorOutOfMemory ? DSMC_ENOMEM : DSMC_EDEVICE, "%s: %s", \
-                  #expr, hipGetErrorString(e_));                                   \
-  } while (0)
-
 extern "C" const char* dsmc_last_error(void) { return g_err.c_str(); }
 
 // ------------------------------------------------------------------- model
-struct dsmc_model {
-  void* dmem = nullptr;  // DevModel header followed by its arrays
-  DevModel* dev = nullptr;
-  int K = 0, dx = 0;
-};
 
 // Inverse of a lower-triangular matrix (forward substitution), fp64.
 static bool tri_inverse(const double* L, int d, double* out) {
@@ -213,9 +201,6 @@ extern "C" void dsmc_model_destroy(dsmc_model_t* m) {
 extern "C" int dsmc_model_K(const dsmc_model_t* m) { return m ? m->K : -1; }
 
 // -------------------------------------------------------------------- plan
-struct TileChoice {
-  int RPL, W, CS;
-};
 
 struct dsmc_plan_impl {
   dsmc_plan_desc d{};
@@ -273,7 +258,7 @@ static void plan_free(dsmc_plan_t* p) {
   if (p->staged) (void)hipEventDestroy(p->staged);
 }
 
-static int padded_dx(int dx) {
+int dsmc::padded_dx(int dx) {
   int q = 1;
   while (q < dx) q <<= 1;
   return q;
@@ -448,7 +433,7 @@ static void build_schedule(dsmc_plan_t* p, const std::vector<int>& Ks, const std
   for (int s = 0; s < B; ++s) p->roots[s] = blocks[s][0].former;
 }
 
-static int check_output(const dsmc_output* o) {
+int dsmc::check_output(const dsmc_output* o) {
   if (!o) return fail(DSMC_EINVAL, "null output");
   if (!o->traj || !o->log_Z || !o->status)
     return fail(DSMC_EINVAL, "output traj, log_Z and status are required");
@@ -458,7 +443,7 @@ static int check_output(const dsmc_output* o) {
 // Column splits that bring a launch to about `want` waves (8 waves per SIMD).
 // With one split the rows kernel also forms the row sums; with more, the
 // sampler re-reads the chunk sums to form them.
-static int pick_cs(int nodes, int N, int Nc, int rpl, int W) {
+int dsmc::pick_cs(int nodes, int N, int Nc, int rpl, int W) {
   const long rb = (N + 64L * rpl * W - 1) / (64L * rpl * W);
   const long waves = (long)nodes * rb * W;
   const long want = 8192;
@@ -468,7 +453,7 @@ static int pick_cs(int nodes, int N, int Nc, int rpl, int W) {
 
 // Heuristic rows-kernel tile: most rows per lane that still gives 16 waves
 // per CU without column splits, else one row per lane and column splits.
-static TileChoice heuristic_tile(int nodes, int N, int Nc) {
+TileChoice dsmc::heuristic_tile(int nodes, int N, int Nc) {
   const int rpls[3] = {4, 2, 1};
   for (int rpl : rpls) {
     const long waves = (long)nodes * ((N + 64 * rpl - 1) / (64 * rpl));
@@ -481,7 +466,7 @@ static TileChoice heuristic_tile(int nodes, int N, int Nc) {
   return {1, 1, 1};
 }
 
-static void set_tile(LevelLaunch& L, TileChoice tc) {
+void dsmc::set_tile(LevelLaunch& L, TileChoice tc) {
   L.RPL = tc.RPL;
   L.W = tc.W;
   L.RB = (L.N + 64 * tc.RPL * tc.W - 1) / (64 * tc.RPL * tc.W);
@@ -526,6 +511,74 @@ static TileChoice autotune_tile(dsmc_plan_t* p, LevelLaunch L) {
   (void)hipEventDestroy(e0);
   (void)hipEventDestroy(e1);
   return best;
+}
+
+void dsmc::build_series_schedule(int K, int series, int node_base, std::vector<NodeDesc>& nodes,
+                                 std::vector<int>& lvl_off, std::vector<int>& lvl_cnt,
+                                 std::vector<int32_t>& leaf_cons, int* root) {
+  struct Blk {
+    int a, b, former;
+  };
+  std::vector<Blk> bl;
+  bl.reserve(K);
+  for (int t = 0; t < K; ++t) bl.push_back({t, t + 1, -1});
+  leaf_cons.assign(K, -1);
+  lvl_off.clear();
+  lvl_cnt.clear();
+  const size_t first = nodes.size();
+  int n = 0;
+  while (bl.size() > 1) {
+    lvl_off.push_back(n);
+    std::vector<Blk> nxt;
+    nxt.reserve((bl.size() + 1) / 2);
+    for (size_t k = 0; k < bl.size(); k += 2) {
+      if (k + 1 == bl.size()) {
+        nxt.push_back(bl[k]);
+        continue;
+      }
+      const Blk L = bl[k], R = bl[k + 1];
+      const int id = node_base + n++;
+      NodeDesc nd;
+      nd.series = series;
+      nd.a = L.a;
+      nd.c = R.a;
+      nd.b = R.b;
+      nd.lchild = L.former;
+      nd.rchild = R.former;
+      nd.consumer = -1;
+      nd.role = 0;
+      nodes.push_back(nd);
+      if (L.former >= 0) {
+        nodes[first + (L.former - node_base)].consumer = id;
+        nodes[first + (L.former - node_base)].role = 0;
+      } else {
+        leaf_cons[L.a] = 2 * id;
+      }
+      if (R.former >= 0) {
+        nodes[first + (R.former - node_base)].consumer = id;
+        nodes[first + (R.former - node_base)].role = 1;
+      } else {
+        leaf_cons[R.a] = 2 * id + 1;
+      }
+      nxt.push_back({L.a, R.b, id});
+    }
+    bl.swap(nxt);
+    lvl_cnt.push_back(n - lvl_off.back());
+  }
+  *root = bl.empty() ? -1 : bl[0].former;
+}
+
+PoolSizes dsmc::pool_sizes(int N, int DX, int dx_alloc, size_t rsz) {
+  const size_t Npad = (size_t)(N + kChunk - 1) / kChunk * kChunk;
+  const size_t Nc = Npad / kChunk, NcP = (Nc + 3) / 4 * 4;
+  PoolSizes ps;
+  ps.per_row = (size_t)dx_alloc * N * rsz + N * rsz + 2 * sizeof(double)  // particles, weights, log L, bound
+               + 2 * N * sizeof(int32_t) + sizeof(double)                // ancestry, increment
+               + Npad * (DX + 1) * rsz + Npad * DX * rsz + N * rsz      // column / row data, row weights
+               + sizeof(double) + 2 * N * sizeof(int32_t)                // shift, first/last ancestry
+               + sizeof(NodeDesc) + 2 * sizeof(int32_t);                 // schedule
+  ps.per_node = (size_t)N * NcP * rsz + (size_t)N * sizeof(double);
+  return ps;
 }
 
 extern "C" int dsmc_smooth_batch(dsmc_plan_t* p, int B, const dsmc_model_t* const* models,

@@ -52,6 +52,18 @@ class dsmc_output(C.Structure):
                 ("row_lse", C.c_void_p), ("index", C.c_void_p)]
 
 
+class dsmc_server_desc(C.Structure):
+    _fields_ = [("mem_budget", C.c_size_t), ("max_jobs", C.c_int), ("max_classes", C.c_int),
+                ("precision", C.c_int), ("flags", C.c_int)]
+
+
+class dsmc_job(C.Structure):
+    _fields_ = [("model", C.c_void_p), ("N", C.c_int), ("seed", C.c_uint64), ("out", dsmc_output)]
+
+
+DSMC_JOB_QUEUED, DSMC_JOB_RUNNING, DSMC_JOB_DONE, DSMC_JOB_FAILED = 0, 1, 2, 3
+
+
 class dsmc_profile(C.Structure):
     _fields_ = [("launches", C.c_int * DSMC_NUM_KERNEL_CLASSES),
                 ("ms", C.c_double * DSMC_NUM_KERNEL_CLASSES), ("pairs", C.c_double)]
@@ -71,6 +83,12 @@ def _load() -> C.CDLL:
         "dsmc_smooth": (i, [vp, vp, u64, C.POINTER(dsmc_output)]),
         "dsmc_smooth_batch": (i, [vp, i, C.POINTER(vp), C.POINTER(u64), C.POINTER(dsmc_output)]),
         "dsmc_plan_profile": (i, [vp, C.POINTER(dsmc_profile)]),
+        "dsmc_server_create": (i, [C.POINTER(dsmc_server_desc), C.POINTER(vp)]),
+        "dsmc_server_destroy": (None, [vp]),
+        "dsmc_submit": (i, [vp, C.POINTER(dsmc_job), C.POINTER(u64)]),
+        "dsmc_poll": (i, [vp, u64, C.POINTER(i)]),
+        "dsmc_job_times": (i, [vp, u64, C.POINTER(C.c_double), C.POINTER(C.c_double),
+                               C.POINTER(C.c_double)]),
         "dsmc_last_error": (C.c_char_p, []),
     }
     for name, (res, args) in sig.items():
@@ -134,7 +152,7 @@ class Model:
         self.K, self.d_x = K, dx
 
     def __del__(self):
-        if getattr(self, "handle", None):
+        if getattr(self, "handle", None) and _lib is not None:
             _lib.dsmc_model_destroy(self.handle)
             self.handle = None
 
@@ -167,7 +185,7 @@ class Plan:
         self.dtype = torch.float64 if precision == DSMC_FP64 else torch.float32
 
     def __del__(self):
-        if getattr(self, "handle", None):
+        if getattr(self, "handle", None) and _lib is not None:
             _lib.dsmc_plan_destroy(self.handle)
             self.handle = None
 
@@ -259,3 +277,68 @@ def smooth(spec, N: int, seed: int, precision: int = DSMC_FP32, diagnostics: boo
     if st & DSMC_FLAG_NUMERIC:
         raise DsmcError(DSMC_ENUMERIC, "dsmc_smooth (device)")
     return out
+
+
+class Server:
+    """dsmc_server_create: continuous-batching serving engine.  Keeps a reference
+    to every submitted job's model and output buffers until it is polled done."""
+
+    def __init__(self, mem_budget: int = 16 << 30, max_jobs: int = 1024, max_classes: int = 4,
+                 precision: int = DSMC_FP32):
+        d = dsmc_server_desc()
+        d.mem_budget, d.max_jobs, d.max_classes, d.precision = mem_budget, max_jobs, max_classes, precision
+        h = C.c_void_p()
+        _check(_lib.dsmc_server_create(C.byref(d), C.byref(h)), "dsmc_server_create")
+        self.handle = h
+        self.dtype_is_fp64 = precision == DSMC_FP64
+        self._keep = {}
+
+    def close(self):
+        if getattr(self, "handle", None) and _lib is not None:
+            _lib.dsmc_server_destroy(self.handle)
+            self.handle = None
+            self._keep.clear()
+
+    def __del__(self):
+        self.close()
+
+
+def dsmc_server_create(**kw) -> Server:
+    return Server(**kw)
+
+
+def alloc_job_output(N: int, d_x: int, K: int, fp64: bool = False, diagnostics: bool = False):
+    class _P:
+        pass
+    p = _P()
+    import torch
+    p.N, p.d_x, p.dtype = N, d_x, (torch.float64 if fp64 else torch.float32)
+    return alloc_output(p, K, diagnostics)
+
+
+def dsmc_submit(server: Server, model: Model, N: int, seed: int, out: Output) -> int:
+    j = dsmc_job()
+    j.model = model.handle.value
+    j.N = N
+    j.seed = seed & (2**64 - 1)
+    j.out = out.c_struct()
+    jid = C.c_uint64()
+    _check(_lib.dsmc_submit(server.handle, C.byref(j), C.byref(jid)), "dsmc_submit")
+    server._keep[jid.value] = (model, out)
+    return jid.value
+
+
+def dsmc_poll(server: Server, job_id: int):
+    """(return code, state); code 0 = done, DSMC_EAGAIN = not yet, else failed."""
+    st = C.c_int()
+    rc = _lib.dsmc_poll(server.handle, C.c_uint64(job_id), C.byref(st))
+    if rc != DSMC_EAGAIN:
+        server._keep.pop(job_id, None)
+    return rc, st.value
+
+
+def dsmc_job_times(server: Server, job_id: int):
+    a, b, c = C.c_double(), C.c_double(), C.c_double()
+    _check(_lib.dsmc_job_times(server.handle, C.c_uint64(job_id), C.byref(a), C.byref(b),
+                               C.byref(c)), "dsmc_job_times")
+    return a.value, b.value, c.value

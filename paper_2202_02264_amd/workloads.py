@@ -249,14 +249,16 @@ def lg1d_batch(B: int = 512, K_lo: int = 64, K_hi: int = 8192, seed: int = DATA_
     return out
 
 
-def lg4d(K: int, seed: int = DATA_SEED, weighting: str = "leaf_obs") -> SSM:
+def lg4d(K: int, seed: int = DATA_SEED, weighting: str = "leaf_obs",
+         proposal: str = "prior") -> SSM:
     """4-D linear-Gaussian model: A = 0.9 * random orthogonal, Q = 0.5 I, H = I, R = I,
-    x_0 stationary, prior-marginal proposals."""
+    x_0 stationary; prior-marginal ("prior") or RTS smoothing-marginal ("rts")
+    proposals."""
     g = _rng(seed + 3)
     F = 0.9 * random_orthogonal(4, g)
     P0 = np.eye(4) * 0.5 / (1.0 - 0.81)
     return lg(K, F, np.sqrt(0.5) * np.eye(4), np.eye(4), np.eye(4), np.zeros(4),
-              np.linalg.cholesky(P0), seed=seed, proposal="prior", weighting=weighting,
+              np.linalg.cholesky(P0), seed=seed, proposal=proposal, weighting=weighting,
               name=f"lg4d(K={K})")
 
 
@@ -268,3 +270,24 @@ def c1_lg1d() -> SSM:
 def c2_sv() -> SSM:
     """Headline workload: stochastic volatility, K = 4096 time points."""
     return sv(4096)
+
+
+def serving_jobs(J: int, seed: int = DATA_SEED, K_median: float = 512.0, sigma_log: float = 1.0,
+                 K_cap: int = 16384, Ns=(256, 1024, 4096), bases: int = 4):
+    """A seeded stream of J smoothing jobs: half stochastic-volatility, half
+    4-D linear-Gaussian (RTS proposals); K = floor(lognormal(log K_median,
+    sigma_log)) clipped to [2, K_cap]; N uniform over Ns.  Each job's model is
+    the first K points of one of `bases` long series per model family.
+    Returns (spec, N, seed) triples."""
+    g = _rng(seed + 11)
+    sv_b = [sv(K_cap, seed=seed + 100 + i) for i in range(bases)]
+    lg_b = [lg4d(K_cap, seed=seed + 200 + i, proposal="rts") for i in range(bases)]
+    jobs = []
+    for j in range(J):
+        K = int(np.clip(np.floor(np.exp(np.log(K_median) + sigma_log * g.standard_normal())),
+                        2, K_cap))
+        fam = sv_b if g.random() < 0.5 else lg_b
+        base = fam[int(g.integers(bases))]
+        N = int(Ns[int(g.integers(len(Ns)))])
+        jobs.append((base.truncated(K), N, 1 + j))
+    return jobs

@@ -21,7 +21,7 @@ def _declared_functions():
 def test_header_declares_the_entry_points():
     names = _declared_functions()
     for n in ("dsmc_plan", "dsmc_smooth", "dsmc_smooth_batch", "dsmc_model_create",
-              "dsmc_last_error"):
+              "dsmc_server_create", "dsmc_submit", "dsmc_poll", "dsmc_last_error"):
         assert n in names
 
 
@@ -40,7 +40,8 @@ def test_struct_layout_matches_header(tmp_path):
     from paper_2202_02264_amd import dsmc
     if shutil.which("gcc") is None:
         pytest.skip("gcc not available")
-    structs = [dsmc.dsmc_model_desc, dsmc.dsmc_plan_desc, dsmc.dsmc_output, dsmc.dsmc_profile]
+    structs = [dsmc.dsmc_model_desc, dsmc.dsmc_plan_desc, dsmc.dsmc_output, dsmc.dsmc_profile,
+               dsmc.dsmc_server_desc, dsmc.dsmc_job]
     lines = ["#include <stdio.h>", "#include <stddef.h>", '#include "dsmc.h"', "int main(void){"]
     for s in structs:
         lines.append(f'printf("%zu\\n", sizeof({s.__name__}));')
@@ -93,3 +94,14 @@ def test_invalid_arguments_rejected_on_host():
     p.N, p.precision = 64, 9
     assert lib.dsmc_plan(C.byref(p), C.byref(hp)) == dsmc.DSMC_EUNSUPPORTED
     assert lib.dsmc_smooth(None, None, 0, None) == dsmc.DSMC_EINVAL
+    # serving entry points
+    sd = dsmc.dsmc_server_desc()
+    hs = C.c_void_p()
+    sd.precision = 9
+    assert lib.dsmc_server_create(C.byref(sd), C.byref(hs)) == dsmc.DSMC_EUNSUPPORTED
+    assert lib.dsmc_server_create(None, C.byref(hs)) == dsmc.DSMC_EINVAL
+    jid = C.c_uint64()
+    job = dsmc.dsmc_job()
+    assert lib.dsmc_submit(None, C.byref(job), C.byref(jid)) == dsmc.DSMC_EINVAL
+    assert lib.dsmc_poll(None, 1, None) == dsmc.DSMC_EINVAL
+    assert lib.dsmc_job_times(None, 1, None, None, None) == dsmc.DSMC_EINVAL
