@@ -32,6 +32,17 @@ LANE_OPS_PER_S = 256 * 4 * 16 * 2.4e9
 # co-issue with it: measured 1.85e13 vs 3.5e13 lane-instructions/s).
 TRANS_SLOTS = 2.0
 SLOTS_PER_PAIR = 3.0 + TRANS_SLOTS
+# bf16 matrix-core pair rows (d_x = 16, 32): the dot products run on the
+# matrix cores; per pair the VALU issues the accumulator start (one v_sub),
+# v_exp_f32 (TRANS_SLOTS) and the chunk-sum add.
+SLOTS_PER_PAIR_MFMA = 2.0 + TRANS_SLOTS
+# dense bf16 matrix-core peak of MI355X, and flops per pair at d_x = 32
+BF16_MFMA_PEAK = 2.5e15
+# HBM traffic of one pair-row launch of the default workload (K = 4096,
+# N = 1024), averaged over the 12 levels: rocprofv3 FETCH_SIZE / WRITE_SIZE,
+# each scaled by the same counter's reading for a 256 MiB device copy (see
+# profiles/k_rows_sv_K4096_N1024.md).  Reset to None when k_rows changes.
+K_ROWS_SV_TRAFFIC_MIB = {"read": 17.83, "write": 88.59}
 
 
 def parse():
@@ -45,7 +56,7 @@ def parse():
                     help="wall-clock budget of the oracle baseline sample (0 = skip)")
     ap.add_argument("--no-kernel-events", action="store_true",
                     help="time the steps without per-kernel HIP events")
-    ap.add_argument("--workload", choices=("sv", "batch", "serve"), default="sv",
+    ap.add_argument("--workload", choices=("sv", "batch", "serve", "highdim"), default="sv",
                     help="sv: one long stochastic-volatility series (default); batch: "
                          "B linear-Gaussian series of uneven length, packed vs one at a time")
     ap.add_argument("--B", type=int, default=512)
@@ -53,6 +64,8 @@ def parse():
     ap.add_argument("--rates", type=str, default="0.25,0.5,0.75,0.9,1.1",
                     help="serving: Poisson arrival rates as fractions of the saturated rate")
     ap.add_argument("--serve-mem-gib", type=int, default=72)
+    ap.add_argument("--copy-calibration", action="store_true",
+                    help="only run 10 device copies of 256 MiB (HBM counter calibration)")
     return ap.parse_args()
 
 
@@ -71,7 +84,7 @@ def cpu_baseline(spec, N: int, budget_s: float) -> dict:
         sub = spec.truncated(c + 1)
         xs = []
         for t in (c - 1, c):
-            z = P.leaf_normals(seed, t, N, 1)
+            z = P.leaf_normals(seed, t, N, spec.d_x)
             xs.append(sub.q_mean[t][None, :] + z @ sub.q_chol[t].T)
         lws = [D.normalise(D.leaf_logweights(sub, t, x))[0] for t, x in zip((c - 1, c), xs)]
         u1, u2 = P.combine_uniforms(seed, c, N)
@@ -259,13 +272,95 @@ def bench_serve(args):
     print(json.dumps(res))
 
 
+def bench_highdim(args):
+    """d_x = 32 linear-Gaussian model (A = 0.95 orth, Q = 0.1 I, d_y = 8,
+    R = 0.5 I, RTS proposals), K = 2048, N = 4096: the bf16 matrix-core
+    pair-row path (DSMC_BF16), with the fp32 VALU path on the same model
+    beside it."""
+    import torch
+
+    from paper_2202_02264_amd import dsmc as G
+    from paper_2202_02264_amd import workloads as W
+    K = 2048 if args.K == 4096 else args.K
+    N = 4096 if args.N == 1024 else args.N
+    spec = W.lg_highdim(K=K)
+    model = G.Model(spec)
+    pairs = (K - 1) * N * N
+    runs = {}
+    for name, prec, steps in (("bf16", G.DSMC_BF16, max(1, min(args.steps, 10))),
+                              ("fp32", G.DSMC_FP32, max(1, min(args.steps, 3)))):
+        plan = G.Plan(N, spec.d_x, K, precision=prec, profile=not args.no_kernel_events)
+        out = G.alloc_output(plan, K)
+        for s in range(max(1, args.warmup)):
+            G.dsmc_smooth(plan, model, 1000 + s, out)
+        torch.cuda.synchronize()
+        if not args.no_kernel_events:
+            G.dsmc_plan_profile(plan)
+        t0 = time.perf_counter()
+        for s in range(steps):
+            G.dsmc_smooth(plan, model, s + 1, out)
+        torch.cuda.synchronize()
+        dt = (time.perf_counter() - t0) / steps
+        status = int(out.status.item())
+        if status:
+            raise RuntimeError(f"{name}: device status {status}")
+        r = {"ms_per_step": dt * 1e3, "pair_evals_per_sec": pairs / dt, "steps": steps,
+             "log_Z_last": float(out.log_Z.item())}
+        if not args.no_kernel_events:
+            prof = G.dsmc_plan_profile(plan)
+            r["kernel_ms_per_step"] = {k: v / steps for k, v in prof["ms"].items()}
+            r["rows_pairs_per_sec"] = prof["pairs"] / (prof["ms"]["rows"] * 1e-3)
+            r["rows_launches"] = prof["launches"]["rows"]
+            r["rows_pairs"] = prof["pairs"]
+        runs[name] = r
+        print(f"# highdim {name}: {dt * 1e3:.2f} ms/step", file=sys.stderr, flush=True)
+        del plan, out
+        torch.cuda.empty_cache()
+    b = runs["bf16"]
+    res = {"metric": "pair-evals/sec", "value": b["pair_evals_per_sec"], "unit": "pair-evals/s",
+           "n_gpus": 1, "steps": b["steps"], "warmup": args.warmup, "ms_per_step": b["ms_per_step"],
+           "higher_is_better": True, "scaling": "weak", "vs_baseline": None, "dtype": "bf16",
+           "data": "synthetic",
+           "config": {"workload": f"linear-Gaussian d_x=32 (d_y=8, A=0.95 orth, Q=0.1I, R=0.5I, "
+                                  f"RTS proposals), K={K}, N={N}, one smoother per step",
+                      "K": K, "N": N, "d_x": 32,
+                      "precision": "bf16 matrix-core dot products, fp32 accumulation and "
+                                   "exponentials, fp64 row sums and CDFs"},
+           "smoothers_per_sec": 1e3 / b["ms_per_step"], "fp32_valu": runs["fp32"],
+           "speedup_vs_fp32": runs["fp32"]["ms_per_step"] / b["ms_per_step"]}
+    if "rows_pairs_per_sec" in b:
+        ach = b["rows_pairs_per_sec"]
+        peak = LANE_OPS_PER_S / SLOTS_PER_PAIR_MFMA
+        ms_rows = b["kernel_ms_per_step"]["rows"] * b["steps"]
+        res["roofline"] = {"bound": "alu", "kernel": "k_rows_mfma<32,MB>", "achieved": ach / 1e9,
+                           "peak": peak / 1e9, "unit": "Gpair/s", "frac": ach / peak,
+                           "traffic": None, "avg_launch_ms": ms_rows / max(1, b["rows_launches"]),
+                           "pairs_per_launch": b["rows_pairs"] / max(1, b["rows_launches"]),
+                           "mfma_utilisation": ach * 2 * spec.d_x / BF16_MFMA_PEAK}
+        res["kernel_ms_per_step"] = b["kernel_ms_per_step"]
+    if args.cpu_seconds > 0:
+        res["cpu_baseline"] = cpu_baseline(spec, N, args.cpu_seconds)
+    print(json.dumps(res))
+
+
 def main():
     args = parse()
     if args.gpus != 1:
         print(json.dumps({"error": "this build runs on one GPU only; --gpus must be 1"}))
         sys.exit(2)
+    if args.copy_calibration:
+        import torch
+        x = torch.ones(64 << 20, dtype=torch.float32, device="cuda")
+        y = torch.empty_like(x)
+        for _ in range(10):
+            y.copy_(x)
+        torch.cuda.synchronize()
+        print(json.dumps({"copy_calibration_bytes_per_launch": 2 * x.numel() * 4, "launches": 10}))
+        return
     if args.workload == "serve":
         return bench_serve(args)
+    if args.workload == "highdim":
+        return bench_highdim(args)
     if args.workload == "batch":
         return bench_batch(args)
     import torch
@@ -321,9 +416,17 @@ def main():
         ms_rows = prof["ms"]["rows"]
         achieved = prof["pairs"] / (ms_rows * 1e-3)
         peak = LANE_OPS_PER_S / SLOTS_PER_PAIR
+        traffic = None
+        if K_ROWS_SV_TRAFFIC_MIB and (K, N) == (4096, 1024):
+            traffic = (K_ROWS_SV_TRAFFIC_MIB["read"] + K_ROWS_SV_TRAFFIC_MIB["write"]) * 2 ** 20
+        nodes = K - 1
+        Npad = (N + 31) // 32 * 32
+        algo_bytes = nodes * (Npad * 2 * 4 + Npad * 4 + N * ((Npad // 32 + 3) // 4 * 4) * 4
+                              + N * 8) / max(1, n_rows / args.steps)
         res["roofline"] = {"bound": "alu", "kernel": "k_rows<float,1,RPL>",
                            "achieved": achieved / 1e9, "peak": peak / 1e9, "unit": "Gpair/s",
-                           "frac": achieved / peak, "traffic": None,
+                           "frac": achieved / peak, "traffic": traffic,
+                           "traffic_algorithmic": algo_bytes,
                            "avg_launch_ms": ms_rows / max(1, n_rows),
                            "pairs_per_launch": prof["pairs"] / max(1, n_rows)}
         res["kernel_ms_per_step"] = {k: v / args.steps for k, v in prof["ms"].items()}

@@ -129,7 +129,13 @@ int dsmc_model_K(const dsmc_model_t *model);
 /* ----------------------------------------------------------------- plan */
 
 enum { DSMC_FP32 = 0, /* particles and pair weights in fp32, sums and CDFs in fp64 */
-       DSMC_FP64 = 1  /* everything in fp64 */ };
+       DSMC_FP64 = 1, /* everything in fp64 */
+       DSMC_BF16 = 2  /* d_x >= 9 only (padded to 16 or 32): as DSMC_FP32, except that the
+                         whitened boundary coordinates u, v of Algorithm 1's pair weight
+                         are rounded to bf16 and the quadratic form ||u - v||^2 is
+                         formed as ||u||^2 + ||v||^2 - 2 u.v with the dot products on
+                         bf16 matrix cores (fp32 accumulation); results differ from the
+                         fp64 oracle by the bf16 rounding of u and v */ };
 
 #define DSMC_PLAN_PROFILE 1  /* record HIP events around every kernel launch */
 #define DSMC_PLAN_AUTOTUNE 2 /* time the pair-row kernel's tile shapes on first use of each
@@ -140,7 +146,7 @@ typedef struct dsmc_plan_desc {
   int d_x;         /* state dimension of the models run with this plan */
   int max_K;       /* largest K of one series */
   int max_total_K; /* largest sum of K over one dsmc_smooth_batch call (0 = max_K) */
-  int precision;   /* DSMC_FP32 or DSMC_FP64 */
+  int precision;   /* DSMC_FP32, DSMC_FP64 or DSMC_BF16 */
   int flags;       /* DSMC_PLAN_* */
   void *stream;    /* hipStream_t all work is enqueued on; NULL = null stream */
 } dsmc_plan_desc;
@@ -150,15 +156,17 @@ typedef struct dsmc_plan_impl dsmc_plan_t;
 /* Allocate the plan's device workspace: about
  * max_total_K * N * ((3 d_x + 2) s + 28) bytes for particles, weights, ancestry
  * and per-combine data, plus at most 1 GiB of per-level chunk sums
- * (N * N * s / 32 per combine of a launch), s = sizeof the real type.
- * Errors: DSMC_EINVAL, DSMC_EUNSUPPORTED, DSMC_ENOMEM. */
+ * (N * N * s / 32 per combine of a launch), s = sizeof the real type;
+ * DSMC_BF16 adds max_total_K * N * (4 d_x + 8) bytes of bf16 operands.
+ * Errors: DSMC_EINVAL, DSMC_EUNSUPPORTED (also DSMC_BF16 with d_x <= 8),
+ * DSMC_ENOMEM. */
 int dsmc_plan(const dsmc_plan_desc *desc, dsmc_plan_t **out);
 void dsmc_plan_destroy(dsmc_plan_t *plan);
 
 /* ---------------------------------------------------------------- output */
 
 /* Caller-owned DEVICE buffers for one series of K time points.  `real` is
- * float for DSMC_FP32 plans and double for DSMC_FP64 plans. */
+ * float for DSMC_FP32 and DSMC_BF16 plans and double for DSMC_FP64 plans. */
 typedef struct dsmc_output {
   void *traj;      /* real [d_x][K][N]: trajectory n is traj[.][0..K-1][n] (required) */
   void *logw;      /* real [N]: log-weights of the trajectories; -log N when K >= 2,

@@ -206,6 +206,7 @@ struct dsmc_plan_impl {
   dsmc_plan_desc d{};
   int DX = 1;
   bool fp64 = false;
+  bool bf16 = false;
   size_t rsz = 4;
   hipStream_t stream = nullptr;
   int Npad = 0, Nc = 0, NcP = 0;
@@ -223,6 +224,7 @@ struct dsmc_plan_impl {
   // per launch slice
   void* P = nullptr;
   double* Rsum = nullptr;
+  float* Rshift = nullptr;
   // schedule
   NodeDesc* d_nodes = nullptr;
   int32_t* d_series_of_t = nullptr;
@@ -250,8 +252,9 @@ struct dsmc_plan_impl {
 
 static void plan_free(dsmc_plan_t* p) {
   void* dev[] = {p->leafX, p->leafW, p->leafL, p->bmerged, p->anc, p->zinc, p->nb.col, p->nb.row,
-                 p->nb.alpha, p->nb.bcol, p->nb.sfirst, p->nb.slast, p->P, p->Rsum, p->d_nodes,
-                 p->d_series_of_t, p->d_leaf_cons, p->d_series};
+                 p->nb.alpha, p->nb.bcol, p->nb.sfirst, p->nb.slast, p->nb.colh, p->nb.colb,
+                 p->nb.rowh, p->nb.rown, p->P, p->Rsum, p->Rshift, p->d_nodes, p->d_series_of_t,
+                 p->d_leaf_cons, p->d_series};
   for (void* q : dev) (void)hipFree(q);
   void* host[] = {p->h_nodes, p->h_series_of_t, p->h_leaf_cons, p->h_series};
   for (void* q : host) (void)hipHostFree(q);
@@ -270,13 +273,16 @@ extern "C" int dsmc_plan(const dsmc_plan_desc* d, dsmc_plan_t** out) {
   if (d->N < 1 || d->N > DSMC_MAX_N) return fail(DSMC_EUNSUPPORTED, "N must be in 1..%d", DSMC_MAX_N);
   if (d->d_x < 1 || d->d_x > DSMC_MAX_DX) return fail(DSMC_EUNSUPPORTED, "d_x must be in 1..%d", DSMC_MAX_DX);
   if (d->max_K < 1) return fail(DSMC_EINVAL, "max_K must be >= 1");
-  if (d->precision != DSMC_FP32 && d->precision != DSMC_FP64)
+  if (d->precision != DSMC_FP32 && d->precision != DSMC_FP64 && d->precision != DSMC_BF16)
     return fail(DSMC_EUNSUPPORTED, "precision %d not supported", d->precision);
+  if (d->precision == DSMC_BF16 && padded_dx(d->d_x) < 16)
+    return fail(DSMC_EUNSUPPORTED, "DSMC_BF16 needs d_x >= 9 (got %d)", d->d_x);
   auto* p = new dsmc_plan_t;
   p->d = *d;
   if (p->d.max_total_K < p->d.max_K) p->d.max_total_K = p->d.max_K;
   p->DX = padded_dx(d->d_x);
   p->fp64 = d->precision == DSMC_FP64;
+  p->bf16 = d->precision == DSMC_BF16;
   p->rsz = p->fp64 ? 8 : 4;
   p->stream = (hipStream_t)d->stream;
   p->timer.on = (d->flags & DSMC_PLAN_PROFILE) != 0;
@@ -287,7 +293,7 @@ extern "C" int dsmc_plan(const dsmc_plan_desc* d, dsmc_plan_t** out) {
   p->NcP = (p->Nc + 3) / 4 * 4;
   const size_t TK = (size_t)p->d.max_total_K;
   const size_t max_nodes = std::max<size_t>(1, TK / 2);
-  const size_t per_node_P = (size_t)N * p->NcP * p->rsz + (size_t)N * sizeof(double);
+  const size_t per_node_P = (size_t)N * p->NcP * p->rsz + (size_t)N * (sizeof(double) + sizeof(float));
   const size_t cap_by_mem = std::max<size_t>(1, ((size_t)1 << 30) / per_node_P);
   p->node_cap = (int)std::min(max_nodes, cap_by_mem);
   const size_t nc = (size_t)p->node_cap;
@@ -312,11 +318,19 @@ extern "C" int dsmc_plan(const dsmc_plan_desc* d, dsmc_plan_t** out) {
       {(void**)&p->nb.slast, TK * N * sizeof(int32_t), "last-time ancestry"},
       {&p->P, nc * N * p->NcP * R, "chunk sums"},
       {(void**)&p->Rsum, nc * N * sizeof(double), "row sums"},
+      {(void**)&p->Rshift, nc * N * sizeof(float), "row shifts"},
       {(void**)&p->d_nodes, TK * sizeof(NodeDesc), "schedule"},
       {(void**)&p->d_series_of_t, TK * sizeof(int32_t), "series map"},
       {(void**)&p->d_leaf_cons, TK * sizeof(int32_t), "leaf consumers"},
   };
-  for (auto& a : allocs) {
+  std::vector<A> all(std::begin(allocs), std::end(allocs));
+  if (p->bf16) {
+    all.push_back({(void**)&p->nb.colh, TK * p->Npad * DXp * 2, "bf16 column operands"});
+    all.push_back({(void**)&p->nb.colb, TK * p->Npad * sizeof(float), "column norms"});
+    all.push_back({(void**)&p->nb.rowh, TK * p->Npad * DXp * 2, "bf16 row operands"});
+    all.push_back({(void**)&p->nb.rown, TK * p->Npad * sizeof(float), "row norms"});
+  }
+  for (auto& a : all) {
     hipError_t e = hipMalloc(a.ptr, std::max<size_t>(a.bytes, 256));
     if (e != hipSuccess) {
       rc = fail(DSMC_ENOMEM, "hipMalloc(%s, %zu B): %s", a.what, a.bytes, hipGetErrorString(e));
@@ -577,7 +591,7 @@ PoolSizes dsmc::pool_sizes(int N, int DX, int dx_alloc, size_t rsz) {
                + Npad * (DX + 1) * rsz + Npad * DX * rsz + N * rsz      // column / row data, row weights
                + sizeof(double) + 2 * N * sizeof(int32_t)                // shift, first/last ancestry
                + sizeof(NodeDesc) + 2 * sizeof(int32_t);                 // schedule
-  ps.per_node = (size_t)N * NcP * rsz + (size_t)N * sizeof(double);
+  ps.per_node = (size_t)N * NcP * rsz + (size_t)N * (sizeof(double) + sizeof(float));
   return ps;
 }
 
@@ -676,6 +690,7 @@ extern "C" int dsmc_smooth_batch(dsmc_plan_t* p, int B, const dsmc_model_t* cons
       const int nodes = std::min(p->node_cap, cnt - s0);
       LevelLaunch L{};
       L.fp64 = p->fp64;
+      L.bf16 = p->bf16;
       L.DX = p->DX;
       L.node_list = nullptr;
       L.node0 = p->level_off[l] + s0;
@@ -691,6 +706,7 @@ extern "C" int dsmc_smooth_batch(dsmc_plan_t* p, int B, const dsmc_model_t* cons
       L.bmerged = p->bmerged;
       L.P = p->P;
       L.Rsum = p->Rsum;
+      L.Rshift = p->Rshift;
       L.nb = p->nb;
       auto it = p->tiles.find(nodes);
       TileChoice tc;

@@ -77,6 +77,12 @@ struct NodeBufs {
   double* bcol;     // [nodes]              B: shift of the node's beta (log2 units: beta = log2e (b - B))
   int32_t* sfirst;  // [nodes][N]           leaf index, at the block's first time, of trajectory n
   int32_t* slast;   // [nodes][N]           same at the block's last time
+  // bf16 matrix-core operands (null unless the plan is DSMC_BF16).  col and row
+  // then hold the bf16-rounded u and v as fp32.
+  uint16_t* colh;   // [nodes][Npad][DX]    bf16 bits of 2 u_n (zero in padding columns)
+  float* colb;      // [nodes][Npad]        beta_n - ||u_n||^2 (-inf in padding columns)
+  uint16_t* rowh;   // [nodes][Npad][DX]    bf16 bits of v_m
+  float* rown;      // [nodes][Npad]        ||v_m||^2
 };
 
 enum : int32_t { kFlagDegenerate = 1, kFlagNumeric = 2 };

@@ -25,6 +25,11 @@
 
 namespace dsmc {
 
+// Row sums of combines with DX >= 8 are formed relative to a per-row shift
+// (see k_rows); below that the column bound alone keeps them in range.
+template <int DX>
+inline constexpr bool kRowShift = DX >= 8;
+
 // Whitened column coordinates of a right-block particle x at boundary c:
 // u = Wcol (x - q_mean[c]).
 template <int DX>
@@ -66,6 +71,93 @@ __device__ __forceinline__ void load_particle(const R* __restrict__ leafX, int t
 #pragma unroll
   for (int i = 0; i < DX; ++i)
     x[i] = (i < dx) ? (double)leafX[((size_t)i * totalK + g) * N + src] : 0.0;
+}
+
+// bf16 bits of x, rounded to nearest even (NaN stays NaN).
+__device__ __forceinline__ uint32_t bf16_bits(float x) {
+  const uint32_t u = __float_as_uint(x);
+  if ((u & 0x7fffffffu) > 0x7f800000u) return 0x7fc0u;
+  return (u + 0x7fffu + ((u >> 16) & 1u)) >> 16;
+}
+__device__ __forceinline__ float bf16_float(uint32_t b) { return __uint_as_float(b << 16); }
+
+// Column data (u_n, beta_n) of right-block particle n of combine `node`.  In a
+// bf16 plan u is rounded to bf16 first and the matrix-core operands are
+// written too: the bits of 2u (exact) and beta - ||u||^2.
+template <typename R, int DX>
+__device__ __forceinline__ void put_col(const NodeBufs& nb, size_t node, int Npad, int n,
+                                        const double (&u)[DX], double beta) {
+  R* cp = (R*)nb.col + (node * Npad + n) * (DX + 1);
+  if constexpr (sizeof(R) == 4 && DX >= 16) {
+    if (nb.colh) {
+      uint32_t w[DX / 2];
+      double nrm = 0.0;
+#pragma unroll
+      for (int i = 0; i < DX; ++i) {
+        const float ur = bf16_float(bf16_bits((float)u[i]));
+        cp[i] = ur;
+        nrm += (double)ur * (double)ur;
+        const uint32_t b2 = bf16_bits(2.0f * ur);
+        w[i >> 1] = (i & 1) ? (w[i >> 1] | (b2 << 16)) : b2;
+      }
+      const float bf = (float)beta;
+      cp[DX] = bf;
+      uint4* dst = (uint4*)(nb.colh + (node * Npad + n) * DX);
+#pragma unroll
+      for (int q = 0; q < DX / 8; ++q) dst[q] = make_uint4(w[4 * q], w[4 * q + 1], w[4 * q + 2], w[4 * q + 3]);
+      nb.colb[node * Npad + n] = (float)((double)bf - nrm);
+      return;
+    }
+  }
+#pragma unroll
+  for (int i = 0; i < DX; ++i) cp[i] = (R)u[i];
+  cp[DX] = (R)beta;
+}
+
+// Padding column n (N <= n < Npad): weight zero.
+template <typename R, int DX>
+__device__ __forceinline__ void put_col_pad(const NodeBufs& nb, size_t node, int Npad, int n) {
+  R* cp = (R*)nb.col + (node * Npad + n) * (DX + 1);
+#pragma unroll
+  for (int i = 0; i < DX; ++i) cp[i] = (R)0;
+  cp[DX] = (R)(-INFINITY);
+  if constexpr (sizeof(R) == 4 && DX >= 16) {
+    if (nb.colh) {
+      uint4* dst = (uint4*)(nb.colh + (node * Npad + n) * DX);
+#pragma unroll
+      for (int q = 0; q < DX / 8; ++q) dst[q] = make_uint4(0u, 0u, 0u, 0u);
+      nb.colb[node * Npad + n] = -INFINITY;
+    }
+  }
+}
+
+// Row data v_m of left-block particle m of combine `node` (bf16 plan: rounded
+// v, its bits and ||v||^2).
+template <typename R, int DX>
+__device__ __forceinline__ void put_row(const NodeBufs& nb, size_t node, int Npad, int m,
+                                        const double (&v)[DX]) {
+  R* rp = (R*)nb.row + (node * Npad + m) * DX;
+  if constexpr (sizeof(R) == 4 && DX >= 16) {
+    if (nb.rowh) {
+      uint32_t w[DX / 2];
+      double nrm = 0.0;
+#pragma unroll
+      for (int i = 0; i < DX; ++i) {
+        const uint32_t b = bf16_bits((float)v[i]);
+        const float vr = bf16_float(b);
+        rp[i] = vr;
+        nrm += (double)vr * (double)vr;
+        w[i >> 1] = (i & 1) ? (w[i >> 1] | (b << 16)) : b;
+      }
+      uint4* dst = (uint4*)(nb.rowh + (node * Npad + m) * DX);
+#pragma unroll
+      for (int q = 0; q < DX / 8; ++q) dst[q] = make_uint4(w[4 * q], w[4 * q + 1], w[4 * q + 2], w[4 * q + 3]);
+      nb.rown[node * Npad + m] = (float)nrm;
+      return;
+    }
+  }
+#pragma unroll
+  for (int i = 0; i < DX; ++i) rp[i] = (R)v[i];
 }
 
 // ================================================================ leaves
@@ -164,32 +256,25 @@ __global__ __launch_bounds__(kBlock) void k_leaves(
   const int P = cons >> 1, role = cons & 1;
   const int c = nodes[P].c;
   if (role == 1) {  // right block of combine P (c == t)
-    R* colp = (R*)nb.col + (size_t)P * Npad * (DX + 1);
     for (int n = threadIdx.x; n < Npad; n += kBlock) {
       if (n < N) {
         double x[DX], u[DX];
         load_particle<R, DX>(leafX, totalK, N, g, n, dx, x);
         col_coords<DX>(M, c, x, u);
-#pragma unroll
-        for (int i = 0; i < DX; ++i) colp[(size_t)n * (DX + 1) + i] = (R)u[i];
         const double beta =
             (bmax > -INFINITY) ? (ell[n] + gq[n] - bmax) * kLog2e : -INFINITY;
-        colp[(size_t)n * (DX + 1) + DX] = (R)beta;
+        put_col<R, DX>(nb, (size_t)P, Npad, n, u, beta);
       } else {
-#pragma unroll
-        for (int i = 0; i < DX; ++i) colp[(size_t)n * (DX + 1) + i] = (R)0;
-        colp[(size_t)n * (DX + 1) + DX] = (R)(-INFINITY);
+        put_col_pad<R, DX>(nb, (size_t)P, Npad, n);
       }
     }
     if (threadIdx.x == 0) nb.bcol[P] = bmax;
   } else {  // left block of combine P (c == t + 1)
-    R* rowp = (R*)nb.row + (size_t)P * Npad * DX;
     for (int n = threadIdx.x; n < N; n += kBlock) {
       double x[DX], v[DX];
       load_particle<R, DX>(leafX, totalK, N, g, n, dx, x);
       row_coords<DX>(M, c, x, v);
-#pragma unroll
-      for (int i = 0; i < DX; ++i) rowp[(size_t)n * DX + i] = (R)v[i];
+      put_row<R, DX>(nb, (size_t)P, Npad, n, v);
       ((R*)nb.alpha)[(size_t)P * N + n] = (R)ell[n];
     }
   }
@@ -219,6 +304,7 @@ template <typename R, int DX, int RPL>
 __global__ __launch_bounds__(kBlock) void k_rows(const R* __restrict__ col,
                                                  const R* __restrict__ row,
                                                  R* __restrict__ P, double* __restrict__ Rsum,
+                                                 float* __restrict__ Rshift,
                                                  const int32_t* __restrict__ node_list,
                                                  int node0, int N, int Npad, int Nc, int NcP,
                                                  int RB, int CS, int KC) {
@@ -241,6 +327,27 @@ __global__ __launch_bounds__(kBlock) void k_rows(const R* __restrict__ col,
 #pragma unroll
     for (int i = 0; i < DX; ++i) v[r][i] = row[(nodeid * Npad + mrow[r]) * DX + i];
   }
+  // Row shift (DX >= 8): the row's largest log2 weight over its first chunk,
+  // so that row sums stay inside the fp32 range when every pair weight is far
+  // below the column bound.  Every column split computes the same value.
+  R sft[RPL];
+#pragma unroll
+  for (int r = 0; r < RPL; ++r) sft[r] = (R)0;
+  if constexpr (kRowShift<DX>) {
+#pragma unroll
+    for (int r = 0; r < RPL; ++r) {
+      R mx = (R)(-INFINITY);
+      for (int jj = 0; jj < kChunk; ++jj) {
+        R u[DX];
+#pragma unroll
+        for (int i = 0; i < DX; ++i) u[i] = colp[jj * (DX + 1) + i];
+        mx = fmax(mx, pair_log2w<R, DX>(u, colp[jj * (DX + 1) + DX], v[r]));
+      }
+      // held at fp32 precision: the sampling kernel reads it back as fp32
+      sft[r] = (mx > (R)(-INFINITY) && mx < (R)INFINITY) ? (R)(float)mx : (R)0;
+      if (cs == 0) Rshift[(size_t)node_local * N + mrow[r]] = (float)sft[r];
+    }
+  }
   double Rm[RPL];
 #pragma unroll
   for (int r = 0; r < RPL; ++r) Rm[r] = 0.0;
@@ -261,8 +368,12 @@ __global__ __launch_bounds__(kBlock) void k_rows(const R* __restrict__ col,
           for (int i = 0; i < DX; ++i) u[i] = cp[jj * (DX + 1) + i];
           const R beta = cp[jj * (DX + 1) + DX];
 #pragma unroll
-          for (int r = 0; r < RPL; ++r)
-            acc[r][q] += Real<R>::exp2(pair_log2w<R, DX>(u, beta, v[r]));
+          for (int r = 0; r < RPL; ++r) {
+            if constexpr (kRowShift<DX>)
+              acc[r][q] += Real<R>::exp2(pair_log2w<R, DX>(u, beta, v[r]) - sft[r]);
+            else
+              acc[r][q] += Real<R>::exp2(pair_log2w<R, DX>(u, beta, v[r]));
+          }
         }
 #pragma unroll
         for (int r = 0; r < RPL; ++r) Rm[r] += (double)acc[r][q];
@@ -275,6 +386,135 @@ __global__ __launch_bounds__(kBlock) void k_rows(const R* __restrict__ col,
   if (CS == 1) {
 #pragma unroll
     for (int r = 0; r < RPL; ++r) Rsum[(size_t)node_local * N + mrow[r]] = Rm[r];
+  }
+}
+
+// ============================================================ rows (bf16)
+// Matrix-core form of k_rows for bf16 plans (DX = 16 or 32).  With u, v
+// rounded to bf16, the pair's log2 weight beta_n - ||u_n - v_m||^2 equals
+// (beta_n - ||u_n||^2) - ||v_m||^2 + (2 u_n) . v_m.  A wave owns 32 MB rows;
+// for each 32-column chunk and each block of 32 rows, DX / 16
+// v_mfma_f32_32x32x16_bf16 add the 32 x 32 dot products (u on the
+// instruction's row side, v on its column side) onto accumulators that start
+// at the two fp32 norm terms, so each accumulator ends as the pair's log2
+// weight.  Lane (j, h) holds column j of the block (row m = block + j) for the
+// 16 chunk columns 8 (r / 4) + 4 h + r % 4, r < 16; the lanes j and j + 32
+// together hold the whole chunk.  Outputs as k_rows (chunk sums, and fp64 row
+// sums in chunk order with one column split).
+typedef __bf16 bf16x8_t __attribute__((ext_vector_type(8)));
+typedef float f32x16_t __attribute__((ext_vector_type(16)));
+
+template <int DX, int MB>
+__global__ __launch_bounds__(kBlock) void k_rows_mfma(
+    const uint16_t* __restrict__ colh, const float* __restrict__ colb,
+    const uint16_t* __restrict__ rowh, const float* __restrict__ rown, float* __restrict__ P,
+    double* __restrict__ Rsum, float* __restrict__ Rshift, const int32_t* __restrict__ node_list,
+    int node0, int N, int Npad, int Nc, int NcP, int RB, int CS, int KC) {
+  static_assert(DX == 16 || DX == 32, "bf16 rows need DX 16 or 32");
+  constexpr int KS = DX / 16;  // instructions per 32 x 32 block
+  const int W = blockDim.x >> 6;
+  const int tiles = RB * CS;
+  const int node_local = blockIdx.x / tiles;
+  const int tile = blockIdx.x - node_local * tiles;
+  const int rb = tile / CS, cs = tile - rb * CS;
+  const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
+  const int j32 = lane & 31, h = lane >> 5;
+  const int base = (rb * W + wave) * 32 * MB;
+  if (base >= N) return;  // wave-uniform
+  const size_t nodeid = node_list ? (size_t)node_list[node_local] : (size_t)node0 + node_local;
+  bf16x8_t vf[MB][KS];
+  float vv[MB];
+  int mrow[MB];
+#pragma unroll
+  for (int b = 0; b < MB; ++b) {
+    const int m = base + 32 * b + j32;
+    mrow[b] = m < N ? m : N - 1;
+    const uint16_t* rp = rowh + ((size_t)nodeid * Npad + mrow[b]) * DX + 8 * h;
+#pragma unroll
+    for (int s = 0; s < KS; ++s) vf[b][s] = *(const bf16x8_t*)(rp + 16 * s);
+    vv[b] = rown[(size_t)nodeid * Npad + mrow[b]];
+  }
+  const uint16_t* __restrict__ ch = colh + (size_t)nodeid * Npad * DX;
+  const float* __restrict__ cb = colb + (size_t)nodeid * Npad;
+  // Row shift: the row's largest log2 weight over chunk 0 (as k_rows), folded
+  // into the row norm term so the main loop pays nothing for it.
+  {
+    bf16x8_t uf[KS];
+    const uint16_t* up = ch + (size_t)j32 * DX + 8 * h;
+#pragma unroll
+    for (int s = 0; s < KS; ++s) uf[s] = *(const bf16x8_t*)(up + 16 * s);
+    float bp[16];
+#pragma unroll
+    for (int g4 = 0; g4 < 4; ++g4) {
+      const float4 t4 = *(const float4*)(cb + 8 * g4 + 4 * h);
+      bp[4 * g4] = t4.x; bp[4 * g4 + 1] = t4.y; bp[4 * g4 + 2] = t4.z; bp[4 * g4 + 3] = t4.w;
+    }
+#pragma unroll
+    for (int b = 0; b < MB; ++b) {
+      f32x16_t acc;
+#pragma unroll
+      for (int r = 0; r < 16; ++r) acc[r] = bp[r] - vv[b];
+#pragma unroll
+      for (int s = 0; s < KS; ++s)
+        acc = __builtin_amdgcn_mfma_f32_32x32x16_bf16(uf[s], vf[b][s], acc, 0, 0, 0);
+      float mx = acc[0];
+#pragma unroll
+      for (int r = 1; r < 16; ++r) mx = fmaxf(mx, acc[r]);
+      mx = fmaxf(mx, __shfl_xor(mx, 32, 64));
+      const float sft = (mx > -INFINITY && mx < INFINITY) ? mx : 0.0f;
+      if (cs == 0 && h == 0) Rshift[(size_t)node_local * N + mrow[b]] = sft;
+      vv[b] += sft;
+    }
+  }
+  double Rm[MB];
+#pragma unroll
+  for (int b = 0; b < MB; ++b) Rm[b] = 0.0;
+  float* __restrict__ Pn = P + (size_t)node_local * N * NcP;
+  const int k0 = cs * KC, k1 = min(Nc, k0 + KC);
+  for (int kg = k0; kg < k1; kg += 4) {
+    float c4[MB][4];
+#pragma unroll
+    for (int q = 0; q < 4; ++q) {
+#pragma unroll
+      for (int b = 0; b < MB; ++b) c4[b][q] = 0.0f;
+      if (kg + q < k1) {  // uniform
+        const int n0 = (kg + q) * kChunk;
+        bf16x8_t uf[KS];
+        const uint16_t* up = ch + (size_t)(n0 + j32) * DX + 8 * h;
+#pragma unroll
+        for (int s = 0; s < KS; ++s) uf[s] = *(const bf16x8_t*)(up + 16 * s);
+        float bp[16];
+#pragma unroll
+        for (int g4 = 0; g4 < 4; ++g4) {
+          const float4 t4 = *(const float4*)(cb + n0 + 8 * g4 + 4 * h);
+          bp[4 * g4] = t4.x; bp[4 * g4 + 1] = t4.y; bp[4 * g4 + 2] = t4.z; bp[4 * g4 + 3] = t4.w;
+        }
+#pragma unroll
+        for (int b = 0; b < MB; ++b) {
+          f32x16_t acc;
+#pragma unroll
+          for (int r = 0; r < 16; ++r) acc[r] = bp[r] - vv[b];
+#pragma unroll
+          for (int s = 0; s < KS; ++s)
+            acc = __builtin_amdgcn_mfma_f32_32x32x16_bf16(uf[s], vf[b][s], acc, 0, 0, 0);
+          float e = 0.0f;
+#pragma unroll
+          for (int r = 0; r < 16; ++r) e += Real<float>::exp2(acc[r]);
+          e += __shfl_xor(e, 32, 64);
+          c4[b][q] = e;
+          Rm[b] += (double)e;
+        }
+      }
+    }
+    if (h == 0) {
+#pragma unroll
+      for (int b = 0; b < MB; ++b)
+        store4<float>(Pn + (size_t)mrow[b] * NcP + kg, c4[b][0], c4[b][1], c4[b][2], c4[b][3]);
+    }
+  }
+  if (CS == 1 && h == 0) {
+#pragma unroll
+    for (int b = 0; b < MB; ++b) Rsum[(size_t)node_local * N + mrow[b]] = Rm[b];
   }
 }
 
@@ -308,7 +548,7 @@ __global__ __launch_bounds__(kBlock) void k_sample(
     const int32_t* __restrict__ node_list, int node0, int DS,
     int totalK, int N, int Npad, int Nc, int NcP, int rows_summed, int col_in_lds,
     const R* __restrict__ leafX, const double* __restrict__ bmerged, const R* __restrict__ P,
-    const double* __restrict__ Rsum, NodeBufs nb) {
+    const double* __restrict__ Rsum, const float* __restrict__ Rshift, NodeBufs nb) {
   extern __shared__ double smem[];
   double* cdf = smem;                        // [Npad]
   double* rs = smem + Npad;                  // [Npad]
@@ -337,9 +577,13 @@ __global__ __launch_bounds__(kBlock) void k_sample(
 
   // ---- row sums (thread owns a contiguous segment of rows)
   __shared__ unsigned need[DSMC_MAX_N / 32];  // rows still to rescue
+  __shared__ unsigned resc[DSMC_MAX_N / 32];  // rescued rows (their chunk sums are not used)
   __shared__ int rescue_list[kBlock];
   __shared__ int n_rescue;
-  for (int i = threadIdx.x; i < DSMC_MAX_N / 32; i += kBlock) need[i] = 0u;
+  for (int i = threadIdx.x; i < DSMC_MAX_N / 32; i += kBlock) {
+    need[i] = 0u;
+    resc[i] = 0u;
+  }
   __syncthreads();
   const int per = (N + kBlock - 1) / kBlock;
   const int m0 = threadIdx.x * per, m1 = min(N, m0 + per);
@@ -361,13 +605,15 @@ __global__ __launch_bounds__(kBlock) void k_sample(
           if (kb + i < Nc) Rm += (double)q[i];
       }
     }
-    if (!(Rm >= Real<R>::kTiny) && !isnan(Rm)) {
+    if ((!(Rm >= Real<R>::kTiny) || isinf(Rm)) && !isnan(Rm)) {
       atomicOr(&need[m >> 5], 1u << (m & 31));
+      atomicOr(&resc[m >> 5], 1u << (m & 31));
       rescued = 1;
     }
     if (isnan(Rm)) row_nan = 1;
     rs[m] = Rm;
-    shift[m] = 0.0f;
+    if constexpr (kRowShift<DX>) shift[m] = Rshift[(size_t)node_local * N + m];
+    else shift[m] = 0.0f;
   }
   rescued = block_or_i(rescued, redi);  // also orders the writes above
   // Underflow rescue, one row at a time by the whole workgroup: exact row
@@ -405,7 +651,7 @@ __global__ __launch_bounds__(kBlock) void k_sample(
         smax = fmax(smax, (double)pair_log2w<R, DX>(u, colp[(size_t)j * (DX + 1) + DX], v));
       }
       smax = block_max(smax, red);
-      const R sh = (R)smax;
+      const R sh = (R)(float)smax;  // the shift is kept as fp32
       double part = 0.0;
       if (smax > -INFINITY)
         for (int j = threadIdx.x; j < N; j += kBlock) {
@@ -417,7 +663,7 @@ __global__ __launch_bounds__(kBlock) void k_sample(
       const double tot = block_sum(part, red);
       if (threadIdx.x == 0) {
         rs[m] = (smax > -INFINITY) ? tot : 0.0;
-        shift[m] = (smax > -INFINITY) ? (float)sh : 0.0f;  // < 0 since the row sum was tiny
+        shift[m] = (smax > -INFINITY) ? (float)sh : 0.0f;
       }
     }
     __syncthreads();
@@ -426,7 +672,7 @@ __global__ __launch_bounds__(kBlock) void k_sample(
   const double Astar = block_max(amax, red);
   // ---- row weights: direct, or in log space when a row carries a shift
   double G = 0.0;
-  if (rescued) {
+  if (rescued || kRowShift<DX>) {
     double gmax = -INFINITY;
     for (int m = m0; m < m1; ++m) {
       const double a = left_leaf ? (double)alp[m] : -logN;
@@ -493,12 +739,7 @@ __global__ __launch_bounds__(kBlock) void k_sample(
   const int ca = nd.a, cb = nd.b;
   const int gA = sd.base + ca, gB = sd.base + cb - 1;
   if (cons >= 0 && crole == 1 && ds == 0) {
-    R* ccol = (R*)nb.col + (size_t)cons * Npad * (DX + 1);
-    for (int n = N + threadIdx.x; n < Npad; n += kBlock) {
-#pragma unroll
-      for (int i = 0; i < DX; ++i) ccol[(size_t)n * (DX + 1) + i] = (R)0;
-      ccol[(size_t)n * (DX + 1) + DX] = (R)(-INFINITY);
-    }
+    for (int n = N + threadIdx.x; n < Npad; n += kBlock) put_col_pad<R, DX>(nb, (size_t)cons, Npad, n);
     if (threadIdx.x == 0) nb.bcol[cons] = bmerged[gA];
   }
   // ---- draws
@@ -527,7 +768,7 @@ __global__ __launch_bounds__(kBlock) void k_sample(
       const double target2 = u2 * rs[l];
       const float sh = shift[l];
       r = -1;
-      if (sh != 0.0f) {
+      if ((resc[l >> 5] >> (l & 31)) & 1u) {
         // rescued row: full scan with the row shift
         double acc = 0.0;
         int lastj = 0;
@@ -582,7 +823,7 @@ __global__ __launch_bounds__(kBlock) void k_sample(
           R u[DX];
 #pragma unroll
           for (int i = 0; i < DX; ++i) u[i] = cp[jj * (DX + 1) + i];
-          const R e = Real<R>::exp2(pair_log2w<R, DX>(u, cp[jj * (DX + 1) + DX], v));
+          const R e = Real<R>::exp2(pair_log2w<R, DX>(u, cp[jj * (DX + 1) + DX], v) - (R)sh);
           acc += e;
           if (e > (R)0) lastj = jj;
           if (r < 0 && rem < (double)acc) r = jj;
@@ -606,17 +847,12 @@ __global__ __launch_bounds__(kBlock) void k_sample(
         col_coords<DX>(M, ca, x, u);
         double b = -logN - log_proposal<DX>(M, ca, x);
         if (M.weighting == 1) b += log_potential<DX>(M, ca, x);
-        R* ccol = (R*)nb.col + (size_t)cons * Npad * (DX + 1);
-#pragma unroll
-        for (int i = 0; i < DX; ++i) ccol[(size_t)n * (DX + 1) + i] = (R)u[i];
-        ccol[(size_t)n * (DX + 1) + DX] = (R)((b - bmerged[gA]) * kLog2e);
+        put_col<R, DX>(nb, (size_t)cons, Npad, n, u, (b - bmerged[gA]) * kLog2e);
       } else {  // merged block is the left block of `cons` (boundary cb)
         double x[DX], v2[DX];
         load_particle<R, DX>(leafX, totalK, N, gB, sl, dx, x);
         row_coords<DX>(M, cb, x, v2);
-        R* crow = (R*)nb.row + (size_t)cons * Npad * DX;
-#pragma unroll
-        for (int i = 0; i < DX; ++i) crow[(size_t)n * DX + i] = (R)v2[i];
+        put_row<R, DX>(nb, (size_t)cons, Npad, n, v2);
         ((R*)nb.alpha)[(size_t)cons * N + n] = (R)(-logN);
       }
     }
@@ -686,24 +922,42 @@ __global__ void k_clear_status(const SeriesDesc* __restrict__ series, int s0, in
 }
 
 // ============================================================ launchers
+template <int DX, int MB>
+static void launch_rows_mfma(const LevelLaunch& L, hipStream_t st, unsigned grid, unsigned block) {
+  k_rows_mfma<DX, MB><<<grid, block, 0, st>>>(L.nb.colh, L.nb.colb, L.nb.rowh, L.nb.rown,
+                                              (float*)L.P, L.Rsum, L.Rshift, L.node_list, L.node0,
+                                              L.N, L.Npad, L.Nc, L.NcP, L.RB, L.CS, L.KC);
+}
+
 template <typename R, int DX>
 static int launch_rows_t(const LevelLaunch& L, hipStream_t st) {
   const unsigned grid = (unsigned)L.nodes * L.RB * L.CS;
   const unsigned block = 64u * L.W;
+  if constexpr (sizeof(R) == 4 && DX >= 16) {
+    if (L.bf16) {  // 64 RPL rows per wave, as the fp32 kernel
+      switch (L.RPL) {
+        case 1: launch_rows_mfma<DX, 2>(L, st, grid, block); return 0;
+        case 2: launch_rows_mfma<DX, 4>(L, st, grid, block); return 0;
+        case 4: launch_rows_mfma<DX, 8>(L, st, grid, block); return 0;
+      }
+      return -1;
+    }
+  }
+  if (L.bf16) return -1;
   switch (L.RPL) {
     case 1:
       k_rows<R, DX, 1><<<grid, block, 0, st>>>((const R*)L.nb.col, (const R*)L.nb.row, (R*)L.P,
-                                               L.Rsum, L.node_list, L.node0, L.N, L.Npad, L.Nc,
+                                               L.Rsum, L.Rshift, L.node_list, L.node0, L.N, L.Npad, L.Nc,
                                                L.NcP, L.RB, L.CS, L.KC);
       return 0;
     case 2:
       k_rows<R, DX, 2><<<grid, block, 0, st>>>((const R*)L.nb.col, (const R*)L.nb.row, (R*)L.P,
-                                               L.Rsum, L.node_list, L.node0, L.N, L.Npad, L.Nc,
+                                               L.Rsum, L.Rshift, L.node_list, L.node0, L.N, L.Npad, L.Nc,
                                                L.NcP, L.RB, L.CS, L.KC);
       return 0;
     case 4:
       k_rows<R, DX, 4><<<grid, block, 0, st>>>((const R*)L.nb.col, (const R*)L.nb.row, (R*)L.P,
-                                               L.Rsum, L.node_list, L.node0, L.N, L.Npad, L.Nc,
+                                               L.Rsum, L.Rshift, L.node_list, L.node0, L.N, L.Npad, L.Nc,
                                                L.NcP, L.RB, L.CS, L.KC);
       return 0;
   }
@@ -723,7 +977,7 @@ static int launch_level_t(const LevelLaunch& L, hipStream_t st, Timer* tm) {
   k_sample<R, DX><<<(unsigned)L.nodes * L.DS, kBlock, lds_samp, st>>>(
       L.d_nodes, L.d_series, L.node_list, L.node0, L.DS, L.totalK, L.N, L.Npad, L.Nc, L.NcP,
       L.CS == 1 ? 1 : 0,
-      col_in_lds, (const R*)L.leafX, L.bmerged, (const R*)L.P, L.Rsum, L.nb);
+      col_in_lds, (const R*)L.leafX, L.bmerged, (const R*)L.P, L.Rsum, L.Rshift, L.nb);
   tm->end(2, st);
   return 0;
 }

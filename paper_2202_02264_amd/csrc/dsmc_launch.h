@@ -52,6 +52,7 @@ struct Timer {
 
 struct LevelLaunch {
   bool fp64;
+  bool bf16;            // pair rows on bf16 matrix cores (DX 16 or 32, fp32 otherwise)
   int DX;
   const int32_t* node_list;  // device list of combine ids, or null: ids node0 .. node0+nodes-1
   int node0;            // id of the first combine of this launch (without a list)
@@ -67,6 +68,7 @@ struct LevelLaunch {
   const double* bmerged;
   void* P;
   double* Rsum;
+  float* Rshift;        // per-row shifts of the row sums (DX >= 8), like Rsum
   NodeBufs nb;
 };
 

@@ -110,6 +110,7 @@ struct Class {
   NodeBufs nb{};
   void* P = nullptr;
   double* Rsum = nullptr;
+  float* Rshift = nullptr;
   NodeDesc* d_nodes = nullptr;
   int32_t* d_series_of_t = nullptr;
   int32_t* d_leaf_cons = nullptr;
@@ -194,6 +195,7 @@ int make_class(dsmc_server_impl* s, int N, int DX, std::unique_ptr<Class>* out) 
       (rc = dalloc(c.get(), &c->nb.slast, TK * N * sizeof(int32_t))) ||
       (rc = dalloc(c.get(), &c->P, nc * N * c->NcP * R)) ||
       (rc = dalloc(c.get(), &c->Rsum, nc * N * sizeof(double))) ||
+      (rc = dalloc(c.get(), &c->Rshift, nc * N * sizeof(float))) ||
       (rc = dalloc(c.get(), &c->d_nodes, TK * sizeof(NodeDesc))) ||
       (rc = dalloc(c.get(), &c->d_series_of_t, TK * sizeof(int32_t))) ||
       (rc = dalloc(c.get(), &c->d_leaf_cons, TK * sizeof(int32_t))) ||
@@ -352,6 +354,7 @@ int tick(dsmc_server_impl* s, Class* c) {
     L.bmerged = c->bmerged;
     L.P = c->P;
     L.Rsum = c->Rsum;
+    L.Rshift = c->Rshift;
     L.nb = c->nb;
     set_tile(L, heuristic_tile(nodes, N, c->Nc));
     const int ds_max = std::max(1, (N + 127) / 128);

@@ -23,7 +23,7 @@ DSMC_EAGAIN, DSMC_EDEGENERATE, DSMC_ENUMERIC, DSMC_EDEVICE, DSMC_ECANCELLED = -4
 DSMC_FLAG_DEGENERATE, DSMC_FLAG_NUMERIC = 1, 2
 DSMC_OBS_LINEAR_GAUSSIAN, DSMC_OBS_STOCH_VOL = 0, 1
 DSMC_WEIGHT_LEAF_OBS, DSMC_WEIGHT_BOUNDARY_OBS = 0, 1
-DSMC_FP32, DSMC_FP64 = 0, 1
+DSMC_FP32, DSMC_FP64, DSMC_BF16 = 0, 1, 2
 DSMC_PLAN_PROFILE = 1
 DSMC_PLAN_AUTOTUNE = 2
 DSMC_MAX_DX, DSMC_MAX_N = 32, 4096

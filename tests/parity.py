@@ -7,6 +7,7 @@ row for the right index).  Index parity is bit-exact outside that band.
 """
 from __future__ import annotations
 
+import os
 import sys
 import time
 from dataclasses import dataclass, field
@@ -22,15 +23,21 @@ TOL64 = 1e-10
 
 
 def log(msg: str) -> None:
-    print(f"[{time.strftime('%H:%M:%S')}] {msg}", flush=True)
+    """Print a progress / result line; also append it to $DSMC_PARITY_LOG if set."""
+    line = f"[{time.strftime('%H:%M:%S')}] {msg}"
+    print(line, flush=True)
     sys.stdout.flush()
+    path = os.environ.get("DSMC_PARITY_LOG")
+    if path:
+        with open(path, "a") as f:
+            f.write(line + "\n")
 
 
 def run_gpu(spec, N: int, seed: int, precision: str = "fp32", plan=None, model=None):
     """dsmc_smooth with every diagnostic output; returns numpy arrays."""
     import torch
     from paper_2202_02264_amd import dsmc as G
-    prec = G.DSMC_FP64 if precision == "fp64" else G.DSMC_FP32
+    prec = {"fp64": G.DSMC_FP64, "fp32": G.DSMC_FP32, "bf16": G.DSMC_BF16}[precision]
     log(f"gpu dsmc_smooth {spec.name} weighting={spec.weighting} N={N} seed={seed} {precision}")
     model = model or G.Model(spec)
     plan = plan or G.Plan(N, spec.d_x, spec.K, precision=prec)
@@ -67,6 +74,8 @@ class ParityReport:
     max_rel_err_Z: float = 0.0
     max_rel_err_row: float = 0.0
     worst: list = field(default_factory=list)
+    abs_err_Z: list = field(default_factory=list)    # filled when tol is None
+    abs_err_row: list = field(default_factory=list)  # arrays, filled when tol is None
 
     def summary(self) -> str:
         f = self.near / max(1, self.draws)
@@ -101,10 +110,11 @@ def check_leaves(spec, N: int, seed: int, g: dict, tol: float) -> None:
     assert np.max(e_L) <= tol, np.max(e_L)
 
 
-def teacher_forced(spec, N: int, seed: int, g: dict, tol: float, select=None) -> ParityReport:
+def teacher_forced(spec, N: int, seed: int, g: dict, tol, select=None) -> ParityReport:
     """Replay the GPU's ancestry; at every selected node run the oracle's combine
     on the GPU's inputs of that level and compare increments, row log-sums and
-    indices.  Also checks the gather: final index and trajectories."""
+    indices.  Also checks the gather: final index and trajectories.  With
+    tol=None the absolute errors are collected instead of asserted."""
     K, dx = spec.K, spec.d_x
     rep = ParityReport()
     leaf_x = g["leaf_x"].astype(np.float64)            # (dx, K, N)
@@ -124,12 +134,17 @@ def teacher_forced(spec, N: int, seed: int, g: dict, tol: float, select=None) ->
                 rep.nodes += 1
                 ez = float(_rel(g["logZ_inc"][c - 1], res.Z))
                 rep.max_rel_err_Z = max(rep.max_rel_err_Z, ez)
-                assert ez <= tol, (c, g["logZ_inc"][c - 1], res.Z)
                 fin = np.isfinite(res.row_lse)
                 er = _rel(g["row_lse"][c - 1][fin], res.row_lse[fin])
+                if tol is None:
+                    rep.abs_err_Z.append(abs(float(g["logZ_inc"][c - 1]) - float(res.Z)))
+                    rep.abs_err_row.append(np.abs(g["row_lse"][c - 1][fin] - res.row_lse[fin]))
+                else:
+                    assert ez <= tol, (c, g["logZ_inc"][c - 1], res.Z)
                 if er.size:
                     rep.max_rel_err_row = max(rep.max_rel_err_row, float(er.max()))
-                    assert er.max() <= tol, (c, int(np.argmax(er)), er.max())
+                    if tol is not None:
+                        assert er.max() <= tol, (c, int(np.argmax(er)), er.max())
                 if res.degenerate:
                     continue
                 row_w = np.exp(res.row_lse - res.row_lse.max())

@@ -93,6 +93,9 @@ def test_invalid_arguments_rejected_on_host():
     assert lib.dsmc_plan(C.byref(p), C.byref(hp)) == dsmc.DSMC_EUNSUPPORTED
     p.N, p.precision = 64, 9
     assert lib.dsmc_plan(C.byref(p), C.byref(hp)) == dsmc.DSMC_EUNSUPPORTED
+    p.precision, p.d_x = dsmc.DSMC_BF16, 8  # bf16 matrix-core rows need d_x >= 9
+    assert lib.dsmc_plan(C.byref(p), C.byref(hp)) == dsmc.DSMC_EUNSUPPORTED
+    p.precision, p.d_x = dsmc.DSMC_FP32, 1
     assert lib.dsmc_smooth(None, None, 0, None) == dsmc.DSMC_EINVAL
     # serving entry points
     sd = dsmc.dsmc_server_desc()

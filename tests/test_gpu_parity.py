@@ -36,6 +36,9 @@ CASES = {
     "sv_n1": (lambda: W.sv(17, seed=16), 1),
     "sv_n4096": (lambda: W.sv(5, seed=17), 4096),
     "sv_k2": (lambda: W.sv(2, seed=18), 512),
+    # d_x >= 8: row sums relative to per-row shifts
+    "lg8d": (lambda: _lg_dx(8, 24), 160),
+    "lg32d_fp32": (lambda: W.lg_highdim(K=20, seed=19), 256),
 }
 
 
