@@ -104,8 +104,9 @@ def cpu_baseline(spec, N: int, budget_s: float) -> dict:
 def bench_batch(args):
     """B independent 1-D linear-Gaussian series (A ~ U[0.5, 0.99], Q, R ~ U[0.1, 2],
     K ~ U{64..8192}), N = 256: dsmc_smooth_batch (every level of every series
-    in shared launches) against dsmc_smooth called once per series (one set of
-    launches per level per series).  Results are bit-identical between the two."""
+    in shared launches, replayed as one hipGraph) against dsmc_smooth called
+    once per series (one set of launches per level per series).  Results are
+    bit-identical between the two."""
     import torch
 
     from paper_2202_02264_amd import dsmc as G
@@ -114,21 +115,30 @@ def bench_batch(args):
     specs = W.lg1d_batch(args.B)
     Ks = [s.K for s in specs]
     models = [G.Model(s) for s in specs]
-    plan = G.Plan(N, 1, max(Ks), max_total_K=sum(Ks), profile=not args.no_kernel_events)
+    # timed: one hipGraph replay per batch (warm-up: eager + tile tuning, then capture)
+    plan = G.Plan(N, 1, max(Ks), max_total_K=sum(Ks), graph=True)
     outs = [G.alloc_output(plan, K) for K in Ks]
     seeds = list(range(1, args.B + 1))
-    for _ in range(max(1, args.warmup)):
+    for _ in range(max(2, args.warmup)):
         G.dsmc_smooth_batch(plan, models, seeds, outs)
     torch.cuda.synchronize()
-    if not args.no_kernel_events:
-        G.dsmc_plan_profile(plan)
     steps = max(1, min(args.steps, 5))
     t0 = time.perf_counter()
     for _ in range(steps):
         G.dsmc_smooth_batch(plan, models, seeds, outs)
     torch.cuda.synchronize()
     dt_b = (time.perf_counter() - t0) / steps
-    prof = G.dsmc_plan_profile(plan) if not args.no_kernel_events else None
+    prof = None
+    if not args.no_kernel_events:  # kernel durations: the same batch eagerly with HIP events
+        plan_p = G.Plan(N, 1, max(Ks), max_total_K=sum(Ks), profile=True)
+        G.dsmc_smooth_batch(plan_p, models, seeds, outs)
+        torch.cuda.synchronize()
+        G.dsmc_plan_profile(plan_p)
+        for _ in range(steps):
+            G.dsmc_smooth_batch(plan_p, models, seeds, outs)
+        torch.cuda.synchronize()
+        prof = G.dsmc_plan_profile(plan_p)
+        del plan_p
     # plain: one series at a time
     plan1 = G.Plan(N, 1, max(Ks))
     out1 = G.alloc_output(plan1, max(Ks))
@@ -372,14 +382,12 @@ def main():
     K, N = args.K, args.N
     spec = W.sv(K)
     model = G.Model(spec)
-    plan = G.Plan(N, 1, K, profile=not args.no_kernel_events)
+    # timed steps: the plan replays one hipGraph per step (first warm-up call
+    # runs eagerly and tunes the tiles, the second captures)
+    plan = G.Plan(N, 1, K, graph=True)
     out = G.alloc_output(plan, K)
-    for s in range(args.warmup):
+    for s in range(max(2, args.warmup)):
         G.dsmc_smooth(plan, model, 1000 + s, out)
-    torch.cuda.synchronize()
-    if not args.no_kernel_events:
-        G.dsmc_plan_profile(plan)  # drop the warm-up records
-    st = torch.cuda.current_stream()
     torch.cuda.synchronize()
     t0 = time.perf_counter()
     for s in range(args.steps):
@@ -389,6 +397,20 @@ def main():
     status = int(out.status.item())
     if status:
         raise RuntimeError(f"device status {status}")
+    prof = None
+    if not args.no_kernel_events:
+        # the same steps once more, eagerly, with HIP events around every launch
+        plan_p = G.Plan(N, 1, K, profile=True)
+        for s in range(max(1, args.warmup)):
+            G.dsmc_smooth(plan_p, model, 1000 + s, out)
+        torch.cuda.synchronize()
+        G.dsmc_plan_profile(plan_p)  # drop the warm-up records
+        t1 = time.perf_counter()
+        for s in range(args.steps):
+            G.dsmc_smooth(plan_p, model, s + 1, out)
+        torch.cuda.synchronize()
+        dt_ev = (time.perf_counter() - t1) / args.steps
+        prof = G.dsmc_plan_profile(plan_p)
     pairs = (K - 1) * N * N
     res = {
         "metric": "pair-evals/sec",
@@ -410,8 +432,8 @@ def main():
         "smoothers_per_sec": 1.0 / dt,
         "pair_evals_T_log2T_N2_per_sec": K * math.log2(K) * N * N / dt,
     }
-    if not args.no_kernel_events:
-        prof = G.dsmc_plan_profile(plan)
+    if prof is not None:
+        res["ms_per_step_with_kernel_events"] = dt_ev * 1e3
         n_rows = prof["launches"]["rows"]
         ms_rows = prof["ms"]["rows"]
         achieved = prof["pairs"] / (ms_rows * 1e-3)

@@ -140,6 +140,13 @@ enum { DSMC_FP32 = 0, /* particles and pair weights in fp32, sums and CDFs in fp
 #define DSMC_PLAN_PROFILE 1  /* record HIP events around every kernel launch */
 #define DSMC_PLAN_AUTOTUNE 2 /* time the pair-row kernel's tile shapes on first use of each
                                 level size and keep the fastest (results do not depend on it) */
+#define DSMC_PLAN_GRAPH 4    /* capture the kernels of dsmc_smooth / dsmc_smooth_batch for one
+                                batch shape (the list of K) in a hipGraph and replay it while
+                                the shape repeats: the first call of a shape runs eagerly, the
+                                second captures, later ones replay (ignored with
+                                DSMC_PLAN_PROFILE).  Models, seeds and outputs may change
+                                between calls; they are read from device memory the call
+                                uploads before the graph runs. */
 
 typedef struct dsmc_plan_desc {
   int N;           /* particles per time point, 1..DSMC_MAX_N */

@@ -241,6 +241,13 @@ struct dsmc_plan_impl {
   // schedule of the last call and the K list it was built for
   std::vector<int> sched_K;
   std::vector<int> roots;
+  // hipGraph of one batch shape (DSMC_PLAN_GRAPH)
+  bool use_graph = false;
+  hipStream_t cap_stream = nullptr;
+  hipGraph_t graph = nullptr;
+  hipGraphExec_t gexec = nullptr;
+  std::vector<int> graph_K;
+  const SeriesDesc* graph_series = nullptr;
   std::vector<int> level_off, level_cnt;
   int total_nodes = 0;
   // rows-kernel tile per launch size (autotuned or heuristic)
@@ -259,6 +266,9 @@ static void plan_free(dsmc_plan_t* p) {
   void* host[] = {p->h_nodes, p->h_series_of_t, p->h_leaf_cons, p->h_series};
   for (void* q : host) (void)hipHostFree(q);
   if (p->staged) (void)hipEventDestroy(p->staged);
+  if (p->gexec) (void)hipGraphExecDestroy(p->gexec);
+  if (p->graph) (void)hipGraphDestroy(p->graph);
+  if (p->cap_stream) (void)hipStreamDestroy(p->cap_stream);
 }
 
 int dsmc::padded_dx(int dx) {
@@ -287,6 +297,7 @@ extern "C" int dsmc_plan(const dsmc_plan_desc* d, dsmc_plan_t** out) {
   p->stream = (hipStream_t)d->stream;
   p->timer.on = (d->flags & DSMC_PLAN_PROFILE) != 0;
   p->autotune = (d->flags & DSMC_PLAN_AUTOTUNE) != 0;
+  p->use_graph = (d->flags & DSMC_PLAN_GRAPH) != 0;
   const int N = d->N;
   p->Npad = (N + kChunk - 1) / kChunk * kChunk;
   p->Nc = p->Npad / kChunk;
@@ -342,7 +353,8 @@ extern "C" int dsmc_plan(const dsmc_plan_desc* d, dsmc_plan_t** out) {
   if (hipHostMalloc((void**)&p->h_nodes, TK * sizeof(NodeDesc), hipHostMallocDefault) != hipSuccess ||
       hipHostMalloc((void**)&p->h_series_of_t, TK * sizeof(int32_t), hipHostMallocDefault) != hipSuccess ||
       hipHostMalloc((void**)&p->h_leaf_cons, TK * sizeof(int32_t), hipHostMallocDefault) != hipSuccess ||
-      hipEventCreateWithFlags(&p->staged, hipEventDisableTiming) != hipSuccess) {
+      hipEventCreateWithFlags(&p->staged, hipEventDisableTiming) != hipSuccess ||
+      (p->use_graph && hipStreamCreateWithFlags(&p->cap_stream, hipStreamNonBlocking) != hipSuccess)) {
     plan_free(p);
     delete p;
     return fail(DSMC_ENOMEM, "host staging allocation failed");
@@ -595,6 +607,9 @@ PoolSizes dsmc::pool_sizes(int N, int DX, int dx_alloc, size_t rsz) {
   return ps;
 }
 
+static bool tiles_known(const dsmc_plan_t* p);
+static int enqueue_batch(dsmc_plan_t* p, int B, int totalK, hipStream_t st);
+
 extern "C" int dsmc_smooth_batch(dsmc_plan_t* p, int B, const dsmc_model_t* const* models,
                                  const uint64_t* seeds, const dsmc_output* outs) {
   if (!p || B < 1 || !models || !seeds || !outs) return fail(DSMC_EINVAL, "bad argument");
@@ -663,6 +678,49 @@ extern "C" int dsmc_smooth_batch(dsmc_plan_t* p, int B, const dsmc_model_t* cons
   HIP_TRY(hipEventRecord(p->staged, st));
   p->staged_pending = true;
 
+  if (p->use_graph && !p->timer.on) {
+    if (p->gexec && Ks == p->graph_K && p->graph_series == p->d_series) {
+      HIP_TRY(hipGraphLaunch(p->gexec, st));
+      return DSMC_OK;
+    }
+    if (tiles_known(p)) {  // capture; the first call of a shape ran eagerly and tuned the tiles
+      if (p->gexec) (void)hipGraphExecDestroy(p->gexec);
+      if (p->graph) (void)hipGraphDestroy(p->graph);
+      p->gexec = nullptr;
+      p->graph = nullptr;
+      p->graph_K.clear();
+      HIP_TRY(hipStreamBeginCapture(p->cap_stream, hipStreamCaptureModeThreadLocal));
+      const int erc = enqueue_batch(p, B, totalK, p->cap_stream);
+      hipGraph_t g = nullptr;
+      const hipError_t e = hipStreamEndCapture(p->cap_stream, &g);
+      if (erc) {
+        if (g) (void)hipGraphDestroy(g);
+        return erc;
+      }
+      if (e != hipSuccess) return fail(DSMC_EDEVICE, "hipStreamEndCapture: %s", hipGetErrorString(e));
+      p->graph = g;
+      HIP_TRY(hipGraphInstantiate(&p->gexec, g, nullptr, nullptr, 0));
+      p->graph_K = Ks;
+      p->graph_series = p->d_series;
+      HIP_TRY(hipGraphLaunch(p->gexec, st));
+      return DSMC_OK;
+    }
+  }
+  return enqueue_batch(p, B, totalK, st);
+}
+
+// True when every launch slice size of the current schedule has a tile.
+static bool tiles_known(const dsmc_plan_t* p) {
+  for (size_t l = 0; l < p->level_cnt.size(); ++l)
+    for (int s0 = 0; s0 < p->level_cnt[l]; s0 += p->node_cap)
+      if (!p->tiles.count(std::min(p->node_cap, p->level_cnt[l] - s0))) return false;
+  return true;
+}
+
+// Every kernel of one dsmc_smooth_batch call, on stream st (capturable: no
+// synchronisation, no memset; tiles must be known when st is capturing).
+static int enqueue_batch(dsmc_plan_t* p, int B, int totalK, hipStream_t st) {
+  const int N = p->d.N;
   launch_clear_status(p->d_series, 0, B, st);
   LeafLaunch LL{};
   LL.fp64 = p->fp64;

@@ -26,6 +26,7 @@ DSMC_WEIGHT_LEAF_OBS, DSMC_WEIGHT_BOUNDARY_OBS = 0, 1
 DSMC_FP32, DSMC_FP64, DSMC_BF16 = 0, 1, 2
 DSMC_PLAN_PROFILE = 1
 DSMC_PLAN_AUTOTUNE = 2
+DSMC_PLAN_GRAPH = 4
 DSMC_MAX_DX, DSMC_MAX_N = 32, 4096
 DSMC_NUM_KERNEL_CLASSES = 4
 KERNEL_CLASSES = ("leaves", "rows", "sample", "output")
@@ -166,14 +167,15 @@ class Plan:
 
     def __init__(self, N: int, d_x: int, max_K: int, max_total_K: int = 0,
                  precision: int = DSMC_FP32, profile: bool = False, autotune: bool = True,
-                 stream=None):
+                 graph: bool = False, stream=None):
         import torch
         if stream is None:
             stream = torch.cuda.current_stream()
         d = dsmc_plan_desc()
         d.N, d.d_x, d.max_K, d.max_total_K = N, d_x, max_K, max_total_K
         d.precision = precision
-        d.flags = (DSMC_PLAN_PROFILE if profile else 0) | (DSMC_PLAN_AUTOTUNE if autotune else 0)
+        d.flags = ((DSMC_PLAN_PROFILE if profile else 0) | (DSMC_PLAN_AUTOTUNE if autotune else 0)
+                   | (DSMC_PLAN_GRAPH if graph else 0))
         d.stream = C.c_void_p(stream.cuda_stream)
         h = C.c_void_p()
         _check(_lib.dsmc_plan(C.byref(d), C.byref(h)), "dsmc_plan")

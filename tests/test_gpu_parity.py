@@ -169,3 +169,44 @@ def test_batch_equals_single():
         single = run_gpu(spec, N, seed, model=m)
         for k in ("traj", "log_Z", "ancestry", "logZ_inc", "row_lse", "index", "leaf_x"):
             np.testing.assert_array_equal(getattr(o, k).cpu().numpy(), single[k])
+
+
+def test_graph_replays_equal_eager():
+    """DSMC_PLAN_GRAPH: the first call of a batch shape runs eagerly, the second
+    captures a hipGraph, later calls replay it.  Every call, with new seeds and
+    ordinary GPU work in between, equals an eager plan's result bit for bit;
+    a new shape is captured afresh."""
+    import torch
+    from paper_2202_02264_amd import dsmc as G
+    N = 128
+    fields = ("traj", "log_Z", "status", "ancestry", "logZ_inc", "row_lse", "index", "leaf_x")
+    shapes = [[70, 1, 33, 128, 2], [40, 64]]
+    plan_e = G.Plan(N, 1, max_K=128, max_total_K=234)
+    plan_g = G.Plan(N, 1, max_K=128, max_total_K=234, graph=True)
+    for shape in shapes:
+        specs = [W.lg1d(K, seed=40 + K) for K in shape]
+        models = [G.Model(s) for s in specs]
+        outs_e = [G.alloc_output(plan_e, s.K, diagnostics=True) for s in specs]
+        outs_g = [G.alloc_output(plan_g, s.K, diagnostics=True) for s in specs]
+        for rep in range(4):
+            seeds = [100 * rep + i for i in range(len(specs))]
+            log(f"graph shape {shape} call {rep}")
+            G.dsmc_smooth_batch(plan_e, models, seeds, outs_e)
+            torch.cuda.synchronize()
+            junk = torch.randn(4096, device="cuda").cumsum(0)  # eager work between replays
+            G.dsmc_smooth_batch(plan_g, models, seeds, outs_g)
+            torch.cuda.synchronize()
+            del junk
+            for oe, og in zip(outs_e, outs_g):
+                for f in fields:
+                    assert torch.equal(getattr(oe, f), getattr(og, f)), (shape, rep, f)
+    # a single series through dsmc_smooth on the graph plan
+    spec = W.sv(100, seed=9)
+    m = G.Model(spec)
+    oe = G.alloc_output(plan_e, spec.K)
+    og = G.alloc_output(plan_g, spec.K)
+    for rep in range(3):
+        G.dsmc_smooth(plan_e, m, rep, oe)
+        G.dsmc_smooth(plan_g, m, rep, og)
+        torch.cuda.synchronize()
+        assert torch.equal(oe.traj, og.traj) and torch.equal(oe.log_Z, og.log_Z)
