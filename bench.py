@@ -322,6 +322,7 @@ def bench_highdim(args):
             r["rows_pairs_per_sec"] = prof["pairs"] / (prof["ms"]["rows"] * 1e-3)
             r["rows_launches"] = prof["launches"]["rows"]
             r["rows_pairs"] = prof["pairs"]
+            r["rescued_rows_per_step"] = prof["rescued_rows"] / steps
         runs[name] = r
         print(f"# highdim {name}: {dt * 1e3:.2f} ms/step", file=sys.stderr, flush=True)
         del plan, out
@@ -452,6 +453,7 @@ def main():
                            "avg_launch_ms": ms_rows / max(1, n_rows),
                            "pairs_per_launch": prof["pairs"] / max(1, n_rows)}
         res["kernel_ms_per_step"] = {k: v / args.steps for k, v in prof["ms"].items()}
+        res["rescued_rows_per_step"] = prof["rescued_rows"] / args.steps
     if args.cpu_seconds > 0:
         res["cpu_baseline"] = cpu_baseline(spec, N, args.cpu_seconds)
     print(json.dumps(res))

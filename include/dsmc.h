@@ -140,6 +140,11 @@ enum { DSMC_FP32 = 0, /* particles and pair weights in fp32, sums and CDFs in fp
 #define DSMC_PLAN_PROFILE 1  /* record HIP events around every kernel launch */
 #define DSMC_PLAN_AUTOTUNE 2 /* time the pair-row kernel's tile shapes on first use of each
                                 level size and keep the fastest (results do not depend on it) */
+#define DSMC_PLAN_RESCUE_ALL 8 /* testing aid: every row of every combine takes the paths that
+                                  rows leaving the fp32 range take (d_x >= 8: the pair-row
+                                  kernel redoes its rows with exact row maxima; the sampling
+                                  kernel recomputes every row's chunk sums with its exact
+                                  maximum as shift); results stay exact */
 #define DSMC_PLAN_GRAPH 4    /* capture the kernels of dsmc_smooth / dsmc_smooth_batch for one
                                 batch shape (the list of K) in a hipGraph and replay it while
                                 the shape repeats: the first call of a shape runs eagerly, the
@@ -161,10 +166,10 @@ typedef struct dsmc_plan_desc {
 typedef struct dsmc_plan_impl dsmc_plan_t;
 
 /* Allocate the plan's device workspace: about
- * max_total_K * N * ((3 d_x + 2) s + 28) bytes for particles, weights, ancestry
- * and per-combine data, plus at most 1 GiB of per-level chunk sums
- * (N * N * s / 32 per combine of a launch), s = sizeof the real type;
- * DSMC_BF16 adds max_total_K * N * (4 d_x + 8) bytes of bf16 operands.
+ * max_total_K * N * ((5 d_x + 2) s + 36) bytes for particles, weights, ancestry
+ * and per-combine data, plus at most 2 GiB of per-level chunk sums
+ * (2 N * N * s / 32 per combine of a launch), s = sizeof the real type;
+ * DSMC_BF16 adds max_total_K * N * (8 d_x + 16) bytes of bf16 operands.
  * Errors: DSMC_EINVAL, DSMC_EUNSUPPORTED (also DSMC_BF16 with d_x <= 8),
  * DSMC_ENOMEM. */
 int dsmc_plan(const dsmc_plan_desc *desc, dsmc_plan_t **out);
@@ -264,6 +269,8 @@ typedef struct dsmc_profile {
   int launches[DSMC_NUM_KERNEL_CLASSES];
   double ms[DSMC_NUM_KERNEL_CLASSES];
   double pairs; /* algorithmic pair evaluations: (K-1) N^2 summed over series */
+  double rescued_rows; /* rows whose sum left the fp32 range and were recomputed with
+                          their exact maximum as shift (counted once per combine) */
 } dsmc_profile;
 int dsmc_plan_profile(dsmc_plan_t *plan, dsmc_profile *out);
 

@@ -223,8 +223,10 @@ struct dsmc_plan_impl {
   NodeBufs nb{};
   // per launch slice
   void* P = nullptr;
+  void* Pr = nullptr;
   double* Rsum = nullptr;
   float* Rshift = nullptr;
+  unsigned long long* d_rescued = nullptr;  // profiling: rescued-row counter
   // schedule
   NodeDesc* d_nodes = nullptr;
   int32_t* d_series_of_t = nullptr;
@@ -260,7 +262,9 @@ struct dsmc_plan_impl {
 static void plan_free(dsmc_plan_t* p) {
   void* dev[] = {p->leafX, p->leafW, p->leafL, p->bmerged, p->anc, p->zinc, p->nb.col, p->nb.row,
                  p->nb.alpha, p->nb.bcol, p->nb.sfirst, p->nb.slast, p->nb.colh, p->nb.colb,
-                 p->nb.rowh, p->nb.rown, p->P, p->Rsum, p->Rshift, p->d_nodes, p->d_series_of_t,
+                 p->nb.rowh, p->nb.rown, p->nb.tcol, p->nb.tgq, p->nb.trow, p->nb.tcolh,
+                 p->nb.tcoln, p->nb.trowh, p->nb.trown, p->P, p->Pr, p->Rsum, p->Rshift, p->d_rescued, p->d_nodes,
+                 p->d_series_of_t,
                  p->d_leaf_cons, p->d_series};
   for (void* q : dev) (void)hipFree(q);
   void* host[] = {p->h_nodes, p->h_series_of_t, p->h_leaf_cons, p->h_series};
@@ -304,8 +308,8 @@ extern "C" int dsmc_plan(const dsmc_plan_desc* d, dsmc_plan_t** out) {
   p->NcP = (p->Nc + 3) / 4 * 4;
   const size_t TK = (size_t)p->d.max_total_K;
   const size_t max_nodes = std::max<size_t>(1, TK / 2);
-  const size_t per_node_P = (size_t)N * p->NcP * p->rsz + (size_t)N * (sizeof(double) + sizeof(float));
-  const size_t cap_by_mem = std::max<size_t>(1, ((size_t)1 << 30) / per_node_P);
+  const size_t per_node_P = 2 * (size_t)N * p->NcP * p->rsz + (size_t)N * (sizeof(double) + sizeof(float));
+  const size_t cap_by_mem = std::max<size_t>(1, ((size_t)2 << 30) / per_node_P);
   p->node_cap = (int)std::min(max_nodes, cap_by_mem);
   const size_t nc = (size_t)p->node_cap;
   const size_t R = p->rsz, DXp = (size_t)p->DX;
@@ -327,7 +331,11 @@ extern "C" int dsmc_plan(const dsmc_plan_desc* d, dsmc_plan_t** out) {
       {(void**)&p->nb.bcol, TK * sizeof(double), "column shifts"},
       {(void**)&p->nb.sfirst, TK * N * sizeof(int32_t), "first-time ancestry"},
       {(void**)&p->nb.slast, TK * N * sizeof(int32_t), "last-time ancestry"},
+      {&p->nb.tcol, TK * N * DXp * R, "column table"},
+      {(void**)&p->nb.tgq, TK * N * sizeof(double), "proposal table"},
+      {&p->nb.trow, TK * N * DXp * R, "row table"},
       {&p->P, nc * N * p->NcP * R, "chunk sums"},
+      {&p->Pr, nc * N * p->NcP * R, "rescued chunk sums"},
       {(void**)&p->Rsum, nc * N * sizeof(double), "row sums"},
       {(void**)&p->Rshift, nc * N * sizeof(float), "row shifts"},
       {(void**)&p->d_nodes, TK * sizeof(NodeDesc), "schedule"},
@@ -335,11 +343,16 @@ extern "C" int dsmc_plan(const dsmc_plan_desc* d, dsmc_plan_t** out) {
       {(void**)&p->d_leaf_cons, TK * sizeof(int32_t), "leaf consumers"},
   };
   std::vector<A> all(std::begin(allocs), std::end(allocs));
+  if (p->timer.on) all.push_back({(void**)&p->d_rescued, sizeof(unsigned long long), "rescue counter"});
   if (p->bf16) {
     all.push_back({(void**)&p->nb.colh, TK * p->Npad * DXp * 2, "bf16 column operands"});
     all.push_back({(void**)&p->nb.colb, TK * p->Npad * sizeof(float), "column norms"});
     all.push_back({(void**)&p->nb.rowh, TK * p->Npad * DXp * 2, "bf16 row operands"});
     all.push_back({(void**)&p->nb.rown, TK * p->Npad * sizeof(float), "row norms"});
+    all.push_back({(void**)&p->nb.tcolh, TK * N * DXp * 2, "bf16 column table"});
+    all.push_back({(void**)&p->nb.tcoln, TK * N * sizeof(float), "column table norms"});
+    all.push_back({(void**)&p->nb.trowh, TK * N * DXp * 2, "bf16 row table"});
+    all.push_back({(void**)&p->nb.trown, TK * N * sizeof(float), "row table norms"});
   }
   for (auto& a : all) {
     hipError_t e = hipMalloc(a.ptr, std::max<size_t>(a.bytes, 256));
@@ -358,6 +371,14 @@ extern "C" int dsmc_plan(const dsmc_plan_desc* d, dsmc_plan_t** out) {
     plan_free(p);
     delete p;
     return fail(DSMC_ENOMEM, "host staging allocation failed");
+  }
+  if (p->d_rescued) {
+    const unsigned long long zero = 0;
+    if (hipMemcpy(p->d_rescued, &zero, sizeof zero, hipMemcpyHostToDevice) != hipSuccess) {
+      plan_free(p);
+      delete p;
+      return fail(DSMC_EDEVICE, "rescue counter initialisation failed");
+    }
   }
   *out = p;
   return DSMC_OK;
@@ -478,15 +499,17 @@ int dsmc::pick_cs(int nodes, int N, int Nc, int rpl, int W) {
 }
 
 // Heuristic rows-kernel tile: most rows per lane that still gives 16 waves
-// per CU without column splits, else one row per lane and column splits.
-TileChoice dsmc::heuristic_tile(int nodes, int N, int Nc) {
+// per CU without column splits, else one row per lane and column splits
+// (split_ok: d_x < 8; wider rows stay whole so a wave can redo its rows with
+// exact shifts).
+TileChoice dsmc::heuristic_tile(int nodes, int N, int Nc, bool split_ok) {
   const int rpls[3] = {4, 2, 1};
   for (int rpl : rpls) {
     const long waves = (long)nodes * ((N + 64 * rpl - 1) / (64 * rpl));
     if (waves >= 4096 || rpl == 1) {
       int W = 4;
       while (W > 1 && 64 * rpl * W > N) W >>= 1;
-      return {rpl, W, pick_cs(nodes, N, Nc, rpl, W)};
+      return {rpl, W, split_ok ? pick_cs(nodes, N, Nc, rpl, W) : 1};
     }
   }
   return {1, 1, 1};
@@ -505,7 +528,8 @@ void dsmc::set_tile(LevelLaunch& L, TileChoice tc) {
 // kernel only writes its own outputs) and keep the fastest.  The tile does
 // not change any result.
 static TileChoice autotune_tile(dsmc_plan_t* p, LevelLaunch L) {
-  TileChoice best = heuristic_tile(L.nodes, L.N, L.Nc);
+  const bool split_ok = L.DX < 8;
+  TileChoice best = heuristic_tile(L.nodes, L.N, L.Nc, split_ok);
   hipEvent_t e0, e1;
   if (hipEventCreate(&e0) != hipSuccess) return best;
   if (hipEventCreate(&e1) != hipSuccess) {
@@ -519,6 +543,7 @@ static TileChoice autotune_tile(dsmc_plan_t* p, LevelLaunch L) {
     for (int w : ws)
       for (int split = 0; split < 2; ++split) {
       if (64 * rpl * w > 2 * L.N && !(rpl == 1 && w == 1)) continue;
+      if (split && !split_ok) continue;
       const TileChoice tc{rpl, w, split ? pick_cs(L.nodes, L.N, L.Nc, rpl, w) : 1};
       if (split && tc.CS == 1) continue;
       set_tile(L, tc);
@@ -602,8 +627,9 @@ PoolSizes dsmc::pool_sizes(int N, int DX, int dx_alloc, size_t rsz) {
                + 2 * N * sizeof(int32_t) + sizeof(double)                // ancestry, increment
                + Npad * (DX + 1) * rsz + Npad * DX * rsz + N * rsz      // column / row data, row weights
                + sizeof(double) + 2 * N * sizeof(int32_t)                // shift, first/last ancestry
+               + 2 * (size_t)N * DX * rsz + N * sizeof(double)          // column / row tables
                + sizeof(NodeDesc) + 2 * sizeof(int32_t);                 // schedule
-  ps.per_node = (size_t)N * NcP * rsz + (size_t)N * (sizeof(double) + sizeof(float));
+  ps.per_node = 2 * (size_t)N * NcP * rsz + (size_t)N * (sizeof(double) + sizeof(float));
   return ps;
 }
 
@@ -763,15 +789,18 @@ static int enqueue_batch(dsmc_plan_t* p, int B, int totalK, hipStream_t st) {
       L.leafX = p->leafX;
       L.bmerged = p->bmerged;
       L.P = p->P;
+      L.Pr = p->Pr;
       L.Rsum = p->Rsum;
       L.Rshift = p->Rshift;
+      L.force_rescue = (p->d.flags & DSMC_PLAN_RESCUE_ALL) != 0;
+      L.rescue_count = p->d_rescued;
       L.nb = p->nb;
       auto it = p->tiles.find(nodes);
       TileChoice tc;
       if (it != p->tiles.end()) {
         tc = it->second;
       } else {
-        tc = p->autotune ? autotune_tile(p, L) : heuristic_tile(nodes, N, p->Nc);
+        tc = p->autotune ? autotune_tile(p, L) : heuristic_tile(nodes, N, p->Nc, p->DX < 8);
         p->tiles[nodes] = tc;
       }
       set_tile(L, tc);
@@ -807,6 +836,11 @@ extern "C" int dsmc_plan_profile(dsmc_plan_t* p, dsmc_profile* out) {
     out->ms[c] += ms;
   }
   out->pairs = p->last_pairs;
+  unsigned long long resc = 0;
+  const unsigned long long zero = 0;
+  HIP_TRY(hipMemcpy(&resc, p->d_rescued, sizeof resc, hipMemcpyDeviceToHost));
+  HIP_TRY(hipMemcpy(p->d_rescued, &zero, sizeof zero, hipMemcpyHostToDevice));
+  out->rescued_rows = (double)resc;
   p->timer.reset();
   p->last_pairs = 0.0;
   return DSMC_OK;

@@ -103,17 +103,29 @@ constexpr double kLog2e = 1.4426950408889634;
 constexpr double kLn2 = 0.6931471805599453;
 
 // -1/2 || Linv (x - mean) ||^2 with Linv lower triangular [dx][dx].
+// For DX >= 8 the row loop is not unrolled (only x stays in registers); the
+// summation order is the same either way.
 template <int DX>
 __device__ __forceinline__ double neg_half_quad(const double* Linv, const double* mean,
                                                 const double (&x)[DX], int dx) {
   double q = 0.0;
-#pragma unroll
-  for (int i = 0; i < DX; ++i) {
-    if (i < dx) {
+  if constexpr (DX >= 8) {
+    for (int i = 0; i < dx; ++i) {
       double z = 0.0;
 #pragma unroll
-      for (int j = 0; j <= i; ++j) z += Linv[i * dx + j] * (x[j] - mean[j]);
+      for (int j = 0; j < DX; ++j)
+        if (j <= i) z += Linv[i * dx + j] * (x[j] - mean[j]);
       q += z * z;
+    }
+  } else {
+#pragma unroll
+    for (int i = 0; i < DX; ++i) {
+      if (i < dx) {
+        double z = 0.0;
+#pragma unroll
+        for (int j = 0; j <= i; ++j) z += Linv[i * dx + j] * (x[j] - mean[j]);
+        q += z * z;
+      }
     }
   }
   return -0.5 * q;

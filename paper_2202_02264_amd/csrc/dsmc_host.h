@@ -37,7 +37,7 @@ struct TileChoice {
 
 int padded_dx(int dx);
 int pick_cs(int nodes, int N, int Nc, int rpl, int W);
-TileChoice heuristic_tile(int nodes, int N, int Nc);
+TileChoice heuristic_tile(int nodes, int N, int Nc, bool split_ok);
 void set_tile(LevelLaunch& L, TileChoice tc);
 int check_output(const dsmc_output* o);
 

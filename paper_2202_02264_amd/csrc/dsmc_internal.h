@@ -83,6 +83,16 @@ struct NodeBufs {
   float* colb;      // [nodes][Npad]        beta_n - ||u_n||^2 (-inf in padding columns)
   uint16_t* rowh;   // [nodes][Npad][DX]    bf16 bits of v_m
   float* rown;      // [nodes][Npad]        ||v_m||^2
+  // Per time row g of the packed time axis (written by the leaf kernel): the
+  // data of every leaf particle for the combines at the two boundaries of its
+  // time t, which merged blocks gather when they reach their consumer.
+  void* tcol;       // [rows][N][DX]  u of particle n for boundary t (t >= 1)
+  double* tgq;      // [rows][N]      -log q_t(x) (+ log h_t(x) under boundary weighting)
+  void* trow;       // [rows][N][DX]  v of particle n for boundary t + 1 (t + 1 < K)
+  uint16_t* tcolh;  // [rows][N][DX]  bf16 plans: bits of 2u
+  float* tcoln;     // [rows][N]      bf16 plans: ||u||^2
+  uint16_t* trowh;  // [rows][N][DX]  bf16 plans: bits of v
+  float* trown;     // [rows][N]      bf16 plans: ||v||^2
 };
 
 enum : int32_t { kFlagDegenerate = 1, kFlagNumeric = 2 };

@@ -81,37 +81,153 @@ __device__ __forceinline__ uint32_t bf16_bits(float x) {
 }
 __device__ __forceinline__ float bf16_float(uint32_t b) { return __uint_as_float(b << 16); }
 
-// Column data (u_n, beta_n) of right-block particle n of combine `node`.  In a
-// bf16 plan u is rounded to bf16 first and the matrix-core operands are
-// written too: the bits of 2u (exact) and beta - ||u||^2.
+// Table entry of particle n of time row g for the combine at boundary t:
+// u (bf16 plans: rounded to bf16, plus the bits of 2u and ||u||^2).
 template <typename R, int DX>
-__device__ __forceinline__ void put_col(const NodeBufs& nb, size_t node, int Npad, int n,
-                                        const double (&u)[DX], double beta) {
-  R* cp = (R*)nb.col + (node * Npad + n) * (DX + 1);
+__device__ __forceinline__ void put_tcol(const NodeBufs& nb, size_t g, int N, int n,
+                                         const double (&u)[DX]) {
+  R* tp = (R*)nb.tcol + (g * N + n) * DX;
   if constexpr (sizeof(R) == 4 && DX >= 16) {
-    if (nb.colh) {
+    if (nb.tcolh) {
       uint32_t w[DX / 2];
       double nrm = 0.0;
 #pragma unroll
       for (int i = 0; i < DX; ++i) {
         const float ur = bf16_float(bf16_bits((float)u[i]));
-        cp[i] = ur;
+        tp[i] = ur;
         nrm += (double)ur * (double)ur;
         const uint32_t b2 = bf16_bits(2.0f * ur);
         w[i >> 1] = (i & 1) ? (w[i >> 1] | (b2 << 16)) : b2;
       }
-      const float bf = (float)beta;
-      cp[DX] = bf;
-      uint4* dst = (uint4*)(nb.colh + (node * Npad + n) * DX);
+      uint4* dst = (uint4*)(nb.tcolh + (g * N + n) * DX);
 #pragma unroll
       for (int q = 0; q < DX / 8; ++q) dst[q] = make_uint4(w[4 * q], w[4 * q + 1], w[4 * q + 2], w[4 * q + 3]);
-      nb.colb[node * Npad + n] = (float)((double)bf - nrm);
+      nb.tcoln[g * N + n] = (float)nrm;
       return;
     }
   }
 #pragma unroll
-  for (int i = 0; i < DX; ++i) cp[i] = (R)u[i];
+  for (int i = 0; i < DX; ++i) tp[i] = (R)u[i];
+}
+
+// Table entry of particle n of time row g for the combine at boundary t + 1:
+// v (bf16 plans: rounded, plus its bits and ||v||^2).
+template <typename R, int DX>
+__device__ __forceinline__ void put_trow(const NodeBufs& nb, size_t g, int N, int n,
+                                         const double (&v)[DX]) {
+  R* tp = (R*)nb.trow + (g * N + n) * DX;
+  if constexpr (sizeof(R) == 4 && DX >= 16) {
+    if (nb.trowh) {
+      uint32_t w[DX / 2];
+      double nrm = 0.0;
+#pragma unroll
+      for (int i = 0; i < DX; ++i) {
+        const uint32_t b = bf16_bits((float)v[i]);
+        const float vr = bf16_float(b);
+        tp[i] = vr;
+        nrm += (double)vr * (double)vr;
+        w[i >> 1] = (i & 1) ? (w[i >> 1] | (b << 16)) : b;
+      }
+      uint4* dst = (uint4*)(nb.trowh + (g * N + n) * DX);
+#pragma unroll
+      for (int q = 0; q < DX / 8; ++q) dst[q] = make_uint4(w[4 * q], w[4 * q + 1], w[4 * q + 2], w[4 * q + 3]);
+      nb.trown[g * N + n] = (float)nrm;
+      return;
+    }
+  }
+#pragma unroll
+  for (int i = 0; i < DX; ++i) tp[i] = (R)v[i];
+}
+
+// Column n of combine `node` := table entry (g, src) with log2 weight beta.
+template <typename R, int DX>
+__device__ __forceinline__ void copy_col(const NodeBufs& nb, size_t node, int Npad, int n, size_t g,
+                                         int N, int src, double beta) {
+  const R* tp = (const R*)nb.tcol + (g * N + src) * DX;
+  R* cp = (R*)nb.col + (node * Npad + n) * (DX + 1);
+#pragma unroll
+  for (int i = 0; i < DX; ++i) cp[i] = tp[i];
   cp[DX] = (R)beta;
+  if constexpr (sizeof(R) == 4 && DX >= 16) {
+    if (nb.colh) {
+      const uint4* s4 = (const uint4*)(nb.tcolh + (g * N + src) * DX);
+      uint4* d4 = (uint4*)(nb.colh + (node * Npad + n) * DX);
+#pragma unroll
+      for (int q = 0; q < DX / 8; ++q) d4[q] = s4[q];
+      nb.colb[node * Npad + n] = (float)beta - nb.tcoln[g * N + src];
+    }
+  }
+}
+
+// Row m of combine `node` := table entry (g, src).
+template <typename R, int DX>
+__device__ __forceinline__ void copy_row(const NodeBufs& nb, size_t node, int Npad, int m, size_t g,
+                                         int N, int src) {
+  const R* tp = (const R*)nb.trow + (g * N + src) * DX;
+  R* rp = (R*)nb.row + (node * Npad + m) * DX;
+#pragma unroll
+  for (int i = 0; i < DX; ++i) rp[i] = tp[i];
+  if constexpr (sizeof(R) == 4 && DX >= 16) {
+    if (nb.rowh) {
+      const uint4* s4 = (const uint4*)(nb.trowh + (g * N + src) * DX);
+      uint4* d4 = (uint4*)(nb.rowh + (node * Npad + m) * DX);
+#pragma unroll
+      for (int q = 0; q < DX / 8; ++q) d4[q] = s4[q];
+      nb.rown[node * Npad + m] = nb.trown[g * N + src];
+    }
+  }
+}
+
+// Table entries for DX >= 8, written coordinate by coordinate (the matrix row
+// loop is not unrolled, so only x stays in registers); same values, order and
+// rounding as col_coords / row_coords followed by put_tcol / put_trow.
+template <typename R, int DX, bool kRow>
+__device__ __forceinline__ void stream_table(const NodeBufs& nb, const DevModel& M, int c, size_t g,
+                                             int N, int n, const double (&x)[DX]) {
+  const int dx = M.dx;
+  const double* qm = M.q_mean + (size_t)c * dx;
+  R* tp = (R*)(kRow ? nb.trow : nb.tcol) + (g * N + n) * DX;
+  uint32_t* th = nullptr;
+  if constexpr (sizeof(R) == 4 && DX >= 16)
+    th = (uint32_t*)(kRow ? nb.trowh : nb.tcolh);
+  if (th) th += (g * N + n) * (DX / 2);
+  double nrm = 0.0;
+#pragma unroll 1
+  for (int i = 0; i < DX; i += 2) {
+    double s2[2];
+#pragma unroll
+    for (int k = 0; k < 2; ++k) {
+      const int ii = i + k;
+      double acc = 0.0;
+      if (ii < dx) {
+        if (kRow) {
+          acc = M.wcol_off[ii];
+#pragma unroll
+          for (int j = 0; j < DX; ++j)
+            if (j < dx) acc += M.Wrow[ii * dx + j] * x[j] - M.Wcol[ii * dx + j] * qm[j];
+        } else {
+#pragma unroll
+          for (int j = 0; j < DX; ++j)
+            if (j < dx) acc += M.Wcol[ii * dx + j] * (x[j] - qm[j]);
+        }
+      }
+      s2[k] = acc;
+    }
+    if (th) {
+      const float r0 = bf16_float(bf16_bits((float)s2[0]));
+      const float r1 = bf16_float(bf16_bits((float)s2[1]));
+      tp[i] = r0;
+      tp[i + 1] = r1;
+      nrm += (double)r0 * (double)r0;
+      nrm += (double)r1 * (double)r1;
+      const uint32_t b0 = bf16_bits(kRow ? r0 : 2.0f * r0), b1 = bf16_bits(kRow ? r1 : 2.0f * r1);
+      th[i >> 1] = b0 | (b1 << 16);
+    } else {
+      tp[i] = (R)s2[0];
+      tp[i + 1] = (R)s2[1];
+    }
+  }
+  if (th) (kRow ? nb.trown : nb.tcoln)[g * N + n] = (float)nrm;
 }
 
 // Padding column n (N <= n < Npad): weight zero.
@@ -129,35 +245,6 @@ __device__ __forceinline__ void put_col_pad(const NodeBufs& nb, size_t node, int
       nb.colb[node * Npad + n] = -INFINITY;
     }
   }
-}
-
-// Row data v_m of left-block particle m of combine `node` (bf16 plan: rounded
-// v, its bits and ||v||^2).
-template <typename R, int DX>
-__device__ __forceinline__ void put_row(const NodeBufs& nb, size_t node, int Npad, int m,
-                                        const double (&v)[DX]) {
-  R* rp = (R*)nb.row + (node * Npad + m) * DX;
-  if constexpr (sizeof(R) == 4 && DX >= 16) {
-    if (nb.rowh) {
-      uint32_t w[DX / 2];
-      double nrm = 0.0;
-#pragma unroll
-      for (int i = 0; i < DX; ++i) {
-        const uint32_t b = bf16_bits((float)v[i]);
-        const float vr = bf16_float(b);
-        rp[i] = vr;
-        nrm += (double)vr * (double)vr;
-        w[i >> 1] = (i & 1) ? (w[i >> 1] | (b << 16)) : b;
-      }
-      uint4* dst = (uint4*)(nb.rowh + (node * Npad + m) * DX);
-#pragma unroll
-      for (int q = 0; q < DX / 8; ++q) dst[q] = make_uint4(w[4 * q], w[4 * q + 1], w[4 * q + 2], w[4 * q + 3]);
-      nb.rown[node * Npad + m] = (float)nrm;
-      return;
-    }
-  }
-#pragma unroll
-  for (int i = 0; i < DX; ++i) rp[i] = (R)v[i];
 }
 
 // ================================================================ leaves
@@ -180,30 +267,68 @@ __global__ __launch_bounds__(kBlock) void k_leaves(
   const int dx = M.dx;
   const double logN = log((double)N);
   int bad = 0;
+  const double* qm = M.q_mean + (size_t)t * dx;
+  const double* qc = M.q_chol + (size_t)t * dx * dx;
   for (int n = threadIdx.x; n < N; n += kBlock) {
-    double z[DX + 3];
-#pragma unroll
-    for (int j = 0; j < (DX + 3) / 4; ++j) {
-      const Words4 w = philox4x64_10((uint64_t)n, (uint64_t)t, kPurposeLeaf, (uint64_t)j,
-                                     sd.seed, kKey1);
-      box_muller(w.w0, w.w1, z[4 * j], z[4 * j + 1]);
-      box_muller(w.w2, w.w3, z[4 * j + 2], z[4 * j + 3]);
-    }
-    const double* qm = M.q_mean + (size_t)t * dx;
-    const double* qc = M.q_chol + (size_t)t * dx * dx;
+    // standard normals, four per Philox block, then x = q_mean + L z in place
+    // from the last coordinate down (x_i needs z_0 .. z_i)
     double x[DX];
+    if constexpr (DX >= 8) {
+      // one Philox block (four normals) at a time, each added into every
+      // x_i it enters: the same terms in the same order as below, without
+      // holding all the normals
 #pragma unroll
-    for (int i = 0; i < DX; ++i) {
-      double xi = 0.0;
-      if (i < dx) {
-        xi = qm[i];
+      for (int i = 0; i < DX; ++i) x[i] = (i < dx) ? qm[i] : 0.0;
+#pragma unroll 1
+      for (int j = 0; j < (DX + 3) / 4; ++j) {
+        const Words4 w = philox4x64_10((uint64_t)n, (uint64_t)t, kPurposeLeaf, (uint64_t)j,
+                                       sd.seed, kKey1);
+        double z[4];
+        box_muller(w.w0, w.w1, z[0], z[1]);
+        box_muller(w.w2, w.w3, z[2], z[3]);
 #pragma unroll
-        for (int j = 0; j <= i; ++j) xi += qc[i * dx + j] * z[j];
-        const R xr = (R)xi;
-        leafX[((size_t)i * totalK + g) * N + n] = xr;
-        xi = (double)xr;  // weights are those of the stored particle
+        for (int i = 0; i < DX; ++i) {
+          if (i < dx) {
+#pragma unroll
+            for (int k = 0; k < 4; ++k)
+              if (4 * j + k <= i) x[i] += qc[i * dx + 4 * j + k] * z[k];
+          }
+        }
       }
-      x[i] = xi;
+#pragma unroll
+      for (int i = 0; i < DX; ++i) {
+        if (i < dx) {
+          const R xr = (R)x[i];
+          leafX[((size_t)i * totalK + g) * N + n] = xr;
+          x[i] = (double)xr;  // weights are those of the stored particle
+        }
+      }
+    } else {
+#pragma unroll
+      for (int j = 0; j < (DX + 3) / 4; ++j) {
+        const Words4 w = philox4x64_10((uint64_t)n, (uint64_t)t, kPurposeLeaf, (uint64_t)j,
+                                       sd.seed, kKey1);
+        double z0, z1, z2, z3;
+        box_muller(w.w0, w.w1, z0, z1);
+        box_muller(w.w2, w.w3, z2, z3);
+        if (4 * j < DX) x[4 * j] = z0;
+        if (4 * j + 1 < DX) x[4 * j + 1] = z1;
+        if (4 * j + 2 < DX) x[4 * j + 2] = z2;
+        if (4 * j + 3 < DX) x[4 * j + 3] = z3;
+      }
+#pragma unroll
+      for (int i = DX - 1; i >= 0; --i) {
+        double xi = 0.0;
+        if (i < dx) {
+          xi = qm[i];
+#pragma unroll
+          for (int j = 0; j <= i; ++j) xi += qc[i * dx + j] * x[j];
+          const R xr = (R)xi;
+          leafX[((size_t)i * totalK + g) * N + n] = xr;
+          xi = (double)xr;  // weights are those of the stored particle
+        }
+        x[i] = xi;
+      }
     }
     const double lq = log_proposal<DX>(M, t, x);
     double l, gg = -lq;
@@ -250,33 +375,46 @@ __global__ __launch_bounds__(kBlock) void k_leaves(
     const int flags = bad | (degenerate ? kFlagDegenerate : 0);
     if (flags) atomicOr(sd.status, flags);
   }
-  // data of the combine that consumes this single-point block
+  // Every particle's data for the combines at both boundaries of t (the
+  // tables merged blocks gather from), and the data of the combine that
+  // consumes this single-point block: its right block (c == t) or its left
+  // block (c == t + 1).
   const int cons = leaf_cons[g];
-  if (cons < 0) return;
   const int P = cons >> 1, role = cons & 1;
-  const int c = nodes[P].c;
-  if (role == 1) {  // right block of combine P (c == t)
-    for (int n = threadIdx.x; n < Npad; n += kBlock) {
-      if (n < N) {
-        double x[DX], u[DX];
-        load_particle<R, DX>(leafX, totalK, N, g, n, dx, x);
-        col_coords<DX>(M, c, x, u);
-        const double beta =
-            (bmax > -INFINITY) ? (ell[n] + gq[n] - bmax) * kLog2e : -INFINITY;
-        put_col<R, DX>(nb, (size_t)P, Npad, n, u, beta);
+  for (int n = threadIdx.x; n < N; n += kBlock) {
+    double x[DX];
+    load_particle<R, DX>(leafX, totalK, N, g, n, dx, x);
+    nb.tgq[(size_t)g * N + n] = gq[n];
+    if (t >= 1) {
+      if constexpr (DX >= 8) {
+        stream_table<R, DX, false>(nb, M, t, (size_t)g, N, n, x);
       } else {
-        put_col_pad<R, DX>(nb, (size_t)P, Npad, n);
+        double u[DX];
+        col_coords<DX>(M, t, x, u);
+        put_tcol<R, DX>(nb, (size_t)g, N, n, u);
+      }
+      if (cons >= 0 && role == 1) {
+        const double beta = (bmax > -INFINITY) ? (ell[n] + gq[n] - bmax) * kLog2e : -INFINITY;
+        copy_col<R, DX>(nb, (size_t)P, Npad, n, (size_t)g, N, n, beta);
       }
     }
-    if (threadIdx.x == 0) nb.bcol[P] = bmax;
-  } else {  // left block of combine P (c == t + 1)
-    for (int n = threadIdx.x; n < N; n += kBlock) {
-      double x[DX], v[DX];
-      load_particle<R, DX>(leafX, totalK, N, g, n, dx, x);
-      row_coords<DX>(M, c, x, v);
-      put_row<R, DX>(nb, (size_t)P, Npad, n, v);
-      ((R*)nb.alpha)[(size_t)P * N + n] = (R)ell[n];
+    if (t + 1 < sd.K) {
+      if constexpr (DX >= 8) {
+        stream_table<R, DX, true>(nb, M, t + 1, (size_t)g, N, n, x);
+      } else {
+        double v[DX];
+        row_coords<DX>(M, t + 1, x, v);
+        put_trow<R, DX>(nb, (size_t)g, N, n, v);
+      }
+      if (cons >= 0 && role == 0) {
+        copy_row<R, DX>(nb, (size_t)P, Npad, n, (size_t)g, N, n);
+        ((R*)nb.alpha)[(size_t)P * N + n] = (R)ell[n];
+      }
     }
+  }
+  if (cons >= 0 && role == 1) {
+    for (int n = N + threadIdx.x; n < Npad; n += kBlock) put_col_pad<R, DX>(nb, (size_t)P, Npad, n);
+    if (threadIdx.x == 0) nb.bcol[P] = bmax;
   }
 }
 
@@ -307,7 +445,7 @@ __global__ __launch_bounds__(kBlock) void k_rows(const R* __restrict__ col,
                                                  float* __restrict__ Rshift,
                                                  const int32_t* __restrict__ node_list,
                                                  int node0, int N, int Npad, int Nc, int NcP,
-                                                 int RB, int CS, int KC) {
+                                                 int RB, int CS, int KC, int force_redo) {
   const int W = blockDim.x >> 6;
   const int tiles = RB * CS;
   const int node_local = blockIdx.x / tiles;
@@ -329,7 +467,7 @@ __global__ __launch_bounds__(kBlock) void k_rows(const R* __restrict__ col,
   }
   // Row shift (DX >= 8): the row's largest log2 weight over its first chunk,
   // so that row sums stay inside the fp32 range when every pair weight is far
-  // below the column bound.  Every column split computes the same value.
+  // below the column bound.
   R sft[RPL];
 #pragma unroll
   for (int r = 0; r < RPL; ++r) sft[r] = (R)0;
@@ -345,43 +483,82 @@ __global__ __launch_bounds__(kBlock) void k_rows(const R* __restrict__ col,
       }
       // held at fp32 precision: the sampling kernel reads it back as fp32
       sft[r] = (mx > (R)(-INFINITY) && mx < (R)INFINITY) ? (R)(float)mx : (R)0;
-      if (cs == 0) Rshift[(size_t)node_local * N + mrow[r]] = (float)sft[r];
     }
   }
   double Rm[RPL];
-#pragma unroll
-  for (int r = 0; r < RPL; ++r) Rm[r] = 0.0;
   R* __restrict__ Pn = P + (size_t)node_local * N * NcP;
   const int k0 = cs * KC, k1 = min(Nc, k0 + KC);
-  for (int kg = k0; kg < k1; kg += 4) {
-    R acc[RPL][4];
+  auto pass = [&]() {
 #pragma unroll
-    for (int q = 0; q < 4; ++q) {
+    for (int r = 0; r < RPL; ++r) Rm[r] = 0.0;
+    for (int kg = k0; kg < k1; kg += 4) {
+      R acc[RPL][4];
 #pragma unroll
-      for (int r = 0; r < RPL; ++r) acc[r][q] = (R)0;
-      if (kg + q < k1) {  // uniform
-        const R* __restrict__ cp = colp + (size_t)(kg + q) * kChunk * (DX + 1);
+      for (int q = 0; q < 4; ++q) {
 #pragma unroll
+        for (int r = 0; r < RPL; ++r) acc[r][q] = (R)0;
+        if (kg + q < k1) {  // uniform
+          const R* __restrict__ cp = colp + (size_t)(kg + q) * kChunk * (DX + 1);
+#pragma unroll
+          for (int jj = 0; jj < kChunk; ++jj) {
+            R u[DX];
+#pragma unroll
+            for (int i = 0; i < DX; ++i) u[i] = cp[jj * (DX + 1) + i];
+            const R beta = cp[jj * (DX + 1) + DX];
+#pragma unroll
+            for (int r = 0; r < RPL; ++r) {
+              if constexpr (kRowShift<DX>)
+                acc[r][q] += Real<R>::exp2(pair_log2w<R, DX>(u, beta, v[r]) - sft[r]);
+              else
+                acc[r][q] += Real<R>::exp2(pair_log2w<R, DX>(u, beta, v[r]));
+            }
+          }
+#pragma unroll
+          for (int r = 0; r < RPL; ++r) Rm[r] += (double)acc[r][q];
+        }
+      }
+#pragma unroll
+      for (int r = 0; r < RPL; ++r)
+        store4<R>(Pn + (size_t)mrow[r] * NcP + kg, acc[r][0], acc[r][1], acc[r][2], acc[r][3]);
+    }
+  };
+  pass();
+  if constexpr (kRowShift<DX>) {
+    // A row whose sum left the fp32 range (its largest weight far above the
+    // chunk-0 estimate, or every weight far below it) takes its exact maximum
+    // as shift and the wave redoes its rows; the other rows recompute the same
+    // values.  Rows are whole here (one column split for DX >= 8).
+    bool bad[RPL];
+    int any = 0;
+#pragma unroll
+    for (int r = 0; r < RPL; ++r) {
+      bad[r] = ((!(Rm[r] >= Real<R>::kTiny) || isinf(Rm[r])) && !isnan(Rm[r])) || force_redo;
+      any |= bad[r] ? 1 : 0;
+    }
+    if (__any(any)) {
+      R mx[RPL];
+#pragma unroll
+      for (int r = 0; r < RPL; ++r) mx[r] = (R)(-INFINITY);
+      for (int k = k0; k < k1; ++k) {
+        const R* __restrict__ cp = colp + (size_t)k * kChunk * (DX + 1);
         for (int jj = 0; jj < kChunk; ++jj) {
           R u[DX];
 #pragma unroll
           for (int i = 0; i < DX; ++i) u[i] = cp[jj * (DX + 1) + i];
           const R beta = cp[jj * (DX + 1) + DX];
 #pragma unroll
-          for (int r = 0; r < RPL; ++r) {
-            if constexpr (kRowShift<DX>)
-              acc[r][q] += Real<R>::exp2(pair_log2w<R, DX>(u, beta, v[r]) - sft[r]);
-            else
-              acc[r][q] += Real<R>::exp2(pair_log2w<R, DX>(u, beta, v[r]));
-          }
+          for (int r = 0; r < RPL; ++r) mx[r] = fmax(mx[r], pair_log2w<R, DX>(u, beta, v[r]));
         }
-#pragma unroll
-        for (int r = 0; r < RPL; ++r) Rm[r] += (double)acc[r][q];
       }
-    }
 #pragma unroll
-    for (int r = 0; r < RPL; ++r)
-      store4<R>(Pn + (size_t)mrow[r] * NcP + kg, acc[r][0], acc[r][1], acc[r][2], acc[r][3]);
+      for (int r = 0; r < RPL; ++r)
+        if (bad[r]) sft[r] = (mx[r] > (R)(-INFINITY) && mx[r] < (R)INFINITY) ? (R)(float)mx[r] : (R)0;
+      pass();
+    }
+    if (cs == 0) {
+#pragma unroll
+      for (int r = 0; r < RPL; ++r) Rshift[(size_t)node_local * N + mrow[r]] = (float)sft[r];
+    }
   }
   if (CS == 1) {
 #pragma unroll
@@ -409,7 +586,7 @@ __global__ __launch_bounds__(kBlock) void k_rows_mfma(
     const uint16_t* __restrict__ colh, const float* __restrict__ colb,
     const uint16_t* __restrict__ rowh, const float* __restrict__ rown, float* __restrict__ P,
     double* __restrict__ Rsum, float* __restrict__ Rshift, const int32_t* __restrict__ node_list,
-    int node0, int N, int Npad, int Nc, int NcP, int RB, int CS, int KC) {
+    int node0, int N, int Npad, int Nc, int NcP, int RB, int CS, int KC, int force_redo) {
   static_assert(DX == 16 || DX == 32, "bf16 rows need DX 16 or 32");
   constexpr int KS = DX / 16;  // instructions per 32 x 32 block
   const int W = blockDim.x >> 6;
@@ -438,79 +615,111 @@ __global__ __launch_bounds__(kBlock) void k_rows_mfma(
   const float* __restrict__ cb = colb + (size_t)nodeid * Npad;
   // Row shift: the row's largest log2 weight over chunk 0 (as k_rows), folded
   // into the row norm term so the main loop pays nothing for it.
-  {
+  float vv0[MB], sft[MB];
+#pragma unroll
+  for (int b = 0; b < MB; ++b) vv0[b] = vv[b];
+  // log2 weights of chunk k for block b, into acc (row-norm term vv[b])
+  auto block = [&](int k, int b, f32x16_t& acc) {
+    const int n0 = k * kChunk;
     bf16x8_t uf[KS];
-    const uint16_t* up = ch + (size_t)j32 * DX + 8 * h;
+    const uint16_t* up = ch + (size_t)(n0 + j32) * DX + 8 * h;
 #pragma unroll
     for (int s = 0; s < KS; ++s) uf[s] = *(const bf16x8_t*)(up + 16 * s);
-    float bp[16];
 #pragma unroll
     for (int g4 = 0; g4 < 4; ++g4) {
-      const float4 t4 = *(const float4*)(cb + 8 * g4 + 4 * h);
-      bp[4 * g4] = t4.x; bp[4 * g4 + 1] = t4.y; bp[4 * g4 + 2] = t4.z; bp[4 * g4 + 3] = t4.w;
+      const float4 t4 = *(const float4*)(cb + n0 + 8 * g4 + 4 * h);
+      acc[4 * g4] = t4.x - vv[b];
+      acc[4 * g4 + 1] = t4.y - vv[b];
+      acc[4 * g4 + 2] = t4.z - vv[b];
+      acc[4 * g4 + 3] = t4.w - vv[b];
     }
 #pragma unroll
+    for (int s = 0; s < KS; ++s)
+      acc = __builtin_amdgcn_mfma_f32_32x32x16_bf16(uf[s], vf[b][s], acc, 0, 0, 0);
+  };
+  // largest log2 weight of each row block over chunks [ka, kb)
+  auto row_max = [&](int ka, int kb, float (&mx)[MB]) {
+#pragma unroll
+    for (int b = 0; b < MB; ++b) mx[b] = -INFINITY;
+    for (int k = ka; k < kb; ++k) {
+#pragma unroll
+      for (int b = 0; b < MB; ++b) {
+        f32x16_t acc;
+        block(k, b, acc);
+#pragma unroll
+        for (int r = 0; r < 16; ++r) mx[b] = fmaxf(mx[b], acc[r]);
+      }
+    }
+#pragma unroll
+    for (int b = 0; b < MB; ++b) mx[b] = fmaxf(mx[b], __shfl_xor(mx[b], 32, 64));
+  };
+  {
+    float mx[MB];
+    row_max(0, 1, mx);
+#pragma unroll
     for (int b = 0; b < MB; ++b) {
-      f32x16_t acc;
-#pragma unroll
-      for (int r = 0; r < 16; ++r) acc[r] = bp[r] - vv[b];
-#pragma unroll
-      for (int s = 0; s < KS; ++s)
-        acc = __builtin_amdgcn_mfma_f32_32x32x16_bf16(uf[s], vf[b][s], acc, 0, 0, 0);
-      float mx = acc[0];
-#pragma unroll
-      for (int r = 1; r < 16; ++r) mx = fmaxf(mx, acc[r]);
-      mx = fmaxf(mx, __shfl_xor(mx, 32, 64));
-      const float sft = (mx > -INFINITY && mx < INFINITY) ? mx : 0.0f;
-      if (cs == 0 && h == 0) Rshift[(size_t)node_local * N + mrow[b]] = sft;
-      vv[b] += sft;
+      sft[b] = (mx[b] > -INFINITY && mx[b] < INFINITY) ? mx[b] : 0.0f;
+      vv[b] = vv0[b] + sft[b];
     }
   }
   double Rm[MB];
-#pragma unroll
-  for (int b = 0; b < MB; ++b) Rm[b] = 0.0;
   float* __restrict__ Pn = P + (size_t)node_local * N * NcP;
   const int k0 = cs * KC, k1 = min(Nc, k0 + KC);
-  for (int kg = k0; kg < k1; kg += 4) {
-    float c4[MB][4];
+  auto pass = [&]() {
 #pragma unroll
-    for (int q = 0; q < 4; ++q) {
+    for (int b = 0; b < MB; ++b) Rm[b] = 0.0;
+    for (int kg = k0; kg < k1; kg += 4) {
+      float c4[MB][4];
 #pragma unroll
-      for (int b = 0; b < MB; ++b) c4[b][q] = 0.0f;
-      if (kg + q < k1) {  // uniform
-        const int n0 = (kg + q) * kChunk;
-        bf16x8_t uf[KS];
-        const uint16_t* up = ch + (size_t)(n0 + j32) * DX + 8 * h;
+      for (int q = 0; q < 4; ++q) {
 #pragma unroll
-        for (int s = 0; s < KS; ++s) uf[s] = *(const bf16x8_t*)(up + 16 * s);
-        float bp[16];
+        for (int b = 0; b < MB; ++b) c4[b][q] = 0.0f;
+        if (kg + q < k1) {  // uniform
 #pragma unroll
-        for (int g4 = 0; g4 < 4; ++g4) {
-          const float4 t4 = *(const float4*)(cb + n0 + 8 * g4 + 4 * h);
-          bp[4 * g4] = t4.x; bp[4 * g4 + 1] = t4.y; bp[4 * g4 + 2] = t4.z; bp[4 * g4 + 3] = t4.w;
-        }
+          for (int b = 0; b < MB; ++b) {
+            f32x16_t acc;
+            block(kg + q, b, acc);
+            float e = 0.0f;
 #pragma unroll
-        for (int b = 0; b < MB; ++b) {
-          f32x16_t acc;
-#pragma unroll
-          for (int r = 0; r < 16; ++r) acc[r] = bp[r] - vv[b];
-#pragma unroll
-          for (int s = 0; s < KS; ++s)
-            acc = __builtin_amdgcn_mfma_f32_32x32x16_bf16(uf[s], vf[b][s], acc, 0, 0, 0);
-          float e = 0.0f;
-#pragma unroll
-          for (int r = 0; r < 16; ++r) e += Real<float>::exp2(acc[r]);
-          e += __shfl_xor(e, 32, 64);
-          c4[b][q] = e;
-          Rm[b] += (double)e;
+            for (int r = 0; r < 16; ++r) e += Real<float>::exp2(acc[r]);
+            e += __shfl_xor(e, 32, 64);
+            c4[b][q] = e;
+            Rm[b] += (double)e;
+          }
         }
       }
-    }
-    if (h == 0) {
+      if (h == 0) {
 #pragma unroll
-      for (int b = 0; b < MB; ++b)
-        store4<float>(Pn + (size_t)mrow[b] * NcP + kg, c4[b][0], c4[b][1], c4[b][2], c4[b][3]);
+        for (int b = 0; b < MB; ++b)
+          store4<float>(Pn + (size_t)mrow[b] * NcP + kg, c4[b][0], c4[b][1], c4[b][2], c4[b][3]);
+      }
     }
+  };
+  pass();
+  // As k_rows: a row whose sum left the fp32 range takes its exact maximum as
+  // shift and the wave redoes its rows (whole rows: one column split).
+  int any = 0;
+  bool bad[MB];
+#pragma unroll
+  for (int b = 0; b < MB; ++b) {
+    bad[b] = ((!(Rm[b] >= Real<float>::kTiny) || isinf(Rm[b])) && !isnan(Rm[b])) || force_redo;
+    any |= bad[b] ? 1 : 0;
+  }
+  if (__any(any)) {
+#pragma unroll
+    for (int b = 0; b < MB; ++b) vv[b] = vv0[b];
+    float mx[MB];
+    row_max(k0, k1, mx);
+#pragma unroll
+    for (int b = 0; b < MB; ++b) {
+      if (bad[b]) sft[b] = (mx[b] > -INFINITY && mx[b] < INFINITY) ? mx[b] : 0.0f;
+      vv[b] = vv0[b] + sft[b];
+    }
+    pass();
+  }
+  if (cs == 0 && h == 0) {
+#pragma unroll
+    for (int b = 0; b < MB; ++b) Rshift[(size_t)node_local * N + mrow[b]] = sft[b];
   }
   if (CS == 1 && h == 0) {
 #pragma unroll
@@ -525,9 +734,10 @@ __global__ __launch_bounds__(kBlock) void k_rows_mfma(
 //   Z_c = A* + B + trans_lognorm + ln C_{N-1}
 //   l_n = first m with C_m > u1 C_{N-1}
 //   r_n = first j with (chunk prefix + within-chunk prefix) > u2 R_l
-// Rows whose R_m underflows fp32 range are recomputed with their exact
-// maximum as shift (R_m then carries a factor 2^shift_m, the weights are
-// formed in log space) and drawn from by a full-row scan.
+// Rows whose R_m leaves the fp32 range (underflow, or overflow when a row
+// shift estimated from one chunk is too low) are recomputed with their exact
+// maximum as shift: their chunk sums go to Pr, R_m carries a factor
+// 2^shift_m and the weights are formed in log space.
 // The combine's column data is staged in LDS when it fits (col_in_lds).
 template <typename R>
 __device__ __forceinline__ void load4(const R* p, R (&q)[4]);
@@ -546,9 +756,10 @@ template <typename R, int DX>
 __global__ __launch_bounds__(kBlock) void k_sample(
     const NodeDesc* __restrict__ nodes, const SeriesDesc* __restrict__ series,
     const int32_t* __restrict__ node_list, int node0, int DS,
-    int totalK, int N, int Npad, int Nc, int NcP, int rows_summed, int col_in_lds,
-    const R* __restrict__ leafX, const double* __restrict__ bmerged, const R* __restrict__ P,
-    const double* __restrict__ Rsum, const float* __restrict__ Rshift, NodeBufs nb) {
+    int N, int Npad, int Nc, int NcP, int rows_summed, int col_in_lds, int force_rescue,
+    const double* __restrict__ bmerged, const R* __restrict__ P, R* __restrict__ Pr,
+    const double* __restrict__ Rsum, const float* __restrict__ Rshift,
+    unsigned long long* __restrict__ rescue_count, NodeBufs nb) {
   extern __shared__ double smem[];
   double* cdf = smem;                        // [Npad]
   double* rs = smem + Npad;                  // [Npad]
@@ -562,12 +773,13 @@ __global__ __launch_bounds__(kBlock) void k_sample(
   const NodeDesc nd = nodes[nodeid];
   const SeriesDesc& sd = series[nd.series];
   const DevModel& M = *sd.model;
-  const int c = nd.c, dx = M.dx;
+  const int c = nd.c;
   const bool left_leaf = nd.lchild < 0;
   const double logN = log((double)N);
   const R* __restrict__ gcol = (const R*)nb.col + (size_t)nodeid * Npad * (DX + 1);
   const R* __restrict__ rowp = (const R*)nb.row + (size_t)nodeid * Npad * DX;
   const R* __restrict__ Pn = P + (size_t)node_local * N * NcP;
+  R* __restrict__ Prn = Pr + (size_t)node_local * N * NcP;
   const double* __restrict__ Rn = Rsum + (size_t)node_local * N;
   const R* __restrict__ alp = (const R*)nb.alpha + (size_t)nodeid * N;
   if (col_in_lds)
@@ -577,7 +789,8 @@ __global__ __launch_bounds__(kBlock) void k_sample(
 
   // ---- row sums (thread owns a contiguous segment of rows)
   __shared__ unsigned need[DSMC_MAX_N / 32];  // rows still to rescue
-  __shared__ unsigned resc[DSMC_MAX_N / 32];  // rescued rows (their chunk sums are not used)
+  __shared__ unsigned resc[DSMC_MAX_N / 32];  // rescued rows: their chunk sums are in Pr
+  __shared__ double csum[DSMC_MAX_N / kChunk];  // chunk sums of the row being rescued
   __shared__ int rescue_list[kBlock];
   __shared__ int n_rescue;
   for (int i = threadIdx.x; i < DSMC_MAX_N / 32; i += kBlock) {
@@ -605,7 +818,7 @@ __global__ __launch_bounds__(kBlock) void k_sample(
           if (kb + i < Nc) Rm += (double)q[i];
       }
     }
-    if ((!(Rm >= Real<R>::kTiny) || isinf(Rm)) && !isnan(Rm)) {
+    if ((!(Rm >= Real<R>::kTiny) || isinf(Rm) || force_rescue) && !isnan(Rm)) {
       atomicOr(&need[m >> 5], 1u << (m & 31));
       atomicOr(&resc[m >> 5], 1u << (m & 31));
       rescued = 1;
@@ -620,6 +833,7 @@ __global__ __launch_bounds__(kBlock) void k_sample(
   // maximum as shift, then the fp64 sum of exp2(s - shift) over a fixed
   // partition of the columns in a fixed reduction order.  Rows are taken in
   // passes of at most kBlock.
+  bool first_pass = true;
   while (rescued) {
     if (threadIdx.x == 0) n_rescue = 0;
     __syncthreads();
@@ -638,6 +852,9 @@ __global__ __launch_bounds__(kBlock) void k_sample(
     __syncthreads();
     const int total = n_rescue;
     const int cnt = min(total, kBlock);
+    if (first_pass && rescue_count && ds == 0 && threadIdx.x == 0)
+      atomicAdd(rescue_count, (unsigned long long)total);
+    first_pass = false;
     for (int i = 0; i < cnt; ++i) {
       const int m = rescue_list[i];
       R v[DX];
@@ -652,21 +869,35 @@ __global__ __launch_bounds__(kBlock) void k_sample(
       }
       smax = block_max(smax, red);
       const R sh = (R)(float)smax;  // the shift is kept as fp32
-      double part = 0.0;
-      if (smax > -INFINITY)
-        for (int j = threadIdx.x; j < N; j += kBlock) {
-          R u[DX];
+      // the row's chunk sums relative to sh, into Pr (thread k owns chunk k;
+      // the same terms in the same order as the draw's chunk recompute; every
+      // workgroup of the combine writes the same values), and their fp64 sum
+      // in chunk order
+      R* Pm = Prn + (size_t)m * NcP;
+      for (int k = threadIdx.x; k < Nc; k += kBlock) {
+        R acc = (R)0;
+        if (smax > -INFINITY) {
+          const R* cp = colp + (size_t)k * kChunk * (DX + 1);
+#pragma unroll 4
+          for (int jj = 0; jj < kChunk; ++jj) {
+            R u[DX];
 #pragma unroll
-          for (int d = 0; d < DX; ++d) u[d] = colp[(size_t)j * (DX + 1) + d];
-          part += (double)Real<R>::exp2(pair_log2w<R, DX>(u, colp[(size_t)j * (DX + 1) + DX], v) - sh);
+            for (int d = 0; d < DX; ++d) u[d] = cp[jj * (DX + 1) + d];
+            acc += Real<R>::exp2(pair_log2w<R, DX>(u, cp[jj * (DX + 1) + DX], v) - sh);
+          }
         }
-      const double tot = block_sum(part, red);
+        Pm[k] = acc;
+        csum[k] = (double)acc;
+      }
+      __syncthreads();
       if (threadIdx.x == 0) {
+        double tot = 0.0;
+        for (int k = 0; k < Nc; ++k) tot += csum[k];
         rs[m] = (smax > -INFINITY) ? tot : 0.0;
         shift[m] = (smax > -INFINITY) ? (float)sh : 0.0f;
       }
+      __syncthreads();
     }
-    __syncthreads();
     if (total <= kBlock) break;
   }
   const double Astar = block_max(amax, red);
@@ -768,24 +999,9 @@ __global__ __launch_bounds__(kBlock) void k_sample(
       const double target2 = u2 * rs[l];
       const float sh = shift[l];
       r = -1;
-      if ((resc[l >> 5] >> (l & 31)) & 1u) {
-        // rescued row: full scan with the row shift
-        double acc = 0.0;
-        int lastj = 0;
-        for (int j = 0; j < N && r < 0; ++j) {
-          R u[DX];
-#pragma unroll
-          for (int i = 0; i < DX; ++i) u[i] = colp[(size_t)j * (DX + 1) + i];
-          const double e = (double)Real<R>::exp2(
-              pair_log2w<R, DX>(u, colp[(size_t)j * (DX + 1) + DX], v) - (R)sh);
-          acc += e;
-          if (e > 0.0) lastj = j;
-          if (target2 < acc) r = j;
-        }
-        if (r < 0) r = lastj;
-      } else {
+      {
         // chunk: first k with prefix_k > target2 (chunk sums read 16 at a time)
-        const R* Pl = Pn + (size_t)l * NcP;
+        const R* Pl = (((resc[l >> 5] >> (l & 31)) & 1u) ? Prn : Pn) + (size_t)l * NcP;
         double pref = 0.0, pref_last = 0.0;
         int k = -1, klast = 0;
         for (int kb = 0; kb < Nc && k < 0; kb += 16) {
@@ -842,17 +1058,10 @@ __global__ __launch_bounds__(kBlock) void k_sample(
     nb.slast[(size_t)nodeid * N + n] = sl;
     if (cons >= 0) {
       if (crole == 1) {  // merged block is the right block of `cons` (boundary ca)
-        double x[DX], u[DX];
-        load_particle<R, DX>(leafX, totalK, N, gA, sf, dx, x);
-        col_coords<DX>(M, ca, x, u);
-        double b = -logN - log_proposal<DX>(M, ca, x);
-        if (M.weighting == 1) b += log_potential<DX>(M, ca, x);
-        put_col<R, DX>(nb, (size_t)cons, Npad, n, u, (b - bmerged[gA]) * kLog2e);
+        const double b = -logN + nb.tgq[(size_t)gA * N + sf];
+        copy_col<R, DX>(nb, (size_t)cons, Npad, n, (size_t)gA, N, sf, (b - bmerged[gA]) * kLog2e);
       } else {  // merged block is the left block of `cons` (boundary cb)
-        double x[DX], v2[DX];
-        load_particle<R, DX>(leafX, totalK, N, gB, sl, dx, x);
-        row_coords<DX>(M, cb, x, v2);
-        put_row<R, DX>(nb, (size_t)cons, Npad, n, v2);
+        copy_row<R, DX>(nb, (size_t)cons, Npad, n, (size_t)gB, N, sl);
         ((R*)nb.alpha)[(size_t)cons * N + n] = (R)(-logN);
       }
     }
@@ -926,7 +1135,8 @@ template <int DX, int MB>
 static void launch_rows_mfma(const LevelLaunch& L, hipStream_t st, unsigned grid, unsigned block) {
   k_rows_mfma<DX, MB><<<grid, block, 0, st>>>(L.nb.colh, L.nb.colb, L.nb.rowh, L.nb.rown,
                                               (float*)L.P, L.Rsum, L.Rshift, L.node_list, L.node0,
-                                              L.N, L.Npad, L.Nc, L.NcP, L.RB, L.CS, L.KC);
+                                              L.N, L.Npad, L.Nc, L.NcP, L.RB, L.CS, L.KC,
+                                              L.force_rescue ? 1 : 0);
 }
 
 template <typename R, int DX>
@@ -948,17 +1158,20 @@ static int launch_rows_t(const LevelLaunch& L, hipStream_t st) {
     case 1:
       k_rows<R, DX, 1><<<grid, block, 0, st>>>((const R*)L.nb.col, (const R*)L.nb.row, (R*)L.P,
                                                L.Rsum, L.Rshift, L.node_list, L.node0, L.N, L.Npad, L.Nc,
-                                               L.NcP, L.RB, L.CS, L.KC);
+                                               L.NcP, L.RB, L.CS, L.KC,
+                                               L.force_rescue ? 1 : 0);
       return 0;
     case 2:
       k_rows<R, DX, 2><<<grid, block, 0, st>>>((const R*)L.nb.col, (const R*)L.nb.row, (R*)L.P,
                                                L.Rsum, L.Rshift, L.node_list, L.node0, L.N, L.Npad, L.Nc,
-                                               L.NcP, L.RB, L.CS, L.KC);
+                                               L.NcP, L.RB, L.CS, L.KC,
+                                               L.force_rescue ? 1 : 0);
       return 0;
     case 4:
       k_rows<R, DX, 4><<<grid, block, 0, st>>>((const R*)L.nb.col, (const R*)L.nb.row, (R*)L.P,
                                                L.Rsum, L.Rshift, L.node_list, L.node0, L.N, L.Npad, L.Nc,
-                                               L.NcP, L.RB, L.CS, L.KC);
+                                               L.NcP, L.RB, L.CS, L.KC,
+                                               L.force_rescue ? 1 : 0);
       return 0;
   }
   return -1;
@@ -975,9 +1188,9 @@ static int launch_level_t(const LevelLaunch& L, hipStream_t st, Timer* tm) {
   if (col_in_lds) lds_samp += lds_col;
   tm->begin(2, st);
   k_sample<R, DX><<<(unsigned)L.nodes * L.DS, kBlock, lds_samp, st>>>(
-      L.d_nodes, L.d_series, L.node_list, L.node0, L.DS, L.totalK, L.N, L.Npad, L.Nc, L.NcP,
-      L.CS == 1 ? 1 : 0,
-      col_in_lds, (const R*)L.leafX, L.bmerged, (const R*)L.P, L.Rsum, L.Rshift, L.nb);
+      L.d_nodes, L.d_series, L.node_list, L.node0, L.DS, L.N, L.Npad, L.Nc, L.NcP,
+      L.CS == 1 ? 1 : 0, col_in_lds, L.force_rescue ? 1 : 0, L.bmerged, (const R*)L.P,
+      (R*)L.Pr, L.Rsum, L.Rshift, L.rescue_count, L.nb);
   tm->end(2, st);
   return 0;
 }

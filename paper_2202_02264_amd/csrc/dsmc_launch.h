@@ -67,8 +67,11 @@ struct LevelLaunch {
   const void* leafX;
   const double* bmerged;
   void* P;
+  void* Pr;             // chunk sums of rescued rows (same layout as P)
   double* Rsum;
   float* Rshift;        // per-row shifts of the row sums (DX >= 8), like Rsum
+  bool force_rescue;    // testing aid: every row takes the rescue path
+  unsigned long long* rescue_count;  // rescued rows are added here when non-null
   NodeBufs nb;
 };
 

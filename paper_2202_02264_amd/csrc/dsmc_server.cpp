@@ -109,6 +109,7 @@ struct Class {
   double* zinc = nullptr;
   NodeBufs nb{};
   void* P = nullptr;
+  void* Pr = nullptr;
   double* Rsum = nullptr;
   float* Rshift = nullptr;
   NodeDesc* d_nodes = nullptr;
@@ -193,7 +194,11 @@ int make_class(dsmc_server_impl* s, int N, int DX, std::unique_ptr<Class>* out) 
       (rc = dalloc(c.get(), &c->nb.bcol, TK * sizeof(double))) ||
       (rc = dalloc(c.get(), &c->nb.sfirst, TK * N * sizeof(int32_t))) ||
       (rc = dalloc(c.get(), &c->nb.slast, TK * N * sizeof(int32_t))) ||
+      (rc = dalloc(c.get(), &c->nb.tcol, TK * N * DX * R)) ||
+      (rc = dalloc(c.get(), &c->nb.tgq, TK * N * sizeof(double))) ||
+      (rc = dalloc(c.get(), &c->nb.trow, TK * N * DX * R)) ||
       (rc = dalloc(c.get(), &c->P, nc * N * c->NcP * R)) ||
+      (rc = dalloc(c.get(), &c->Pr, nc * N * c->NcP * R)) ||
       (rc = dalloc(c.get(), &c->Rsum, nc * N * sizeof(double))) ||
       (rc = dalloc(c.get(), &c->Rshift, nc * N * sizeof(float))) ||
       (rc = dalloc(c.get(), &c->d_nodes, TK * sizeof(NodeDesc))) ||
@@ -353,10 +358,11 @@ int tick(dsmc_server_impl* s, Class* c) {
     L.leafX = c->leafX;
     L.bmerged = c->bmerged;
     L.P = c->P;
+    L.Pr = c->Pr;
     L.Rsum = c->Rsum;
     L.Rshift = c->Rshift;
     L.nb = c->nb;
-    set_tile(L, heuristic_tile(nodes, N, c->Nc));
+    set_tile(L, heuristic_tile(nodes, N, c->Nc, c->DX < 8));
     const int ds_max = std::max(1, (N + 127) / 128);
     L.DS = nodes >= 256 ? 1 : (int)std::min<long>(ds_max, (512 + nodes - 1) / nodes);
     if (launch_level(L, c->stream, &s->no_timer)) return fail(DSMC_EUNSUPPORTED, "no combine kernel");

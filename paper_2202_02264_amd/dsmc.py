@@ -27,6 +27,7 @@ DSMC_FP32, DSMC_FP64, DSMC_BF16 = 0, 1, 2
 DSMC_PLAN_PROFILE = 1
 DSMC_PLAN_AUTOTUNE = 2
 DSMC_PLAN_GRAPH = 4
+DSMC_PLAN_RESCUE_ALL = 8
 DSMC_MAX_DX, DSMC_MAX_N = 32, 4096
 DSMC_NUM_KERNEL_CLASSES = 4
 KERNEL_CLASSES = ("leaves", "rows", "sample", "output")
@@ -67,7 +68,8 @@ DSMC_JOB_QUEUED, DSMC_JOB_RUNNING, DSMC_JOB_DONE, DSMC_JOB_FAILED = 0, 1, 2, 3
 
 class dsmc_profile(C.Structure):
     _fields_ = [("launches", C.c_int * DSMC_NUM_KERNEL_CLASSES),
-                ("ms", C.c_double * DSMC_NUM_KERNEL_CLASSES), ("pairs", C.c_double)]
+                ("ms", C.c_double * DSMC_NUM_KERNEL_CLASSES), ("pairs", C.c_double),
+                ("rescued_rows", C.c_double)]
 
 
 def _load() -> C.CDLL:
@@ -167,7 +169,7 @@ class Plan:
 
     def __init__(self, N: int, d_x: int, max_K: int, max_total_K: int = 0,
                  precision: int = DSMC_FP32, profile: bool = False, autotune: bool = True,
-                 graph: bool = False, stream=None):
+                 graph: bool = False, rescue_all: bool = False, stream=None):
         import torch
         if stream is None:
             stream = torch.cuda.current_stream()
@@ -175,7 +177,7 @@ class Plan:
         d.N, d.d_x, d.max_K, d.max_total_K = N, d_x, max_K, max_total_K
         d.precision = precision
         d.flags = ((DSMC_PLAN_PROFILE if profile else 0) | (DSMC_PLAN_AUTOTUNE if autotune else 0)
-                   | (DSMC_PLAN_GRAPH if graph else 0))
+                   | (DSMC_PLAN_GRAPH if graph else 0) | (DSMC_PLAN_RESCUE_ALL if rescue_all else 0))
         d.stream = C.c_void_p(stream.cuda_stream)
         h = C.c_void_p()
         _check(_lib.dsmc_plan(C.byref(d), C.byref(h)), "dsmc_plan")
@@ -256,7 +258,8 @@ def dsmc_plan_profile(plan: Plan) -> dict:
     p = dsmc_profile()
     _check(_lib.dsmc_plan_profile(plan.handle, C.byref(p)), "dsmc_plan_profile")
     return {"launches": dict(zip(KERNEL_CLASSES, list(p.launches))),
-            "ms": dict(zip(KERNEL_CLASSES, list(p.ms))), "pairs": p.pairs}
+            "ms": dict(zip(KERNEL_CLASSES, list(p.ms))), "pairs": p.pairs,
+            "rescued_rows": p.rescued_rows}
 
 
 def check_status(out: Output) -> int:

@@ -33,14 +33,15 @@ def log(msg: str) -> None:
             f.write(line + "\n")
 
 
-def run_gpu(spec, N: int, seed: int, precision: str = "fp32", plan=None, model=None):
+def run_gpu(spec, N: int, seed: int, precision: str = "fp32", plan=None, model=None,
+            rescue_all: bool = False):
     """dsmc_smooth with every diagnostic output; returns numpy arrays."""
     import torch
     from paper_2202_02264_amd import dsmc as G
     prec = {"fp64": G.DSMC_FP64, "fp32": G.DSMC_FP32, "bf16": G.DSMC_BF16}[precision]
     log(f"gpu dsmc_smooth {spec.name} weighting={spec.weighting} N={N} seed={seed} {precision}")
     model = model or G.Model(spec)
-    plan = plan or G.Plan(N, spec.d_x, spec.K, precision=prec)
+    plan = plan or G.Plan(N, spec.d_x, spec.K, precision=prec, rescue_all=rescue_all)
     out = G.alloc_output(plan, spec.K, diagnostics=True)
     G.dsmc_smooth(plan, model, seed, out)
     torch.cuda.synchronize()

@@ -84,3 +84,16 @@ def test_bf16_precision_workload_sampled():
     er, ez, agree = _errors(spec, 4096, 1, select=lambda a, c, b: c in chosen, leaves=False)
     assert np.median(er) < 0.1 and er.max() < 1.0
     assert ez.max() < 0.5
+
+
+def test_bf16_rescue_paths():
+    """DSMC_PLAN_RESCUE_ALL with bf16: the matrix-core kernel redoes every row
+    with its exact maximum and the sampler recomputes every row; the errors
+    against the oracle stay at the bf16 level."""
+    spec = W.lg_highdim(K=24, seed=34)
+    g = run_gpu(spec, 256, 8, precision="bf16", rescue_all=True)
+    assert g["status"][0] == 0
+    rep = teacher_forced(spec, 256, 8, g, None)
+    er = np.concatenate(rep.abs_err_row)
+    log(f"bf16 rescue-all: |d row_lse| median {np.median(er):.3g} max {er.max():.3g}")
+    assert np.median(er) < 0.1 and er.max() < 1.0

@@ -132,6 +132,29 @@ def test_underflow_rescue_rows(N):
     assert rep.mismatches_outside_band == 0, rep.worst[:5]
 
 
+@pytest.mark.parametrize("case", ["sv_ragged", "lg4d", "lg8d", "lg32d_fp32", "sv_n4096"])
+def test_rescue_path_parity(case):
+    """DSMC_PLAN_RESCUE_ALL sends every row through the path taken by rows whose
+    sum leaves the fp32 range (exact row maximum, chunk sums recomputed into
+    their own buffer, draws through them); results still match the oracle."""
+    build, N = CASES[case]
+    spec = build()
+    seed = 2000 + len(case)
+    g = run_gpu(spec, N, seed, rescue_all=True)
+    assert g["status"][0] == 0
+    rep = teacher_forced(spec, N, seed, g, TOL32)
+    log(f"rescue-all {case}: {rep.summary()}")
+    assert rep.mismatches_outside_band == 0, rep.worst[:5]
+
+
+def test_rescue_path_fp64_end_to_end():
+    spec = W.c1_lg1d()
+    g = run_gpu(spec, 64, 7, precision="fp64", rescue_all=True)
+    ref = D.smooth(spec, 64, 7)
+    np.testing.assert_array_equal(g["ancestry"], ref.ancestry)
+    assert abs(g["log_Z"][0] - ref.logZ) <= TOL64 * max(1.0, abs(ref.logZ))
+
+
 def test_degenerate_leaf_flagged():
     spec = W.lg1d(20, seed=22)
     spec.y = spec.y.copy()
