@@ -99,6 +99,11 @@ __device__ __forceinline__ R pair_log2w(const R* u, R beta, const R* v) {
 }
 
 // ------------------------------------------------------------ model terms
+// Model fields are uniform across a workgroup (one model per time row or
+// combine); readfirstlane tells the compiler so, keeping branches and loop
+// bounds on them scalar.
+__device__ __forceinline__ int uniform(int v) { return __builtin_amdgcn_readfirstlane(v); }
+
 constexpr double kLog2e = 1.4426950408889634;
 constexpr double kLn2 = 0.6931471805599453;
 
@@ -133,12 +138,12 @@ __device__ __forceinline__ double neg_half_quad(const double* Linv, const double
 
 template <int DX>
 __device__ __forceinline__ double log_prior(const DevModel& M, const double (&x)[DX]) {
-  return neg_half_quad<DX>(M.P0_inv, M.m0, x, M.dx) + M.prior_lognorm;
+  return neg_half_quad<DX>(M.P0_inv, M.m0, x, uniform(M.dx)) + M.prior_lognorm;
 }
 
 template <int DX>
 __device__ __forceinline__ double log_proposal(const DevModel& M, int t, const double (&x)[DX]) {
-  const int dx = M.dx;
+  const int dx = uniform(M.dx);
   return neg_half_quad<DX>(M.q_inv + (size_t)t * dx * dx, M.q_mean + (size_t)t * dx, x, dx) +
          M.q_lognorm[t];
 }
@@ -147,11 +152,11 @@ __device__ __forceinline__ double log_proposal(const DevModel& M, int t, const d
 // (H <- R_inv H, y <- R_inv (y - h)), so the quadratic needs no temporaries.
 template <int DX>
 __device__ __forceinline__ double log_potential(const DevModel& M, int t, const double (&x)[DX]) {
-  if (M.obs_kind == 1) {  // stochastic volatility: y ~ N(0, exp(x))
+  if (uniform(M.obs_kind) == 1) {  // stochastic volatility: y ~ N(0, exp(x))
     const double y = M.y[t];
     return -0.9189385332046728 - 0.5 * x[0] - 0.5 * y * y * exp(-x[0]);
   }
-  const int dx = M.dx, dy = M.dy;
+  const int dx = uniform(M.dx), dy = uniform(M.dy);
   const double* yt = M.y + (size_t)t * dy;
   double q = 0.0;
   for (int i = 0; i < dy; ++i) {

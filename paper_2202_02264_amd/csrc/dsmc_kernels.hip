@@ -35,7 +35,7 @@ inline constexpr bool kRowShift = DX >= 8;
 template <int DX>
 __device__ __forceinline__ void col_coords(const DevModel& M, int c, const double (&x)[DX],
                                            double (&u)[DX]) {
-  const int dx = M.dx;
+  const int dx = uniform(M.dx);
   const double* qm = M.q_mean + (size_t)c * dx;
 #pragma unroll
   for (int i = 0; i < DX; ++i) {
@@ -52,7 +52,7 @@ __device__ __forceinline__ void col_coords(const DevModel& M, int c, const doubl
 template <int DX>
 __device__ __forceinline__ void row_coords(const DevModel& M, int c, const double (&x)[DX],
                                            double (&v)[DX]) {
-  const int dx = M.dx;
+  const int dx = uniform(M.dx);
   const double* qm = M.q_mean + (size_t)c * dx;
 #pragma unroll
   for (int i = 0; i < DX; ++i) {
@@ -181,11 +181,13 @@ __device__ __forceinline__ void copy_row(const NodeBufs& nb, size_t node, int Np
 // Table entries for DX >= 8, written coordinate by coordinate (the matrix row
 // loop is not unrolled, so only x stays in registers); same values, order and
 // rounding as col_coords / row_coords followed by put_tcol / put_trow.
+// Wc, Wr: the whitening matrices, woff: kappa Q_inv f, qm: q_mean at the
+// boundary (any address space: the leaf kernel passes copies in LDS).
 template <typename R, int DX, bool kRow>
-__device__ __forceinline__ void stream_table(const NodeBufs& nb, const DevModel& M, int c, size_t g,
+__device__ __forceinline__ void stream_table(const NodeBufs& nb, const double* Wc, const double* Wr,
+                                             const double* woff, const double* qm, int, size_t g,
                                              int N, int n, const double (&x)[DX]) {
-  const int dx = M.dx;
-  const double* qm = M.q_mean + (size_t)c * dx;
+  constexpr int dx = DX;  // zero-padded matrices and vectors
   R* tp = (R*)(kRow ? nb.trow : nb.tcol) + (g * N + n) * DX;
   uint32_t* th = nullptr;
   if constexpr (sizeof(R) == 4 && DX >= 16)
@@ -201,14 +203,14 @@ __device__ __forceinline__ void stream_table(const NodeBufs& nb, const DevModel&
       double acc = 0.0;
       if (ii < dx) {
         if (kRow) {
-          acc = M.wcol_off[ii];
+          acc = woff[ii];
 #pragma unroll
           for (int j = 0; j < DX; ++j)
-            if (j < dx) acc += M.Wrow[ii * dx + j] * x[j] - M.Wcol[ii * dx + j] * qm[j];
+            if (j < dx) acc += Wr[ii * dx + j] * x[j] - Wc[ii * dx + j] * qm[j];
         } else {
 #pragma unroll
           for (int j = 0; j < DX; ++j)
-            if (j < dx) acc += M.Wcol[ii * dx + j] * (x[j] - qm[j]);
+            if (j < dx) acc += Wc[ii * dx + j] * (x[j] - qm[j]);
         }
       }
       s2[k] = acc;
@@ -250,25 +252,71 @@ __device__ __forceinline__ void put_col_pad(const NodeBufs& nb, size_t node, int
 // ================================================================ leaves
 // One workgroup per time row g of the packed time axis.
 template <typename R, int DX>
-__global__ __launch_bounds__(kBlock) void k_leaves(
+__global__ __launch_bounds__(kBlock, 3) void k_leaves(
     const SeriesDesc* __restrict__ series, const int32_t* __restrict__ series_of_t,
     const int32_t* __restrict__ leaf_cons, const NodeDesc* __restrict__ nodes, int row0,
     int totalK, int N, int Npad, R* __restrict__ leafX, R* __restrict__ leafW,
     double* __restrict__ leafL, double* __restrict__ bmerged, NodeBufs nb) {
   extern __shared__ double sh[];
-  double* ell = sh;      // [N] unnormalised leaf log-weights
-  double* gq = sh + N;   // [N] -log q_t(x) (+ log h_t(x) under boundary weighting)
-  __shared__ double red[kBlock / 64];
-  __shared__ int redi[kBlock / 64];
   const int g = row0 + blockIdx.x;
   const SeriesDesc& sd = series[series_of_t[g]];
   const DevModel& M = *sd.model;
-  const int t = g - sd.base;
-  const int dx = M.dx;
+  const int t = uniform(g - sd.base);
+  const int dx = uniform(M.dx);
+  const int K = uniform(sd.K);
+  const int weighting = uniform(M.weighting);
+  // LDS: ell [N]; gq [N] (DX >= 8: gq lives in its table in global memory and
+  // LDS holds this time's matrices instead)
+  double* ell = sh;  // unnormalised leaf log-weights
+  double* gq = (DX >= 8) ? nb.tgq + (size_t)g * N : sh + N;  // -log q_t (+ log h_t, boundary weighting)
+  __shared__ double red[kBlock / 64];
+  __shared__ int redi[kBlock / 64];
   const double logN = log((double)N);
   int bad = 0;
   const double* qm = M.q_mean + (size_t)t * dx;
   const double* qc = M.q_chol + (size_t)t * dx * dx;
+  const double* qi = M.q_inv + (size_t)t * dx * dx;
+  const double* Wc = M.Wcol;
+  const double* Wr = M.Wrow;
+  const double* qm1 = (t + 1 < K) ? qm + dx : qm;  // q_mean[t + 1]
+  // DX >= 8: this time's matrices and vectors in LDS, zero-padded to DX x DX
+  // (triangular factors with zero upper triangles), so the particle loops
+  // below run without per-element bounds checks; the extra terms are exact
+  // zeros and leave every sum unchanged.
+  const bool lds_obs = uniform(M.obs_kind) == 0 && uniform(M.dy) <= DX;
+  double *Lc = nullptr, *Li = nullptr, *Hl = nullptr, *vy = nullptr, *vw = nullptr;
+  if constexpr (DX >= 8) {
+    const int dy = uniform(M.dy);
+    Lc = sh + N;
+    Li = Lc + DX * DX;
+    double* Wcl = Li + DX * DX;
+    double* Wrl = Wcl + DX * DX;
+    Hl = Wrl + DX * DX;
+    double* vq = Hl + DX * DX;
+    double* vq1 = vq + DX;
+    vw = vq1 + DX;
+    vy = vw + DX;
+    for (int e = threadIdx.x; e < DX * DX; e += kBlock) {
+      const int i = e / DX, j = e - (e / DX) * DX;
+      const bool in = i < dx && j < dx;
+      Lc[e] = (in && j <= i) ? qc[i * dx + j] : 0.0;
+      Li[e] = (in && j <= i) ? qi[i * dx + j] : 0.0;
+      Wcl[e] = in ? Wc[i * dx + j] : 0.0;
+      Wrl[e] = in ? Wr[i * dx + j] : 0.0;
+      Hl[e] = (lds_obs && i < dy && j < dx) ? M.H[i * dx + j] : 0.0;
+    }
+    for (int i = threadIdx.x; i < DX; i += kBlock) {
+      vq[i] = i < dx ? qm[i] : 0.0;
+      vq1[i] = i < dx ? qm1[i] : 0.0;
+      vw[i] = i < dx ? M.wcol_off[i] : 0.0;
+      vy[i] = (lds_obs && i < dy) ? M.y[(size_t)t * dy + i] : 0.0;
+    }
+    __syncthreads();
+    Wc = Wcl;
+    Wr = Wrl;
+    qm = vq;
+    qm1 = vq1;
+  }
   for (int n = threadIdx.x; n < N; n += kBlock) {
     // standard normals, four per Philox block, then x = q_mean + L z in place
     // from the last coordinate down (x_i needs z_0 .. z_i)
@@ -278,7 +326,7 @@ __global__ __launch_bounds__(kBlock) void k_leaves(
       // x_i it enters: the same terms in the same order as below, without
       // holding all the normals
 #pragma unroll
-      for (int i = 0; i < DX; ++i) x[i] = (i < dx) ? qm[i] : 0.0;
+      for (int i = 0; i < DX; ++i) x[i] = qm[i];
 #pragma unroll 1
       for (int j = 0; j < (DX + 3) / 4; ++j) {
         const Words4 w = philox4x64_10((uint64_t)n, (uint64_t)t, kPurposeLeaf, (uint64_t)j,
@@ -288,20 +336,15 @@ __global__ __launch_bounds__(kBlock) void k_leaves(
         box_muller(w.w2, w.w3, z[2], z[3]);
 #pragma unroll
         for (int i = 0; i < DX; ++i) {
-          if (i < dx) {
 #pragma unroll
-            for (int k = 0; k < 4; ++k)
-              if (4 * j + k <= i) x[i] += qc[i * dx + 4 * j + k] * z[k];
-          }
+          for (int k = 0; k < 4; ++k) x[i] += Lc[i * DX + 4 * j + k] * z[k];
         }
       }
 #pragma unroll
       for (int i = 0; i < DX; ++i) {
-        if (i < dx) {
-          const R xr = (R)x[i];
-          leafX[((size_t)i * totalK + g) * N + n] = xr;
-          x[i] = (double)xr;  // weights are those of the stored particle
-        }
+        const R xr = (R)x[i];
+        if (i < dx) leafX[((size_t)i * totalK + g) * N + n] = xr;
+        x[i] = (double)xr;  // weights are those of the stored particle (0 past dx)
       }
     } else {
 #pragma unroll
@@ -330,16 +373,44 @@ __global__ __launch_bounds__(kBlock) void k_leaves(
         x[i] = xi;
       }
     }
-    const double lq = log_proposal<DX>(M, t, x);
+    double lq, lh;  // log q_t(x), log h_t(x)
+    if constexpr (DX >= 8) {
+      double q = 0.0;
+#pragma unroll 1
+      for (int i = 0; i < DX; ++i) {
+        double zi = 0.0;
+#pragma unroll
+        for (int j = 0; j < DX; ++j) zi += Li[i * DX + j] * (x[j] - qm[j]);
+        q += zi * zi;
+      }
+      lq = -0.5 * q + M.q_lognorm[t];
+      if (lds_obs) {
+        double qh = 0.0;
+        const int dy = uniform(M.dy);
+#pragma unroll 1
+        for (int i = 0; i < dy; ++i) {
+          double r = vy[i];
+#pragma unroll
+          for (int k = 0; k < DX; ++k) r -= Hl[i * DX + k] * x[k];
+          qh += r * r;
+        }
+        lh = -0.5 * qh + M.obs_lognorm;
+      } else {
+        lh = log_potential<DX>(M, t, x);
+      }
+    } else {
+      lq = log_proposal<DX>(M, t, x);
+      lh = log_potential<DX>(M, t, x);
+    }
     double l, gg = -lq;
     if (t == 0) {
-      l = log_potential<DX>(M, 0, x) + log_prior<DX>(M, x) - lq;
-      if (M.weighting == 1) gg += log_potential<DX>(M, 0, x);
-    } else if (M.weighting == 0) {
-      l = log_potential<DX>(M, t, x);
+      l = lh + log_prior<DX>(M, x) - lq;
+      if (weighting == 1) gg += lh;
+    } else if (weighting == 0) {
+      l = lh;
     } else {
       l = 0.0;
-      gg += log_potential<DX>(M, t, x);
+      gg += lh;
     }
     if (isnan(l) || isnan(gg)) bad = kFlagNumeric;
     ell[n] = l;
@@ -384,10 +455,10 @@ __global__ __launch_bounds__(kBlock) void k_leaves(
   for (int n = threadIdx.x; n < N; n += kBlock) {
     double x[DX];
     load_particle<R, DX>(leafX, totalK, N, g, n, dx, x);
-    nb.tgq[(size_t)g * N + n] = gq[n];
+    if constexpr (DX < 8) nb.tgq[(size_t)g * N + n] = gq[n];
     if (t >= 1) {
       if constexpr (DX >= 8) {
-        stream_table<R, DX, false>(nb, M, t, (size_t)g, N, n, x);
+        stream_table<R, DX, false>(nb, Wc, Wr, vw, qm, DX, (size_t)g, N, n, x);
       } else {
         double u[DX];
         col_coords<DX>(M, t, x, u);
@@ -398,9 +469,9 @@ __global__ __launch_bounds__(kBlock) void k_leaves(
         copy_col<R, DX>(nb, (size_t)P, Npad, n, (size_t)g, N, n, beta);
       }
     }
-    if (t + 1 < sd.K) {
+    if (t + 1 < K) {
       if constexpr (DX >= 8) {
-        stream_table<R, DX, true>(nb, M, t + 1, (size_t)g, N, n, x);
+        stream_table<R, DX, true>(nb, Wc, Wr, vw, qm1, DX, (size_t)g, N, n, x);
       } else {
         double v[DX];
         row_coords<DX>(M, t + 1, x, v);
@@ -1238,7 +1309,8 @@ int launch_rows_only(const LevelLaunch& L, hipStream_t st) {
 template <typename R, int DX>
 static void launch_leaves_t(const LeafLaunch& L, hipStream_t st, Timer* tm) {
   tm->begin(0, st);
-  k_leaves<R, DX><<<L.rows, kBlock, 2 * (size_t)L.N * sizeof(double), st>>>(
+  const size_t lds = (DX >= 8 ? (size_t)L.N + 5 * DX * DX + 4 * DX : 2 * (size_t)L.N) * sizeof(double);
+  k_leaves<R, DX><<<L.rows, kBlock, lds, st>>>(
       L.d_series, L.d_series_of_t, L.d_leaf_cons, L.d_nodes, L.row0, L.totalK, L.N, L.Npad,
       (R*)L.leafX, (R*)L.leafW, L.leafL, L.bmerged, L.nb);
   tm->end(0, st);
