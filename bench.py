@@ -42,7 +42,7 @@ BF16_MFMA_PEAK = 2.5e15
 # N = 1024), averaged over the 12 levels: rocprofv3 FETCH_SIZE / WRITE_SIZE,
 # each scaled by the same counter's reading for a 256 MiB device copy (see
 # profiles/k_rows_sv_K4096_N1024.md).  Reset to None when k_rows changes.
-K_ROWS_SV_TRAFFIC_MIB = {"read": 17.83, "write": 88.59}
+K_ROWS_SV_TRAFFIC_MIB = {"read": 16.73, "write": 87.40}
 
 
 def parse():
