@@ -63,7 +63,7 @@ def parse():
     ap.add_argument("--jobs", type=int, default=600, help="serving: jobs per arrival run")
     ap.add_argument("--rates", type=str, default="0.25,0.5,0.75,0.9,1.1",
                     help="serving: Poisson arrival rates as fractions of the saturated rate")
-    ap.add_argument("--serve-mem-gib", type=int, default=72)
+    ap.add_argument("--serve-mem-gib", type=int, default=192)
     ap.add_argument("--copy-calibration", action="store_true",
                     help="only run 10 device copies of 256 MiB (HBM counter calibration)")
     return ap.parse_args()

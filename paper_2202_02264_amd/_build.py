@@ -16,9 +16,13 @@ HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
 SOURCES = ["dsmc_kernels.hip", "dsmc_api.cpp", "dsmc_server.cpp"]
 
 # Packed-fp32 instructions are disabled for all device code (the compiler
-# would otherwise form v_pk_* from plain float arithmetic).
+# would otherwise form v_pk_* from plain float arithmetic).  Matrix-core
+# accumulators stay in ordinary VGPRs (gfx950 has one register file): the
+# default heuristic put them in AGPRs and paid a v_accvgpr_write and a
+# v_accvgpr_read per accumulator element, two extra VALU slots per pair.
 FLAGS = ["-O3", "-std=c++17", "-fPIC", "--offload-arch=gfx950",
          "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops",
+         "-mllvm", "-amdgpu-mfma-vgpr-form",
          "-Wall", "-Wno-unused-function", "-Wno-unused-result", "-Wno-unused-value",
          "-I", INCLUDE, "-I", CSRC]
 
