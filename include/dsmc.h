@@ -64,7 +64,8 @@ typedef enum dsmc_status {
   DSMC_EDEGENERATE = -5,  /* a combine had zero total weight */
   DSMC_ENUMERIC = -6,     /* a weight was NaN */
   DSMC_EDEVICE = -8,      /* HIP runtime error */
-  DSMC_ECANCELLED = -9    /* server shut down before the job ran */
+  DSMC_ECANCELLED = -9,   /* job cancelled, or server shut down, before the job ran */
+  DSMC_EDEADLINE = -10    /* serving: the job was still queued at its admission deadline */
 } dsmc_status;
 
 /* Bits written to dsmc_output.status by the device (0 = clean run). */
@@ -236,6 +237,9 @@ typedef struct dsmc_job {
   int N;          /* particles, 1..DSMC_MAX_N */
   uint64_t seed;
   dsmc_output out;
+  double admit_deadline; /* seconds after submission by which the job must have been
+                            admitted (placed on the GPU), else it fails with
+                            DSMC_EDEADLINE; 0 = none */
 } dsmc_job;
 
 enum { DSMC_JOB_QUEUED = 0, DSMC_JOB_RUNNING = 1, DSMC_JOB_DONE = 2, DSMC_JOB_FAILED = 3 };
@@ -249,9 +253,16 @@ void dsmc_server_destroy(dsmc_server_t *server);
 /* Queue a job (its descriptor is copied).  Errors (job not created):
  * DSMC_EINVAL (bad arguments), DSMC_EUNSUPPORTED (N or d_x out of range). */
 int dsmc_submit(dsmc_server_t *server, const dsmc_job *job, uint64_t *job_id);
+/* Cancel a queued job: it becomes FAILED (DSMC_ECANCELLED) and its outputs
+ * are not written.  Returns DSMC_OK, DSMC_EAGAIN if the job is already
+ * running or finished (it completes normally), DSMC_EINVAL for an unknown id.
+ * The cancellation takes effect at the scheduler's next step: poll for the
+ * final state. */
+int dsmc_cancel(dsmc_server_t *server, uint64_t job_id);
 /* State of a job: returns DSMC_OK when DONE (outputs complete on the device),
  * DSMC_EAGAIN while QUEUED or RUNNING, the job's error code when FAILED
- * (DSMC_ENOMEM: it can never fit the class pool; DSMC_ECANCELLED).  `state`
+ * (DSMC_ENOMEM: it can never fit the class pool; DSMC_ECANCELLED;
+ * DSMC_EDEADLINE).  `state`
  * may be NULL.  DSMC_EINVAL for an unknown id. */
 int dsmc_poll(dsmc_server_t *server, uint64_t job_id, int *state);
 /* Host steady-clock times in seconds of a job's submission, admission and
@@ -273,6 +284,14 @@ typedef struct dsmc_profile {
                           their exact maximum as shift (counted once per combine) */
 } dsmc_profile;
 int dsmc_plan_profile(dsmc_plan_t *plan, dsmc_profile *out);
+
+/* The combine tree the library runs for a series of K points (Algorithm 5:
+ * at level l, adjacent blocks 2k and 2k+1 of the previous level are combined;
+ * a trailing block without a right neighbour passes through).  Host only, no
+ * device work.  Writes K - 1 combines, ordered by level, as left block
+ * [a, c), right block [c, b) and level; cap is the length of the four
+ * caller-owned arrays.  Returns the number of combines, or DSMC_EINVAL. */
+int dsmc_schedule(int K, int cap, int32_t *a, int32_t *c, int32_t *b, int32_t *level);
 
 /* Message describing the last error on this thread ("" if none). */
 const char *dsmc_last_error(void);

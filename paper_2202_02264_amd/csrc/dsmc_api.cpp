@@ -816,6 +816,27 @@ static int enqueue_batch(dsmc_plan_t* p, int B, int totalK, hipStream_t st) {
   return DSMC_OK;
 }
 
+extern "C" int dsmc_schedule(int K, int cap, int32_t* a, int32_t* c, int32_t* b, int32_t* level) {
+  if (K < 1) return fail(DSMC_EINVAL, "K must be >= 1");
+  if (K - 1 > cap) return fail(DSMC_EINVAL, "cap %d < K - 1 = %d", cap, K - 1);
+  if (K > 1 && (!a || !c || !b || !level)) return fail(DSMC_EINVAL, "null output");
+  std::vector<NodeDesc> nodes;
+  std::vector<int> lvl_off, lvl_cnt;
+  std::vector<int32_t> leaf_cons;
+  int root = -1;
+  build_series_schedule(K, 0, 0, nodes, lvl_off, lvl_cnt, leaf_cons, &root);
+  for (size_t l = 0; l < lvl_cnt.size(); ++l)
+    for (int i = 0; i < lvl_cnt[l]; ++i) {
+      const NodeDesc& nd = nodes[lvl_off[l] + i];
+      const int id = lvl_off[l] + i;
+      a[id] = nd.a;
+      c[id] = nd.c;
+      b[id] = nd.b;
+      level[id] = (int32_t)l;
+    }
+  return (int)nodes.size();
+}
+
 extern "C" int dsmc_smooth(dsmc_plan_t* p, const dsmc_model_t* model, uint64_t seed,
                            const dsmc_output* out) {
   const dsmc_model_t* ms[1] = {model};

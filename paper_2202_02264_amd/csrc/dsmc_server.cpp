@@ -29,6 +29,7 @@
 #include "dsmc_host.h"
 #include "dsmc_internal.h"
 #include "dsmc_launch.h"
+#include "dsmc_range_alloc.h"
 
 using namespace dsmc;
 
@@ -38,51 +39,13 @@ double now_s() {
   return std::chrono::duration<double>(std::chrono::steady_clock::now().time_since_epoch()).count();
 }
 
-// First-fit allocator of integer ranges in [0, cap).
-class RangeAlloc {
- public:
-  void reset(int cap) {
-    free_.clear();
-    if (cap > 0) free_[0] = cap;
-  }
-  int alloc(int len) {
-    for (auto it = free_.begin(); it != free_.end(); ++it) {
-      if (it->second >= len) {
-        const int start = it->first, rem = it->second - len;
-        free_.erase(it);
-        if (rem) free_[start + len] = rem;
-        return start;
-      }
-    }
-    return -1;
-  }
-  void release(int start, int len) {
-    if (len <= 0) return;
-    auto it = free_.emplace(start, len).first;
-    auto nx = std::next(it);
-    if (nx != free_.end() && it->first + it->second == nx->first) {
-      it->second += nx->second;
-      free_.erase(nx);
-    }
-    if (it != free_.begin()) {
-      auto pv = std::prev(it);
-      if (pv->first + pv->second == it->first) {
-        pv->second += it->second;
-        free_.erase(it);
-      }
-    }
-  }
-
- private:
-  std::map<int, int> free_;
-};
-
 struct Job {
   uint64_t id = 0;
   dsmc_job job{};
   int K = 0, dx = 0;
   int state = DSMC_JOB_QUEUED;
   int code = DSMC_EAGAIN;
+  bool cancel = false;  // set by dsmc_cancel (under the server mutex)
   double t_submit = 0, t_start = 0, t_done = 0;
   int row0 = -1, node0 = -1, slot = -1;
   std::vector<int> lvl_off, lvl_cnt;
@@ -413,6 +376,26 @@ bool service_class(dsmc_server_impl* s, Class* c, bool admitting) {
       ++i;
     }
   }
+  // cancelled jobs and missed admission deadlines leave the queue
+  {
+    const double now = now_s();
+    for (size_t i = 0; i < c->queue.size();) {
+      Job* j = c->queue[i];
+      bool cancelled;
+      {
+        std::lock_guard<std::mutex> lk(s->mu);
+        cancelled = j->cancel;
+      }
+      const bool late = j->job.admit_deadline > 0 && now > j->t_submit + j->job.admit_deadline;
+      if (cancelled || late) {
+        c->queue.erase(c->queue.begin() + i);
+        set_state(s, j, DSMC_JOB_FAILED, cancelled ? DSMC_ECANCELLED : DSMC_EDEADLINE);
+        did = true;
+      } else {
+        ++i;
+      }
+    }
+  }
   // admissions (arrival order, first fit)
   if (admitting) {
     for (size_t i = 0; i < c->queue.size();) {
@@ -537,6 +520,7 @@ extern "C" int dsmc_submit(dsmc_server_t* s, const dsmc_job* job, uint64_t* job_
   if (!s || !job || !job_id) return fail(DSMC_EINVAL, "null argument");
   if (!job->model) return fail(DSMC_EINVAL, "null model");
   if (job->N < 1 || job->N > DSMC_MAX_N) return fail(DSMC_EUNSUPPORTED, "N must be in 1..%d", DSMC_MAX_N);
+  if (!(job->admit_deadline >= 0.0)) return fail(DSMC_EINVAL, "admit_deadline must be >= 0");
   int rc = check_output(&job->out);
   if (rc) return rc;
   auto j = std::make_unique<Job>();
@@ -550,6 +534,18 @@ extern "C" int dsmc_submit(dsmc_server_t* s, const dsmc_job* job, uint64_t* job_
   *job_id = j->id;
   s->incoming.push_back(j.get());
   s->jobs.emplace(j->id, std::move(j));
+  s->cv.notify_all();
+  return DSMC_OK;
+}
+
+extern "C" int dsmc_cancel(dsmc_server_t* s, uint64_t job_id) {
+  if (!s) return fail(DSMC_EINVAL, "null server");
+  std::lock_guard<std::mutex> lk(s->mu);
+  auto it = s->jobs.find(job_id);
+  if (it == s->jobs.end()) return fail(DSMC_EINVAL, "unknown job %llu", (unsigned long long)job_id);
+  Job* j = it->second.get();
+  if (j->state != DSMC_JOB_QUEUED) return DSMC_EAGAIN;
+  j->cancel = true;
   s->cv.notify_all();
   return DSMC_OK;
 }

@@ -20,6 +20,7 @@ LIB_PATH = os.path.join(_PKG, "libdsmc.so")
 
 DSMC_OK, DSMC_EINVAL, DSMC_ENOMEM, DSMC_EUNSUPPORTED = 0, -1, -2, -3
 DSMC_EAGAIN, DSMC_EDEGENERATE, DSMC_ENUMERIC, DSMC_EDEVICE, DSMC_ECANCELLED = -4, -5, -6, -8, -9
+DSMC_EDEADLINE = -10
 DSMC_FLAG_DEGENERATE, DSMC_FLAG_NUMERIC = 1, 2
 DSMC_OBS_LINEAR_GAUSSIAN, DSMC_OBS_STOCH_VOL = 0, 1
 DSMC_WEIGHT_LEAF_OBS, DSMC_WEIGHT_BOUNDARY_OBS = 0, 1
@@ -60,7 +61,8 @@ class dsmc_server_desc(C.Structure):
 
 
 class dsmc_job(C.Structure):
-    _fields_ = [("model", C.c_void_p), ("N", C.c_int), ("seed", C.c_uint64), ("out", dsmc_output)]
+    _fields_ = [("model", C.c_void_p), ("N", C.c_int), ("seed", C.c_uint64), ("out", dsmc_output),
+                ("admit_deadline", C.c_double)]
 
 
 DSMC_JOB_QUEUED, DSMC_JOB_RUNNING, DSMC_JOB_DONE, DSMC_JOB_FAILED = 0, 1, 2, 3
@@ -90,8 +92,11 @@ def _load() -> C.CDLL:
         "dsmc_server_destroy": (None, [vp]),
         "dsmc_submit": (i, [vp, C.POINTER(dsmc_job), C.POINTER(u64)]),
         "dsmc_poll": (i, [vp, u64, C.POINTER(i)]),
+        "dsmc_cancel": (i, [vp, u64]),
         "dsmc_job_times": (i, [vp, u64, C.POINTER(C.c_double), C.POINTER(C.c_double),
                                C.POINTER(C.c_double)]),
+        "dsmc_schedule": (i, [i, i, C.POINTER(C.c_int32), C.POINTER(C.c_int32),
+                              C.POINTER(C.c_int32), C.POINTER(C.c_int32)]),
         "dsmc_last_error": (C.c_char_p, []),
     }
     for name, (res, args) in sig.items():
@@ -321,16 +326,26 @@ def alloc_job_output(N: int, d_x: int, K: int, fp64: bool = False, diagnostics: 
     return alloc_output(p, K, diagnostics)
 
 
-def dsmc_submit(server: Server, model: Model, N: int, seed: int, out: Output) -> int:
+def dsmc_submit(server: Server, model: Model, N: int, seed: int, out: Output,
+                admit_deadline: float = 0.0) -> int:
     j = dsmc_job()
     j.model = model.handle.value
     j.N = N
     j.seed = seed & (2**64 - 1)
     j.out = out.c_struct()
+    j.admit_deadline = admit_deadline
     jid = C.c_uint64()
     _check(_lib.dsmc_submit(server.handle, C.byref(j), C.byref(jid)), "dsmc_submit")
     server._keep[jid.value] = (model, out)
     return jid.value
+
+
+def dsmc_cancel(server: Server, job_id: int) -> int:
+    """DSMC_OK if the queued job will be cancelled, DSMC_EAGAIN if it already runs."""
+    rc = _lib.dsmc_cancel(server.handle, C.c_uint64(job_id))
+    if rc not in (DSMC_OK, DSMC_EAGAIN):
+        _check(rc, "dsmc_cancel")
+    return rc
 
 
 def dsmc_poll(server: Server, job_id: int):
@@ -347,3 +362,19 @@ def dsmc_job_times(server: Server, job_id: int):
     _check(_lib.dsmc_job_times(server.handle, C.c_uint64(job_id), C.byref(a), C.byref(b),
                                C.byref(c)), "dsmc_job_times")
     return a.value, b.value, c.value
+
+
+def dsmc_schedule(K: int):
+    """Algorithm 5's combines for K points as the library runs them: a list of
+    levels, each a list of (a, c, b)."""
+    n = max(K - 1, 1)
+    arrs = [np.zeros(n, dtype=np.int32) for _ in range(4)]
+    ptrs = [x.ctypes.data_as(C.POINTER(C.c_int32)) for x in arrs]
+    cnt = _lib.dsmc_schedule(K, n, *ptrs)
+    if cnt < 0:
+        _check(cnt, "dsmc_schedule")
+    a, c, b, lv = (x[:cnt] for x in arrs)
+    levels = [[] for _ in range(int(lv.max()) + 1)] if cnt else []
+    for i in range(cnt):
+        levels[lv[i]].append((int(a[i]), int(c[i]), int(b[i])))
+    return levels

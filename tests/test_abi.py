@@ -21,7 +21,8 @@ def _declared_functions():
 def test_header_declares_the_entry_points():
     names = _declared_functions()
     for n in ("dsmc_plan", "dsmc_smooth", "dsmc_smooth_batch", "dsmc_model_create",
-              "dsmc_server_create", "dsmc_submit", "dsmc_poll", "dsmc_last_error"):
+              "dsmc_server_create", "dsmc_submit", "dsmc_poll", "dsmc_cancel",
+              "dsmc_schedule", "dsmc_last_error"):
         assert n in names
 
 
@@ -107,4 +108,5 @@ def test_invalid_arguments_rejected_on_host():
     job = dsmc.dsmc_job()
     assert lib.dsmc_submit(None, C.byref(job), C.byref(jid)) == dsmc.DSMC_EINVAL
     assert lib.dsmc_poll(None, 1, None) == dsmc.DSMC_EINVAL
+    assert lib.dsmc_cancel(None, 1) == dsmc.DSMC_EINVAL
     assert lib.dsmc_job_times(None, 1, None, None, None) == dsmc.DSMC_EINVAL

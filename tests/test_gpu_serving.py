@@ -79,3 +79,35 @@ def test_job_too_large_fails_cleanly():
     codes = _wait(G, srv, [jid2], timeout=30)
     assert codes[jid2] == 0
     srv.close()
+
+
+def test_cancel_and_admission_deadline():
+    """One series slot per class: a long job occupies it, so jobs behind it stay
+    queued.  A cancelled one fails with DSMC_ECANCELLED, one with a 1 ms
+    admission deadline fails with DSMC_EDEADLINE, an unconstrained one runs
+    after the first and equals dsmc_smooth alone; cancelling a running or
+    finished job is refused with DSMC_EAGAIN."""
+    from paper_2202_02264_amd import dsmc as G
+    srv = G.Server(mem_budget=16 << 30, max_jobs=1, max_classes=2)
+    big = W.sv(8192, seed=1)
+    small = W.sv(50, seed=2)
+    mb, ms = G.Model(big), G.Model(small)
+    ob = G.alloc_job_output(4096, 1, big.K)
+    oc = G.alloc_job_output(4096, 1, small.K)
+    od = G.alloc_job_output(4096, 1, small.K)
+    oe = G.alloc_job_output(4096, 1, small.K, diagnostics=True)
+    log("serving: cancel / deadline")
+    jb = G.dsmc_submit(srv, mb, 4096, 1, ob)
+    jc = G.dsmc_submit(srv, ms, 4096, 2, oc)
+    jd = G.dsmc_submit(srv, ms, 4096, 3, od, admit_deadline=0.001)
+    je = G.dsmc_submit(srv, ms, 4096, 4, oe)
+    assert G.dsmc_cancel(srv, jc) == G.DSMC_OK
+    codes = _wait(G, srv, [jb, jc, jd, je])
+    assert codes[jb] == 0
+    assert codes[jc] == G.DSMC_ECANCELLED
+    assert codes[jd] == G.DSMC_EDEADLINE
+    assert codes[je] == 0
+    assert G.dsmc_cancel(srv, je) == G.DSMC_EAGAIN
+    single = run_gpu(small, 4096, 4, model=ms)
+    np.testing.assert_array_equal(oe.traj.cpu().numpy(), single["traj"])
+    srv.close()
