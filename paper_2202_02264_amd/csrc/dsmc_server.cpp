@@ -137,7 +137,7 @@ int make_class(dsmc_server_impl* s, int N, int DX, std::unique_ptr<Class>* out) 
   c->NcP = (c->Nc + 3) / 4 * 4;
   const size_t budget = s->d.mem_budget / (size_t)s->d.max_classes;
   const PoolSizes ps = pool_sizes(N, DX, DX, c->rsz);
-  const size_t p_budget = std::min<size_t>(budget / 4, (size_t)512 << 20);
+  const size_t p_budget = std::min<size_t>(budget / 4, (size_t)2 << 30);  // chunk sums + rescued copies
   c->node_cap = (int)std::max<size_t>(1, p_budget / ps.per_node);
   const size_t rest = budget > c->node_cap * ps.per_node ? budget - c->node_cap * ps.per_node : 0;
   c->rows_cap = (int)std::min<size_t>(rest / ps.per_row, (size_t)1 << 30);
