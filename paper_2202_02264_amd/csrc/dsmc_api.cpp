@@ -524,9 +524,12 @@ void dsmc::set_tile(LevelLaunch& L, TileChoice tc) {
 }
 
 // Time every (rows per lane, waves per workgroup) candidate, each with the
-// column splits that fill the chip, on this launch's real inputs (the rows
-// kernel only writes its own outputs) and keep the fastest.  The tile does
-// not change any result.
+// column splits that fill the chip, on this launch's real inputs, and keep
+// the fastest.  A trial runs the whole level (pair rows and sampling): with
+// column splits the rows kernel leaves the row sums to every sampling
+// workgroup, which can cost more than the splits save.  Re-running a level
+// rewrites the same values (its kernels never modify their own inputs), and
+// the tile does not change any result.
 static TileChoice autotune_tile(dsmc_plan_t* p, LevelLaunch L) {
   const bool split_ok = L.DX < 8;
   TileChoice best = heuristic_tile(L.nodes, L.N, L.Nc, split_ok);
@@ -549,8 +552,9 @@ static TileChoice autotune_tile(dsmc_plan_t* p, LevelLaunch L) {
       set_tile(L, tc);
       float ms = 0.0f;
       bool ok = true;
+      Timer untimed;
       for (int rep = 0; rep < 2 && ok; ++rep) {
-        ok = hipEventRecord(e0, p->stream) == hipSuccess && launch_rows_only(L, p->stream) == 0 &&
+        ok = hipEventRecord(e0, p->stream) == hipSuccess && launch_level(L, p->stream, &untimed) == 0 &&
              hipEventRecord(e1, p->stream) == hipSuccess && hipEventSynchronize(e1) == hipSuccess &&
              hipEventElapsedTime(&ms, e0, e1) == hipSuccess;
       }
@@ -795,6 +799,9 @@ static int enqueue_batch(dsmc_plan_t* p, int B, int totalK, hipStream_t st) {
       L.force_rescue = (p->d.flags & DSMC_PLAN_RESCUE_ALL) != 0;
       L.rescue_count = p->d_rescued;
       L.nb = p->nb;
+      // sampling: enough workgroups to cover the chip when a level has few combines
+      const int ds_max = std::max(1, (N + 127) / 128);
+      L.DS = nodes >= 256 ? 1 : (int)std::min<long>(ds_max, (512 + nodes - 1) / nodes);
       auto it = p->tiles.find(nodes);
       TileChoice tc;
       if (it != p->tiles.end()) {
@@ -804,9 +811,6 @@ static int enqueue_batch(dsmc_plan_t* p, int B, int totalK, hipStream_t st) {
         p->tiles[nodes] = tc;
       }
       set_tile(L, tc);
-      // sampling: enough workgroups to cover the chip when a level has few combines
-      const int ds_max = std::max(1, (N + 127) / 128);
-      L.DS = nodes >= 256 ? 1 : (int)std::min<long>(ds_max, (512 + nodes - 1) / nodes);
       if (launch_level(L, st, &p->timer)) return fail(DSMC_EUNSUPPORTED, "no combine kernel for d_x");
       HIP_TRY(hipGetLastError());
     }

@@ -1283,29 +1283,6 @@ int launch_level(const LevelLaunch& L, hipStream_t st, Timer* tm) {
   return L.fp64 ? launch_level_r<double>(L, st, tm) : launch_level_r<float>(L, st, tm);
 }
 
-int launch_rows_only(const LevelLaunch& L, hipStream_t st) {
-  if (L.fp64) {
-    switch (L.DX) {
-      case 1: return launch_rows_t<double, 1>(L, st);
-      case 2: return launch_rows_t<double, 2>(L, st);
-      case 4: return launch_rows_t<double, 4>(L, st);
-      case 8: return launch_rows_t<double, 8>(L, st);
-      case 16: return launch_rows_t<double, 16>(L, st);
-      case 32: return launch_rows_t<double, 32>(L, st);
-    }
-  } else {
-    switch (L.DX) {
-      case 1: return launch_rows_t<float, 1>(L, st);
-      case 2: return launch_rows_t<float, 2>(L, st);
-      case 4: return launch_rows_t<float, 4>(L, st);
-      case 8: return launch_rows_t<float, 8>(L, st);
-      case 16: return launch_rows_t<float, 16>(L, st);
-      case 32: return launch_rows_t<float, 32>(L, st);
-    }
-  }
-  return -1;
-}
-
 template <typename R, int DX>
 static void launch_leaves_t(const LeafLaunch& L, hipStream_t st, Timer* tm) {
   tm->begin(0, st);

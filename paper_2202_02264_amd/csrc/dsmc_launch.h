@@ -93,7 +93,6 @@ struct LeafLaunch {
 
 int launch_leaves(const LeafLaunch& L, hipStream_t st, Timer* tm);
 int launch_level(const LevelLaunch& L, hipStream_t st, Timer* tm);
-int launch_rows_only(const LevelLaunch& L, hipStream_t st);
 void launch_output(const LeafLaunch& L, int s0, int B, int dx, hipStream_t st, Timer* tm);
 void launch_clear_status(const SeriesDesc* d_series, int s0, int B, hipStream_t st);
 
