@@ -181,8 +181,9 @@ __device__ __forceinline__ void copy_row(const NodeBufs& nb, size_t node, int Np
 // Table entries for DX >= 8, written coordinate by coordinate (the matrix row
 // loop is not unrolled, so only x stays in registers); same values, order and
 // rounding as col_coords / row_coords followed by put_tcol / put_trow.
-// Wc, Wr: the whitening matrices, woff: kappa Q_inv f, qm: q_mean at the
-// boundary (any address space: the leaf kernel passes copies in LDS).
+// Wc, Wr: the whitening matrices; column table: qm = q_mean[t]; row table:
+// woff = kappa Q_inv f - Wcol q_mean[t + 1] (formed once per time); any
+// address space (the leaf kernel passes copies in LDS).
 template <typename R, int DX, bool kRow>
 __device__ __forceinline__ void stream_table(const NodeBufs& nb, const double* Wc, const double* Wr,
                                              const double* woff, const double* qm, int, size_t g,
@@ -202,11 +203,11 @@ __device__ __forceinline__ void stream_table(const NodeBufs& nb, const double* W
       const int ii = i + k;
       double acc = 0.0;
       if (ii < dx) {
-        if (kRow) {
+        if (kRow) {  // woff here holds kappa Q_inv f - Wcol q_mean[t + 1] (per time)
           acc = woff[ii];
 #pragma unroll
           for (int j = 0; j < DX; ++j)
-            if (j < dx) acc += Wr[ii * dx + j] * x[j] - Wc[ii * dx + j] * qm[j];
+            if (j < dx) acc += Wr[ii * dx + j] * x[j];
         } else {
 #pragma unroll
           for (int j = 0; j < DX; ++j)
@@ -308,8 +309,13 @@ __global__ __launch_bounds__(kBlock, 3) void k_leaves(
     for (int i = threadIdx.x; i < DX; i += kBlock) {
       vq[i] = i < dx ? qm[i] : 0.0;
       vq1[i] = i < dx ? qm1[i] : 0.0;
-      vw[i] = i < dx ? M.wcol_off[i] : 0.0;
       vy[i] = (lds_obs && i < dy) ? M.y[(size_t)t * dy + i] : 0.0;
+      double w = 0.0;  // the row coordinates' per-time offset
+      if (i < dx) {
+        w = M.wcol_off[i];
+        for (int j = 0; j < dx; ++j) w -= Wc[i * dx + j] * qm1[j];
+      }
+      vw[i] = w;
     }
     __syncthreads();
     Wc = Wcl;
