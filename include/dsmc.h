@@ -139,8 +139,10 @@ enum { DSMC_FP32 = 0, /* particles and pair weights in fp32, sums and CDFs in fp
                          fp64 oracle by the bf16 rounding of u and v */ };
 
 #define DSMC_PLAN_PROFILE 1  /* record HIP events around every kernel launch */
-#define DSMC_PLAN_AUTOTUNE 2 /* time the pair-row kernel's tile shapes on first use of each
-                                level size and keep the fastest (results do not depend on it) */
+#define DSMC_PLAN_AUTOTUNE 2 /* on first use of each level size (combines per launch), run the
+                                level with every pair-row tile shape and keep the fastest;
+                                costs several level runs per new size, results do not depend
+                                on it */
 #define DSMC_PLAN_RESCUE_ALL 8 /* testing aid: every row of every combine takes the paths that
                                   rows leaving the fp32 range take (d_x >= 8: the pair-row
                                   kernel redoes its rows with exact row maxima; the sampling
