@@ -238,4 +238,66 @@ __device__ __forceinline__ int block_or_i(int v, int* red) {
   return r;
 }
 
+// Two reductions for the price of one exchange (max and OR are order-free, so
+// the results equal those of the separate calls).  red / redi hold
+// 2 * kBlock / 64 values.
+__device__ __forceinline__ void block_max_or(double& v, int& f, double* red, int* redi) {
+  v = wave_max(v);
+  f = wave_or_i(f);
+  const int w = threadIdx.x >> 6;
+  __syncthreads();
+  if ((threadIdx.x & 63) == 0) {
+    red[w] = v;
+    redi[w] = f;
+  }
+  __syncthreads();
+  double r = red[0];
+  int o = redi[0];
+#pragma unroll
+  for (int i = 1; i < kBlock / 64; ++i) {
+    r = fmax(r, red[i]);
+    o |= redi[i];
+  }
+  v = r;
+  f = o;
+}
+__device__ __forceinline__ void block_max2(double& a, double& b, double* red) {
+  a = wave_max(a);
+  b = wave_max(b);
+  const int w = threadIdx.x >> 6;
+  __syncthreads();
+  if ((threadIdx.x & 63) == 0) {
+    red[w] = a;
+    red[kBlock / 64 + w] = b;
+  }
+  __syncthreads();
+  double ra = red[0], rb = red[kBlock / 64];
+#pragma unroll
+  for (int i = 1; i < kBlock / 64; ++i) {
+    ra = fmax(ra, red[i]);
+    rb = fmax(rb, red[kBlock / 64 + i]);
+  }
+  a = ra;
+  b = rb;
+}
+__device__ __forceinline__ void block_max_i_or(int& a, int& b, int* redi) {
+  a = wave_max_i(a);
+  b = wave_or_i(b);
+  const int w = threadIdx.x >> 6;
+  __syncthreads();
+  if ((threadIdx.x & 63) == 0) {
+    redi[w] = a;
+    redi[kBlock / 64 + w] = b;
+  }
+  __syncthreads();
+  int ra = redi[0], rb = redi[kBlock / 64];
+#pragma unroll
+  for (int i = 1; i < kBlock / 64; ++i) {
+    ra = max(ra, redi[i]);
+    rb |= redi[kBlock / 64 + i];
+  }
+  a = ra;
+  b = rb;
+}
+
 }  // namespace dsmc

@@ -270,8 +270,8 @@ __global__ __launch_bounds__(kBlock, 3) void k_leaves(
   // LDS holds this time's matrices instead)
   double* ell = sh;  // unnormalised leaf log-weights
   double* gq = (DX >= 8) ? nb.tgq + (size_t)g * N : sh + N;  // -log q_t (+ log h_t, boundary weighting)
-  __shared__ double red[kBlock / 64];
-  __shared__ int redi[kBlock / 64];
+  __shared__ double red[2 * kBlock / 64];
+  __shared__ int redi[2 * kBlock / 64];
   const double logN = log((double)N);
   int bad = 0;
   const double* qm = M.q_mean + (size_t)t * dx;
@@ -428,8 +428,7 @@ __global__ __launch_bounds__(kBlock, 3) void k_leaves(
     mx = fmax(mx, ell[n]);
     gmx = fmax(gmx, gq[n]);
   }
-  mx = block_max(mx, red);
-  gmx = block_max(gmx, red);
+  block_max2(mx, gmx, red);
   double s = 0.0;
   if (mx > -INFINITY)
     for (int n = threadIdx.x; n < N; n += kBlock) s += exp(ell[n] - mx);
@@ -444,8 +443,7 @@ __global__ __launch_bounds__(kBlock, 3) void k_leaves(
     ell[n] = (double)lr;  // the stored (rounded) weight is what every consumer sees
     bmax = fmax(bmax, (double)lr + gq[n]);
   }
-  bmax = block_max(bmax, red);
-  bad = block_or_i(bad, redi);
+  block_max_or(bmax, bad, red, redi);
   if (threadIdx.x == 0) {
     leafL[g] = degenerate ? -INFINITY : lse - logN;
     bmerged[g] = -logN + gmx;
@@ -842,8 +840,8 @@ __global__ __launch_bounds__(kBlock) void k_sample(
   double* rs = smem + Npad;                  // [Npad]
   float* shift = (float*)(smem + 2 * Npad);  // [Npad]
   R* lcol = (R*)(shift + Npad);              // [Npad][DX+1] when col_in_lds
-  __shared__ double red[kBlock / 64];
-  __shared__ int redi[kBlock / 64];
+  __shared__ double red[2 * kBlock / 64];
+  __shared__ int redi[2 * kBlock / 64];
   const int node_local = blockIdx.x / DS;
   const int ds = blockIdx.x - node_local * DS;
   const int nodeid = node_list ? node_list[node_local] : node0 + node_local;
@@ -905,7 +903,8 @@ __global__ __launch_bounds__(kBlock) void k_sample(
     if constexpr (kRowShift<DX>) shift[m] = Rshift[(size_t)node_local * N + m];
     else shift[m] = 0.0f;
   }
-  rescued = block_or_i(rescued, redi);  // also orders the writes above
+  double Astar = amax;
+  block_max_or(Astar, rescued, red, redi);  // also orders the writes above
   // Underflow rescue, one row at a time by the whole workgroup: exact row
   // maximum as shift, then the fp64 sum of exp2(s - shift) over a fixed
   // partition of the columns in a fixed reduction order.  Rows are taken in
@@ -977,7 +976,7 @@ __global__ __launch_bounds__(kBlock) void k_sample(
     }
     if (total <= kBlock) break;
   }
-  const double Astar = block_max(amax, red);
+
   // ---- row weights: direct, or in log space when a row carries a shift
   double G = 0.0;
   if (rescued || kRowShift<DX>) {
@@ -1021,8 +1020,8 @@ __global__ __launch_bounds__(kBlock) void k_sample(
     for (int i = 0; i < wid; ++i) off += red[i];
     for (int m = m0; m < m1; ++m) cdf[m] += off;
   }
-  lastpos = block_max_i(lastpos, redi);
-  const int any_nan = block_or_i(row_nan, redi);
+  int any_nan = row_nan;
+  block_max_i_or(lastpos, any_nan, redi);
   __syncthreads();
   const double T = cdf[N - 1];
   const bool degenerate = !(T > 0.0);
