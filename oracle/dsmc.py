@@ -14,7 +14,7 @@ Steps, in the paper's order:
                       the balanced tree actually executed.
 * ``smooth``          leaves, then the tree, then the output.
 
-Readings of the paper this file takes (each also listed in the design doc):
+Readings of the paper this file takes:
 
 * Time points are t = 0..K-1.
 * Weights are carried normalised, with a separate log L per block (Algorithm 2
