@@ -358,7 +358,7 @@ def bench_highdim(args):
 def main():
     args = parse()
     if args.gpus != 1:
-        print(json.dumps({"error": "this build runs on one GPU only; --gpus must be 1"}))
+        print(json.dumps({"error": "the smoother runs on one GPU; --gpus must be 1"}))
         sys.exit(2)
     if args.copy_calibration:
         import torch

@@ -59,7 +59,7 @@ typedef enum dsmc_status {
   DSMC_OK = 0,
   DSMC_EINVAL = -1,       /* invalid argument */
   DSMC_ENOMEM = -2,       /* device or host allocation failed, or plan too small */
-  DSMC_EUNSUPPORTED = -3, /* size or option this build does not support */
+  DSMC_EUNSUPPORTED = -3, /* size or option the library does not support */
   DSMC_EAGAIN = -4,       /* dsmc_poll: the job has not finished */
   DSMC_EDEGENERATE = -5,  /* a combine had zero total weight */
   DSMC_ENUMERIC = -6,     /* a weight was NaN */
@@ -72,7 +72,7 @@ typedef enum dsmc_status {
 #define DSMC_FLAG_DEGENERATE 1 /* some combine (or leaf) had total weight 0; log_Z = -inf */
 #define DSMC_FLAG_NUMERIC 2    /* a NaN weight was met; outputs are undefined */
 
-/* Largest state dimension and particle count this build accepts. */
+/* Largest state dimension and particle count the library accepts. */
 #define DSMC_MAX_DX 32
 #define DSMC_MAX_N 4096
 
