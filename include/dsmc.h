@@ -7,7 +7,7 @@
  *   leaves   Algorithm 2: for every time t, N particles X_t^n ~ q_t with
  *            normalised log-weights and log L_t = log mean_n w_t^n; the t = 0
  *            weight is h_0 dP_0/dq_0 (Proposition 2.2).
- *   tree     Algorithm 5 (appendix, parallel combination by array reshaping):
+ *   tree     Algorithm 6 (appendix, parallel combination by array reshaping):
  *            ceil(log2 K) levels; at level l, adjacent blocks of 2^l time
  *            points are merged at boundary c = (2k+1) 2^l, and a block whose
  *            right neighbour is padding is left as it is.
@@ -287,7 +287,7 @@ typedef struct dsmc_profile {
 } dsmc_profile;
 int dsmc_plan_profile(dsmc_plan_t *plan, dsmc_profile *out);
 
-/* The combine tree the library runs for a series of K points (Algorithm 5:
+/* The combine tree the library runs for a series of K points (Algorithm 6:
  * at level l, adjacent blocks 2k and 2k+1 of the previous level are combined;
  * a trailing block without a right neighbour passes through).  Host only, no
  * device work.  Writes K - 1 combines, ordered by level, as left block

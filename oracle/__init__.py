@@ -11,7 +11,8 @@ from the generator's published definition.
 Modules:
   philox   Philox4x64-10 counter-based generator and the uniform / normal draws
   ssm      model log densities (prior, transition, potential, proposal)
-  dsmc     Algorithm 2 (leaves), Algorithm 1 (combine), Algorithm 5 (tree)
+  dsmc     Algorithm 2 (leaves), Algorithm 1 (combine), Algorithm 6 (tree),
+           conditional dSMC (Section 3.1, Algorithm 4)
   kalman   Kalman filter / RTS smoother / exact log-likelihood (closed-form pins)
 
 Parity pins for each function are in tests/test_oracle_*.py.

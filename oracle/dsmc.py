@@ -10,9 +10,13 @@ Steps, in the paper's order:
                       W_c^{mn} (Section 2.2, normalised-weights equation), the
                       normalising-constant increment (equation for L_{a:b}),
                       multinomial resampling of N index pairs, and the gather.
-* ``schedule``        Algorithm 5 (parallel combination by array reshaping):
+* ``schedule``        Algorithm 6 (parallel combination by array reshaping):
                       the balanced tree actually executed.
 * ``smooth``          leaves, then the tree, then the output.
+* ``smooth_conditional``  conditional dSMC (Section 3.1): the initialisation of
+                      Algorithm 2 with a star trajectory put in front of the
+                      proposal draws, and Algorithm 4 (conditional block
+                      combination) at every node.
 
 Readings of the paper this file takes:
 
@@ -36,6 +40,10 @@ Readings of the paper this file takes:
   cumulative sums, so zero-weight entries are never drawn.
 * If every pair weight of a combine is zero the increment is -inf, the status
   is "degenerate" and indices are drawn uniformly: l = floor(u1 N), r = floor(u2 N).
+* Conditional runs: the star trajectory takes slot 0 (the paper's slot 1) and
+  slot n >= 1 holds the proposal draw an unconditional run puts there; the N - 1
+  draws of Algorithm 4 are those of slots 1..N-1 (uniforms of counter n), and
+  slot 0 keeps the index pair (0, 0), degenerate combines included.
 """
 from __future__ import annotations
 
@@ -174,11 +182,11 @@ def combine(spec, c: int, xL, xR, lwL, lwR, u1, u2, keep_S: bool = False) -> Com
 
 
 # --------------------------------------------------------------------------
-# Tree: Algorithm 5
+# Tree: Algorithm 6
 # --------------------------------------------------------------------------
 
 def schedule(K: int):
-    """Algorithm 5 as a list of levels; each level is a list of
+    """Algorithm 6 as a list of levels; each level is a list of
     (a, c, b) = left block [a, c), right block [c, b) to combine at boundary c.
     Blocks are padded to 2^L with null blocks; a block whose right neighbour is
     padding is left unchanged."""
@@ -225,7 +233,9 @@ class SmoothResult:
     levels: list = field(default_factory=list)
 
 
-def run_tree(spec, leaves: Leaves, seed: int) -> SmoothResult:
+def run_tree(spec, leaves: Leaves, seed: int, conditional: bool = False) -> SmoothResult:
+    """Algorithm 6 over the leaves; ``conditional`` runs Algorithm 4 at every
+    node instead of Algorithm 1."""
     K, N = leaves.x.shape[0], leaves.x.shape[1]
     blocks = {t: Block(t, t + 1, leaves.x[t:t + 1], leaves.logw[t].copy(), float(leaves.logL[t]),
                        np.arange(N)[None, :].copy()) for t in range(K)}
@@ -240,7 +250,8 @@ def run_tree(spec, leaves: Leaves, seed: int) -> SmoothResult:
         for (a, c, b) in nodes:
             L, R = blocks.pop(a), blocks.pop(c)
             u1, u2 = philox.combine_uniforms(seed, c, N)
-            res = combine(spec, c, L.x[-1], R.x[0], L.logw, R.logw, u1, u2)
+            step = conditional_combine if conditional else combine
+            res = step(spec, c, L.x[-1], R.x[0], L.logw, R.logw, u1, u2)
             degenerate |= res.degenerate
             anc[c - 1, 0], anc[c - 1, 1] = res.l, res.r
             Zc[c - 1] = res.Z
@@ -254,6 +265,42 @@ def run_tree(spec, leaves: Leaves, seed: int) -> SmoothResult:
 
 
 def smooth(spec, N: int, seed: int) -> SmoothResult:
-    """Leaves (Algorithm 2), then the tree of Algorithm 5 with Algorithm 1 at
+    """Leaves (Algorithm 2), then the tree of Algorithm 6 with Algorithm 1 at
     every node; log Z = sum_t log L_t + sum_c Z_c."""
     return run_tree(spec, sample_leaves(spec, N, seed), seed)
+
+
+# --------------------------------------------------------------------------
+# Conditional dSMC: Section 3.1 and Algorithm 4
+# --------------------------------------------------------------------------
+
+def sample_leaves_conditional(spec, N: int, seed: int, star) -> Leaves:
+    """Conditional initialisation (Section 3.2): the star trajectory star[t]
+    (K, d_x) is put in front of N - 1 proposal draws, so slot 0 of time t holds
+    x*_t and slot n >= 1 the draw an unconditional run puts in slot n; the
+    weights of Algorithm 2 are then computed over all N particles."""
+    K, d = spec.K, spec.d_x
+    star = np.asarray(star, dtype=np.float64).reshape(K, d)
+    x = np.empty((K, N, d))
+    for t in range(K):
+        x[t] = proposal_draw(spec, t, philox.leaf_normals(seed, t, N, d))
+    x[:, 0] = star
+    return sample_leaves(spec, N, seed, x=x)
+
+
+def conditional_combine(spec, c: int, xL, xR, lwL, lwR, u1, u2) -> CombineResult:
+    """Algorithm 4 at boundary c: the pair weights, row sums and increment of
+    Algorithm 1 over all N x N pairs, the star's included; N - 1 index pairs
+    drawn for slots 1..N-1, while slot 0 keeps (0, 0), so the star trajectory,
+    slot 0 of both blocks, is slot 0 of the merged block."""
+    res = combine(spec, c, xL, xR, lwL, lwR, u1, u2)
+    res.l[0] = 0
+    res.r[0] = 0
+    return res
+
+
+def smooth_conditional(spec, N: int, seed: int, star) -> SmoothResult:
+    """Conditional dSMC: conditional leaves, then the tree of Algorithm 6 with
+    Algorithm 4 at every node.  Output slot 0 is the star trajectory; log Z is
+    computed as in the unconditional run, over all particles."""
+    return run_tree(spec, sample_leaves_conditional(spec, N, seed, star), seed, conditional=True)

@@ -406,7 +406,7 @@ static int ensure_series_cap(dsmc_plan_t* p, int B) {
   return DSMC_OK;
 }
 
-// Algorithm 5 for every series.  Blocks start as single time points; at each
+// Algorithm 6 for every series.  Blocks start as single time points; at each
 // level adjacent blocks (2k, 2k+1) are merged by one combine and a trailing
 // block without a right neighbour is kept as it is.  Combines get ids level
 // by level (all series of a level contiguous), and each records the combine

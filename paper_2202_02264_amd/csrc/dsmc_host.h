@@ -41,7 +41,7 @@ TileChoice heuristic_tile(int nodes, int N, int Nc, bool split_ok);
 void set_tile(LevelLaunch& L, TileChoice tc);
 int check_output(const dsmc_output* o);
 
-// Algorithm 5 for one series of K points whose combines get ids
+// Algorithm 6 for one series of K points whose combines get ids
 // node_base + (0 .. K-2), ordered by level; `series` is its index in the
 // series table and row_base the first time row.  Appends the combines to
 // `nodes`, writes per-level offsets/counts (relative to node_base), the

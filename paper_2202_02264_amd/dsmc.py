@@ -365,7 +365,7 @@ def dsmc_job_times(server: Server, job_id: int):
 
 
 def dsmc_schedule(K: int):
-    """Algorithm 5's combines for K points as the library runs them: a list of
+    """Algorithm 6's combines for K points as the library runs them: a list of
     levels, each a list of (a, c, b)."""
     n = max(K - 1, 1)
     arrs = [np.zeros(n, dtype=np.int32) for _ in range(4)]

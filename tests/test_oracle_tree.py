@@ -1,4 +1,4 @@
-"""Pins of the oracle's tree (Algorithm 5), gather and whole-tree law."""
+"""Pins of the oracle's tree (Algorithm 6), gather and whole-tree law."""
 import itertools
 import math
 

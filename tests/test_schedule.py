@@ -1,4 +1,4 @@
-"""The library's host-side combine schedule (Algorithm 5, appendix A) equals the
+"""The library's host-side combine schedule (Algorithm 6, appendix A) equals the
 oracle's padded power-of-two tree for every K up to 600 and a few large K
 (CPU only: dsmc_schedule does no device work)."""
 import pytest
