@@ -19,6 +19,8 @@
  *            Proposition 2.4), and the gather of the chosen trajectories.
  *   output   equally weighted trajectories approximating Q_{0:K-1} and
  *            log L^N = sum_t log L_t + sum_c Z_c.
+ *   conditional  (Section 3.1, Algorithm 4) the same with a given star
+ *            trajectory kept in slot 0 throughout: dsmc_smooth_conditional.
  *
  * Time points are t = 0..K-1 (the paper's t = 0..T with K = T + 1).
  *
@@ -41,8 +43,9 @@
  *     owned by the caller.
  *   - Matrices are row-major, fp64.  Cholesky factors are lower triangular
  *     with positive diagonal.
- *   - dsmc_smooth / dsmc_smooth_batch validate their arguments, enqueue all
- *     work on the plan's stream and return without synchronising.  Numerical
+ *   - dsmc_smooth / dsmc_smooth_conditional / dsmc_smooth_batch validate
+ *     their arguments, enqueue all work on the plan's stream and return
+ *     without synchronising.  Numerical
  *     conditions found on the device are reported in dsmc_output.status.
  */
 #ifndef DSMC_H
@@ -206,6 +209,20 @@ typedef struct dsmc_output {
  * overlap (they share its workspace).  Errors: DSMC_EINVAL, DSMC_EDEVICE. */
 int dsmc_smooth(dsmc_plan_t *plan, const dsmc_model_t *model, uint64_t seed,
                 const dsmc_output *out);
+
+/* Conditional dSMC (Section 3.1; Algorithm 4 and the conditional
+ * initialisation of Section 3.2), the sampling step of parallel-in-time
+ * particle Gibbs.  `star` is a DEVICE buffer, real [d_x][K] (the layout of
+ * traj with one particle), owned by the caller and read until the stream
+ * reaches this work.  The star trajectory takes slot 0 at every time point;
+ * slot n >= 1 holds the proposal draw dsmc_smooth puts there.  Weights, row
+ * sums, increments and log L^N cover all N x N pairs, the star's included;
+ * every combine draws slots 1..N-1 as dsmc_smooth does and keeps (0, 0) for
+ * slot 0, so traj[.][.][0] equals the star and index[.][0] is 0.  A new star
+ * for the next Gibbs sweep is any output trajectory picked uniformly.
+ * Errors as dsmc_smooth; a null `star` is DSMC_EINVAL. */
+int dsmc_smooth_conditional(dsmc_plan_t *plan, const dsmc_model_t *model, uint64_t seed,
+                            const void *star, const dsmc_output *out);
 
 /* B independent series (each with its own model, K and seed) in packed
  * launches: every level's combines of all series run in the same kernels.

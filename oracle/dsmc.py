@@ -288,12 +288,13 @@ def sample_leaves_conditional(spec, N: int, seed: int, star) -> Leaves:
     return sample_leaves(spec, N, seed, x=x)
 
 
-def conditional_combine(spec, c: int, xL, xR, lwL, lwR, u1, u2) -> CombineResult:
+def conditional_combine(spec, c: int, xL, xR, lwL, lwR, u1, u2,
+                        keep_S: bool = False) -> CombineResult:
     """Algorithm 4 at boundary c: the pair weights, row sums and increment of
     Algorithm 1 over all N x N pairs, the star's included; N - 1 index pairs
     drawn for slots 1..N-1, while slot 0 keeps (0, 0), so the star trajectory,
     slot 0 of both blocks, is slot 0 of the merged block."""
-    res = combine(spec, c, xL, xR, lwL, lwR, u1, u2)
+    res = combine(spec, c, xL, xR, lwL, lwR, u1, u2, keep_S=keep_S)
     res.l[0] = 0
     res.r[0] = 0
     return res

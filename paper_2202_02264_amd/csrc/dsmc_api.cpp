@@ -640,8 +640,8 @@ PoolSizes dsmc::pool_sizes(int N, int DX, int dx_alloc, size_t rsz) {
 static bool tiles_known(const dsmc_plan_t* p);
 static int enqueue_batch(dsmc_plan_t* p, int B, int totalK, hipStream_t st);
 
-extern "C" int dsmc_smooth_batch(dsmc_plan_t* p, int B, const dsmc_model_t* const* models,
-                                 const uint64_t* seeds, const dsmc_output* outs) {
+static int smooth_batch(dsmc_plan_t* p, int B, const dsmc_model_t* const* models,
+                        const uint64_t* seeds, const void* const* stars, const dsmc_output* outs) {
   if (!p || B < 1 || !models || !seeds || !outs) return fail(DSMC_EINVAL, "bad argument");
   const int N = p->d.N;
   std::vector<int> Ks(B), bases(B);
@@ -689,6 +689,7 @@ extern "C" int dsmc_smooth_batch(dsmc_plan_t* p, int B, const dsmc_model_t* cons
     sd.leaf_logw = o.leaf_logw;
     sd.leaf_logL = o.leaf_logL;
     sd.index = o.index;
+    sd.star = stars ? stars[s] : nullptr;
     p->h_series[s] = sd;
     pairs += (double)(Ks[s] - 1) * N * (double)N;
   }
@@ -841,10 +842,23 @@ extern "C" int dsmc_schedule(int K, int cap, int32_t* a, int32_t* c, int32_t* b,
   return (int)nodes.size();
 }
 
+extern "C" int dsmc_smooth_batch(dsmc_plan_t* p, int B, const dsmc_model_t* const* models,
+                                 const uint64_t* seeds, const dsmc_output* outs) {
+  return smooth_batch(p, B, models, seeds, nullptr, outs);
+}
+
 extern "C" int dsmc_smooth(dsmc_plan_t* p, const dsmc_model_t* model, uint64_t seed,
                            const dsmc_output* out) {
   const dsmc_model_t* ms[1] = {model};
-  return dsmc_smooth_batch(p, 1, ms, &seed, out);
+  return smooth_batch(p, 1, ms, &seed, nullptr, out);
+}
+
+extern "C" int dsmc_smooth_conditional(dsmc_plan_t* p, const dsmc_model_t* model, uint64_t seed,
+                                       const void* star, const dsmc_output* out) {
+  if (!star) return fail(DSMC_EINVAL, "null star trajectory");
+  const dsmc_model_t* ms[1] = {model};
+  const void* stars[1] = {star};
+  return smooth_batch(p, 1, ms, &seed, stars, out);
 }
 
 extern "C" int dsmc_plan_profile(dsmc_plan_t* p, dsmc_profile* out) {

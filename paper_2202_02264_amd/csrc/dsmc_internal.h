@@ -52,6 +52,7 @@ struct SeriesDesc {
   void* leaf_logw;        // [K][N] or null
   double* leaf_logL;      // [K] or null
   int32_t* index;         // [K][N] or null
+  const void* star;       // [dx][K] star trajectory of a conditional run (slot 0), or null
 };
 
 // One combine at boundary c of series `series`: left block [a, c), right

@@ -379,6 +379,21 @@ __global__ __launch_bounds__(kBlock, 3) void k_leaves(
         x[i] = xi;
       }
     }
+    if (n == 0 && sd.star != nullptr) {
+      // conditional run: slot 0 holds the star trajectory (its proposal draw
+      // above is discarded), weighted like every other particle
+      const R* st = (const R*)sd.star;
+#pragma unroll
+      for (int i = 0; i < DX; ++i) {
+        double xi = 0.0;
+        if (i < dx) {
+          const R xr = st[(size_t)i * K + t];
+          leafX[((size_t)i * totalK + g) * N + n] = xr;
+          xi = (double)xr;
+        }
+        x[i] = xi;
+      }
+    }
     double lq, lh;  // log q_t(x), log h_t(x)
     if constexpr (DX >= 8) {
       double q = 0.0;
@@ -1054,6 +1069,7 @@ __global__ __launch_bounds__(kBlock) void k_sample(
   const int n0 = ds * dper, n1 = min(N, n0 + dper);
   int32_t* ancL = sd.anc + (size_t)(c - 1) * 2 * N;
   int32_t* ancR = ancL + N;
+  const bool star = sd.star != nullptr;
   for (int n = n0 + threadIdx.x; n < n1; n += kBlock) {
     const Words4 w = philox4x64_10((uint64_t)n, (uint64_t)c, kPurposeCombine, 0ull, sd.seed, kKey1);
     const double u1 = unif53(w.w0), u2 = unif53(w.w1);
@@ -1124,6 +1140,10 @@ __global__ __launch_bounds__(kBlock) void k_sample(
         r += k * kChunk;
       }
       if (r >= N) r = N - 1;  // only reachable through NaN weights
+    }
+    if (n == 0 && star) {  // conditional combine: slot 0 keeps the star, (0, 0)
+      l = 0;
+      r = 0;
     }
     ancL[n] = l;
     ancR[n] = r;

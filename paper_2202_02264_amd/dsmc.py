@@ -87,6 +87,7 @@ def _load() -> C.CDLL:
         "dsmc_plan_destroy": (None, [vp]),
         "dsmc_smooth": (i, [vp, vp, u64, C.POINTER(dsmc_output)]),
         "dsmc_smooth_batch": (i, [vp, i, C.POINTER(vp), C.POINTER(u64), C.POINTER(dsmc_output)]),
+        "dsmc_smooth_conditional": (i, [vp, vp, u64, vp, C.POINTER(dsmc_output)]),
         "dsmc_plan_profile": (i, [vp, C.POINTER(dsmc_profile)]),
         "dsmc_server_create": (i, [C.POINTER(dsmc_server_desc), C.POINTER(vp)]),
         "dsmc_server_destroy": (None, [vp]),
@@ -248,6 +249,20 @@ def dsmc_smooth(plan: Plan, model: Model, seed: int, out: Output) -> None:
     o = out.c_struct()
     _check(_lib.dsmc_smooth(plan.handle, model.handle, C.c_uint64(seed & (2**64 - 1)),
                             C.byref(o)), "dsmc_smooth")
+
+
+def dsmc_smooth_conditional(plan: Plan, model: Model, seed: int, star, out: Output) -> None:
+    """Conditional dSMC with the star trajectory ``star``: a contiguous device
+    tensor [d_x][K] of the plan's real type, kept in slot 0 of the output."""
+    if (not star.is_cuda or star.dtype != plan.dtype or not star.is_contiguous()
+            or tuple(star.shape) != (plan.d_x, model.K)):
+        raise ValueError(f"star must be a contiguous {plan.dtype} device tensor of shape "
+                         f"({plan.d_x}, {model.K})")
+    o = out.c_struct()
+    _check(_lib.dsmc_smooth_conditional(plan.handle, model.handle,
+                                        C.c_uint64(seed & (2**64 - 1)),
+                                        C.c_void_p(star.data_ptr()), C.byref(o)),
+           "dsmc_smooth_conditional")
 
 
 def dsmc_smooth_batch(plan: Plan, models: Sequence[Model], seeds: Sequence[int],

@@ -34,8 +34,9 @@ def log(msg: str) -> None:
 
 
 def run_gpu(spec, N: int, seed: int, precision: str = "fp32", plan=None, model=None,
-            rescue_all: bool = False):
-    """dsmc_smooth with every diagnostic output; returns numpy arrays."""
+            rescue_all: bool = False, star=None):
+    """dsmc_smooth (dsmc_smooth_conditional if ``star`` (K, d_x) is given) with
+    every diagnostic output; returns numpy arrays."""
     import torch
     from paper_2202_02264_amd import dsmc as G
     prec = {"fp64": G.DSMC_FP64, "fp32": G.DSMC_FP32, "bf16": G.DSMC_BF16}[precision]
@@ -43,7 +44,12 @@ def run_gpu(spec, N: int, seed: int, precision: str = "fp32", plan=None, model=N
     model = model or G.Model(spec)
     plan = plan or G.Plan(N, spec.d_x, spec.K, precision=prec, rescue_all=rescue_all)
     out = G.alloc_output(plan, spec.K, diagnostics=True)
-    G.dsmc_smooth(plan, model, seed, out)
+    if star is None:
+        G.dsmc_smooth(plan, model, seed, out)
+    else:
+        st = torch.tensor(np.ascontiguousarray(np.asarray(star, np.float64).reshape(spec.K, -1).T),
+                          dtype=plan.dtype, device="cuda")
+        G.dsmc_smooth_conditional(plan, model, seed, st, out)
     torch.cuda.synchronize()
     res = {}
     for k in ("traj", "logw", "log_Z", "status", "leaf_x", "leaf_logw", "leaf_logL", "ancestry",
@@ -93,12 +99,14 @@ def _rel(a, b):
     return np.where(both_inf, 0.0, err)
 
 
-def check_leaves(spec, N: int, seed: int, g: dict, tol: float) -> None:
+def check_leaves(spec, N: int, seed: int, g: dict, tol: float, star=None) -> None:
     """Leaf particles equal the oracle's draws rounded to the stored type; leaf
-    log-weights and log L_t equal the oracle's on the stored particles."""
+    log-weights and log L_t equal the oracle's on the stored particles.  With
+    ``star`` (already in the stored type) the conditional leaves are checked."""
     K, dx = spec.K, spec.d_x
     xg = np.moveaxis(g["leaf_x"], 0, -1).astype(np.float64)  # (K, N, dx)
-    ref = D.sample_leaves(spec, N, seed)
+    ref = (D.sample_leaves(spec, N, seed) if star is None
+           else D.sample_leaves_conditional(spec, N, seed, star))
     xr = ref.x.astype(g["leaf_x"].dtype).astype(np.float64)
     diff = np.abs(xg - xr)
     ulp = np.spacing(np.abs(xr).astype(g["leaf_x"].dtype)).astype(np.float64)
@@ -111,11 +119,13 @@ def check_leaves(spec, N: int, seed: int, g: dict, tol: float) -> None:
     assert np.max(e_L) <= tol, np.max(e_L)
 
 
-def teacher_forced(spec, N: int, seed: int, g: dict, tol, select=None) -> ParityReport:
+def teacher_forced(spec, N: int, seed: int, g: dict, tol, select=None,
+                   conditional: bool = False) -> ParityReport:
     """Replay the GPU's ancestry; at every selected node run the oracle's combine
     on the GPU's inputs of that level and compare increments, row log-sums and
-    indices.  Also checks the gather: final index and trajectories.  With
-    tol=None the absolute errors are collected instead of asserted."""
+    indices (Algorithm 4's with ``conditional``).  Also checks the gather:
+    final index and trajectories.  With tol=None the absolute errors are
+    collected instead of asserted."""
     K, dx = spec.K, spec.d_x
     rep = ParityReport()
     leaf_x = g["leaf_x"].astype(np.float64)            # (dx, K, N)
@@ -131,7 +141,8 @@ def teacher_forced(spec, N: int, seed: int, g: dict, tol, select=None) -> Parity
                 lwL = g["leaf_logw"][c - 1].astype(np.float64) if c - a == 1 else np.full(N, -logN)
                 lwR = g["leaf_logw"][c].astype(np.float64) if b - c == 1 else np.full(N, -logN)
                 u1, u2 = P.combine_uniforms(seed, c, N)
-                res = D.combine(spec, c, xL, xR, lwL, lwR, u1, u2, keep_S=True)
+                step = D.conditional_combine if conditional else D.combine
+                res = step(spec, c, xL, xR, lwL, lwR, u1, u2, keep_S=True)
                 rep.nodes += 1
                 ez = float(_rel(g["logZ_inc"][c - 1], res.Z))
                 rep.max_rel_err_Z = max(rep.max_rel_err_Z, ez)

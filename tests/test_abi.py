@@ -20,7 +20,8 @@ def _declared_functions():
 
 def test_header_declares_the_entry_points():
     names = _declared_functions()
-    for n in ("dsmc_plan", "dsmc_smooth", "dsmc_smooth_batch", "dsmc_model_create",
+    for n in ("dsmc_plan", "dsmc_smooth", "dsmc_smooth_batch", "dsmc_smooth_conditional",
+              "dsmc_model_create",
               "dsmc_server_create", "dsmc_submit", "dsmc_poll", "dsmc_cancel",
               "dsmc_schedule", "dsmc_last_error"):
         assert n in names
@@ -98,6 +99,7 @@ def test_invalid_arguments_rejected_on_host():
     assert lib.dsmc_plan(C.byref(p), C.byref(hp)) == dsmc.DSMC_EUNSUPPORTED
     p.precision, p.d_x = dsmc.DSMC_FP32, 1
     assert lib.dsmc_smooth(None, None, 0, None) == dsmc.DSMC_EINVAL
+    assert lib.dsmc_smooth_conditional(None, None, 0, None, None) == dsmc.DSMC_EINVAL
     # serving entry points
     sd = dsmc.dsmc_server_desc()
     hs = C.c_void_p()

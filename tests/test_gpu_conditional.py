@@ -1,0 +1,145 @@
+"""GPU parity of conditional dSMC (dsmc_smooth_conditional; Section 3.1,
+Algorithm 4) against the oracle's smooth_conditional.
+
+fp64 runs equal the oracle end to end (every index); fp32 runs are compared
+level by level on the GPU's own inputs with the tolerances of the
+unconditional parity tests.  In every run the star trajectory is output slot 0
+exactly and its leaf index is 0 at every time.
+"""
+import numpy as np
+import pytest
+
+from oracle import dsmc as D
+from paper_2202_02264_amd import workloads as W
+
+from parity import TOL32, TOL64, check_leaves, log, run_gpu, teacher_forced
+
+pytestmark = pytest.mark.gpu
+
+
+def _lg_dx(dx, K, seed=5):
+    g = np.random.Generator(np.random.Philox(seed))
+    F = 0.8 * W.random_orthogonal(dx, g)
+    return W.lg(K, F, 0.7 * np.eye(dx), np.eye(1, dx) + 0.3, np.eye(1) * 0.8, np.zeros(dx),
+                np.eye(dx) * 1.5, seed=seed, proposal="prior", name=f"lg(d_x={dx},K={K})")
+
+
+def _star(spec, dtype):
+    """A star trajectory in the stored type: the model's simulated states."""
+    return spec.x_true.astype(dtype).astype(np.float64)
+
+
+def _assert_star_kept(g, star):
+    np.testing.assert_array_equal(g["traj"][:, :, 0], star.T)
+    assert np.all(g["index"][:, 0] == 0)
+    assert np.all(g["ancestry"][:, :, 0] == 0)
+
+
+def test_fp64_end_to_end_conditional_correctness_workload():
+    spec = W.c1_lg1d()
+    N, seed = 64, 7
+    star = _star(spec, np.float64)
+    g = run_gpu(spec, N, seed, precision="fp64", star=star)
+    ref = D.smooth_conditional(spec, N, seed, star)
+    assert g["status"][0] == 0
+    _assert_star_kept(g, star)
+    np.testing.assert_array_equal(g["ancestry"], ref.ancestry)
+    np.testing.assert_array_equal(g["index"], ref.idx)
+    np.testing.assert_allclose(g["traj"][0], ref.x[:, :, 0], rtol=1e-13, atol=1e-13)
+    np.testing.assert_allclose(g["logZ_inc"], ref.Zc, rtol=TOL64, atol=TOL64)
+    assert abs(g["log_Z"][0] - ref.logZ) <= TOL64 * max(1.0, abs(ref.logZ))
+    rep = teacher_forced(spec, N, seed, g, TOL64, conditional=True)
+    assert rep.mismatches == 0
+
+
+@pytest.mark.parametrize("weighting", ["leaf_obs", "boundary_obs"])
+def test_fp64_conditional_many_seeds(weighting):
+    spec = W.sv(45, seed=3, weighting=weighting)
+    star = _star(spec, np.float64)
+    for seed in (1, 2, 3):
+        g = run_gpu(spec, 48, seed, precision="fp64", star=star)
+        ref = D.smooth_conditional(spec, 48, seed, star)
+        _assert_star_kept(g, star)
+        np.testing.assert_array_equal(g["ancestry"], ref.ancestry)
+        assert abs(g["log_Z"][0] - ref.logZ) <= TOL64 * max(1.0, abs(ref.logZ))
+
+
+CASES = {
+    "sv_ragged": (lambda: W.sv(300, seed=11), 256),
+    "lg4d": (lambda: W.lg4d(40, seed=15), 128),
+    "lg8d": (lambda: _lg_dx(8, 24), 160),
+    "lg32d": (lambda: W.lg_highdim(K=20, seed=19), 256),
+    "sv_n1": (lambda: W.sv(17, seed=16), 1),
+    "sv_k2": (lambda: W.sv(2, seed=18), 512),
+}
+
+
+@pytest.mark.parametrize("case", sorted(CASES))
+def test_conditional_teacher_forced_parity(case):
+    build, N = CASES[case]
+    spec = build()
+    seed = 2000 + len(case)
+    star = _star(spec, np.float32)
+    g = run_gpu(spec, N, seed, star=star)
+    assert g["status"][0] == 0
+    _assert_star_kept(g, star)
+    check_leaves(spec, N, seed, g, TOL32, star=star)
+    rep = teacher_forced(spec, N, seed, g, TOL32, conditional=True)
+    log(f"conditional {case}: {rep.summary()}")
+    assert rep.mismatches_outside_band == 0, rep.worst[:5]
+
+
+def test_particle_gibbs_chain_equals_oracle():
+    """Three sweeps of particle Gibbs with a fixed model: each sweep's star is
+    an output trajectory of the previous sweep, each chain feeding its own.
+    fp64 GPU and oracle chains agree in every index and in every star (within
+    the last bits of the fp64 particles); a plain dsmc_smooth on the same plan
+    afterwards is unconditional again."""
+    import torch
+    from paper_2202_02264_amd import dsmc as G
+    spec = W.lg1d(37, A=0.95, Q=0.3, R=2.0, seed=14)
+    N = 33
+    plan = G.Plan(N, 1, spec.K, precision=G.DSMC_FP64)
+    model = G.Model(spec)
+    star_g = star_o = _star(spec, np.float64)
+    for sweep in range(3):
+        seed = 300 + sweep
+        g = run_gpu(spec, N, seed, precision="fp64", plan=plan, model=model, star=star_g)
+        ref = D.smooth_conditional(spec, N, seed, star_o)
+        _assert_star_kept(g, star_g)
+        np.testing.assert_array_equal(g["ancestry"], ref.ancestry)
+        j = (7 * sweep + 5) % N
+        star_g = g["traj"][:, :, j].T.astype(np.float64)
+        star_o = ref.x[:, j, :]
+        # fp64 leaf particles agree with the oracle's to the last bits only
+        np.testing.assert_allclose(star_g, star_o, rtol=1e-13, atol=1e-13)
+    g = run_gpu(spec, N, 99, precision="fp64", plan=plan, model=model)
+    ref = D.smooth(spec, N, 99)
+    np.testing.assert_array_equal(g["ancestry"], ref.ancestry)
+    torch.cuda.synchronize()
+
+
+def test_bf16_conditional_keeps_star():
+    """bf16 matrix-core plan (d_x = 32): the star is output slot 0 and the run
+    is clean; the conditional leaves equal the oracle's (fp32 storage)."""
+    spec = W.lg_highdim(K=16, seed=23)
+    N, seed = 256, 41
+    star = _star(spec, np.float32)
+    g = run_gpu(spec, N, seed, precision="bf16", star=star)
+    assert g["status"][0] == 0
+    _assert_star_kept(g, star)
+    check_leaves(spec, N, seed, g, TOL32, star=star)
+
+
+def test_star_argument_checked():
+    import torch
+    from paper_2202_02264_amd import dsmc as G
+    spec = W.sv(8, seed=2)
+    plan = G.Plan(16, 1, spec.K)
+    model = G.Model(spec)
+    out = G.alloc_output(plan, spec.K)
+    with pytest.raises(ValueError):
+        G.dsmc_smooth_conditional(plan, model, 1, torch.zeros((1, 7), device="cuda"), out)
+    with pytest.raises(ValueError):
+        G.dsmc_smooth_conditional(plan, model, 1, torch.zeros((1, 8), dtype=torch.float64,
+                                                              device="cuda"), out)
