@@ -56,9 +56,11 @@ def parse():
                     help="wall-clock budget of the oracle baseline sample (0 = skip)")
     ap.add_argument("--no-kernel-events", action="store_true",
                     help="time the steps without per-kernel HIP events")
-    ap.add_argument("--workload", choices=("sv", "batch", "serve", "highdim"), default="sv",
+    ap.add_argument("--workload", choices=("sv", "batch", "serve", "highdim", "pgibbs"),
+                    default="sv",
                     help="sv: one long stochastic-volatility series (default); batch: "
-                         "B linear-Gaussian series of uneven length, packed vs one at a time")
+                         "B linear-Gaussian series of uneven length, packed vs one at a time; "
+                         "pgibbs: particle Gibbs sweeps of conditional dSMC on the sv series")
     ap.add_argument("--B", type=int, default=512)
     ap.add_argument("--jobs", type=int, default=600, help="serving: jobs per arrival run")
     ap.add_argument("--rates", type=str, default="0.25,0.5,0.75,0.9,1.1",
@@ -355,6 +357,70 @@ def bench_highdim(args):
     print(json.dumps(res))
 
 
+def bench_pgibbs(args):
+    """Particle Gibbs sweeps (Section 3.2) on the stochastic-volatility
+    workload: each step is one conditional smoother run (Algorithm 4 at every
+    node) with the previous sweep's star in slot 0, then the next star is an
+    output trajectory picked uniformly (a device copy).  The model is fixed
+    (no parameter update between sweeps).  Beside it: the unconditional
+    smoother on the same plan."""
+    import numpy as np
+    import torch
+
+    from paper_2202_02264_amd import dsmc as G
+    from paper_2202_02264_amd import workloads as W
+    torch.cuda.set_device(0)
+    K, N = args.K, args.N
+    spec = W.sv(K)
+    model = G.Model(spec)
+    plan = G.Plan(N, 1, K, graph=True)
+    out = G.alloc_output(plan, K)
+    star = torch.tensor(spec.x_true.T.copy(), dtype=torch.float32, device="cuda")
+    pick = np.random.default_rng(7)
+
+    def sweep(seed):
+        G.dsmc_smooth_conditional(plan, model, seed, star, out)
+        j = int(pick.integers(N))
+        star.copy_(out.traj[:, :, j])
+
+    for s in range(max(2, args.warmup)):
+        sweep(1000 + s)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for s in range(args.steps):
+        sweep(s + 1)
+    torch.cuda.synchronize()
+    dt = (time.perf_counter() - t0) / args.steps
+    status = int(out.status.item())
+    if status:
+        raise RuntimeError(f"device status {status}")
+    # one more sweep with a known star: it must come back in slot 0
+    before = star.clone()
+    G.dsmc_smooth_conditional(plan, model, 77, star, out)
+    torch.cuda.synchronize()
+    if not torch.equal(out.traj[:, :, 0], before):
+        raise RuntimeError("star trajectory not kept in slot 0")
+    for s in range(max(2, args.warmup)):
+        G.dsmc_smooth(plan, model, 1000 + s, out)
+    torch.cuda.synchronize()
+    t1 = time.perf_counter()
+    for s in range(args.steps):
+        G.dsmc_smooth(plan, model, s + 1, out)
+    torch.cuda.synchronize()
+    dt_plain = (time.perf_counter() - t1) / args.steps
+    pairs = (K - 1) * N * N
+    res = {"metric": "pair-evals/sec", "value": pairs / dt, "unit": "pair-evals/s", "n_gpus": 1,
+           "steps": args.steps, "warmup": args.warmup, "ms_per_step": dt * 1e3,
+           "higher_is_better": True, "scaling": "weak", "vs_baseline": None, "dtype": "f32",
+           "data": "synthetic",
+           "config": {"workload": f"particle Gibbs sweeps of conditional dSMC, stochastic "
+                                  f"volatility, K={K}, N={N}, fixed parameters",
+                      "K": K, "N": N, "d_x": 1},
+           "sweeps_per_sec": 1.0 / dt, "unconditional_ms_per_step": dt_plain * 1e3,
+           "conditional_overhead": dt / dt_plain - 1.0}
+    print(json.dumps(res))
+
+
 def main():
     args = parse()
     if args.gpus != 1:
@@ -375,6 +441,8 @@ def main():
         return bench_highdim(args)
     if args.workload == "batch":
         return bench_batch(args)
+    if args.workload == "pgibbs":
+        return bench_pgibbs(args)
     import torch
 
     from paper_2202_02264_amd import dsmc as G
