@@ -13,6 +13,10 @@ Steps, in the paper's order:
 * ``schedule``        Algorithm 6 (parallel combination by array reshaping):
                       the balanced tree actually executed.
 * ``smooth``          leaves, then the tree, then the output.
+* ``mh_resampling`` / ``rs_resampling``  the lazy resampling of Section 4.2,
+                      Algorithms 7 (Metropolis-Hastings, B steps) and 8
+                      (rejection), which replace the multinomial draw of
+                      Algorithm 1; ``smooth_lazy`` runs the tree with them.
 * ``smooth_conditional``  conditional dSMC (Section 3.1): the initialisation of
                       Algorithm 2 with a star trajectory put in front of the
                       proposal draws, and Algorithm 4 (conditional block
@@ -40,6 +44,13 @@ Readings of the paper this file takes:
   cumulative sums, so zero-weight entries are never drawn.
 * If every pair weight of a combine is zero the increment is -inf, the status
   is "degenerate" and indices are drawn uniformly: l = floor(u1 N), r = floor(u2 N).
+* Lazy resampling targets the product-form weight W_c^{mn} (its log is the
+  pair matrix S), which is Algorithms 7 and 8's omega_c when the block weights
+  are uniform.  Proposal k of chain n comes from Philox block
+  (n, c, 4 (MH) or 5 (RS), k).  The rejection bound is
+  max_m a_m + max_n b_n + max log p_c, a bound of every realised pair weight.
+  The rejection loop stops after `cap` proposals (the last one is kept and the
+  run flagged).  No increment is estimated: Z_c is NaN.
 * Conditional runs: the star trajectory takes slot 0 (the paper's slot 1) and
   slot n >= 1 holds the proposal draw an unconditional run puts there; the N - 1
   draws of Algorithm 4 are those of slots 1..N-1 (uniforms of counter n), and
@@ -134,6 +145,7 @@ class CombineResult:
     Z: float                 # log of the normalising-constant increment
     degenerate: bool
     S: np.ndarray | None = None
+    capped: bool = False     # lazy rejection: some chain hit its proposal cap
 
 
 def pair_logweights(spec, c: int, xL, xR, lwL, lwR) -> np.ndarray:
@@ -231,6 +243,7 @@ class SmoothResult:
     idx: np.ndarray          # (K, N) leaf index of every output entry
     degenerate: bool = False
     levels: list = field(default_factory=list)
+    capped: bool = False
 
 
 def run_tree(spec, leaves: Leaves, seed: int, conditional: bool = False) -> SmoothResult:
@@ -305,3 +318,100 @@ def smooth_conditional(spec, N: int, seed: int, star) -> SmoothResult:
     Algorithm 4 at every node.  Output slot 0 is the star trajectory; log Z is
     computed as in the unconditional run, over all particles."""
     return run_tree(spec, sample_leaves_conditional(spec, N, seed, star), seed, conditional=True)
+
+
+# --------------------------------------------------------------------------
+# Lazy resampling: Section 4.2, Algorithms 7 and 8
+# --------------------------------------------------------------------------
+
+def mh_resampling(S: np.ndarray, seed: int, c: int, B: int):
+    """Algorithm 7 on the log pair weights S (N x N, target proportional to
+    exp S): chain n starts at (n, n) and takes B Metropolis-Hastings steps with
+    a proposal uniform over the N^2 pairs, moving when u < W(I*, J*) / W(I, J)."""
+    N = S.shape[0]
+    I, J = np.arange(N), np.arange(N)
+    with np.errstate(invalid="ignore", over="ignore"):
+        for b in range(B):
+            Ip, Jp, u = philox.lazy_proposals(seed, c, N, philox.PURPOSE_LAZY_MH, b)
+            move = u < np.exp(S[Ip, Jp] - S[I, J])
+            I = np.where(move, Ip, I)
+            J = np.where(move, Jp, J)
+    return I, J
+
+
+def rs_resampling(S: np.ndarray, log_bound: float, seed: int, c: int, cap: int):
+    """Algorithm 8 on the log pair weights S with log_bound >= max S: chain n
+    proposes (I, J) uniformly over the N^2 pairs until u < W(I, J) / W_bar.
+    Returns (I, J, capped): after `cap` proposals a chain keeps its last
+    proposal and is marked capped."""
+    N = S.shape[0]
+    I = np.zeros(N, dtype=np.int64)
+    J = np.zeros(N, dtype=np.int64)
+    done = np.zeros(N, dtype=bool)
+    for k in range(cap):
+        Ip, Jp, u = philox.lazy_proposals(seed, c, N, philox.PURPOSE_LAZY_RS, k)
+        open_ = ~done
+        I[open_], J[open_] = Ip[open_], Jp[open_]
+        done |= open_ & (u < np.exp(S[Ip, Jp] - log_bound))
+        if done.all():
+            break
+    return I, J, ~done
+
+
+def rs_log_bound(spec, c: int, xR, lwL, lwR) -> float:
+    """max_m a_m + max_n b_n + max_{x, x'} log p_c(x' | x): every pair weight of
+    the combine is at most its exponential (the Gaussian transition density
+    peaks at zero residual)."""
+    b = lwR - log_proposal(spec, c, xR)
+    if spec.weighting == "boundary_obs":
+        b = b + log_potential(spec, c, xR)
+    d = spec.d_x
+    log_pmax = -np.sum(np.log(np.diag(spec.Q_chol))) - 0.5 * d * np.log(2.0 * np.pi)
+    return float(np.max(lwL) + np.max(b) + log_pmax)
+
+
+def lazy_combine(spec, c: int, xL, xR, lwL, lwR, seed: int, scheme: str, param: int,
+                 keep_S: bool = False) -> CombineResult:
+    """Algorithm 1 with its multinomial draw replaced by Algorithm 7 (scheme
+    "mh", param = B) or Algorithm 8 (scheme "rs", param = cap).  The pair
+    weights are formed here only to evaluate the proposed pairs; row sums and
+    Z_c are not estimated (NaN)."""
+    N = xL.shape[0]
+    xL, xR = np.asarray(xL, np.float64), np.asarray(xR, np.float64)
+    lwL, lwR = np.asarray(lwL, np.float64), np.asarray(lwR, np.float64)
+    S = pair_logweights(spec, c, xL, xR, lwL, lwR)
+    capped = False
+    if scheme == "mh":
+        l, r = mh_resampling(S, seed, c, param)
+    elif scheme == "rs":
+        l, r, cap_hit = rs_resampling(S, rs_log_bound(spec, c, xR, lwL, lwR), seed, c, param)
+        capped = bool(cap_hit.any())
+    else:
+        raise ValueError(scheme)
+    return CombineResult(l, r, np.full(N, np.nan), float("nan"), False, S if keep_S else None,
+                         capped=capped)
+
+
+def smooth_lazy(spec, N: int, seed: int, scheme: str, param: int) -> SmoothResult:
+    """Leaves (Algorithm 2), then the tree of Algorithm 6 with lazy combines."""
+    leaves = sample_leaves(spec, N, seed)
+    K = spec.K
+    blocks = {t: Block(t, t + 1, leaves.x[t:t + 1], leaves.logw[t].copy(), float(leaves.logL[t]),
+                       np.arange(N)[None, :].copy()) for t in range(K)}
+    anc = np.zeros((max(K - 1, 0), 2, N), dtype=np.int64)
+    capped = False
+    levels = schedule(K)
+    for nodes in levels:
+        for (a, c, b) in nodes:
+            L, R = blocks.pop(a), blocks.pop(c)
+            res = lazy_combine(spec, c, L.x[-1], R.x[0], L.logw, R.logw, seed, scheme, param)
+            capped |= res.capped
+            anc[c - 1, 0], anc[c - 1, 1] = res.l, res.r
+            x = np.concatenate([L.x[:, res.l], R.x[:, res.r]], axis=0)
+            idx = np.concatenate([L.idx[:, res.l], R.idx[:, res.r]], axis=0)
+            blocks[a] = Block(a, b, x, np.full(N, -np.log(N)), float("nan"), idx)
+    top = blocks[0]
+    return SmoothResult(x=top.x, logw=top.logw, logZ=top.logL if K > 1 else float(leaves.logL[0]),
+                        leaves=leaves, ancestry=anc, Zc=np.full(max(K - 1, 0), np.nan),
+                        row_lse=np.full((max(K - 1, 0), N), np.nan), idx=top.idx,
+                        degenerate=leaves.degenerate, levels=levels, capped=capped)

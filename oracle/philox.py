@@ -29,6 +29,8 @@ import numpy as np
 KEY1 = 0x64534D43
 PURPOSE_LEAF = 2
 PURPOSE_COMBINE = 3
+PURPOSE_LAZY_MH = 4
+PURPOSE_LAZY_RS = 5
 
 _M0 = np.uint64(0xD2E7470EE14C6C93)
 _M1 = np.uint64(0xCA5A826395121157)
@@ -100,3 +102,14 @@ def combine_uniforms(seed: int, c: int, N: int):
     n = np.arange(N, dtype=np.uint64)
     w = philox4x64_10((n, np.uint64(c), np.uint64(PURPOSE_COMBINE), np.uint64(0)), key_of(seed))
     return to_uniform(w[0]), to_uniform(w[1])
+
+
+def lazy_proposals(seed: int, c: int, N: int, purpose: int, step: int):
+    """Proposal `step` of the N lazy-resampling chains at boundary c: indices
+    I*, J* uniform on {0..N-1} (floor of a 53-bit uniform times N) from words
+    0 and 1 of block (n, c, purpose, step), and u in [0, 1) from word 2."""
+    n = np.arange(N, dtype=np.uint64)
+    w = philox4x64_10((n, np.uint64(c), np.uint64(purpose), np.uint64(step)), key_of(seed))
+    I = np.minimum((to_uniform(w[0]) * N).astype(np.int64), N - 1)
+    J = np.minimum((to_uniform(w[1]) * N).astype(np.int64), N - 1)
+    return I, J, to_uniform(w[2])
