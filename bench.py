@@ -56,11 +56,12 @@ def parse():
                     help="wall-clock budget of the oracle baseline sample (0 = skip)")
     ap.add_argument("--no-kernel-events", action="store_true",
                     help="time the steps without per-kernel HIP events")
-    ap.add_argument("--workload", choices=("sv", "batch", "serve", "highdim", "pgibbs"),
+    ap.add_argument("--workload", choices=("sv", "batch", "serve", "highdim", "pgibbs", "lazy"),
                     default="sv",
                     help="sv: one long stochastic-volatility series (default); batch: "
                          "B linear-Gaussian series of uneven length, packed vs one at a time; "
-                         "pgibbs: particle Gibbs sweeps of conditional dSMC on the sv series")
+                         "pgibbs: particle Gibbs sweeps of conditional dSMC on the sv series; "
+                         "lazy: lazy resampling (MH, rejection) vs exact on the sv series")
     ap.add_argument("--B", type=int, default=512)
     ap.add_argument("--jobs", type=int, default=600, help="serving: jobs per arrival run")
     ap.add_argument("--rates", type=str, default="0.25,0.5,0.75,0.9,1.1",
@@ -421,6 +422,49 @@ def bench_pgibbs(args):
     print(json.dumps(res))
 
 
+def bench_lazy(args):
+    """Lazy resampling (Section 4.2) on the stochastic-volatility workload:
+    whole smoother runs with Algorithm 7 (Metropolis-Hastings, B steps per
+    draw) or Algorithm 8 (rejection) in every combine, beside the exact
+    multinomial draw of Algorithm 1.  Lazy runs estimate no log L^N."""
+    import torch
+
+    from paper_2202_02264_amd import dsmc as G
+    from paper_2202_02264_amd import workloads as W
+    torch.cuda.set_device(0)
+    K, N = args.K, args.N
+    spec = W.sv(K)
+    model = G.Model(spec)
+    runs = {}
+    for name, scheme, param, steps in (("exact", G.DSMC_RESAMPLE_EXACT, 0, args.steps),
+                                       ("mh_B8", G.DSMC_RESAMPLE_MH, 8, args.steps),
+                                       ("mh_B32", G.DSMC_RESAMPLE_MH, 32, args.steps),
+                                       ("rs", G.DSMC_RESAMPLE_RS, 0, max(1, min(args.steps, 3)))):
+        plan = G.Plan(N, 1, K, graph=True, resampling=scheme, lazy_param=param)
+        out = G.alloc_output(plan, K)
+        for s in range(2):
+            G.dsmc_smooth(plan, model, 1000 + s, out)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        for s in range(steps):
+            G.dsmc_smooth(plan, model, s + 1, out)
+        torch.cuda.synchronize()
+        dt = (time.perf_counter() - t0) / steps
+        runs[name] = {"ms_per_step": dt * 1e3, "steps": steps,
+                      "status": int(out.status.item())}
+        print(f"# lazy {name}: {dt * 1e3:.3f} ms/step", file=sys.stderr, flush=True)
+        del plan, out
+    mh = runs["mh_B32"]
+    res = {"metric": "smoothers/sec", "value": 1e3 / mh["ms_per_step"], "unit": "smoothers/s",
+           "n_gpus": 1, "steps": mh["steps"], "warmup": 2, "ms_per_step": mh["ms_per_step"],
+           "higher_is_better": True, "scaling": "weak", "vs_baseline": None, "dtype": "f32",
+           "data": "synthetic",
+           "config": {"workload": f"lazy resampling (Metropolis-Hastings, B=32), stochastic "
+                                  f"volatility, K={K}, N={N}", "K": K, "N": N, "d_x": 1},
+           "runs": runs}
+    print(json.dumps(res))
+
+
 def main():
     args = parse()
     if args.gpus != 1:
@@ -443,6 +487,8 @@ def main():
         return bench_batch(args)
     if args.workload == "pgibbs":
         return bench_pgibbs(args)
+    if args.workload == "lazy":
+        return bench_lazy(args)
     import torch
 
     from paper_2202_02264_amd import dsmc as G

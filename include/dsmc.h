@@ -74,6 +74,7 @@ typedef enum dsmc_status {
 /* Bits written to dsmc_output.status by the device (0 = clean run). */
 #define DSMC_FLAG_DEGENERATE 1 /* some combine (or leaf) had total weight 0; log_Z = -inf */
 #define DSMC_FLAG_NUMERIC 2    /* a NaN weight was met; outputs are undefined */
+#define DSMC_FLAG_LAZY_CAP 4   /* a rejection draw hit its proposal cap (DSMC_RESAMPLE_RS) */
 
 /* Largest state dimension and particle count the library accepts. */
 #define DSMC_MAX_DX 32
@@ -167,7 +168,33 @@ typedef struct dsmc_plan_desc {
   int precision;   /* DSMC_FP32, DSMC_FP64 or DSMC_BF16 */
   int flags;       /* DSMC_PLAN_* */
   void *stream;    /* hipStream_t all work is enqueued on; NULL = null stream */
+  int resampling;  /* DSMC_RESAMPLE_*: how each combine draws its N index pairs */
+  int lazy_param;  /* DSMC_RESAMPLE_MH: steps B per draw (0 = DSMC_MH_STEPS_DEFAULT);
+                      DSMC_RESAMPLE_RS: proposals per draw before giving up
+                      (0 = DSMC_RS_CAP_DEFAULT) */
 } dsmc_plan_desc;
+
+/* Resampling of a combine.  EXACT: Algorithm 1's multinomial draw from all
+ * N x N pair weights (pair-row pass, then two-stage inverse CDF); Z_c and
+ * log L^N are computed.  The lazy schemes of Section 4.2 run no pair-row pass
+ * and evaluate only the pairs they propose, O(N * steps) work per combine:
+ *   MH  Algorithm 7: draw n is a Metropolis-Hastings chain started at (n, n)
+ *       with proposals uniform over the N^2 pairs, `lazy_param` steps; it
+ *       targets W_c but is biased after finitely many steps.
+ *   RS  Algorithm 8: draw n proposes pairs uniformly and accepts with
+ *       probability W_c(pair) / W_bar, W_bar = max_m w_m * max_n w'_n * max p_c
+ *       (a bound of every pair weight of the combine); exact multinomial draws
+ *       with random run time.  A draw still rejecting after `lazy_param`
+ *       proposals keeps its last proposal and sets DSMC_FLAG_LAZY_CAP.
+ * Proposal k of draw n at boundary c uses Philox block (n, c, 4 (MH) or
+ * 5 (RS), k): I = floor(u0 N), J = floor(u1 N), acceptance uniform u2.
+ * Lazy plans estimate no increment: logZ_inc, row_lse and log_Z are NaN.
+ * Conditional runs keep slot 0 as in EXACT plans. */
+#define DSMC_RESAMPLE_EXACT 0
+#define DSMC_RESAMPLE_MH 1
+#define DSMC_RESAMPLE_RS 2
+#define DSMC_MH_STEPS_DEFAULT 32
+#define DSMC_RS_CAP_DEFAULT (1 << 20)
 
 typedef struct dsmc_plan_impl dsmc_plan_t;
 
@@ -178,6 +205,12 @@ typedef struct dsmc_plan_impl dsmc_plan_t;
  * DSMC_BF16 adds max_total_K * N * (8 d_x + 16) bytes of bf16 operands.
  * Errors: DSMC_EINVAL, DSMC_EUNSUPPORTED (also DSMC_BF16 with d_x <= 8),
  * DSMC_ENOMEM. */
+/* Number of GPUs the library's HIP runtime sees (*count, 0 on error).
+ * A process that also uses another copy of the HIP runtime (PyTorch ships
+ * its own) must load that copy before this library.  Errors: DSMC_EINVAL
+ * (null count), DSMC_EDEVICE (no GPU). */
+int dsmc_device_count(int *count);
+
 int dsmc_plan(const dsmc_plan_desc *desc, dsmc_plan_t **out);
 void dsmc_plan_destroy(dsmc_plan_t *plan);
 

@@ -324,38 +324,55 @@ def smooth_conditional(spec, N: int, seed: int, star) -> SmoothResult:
 # Lazy resampling: Section 4.2, Algorithms 7 and 8
 # --------------------------------------------------------------------------
 
-def mh_resampling(S: np.ndarray, seed: int, c: int, B: int):
+def _margin(u, num, den):
+    """Distance of the decision u < exp(num - den) from flipping, in units of
+    the magnitudes of its log terms (for comparisons with other precisions)."""
+    with np.errstate(divide="ignore", invalid="ignore"):
+        m = np.abs(np.log(u) - (num - den)) / (np.maximum(1.0, np.abs(num)) + np.maximum(1.0, np.abs(den)))
+    return np.where(np.isfinite(m), m, np.inf)
+
+
+def mh_resampling(S: np.ndarray, seed: int, c: int, B: int, margins: bool = False):
     """Algorithm 7 on the log pair weights S (N x N, target proportional to
     exp S): chain n starts at (n, n) and takes B Metropolis-Hastings steps with
-    a proposal uniform over the N^2 pairs, moving when u < W(I*, J*) / W(I, J)."""
+    a proposal uniform over the N^2 pairs, moving when u < W(I*, J*) / W(I, J).
+    With ``margins`` also returns each chain's smallest decision margin."""
     N = S.shape[0]
     I, J = np.arange(N), np.arange(N)
+    mg = np.full(N, np.inf)
     with np.errstate(invalid="ignore", over="ignore"):
         for b in range(B):
             Ip, Jp, u = philox.lazy_proposals(seed, c, N, philox.PURPOSE_LAZY_MH, b)
             move = u < np.exp(S[Ip, Jp] - S[I, J])
+            if margins:
+                mg = np.minimum(mg, _margin(u, S[Ip, Jp], S[I, J]))
             I = np.where(move, Ip, I)
             J = np.where(move, Jp, J)
-    return I, J
+    return (I, J, mg) if margins else (I, J)
 
 
-def rs_resampling(S: np.ndarray, log_bound: float, seed: int, c: int, cap: int):
+def rs_resampling(S: np.ndarray, log_bound: float, seed: int, c: int, cap: int,
+                  margins: bool = False):
     """Algorithm 8 on the log pair weights S with log_bound >= max S: chain n
     proposes (I, J) uniformly over the N^2 pairs until u < W(I, J) / W_bar.
     Returns (I, J, capped): after `cap` proposals a chain keeps its last
-    proposal and is marked capped."""
+    proposal and is marked capped.  With ``margins`` also each chain's
+    smallest decision margin."""
     N = S.shape[0]
     I = np.zeros(N, dtype=np.int64)
     J = np.zeros(N, dtype=np.int64)
     done = np.zeros(N, dtype=bool)
+    mg = np.full(N, np.inf)
     for k in range(cap):
         Ip, Jp, u = philox.lazy_proposals(seed, c, N, philox.PURPOSE_LAZY_RS, k)
         open_ = ~done
         I[open_], J[open_] = Ip[open_], Jp[open_]
+        if margins:
+            mg[open_] = np.minimum(mg[open_], _margin(u, S[Ip, Jp], log_bound)[open_])
         done |= open_ & (u < np.exp(S[Ip, Jp] - log_bound))
         if done.all():
             break
-    return I, J, ~done
+    return (I, J, ~done, mg) if margins else (I, J, ~done)
 
 
 def rs_log_bound(spec, c: int, xR, lwL, lwR) -> float:
@@ -371,7 +388,7 @@ def rs_log_bound(spec, c: int, xR, lwL, lwR) -> float:
 
 
 def lazy_combine(spec, c: int, xL, xR, lwL, lwR, seed: int, scheme: str, param: int,
-                 keep_S: bool = False) -> CombineResult:
+                 keep_S: bool = False, margins: bool = False) -> CombineResult:
     """Algorithm 1 with its multinomial draw replaced by Algorithm 7 (scheme
     "mh", param = B) or Algorithm 8 (scheme "rs", param = cap).  The pair
     weights are formed here only to evaluate the proposed pairs; row sums and
@@ -381,15 +398,22 @@ def lazy_combine(spec, c: int, xL, xR, lwL, lwR, seed: int, scheme: str, param: 
     lwL, lwR = np.asarray(lwL, np.float64), np.asarray(lwR, np.float64)
     S = pair_logweights(spec, c, xL, xR, lwL, lwR)
     capped = False
+    mg = None
     if scheme == "mh":
-        l, r = mh_resampling(S, seed, c, param)
+        out = mh_resampling(S, seed, c, param, margins=margins)
+        l, r = out[0], out[1]
+        mg = out[2] if margins else None
     elif scheme == "rs":
-        l, r, cap_hit = rs_resampling(S, rs_log_bound(spec, c, xR, lwL, lwR), seed, c, param)
-        capped = bool(cap_hit.any())
+        out = rs_resampling(S, rs_log_bound(spec, c, xR, lwL, lwR), seed, c, param,
+                            margins=margins)
+        l, r, capped = out[0], out[1], bool(out[2].any())
+        mg = out[3] if margins else None
     else:
         raise ValueError(scheme)
-    return CombineResult(l, r, np.full(N, np.nan), float("nan"), False, S if keep_S else None,
-                         capped=capped)
+    res = CombineResult(l, r, np.full(N, np.nan), float("nan"), False, S if keep_S else None,
+                        capped=capped)
+    res.margin = mg
+    return res
 
 
 def smooth_lazy(spec, N: int, seed: int, scheme: str, param: int) -> SmoothResult:

@@ -212,6 +212,7 @@ struct dsmc_plan_impl {
   int Npad = 0, Nc = 0, NcP = 0;
   int node_cap = 0;  // combines per launch slice
   bool autotune = false;
+  int lazy_param = 0;  // MH steps or rejection cap actually used (defaults resolved)
   // device workspace: per time row
   void* leafX = nullptr;
   void* leafW = nullptr;
@@ -291,11 +292,18 @@ extern "C" int dsmc_plan(const dsmc_plan_desc* d, dsmc_plan_t** out) {
     return fail(DSMC_EUNSUPPORTED, "precision %d not supported", d->precision);
   if (d->precision == DSMC_BF16 && padded_dx(d->d_x) < 16)
     return fail(DSMC_EUNSUPPORTED, "DSMC_BF16 needs d_x >= 9 (got %d)", d->d_x);
+  if (d->resampling != DSMC_RESAMPLE_EXACT && d->resampling != DSMC_RESAMPLE_MH &&
+      d->resampling != DSMC_RESAMPLE_RS)
+    return fail(DSMC_EINVAL, "resampling %d not supported", d->resampling);
+  if (d->lazy_param < 0) return fail(DSMC_EINVAL, "lazy_param must be >= 0");
   auto* p = new dsmc_plan_t;
   p->d = *d;
   if (p->d.max_total_K < p->d.max_K) p->d.max_total_K = p->d.max_K;
   p->DX = padded_dx(d->d_x);
   p->fp64 = d->precision == DSMC_FP64;
+  p->lazy_param = d->lazy_param ? d->lazy_param
+                                : (d->resampling == DSMC_RESAMPLE_MH ? DSMC_MH_STEPS_DEFAULT
+                                                                     : DSMC_RS_CAP_DEFAULT);
   p->bf16 = d->precision == DSMC_BF16;
   p->rsz = p->fp64 ? 8 : 4;
   p->stream = (hipStream_t)d->stream;
@@ -803,12 +811,15 @@ static int enqueue_batch(dsmc_plan_t* p, int B, int totalK, hipStream_t st) {
       // sampling: enough workgroups to cover the chip when a level has few combines
       const int ds_max = std::max(1, (N + 127) / 128);
       L.DS = nodes >= 256 ? 1 : (int)std::min<long>(ds_max, (512 + nodes - 1) / nodes);
+      L.lazy = p->d.resampling;
+      L.lazy_param = p->lazy_param;
       auto it = p->tiles.find(nodes);
       TileChoice tc;
       if (it != p->tiles.end()) {
         tc = it->second;
-      } else {
-        tc = p->autotune ? autotune_tile(p, L) : heuristic_tile(nodes, N, p->Nc, p->DX < 8);
+      } else {  // lazy plans run no pair-row kernel: nothing to tune
+        tc = (p->autotune && !L.lazy) ? autotune_tile(p, L)
+                                      : heuristic_tile(nodes, N, p->Nc, p->DX < 8);
         p->tiles[nodes] = tc;
       }
       set_tile(L, tc);
@@ -840,6 +851,15 @@ extern "C" int dsmc_schedule(int K, int cap, int32_t* a, int32_t* c, int32_t* b,
       level[id] = (int32_t)l;
     }
   return (int)nodes.size();
+}
+
+extern "C" int dsmc_device_count(int* count) {
+  if (!count) return fail(DSMC_EINVAL, "null count");
+  *count = 0;
+  int n = 0;
+  if (hipGetDeviceCount(&n) != hipSuccess || n < 1) return fail(DSMC_EDEVICE, "no GPU visible");
+  *count = n;
+  return DSMC_OK;
 }
 
 extern "C" int dsmc_smooth_batch(dsmc_plan_t* p, int B, const dsmc_model_t* const* models,

@@ -20,6 +20,8 @@ constexpr uint64_t kPhiloxW1 = 0xBB67AE8584CAA73Bull;
 constexpr uint64_t kKey1 = 0x64534D43ull;  // second key word of every stream
 constexpr uint64_t kPurposeLeaf = 2;
 constexpr uint64_t kPurposeCombine = 3;
+constexpr uint64_t kPurposeLazyMH = 4;  // Metropolis-Hastings lazy resampling proposals
+constexpr uint64_t kPurposeLazyRS = 5;  // rejection lazy resampling proposals
 
 struct Words4 {
   uint64_t w0, w1, w2, w3;

@@ -96,6 +96,6 @@ struct NodeBufs {
   float* trown;     // [rows][N]      bf16 plans: ||v||^2
 };
 
-enum : int32_t { kFlagDegenerate = 1, kFlagNumeric = 2 };
+enum : int32_t { kFlagDegenerate = 1, kFlagNumeric = 2, kFlagLazyCap = 4 };
 
 }  // namespace dsmc

@@ -842,6 +842,31 @@ __device__ __forceinline__ void load4<double>(const double* p, double (&q)[4]) {
   q[0] = a.x; q[1] = a.y; q[2] = b.x; q[3] = b.y;
 }
 
+// Draw n of combine `nodeid` is (l, r): its ancestry, the merged block's
+// first/last-time leaf indices, and the data the consuming combine reads.
+template <typename R, int DX>
+__device__ __forceinline__ void record_draw(const NodeBufs& nb, const NodeDesc& nd, int nodeid,
+                                            int N, int Npad, int n, int l, int r,
+                                            int32_t* ancL, int32_t* ancR, int gA, int gB,
+                                            double logN, const double* __restrict__ bmerged) {
+  ancL[n] = l;
+  ancR[n] = r;
+  const int sf = (nd.lchild < 0) ? l : nb.sfirst[(size_t)nd.lchild * N + l];
+  const int sl = (nd.rchild < 0) ? r : nb.slast[(size_t)nd.rchild * N + r];
+  nb.sfirst[(size_t)nodeid * N + n] = sf;
+  nb.slast[(size_t)nodeid * N + n] = sl;
+  const int cons = nd.consumer;
+  if (cons >= 0) {
+    if (nd.role == 1) {  // merged block is the right block of `cons` (boundary a)
+      const double b = -logN + nb.tgq[(size_t)gA * N + sf];
+      copy_col<R, DX>(nb, (size_t)cons, Npad, n, (size_t)gA, N, sf, (b - bmerged[gA]) * kLog2e);
+    } else {  // merged block is the left block of `cons` (boundary b)
+      copy_row<R, DX>(nb, (size_t)cons, Npad, n, (size_t)gB, N, sl);
+      ((R*)nb.alpha)[(size_t)cons * N + n] = (R)(-logN);
+    }
+  }
+}
+
 template <typename R, int DX>
 __global__ __launch_bounds__(kBlock) void k_sample(
     const NodeDesc* __restrict__ nodes, const SeriesDesc* __restrict__ series,
@@ -1145,23 +1170,111 @@ __global__ __launch_bounds__(kBlock) void k_sample(
       l = 0;
       r = 0;
     }
-    ancL[n] = l;
-    ancR[n] = r;
-    // ancestry of the merged block at its first and last times
-    const int sf = left_leaf ? l : nb.sfirst[(size_t)nd.lchild * N + l];
-    const int sl = (nd.rchild < 0) ? r : nb.slast[(size_t)nd.rchild * N + r];
-    nb.sfirst[(size_t)nodeid * N + n] = sf;
-    nb.slast[(size_t)nodeid * N + n] = sl;
-    if (cons >= 0) {
-      if (crole == 1) {  // merged block is the right block of `cons` (boundary ca)
-        const double b = -logN + nb.tgq[(size_t)gA * N + sf];
-        copy_col<R, DX>(nb, (size_t)cons, Npad, n, (size_t)gA, N, sf, (b - bmerged[gA]) * kLog2e);
-      } else {  // merged block is the left block of `cons` (boundary cb)
-        copy_row<R, DX>(nb, (size_t)cons, Npad, n, (size_t)gB, N, sl);
-        ((R*)nb.alpha)[(size_t)cons * N + n] = (R)(-logN);
-      }
+    record_draw<R, DX>(nb, nd, nodeid, N, Npad, n, l, r, ancL, ancR, gA, gB, logN, bmerged);
+  }
+}
+
+
+// ========================================================= lazy sampling
+// Lazy resampling of one combine (Section 4.2): the N index pairs are drawn
+// without the pair-row pass, by N independent chains that evaluate only the
+// pairs they propose.  lazy == 1: Algorithm 7, `param` Metropolis-Hastings
+// steps from (n, n) with proposals uniform over the N^2 pairs; lazy == 2:
+// Algorithm 8, rejection from uniform proposals against the bound
+// max_m a_m + max_n b_n + max log p_c (at most `param` proposals per chain).
+// The target is the pair weight exp(a_m) 2^(beta_n - ||u_n - v_m||^2) relative
+// to that bound.  No increment is estimated (Z_c = NaN).
+template <typename R, int DX>
+__global__ __launch_bounds__(kBlock) void k_sample_lazy(
+    const NodeDesc* __restrict__ nodes, const SeriesDesc* __restrict__ series,
+    const int32_t* __restrict__ node_list, int node0, int DS, int N, int Npad, int lazy,
+    int param, const double* __restrict__ bmerged, NodeBufs nb) {
+  __shared__ double red[2 * kBlock / 64];
+  const int node_local = blockIdx.x / DS;
+  const int ds = blockIdx.x - node_local * DS;
+  const int nodeid = node_list ? node_list[node_local] : node0 + node_local;
+  const NodeDesc nd = nodes[nodeid];
+  const SeriesDesc& sd = series[nd.series];
+  const int c = nd.c;
+  const bool left_leaf = nd.lchild < 0;
+  const double logN = log((double)N);
+  const R* __restrict__ colp = (const R*)nb.col + (size_t)nodeid * Npad * (DX + 1);
+  const R* __restrict__ rowp = (const R*)nb.row + (size_t)nodeid * Npad * DX;
+  const R* __restrict__ alp = (const R*)nb.alpha + (size_t)nodeid * N;
+  // the bound: max_m a_m, and max_n beta_n (the column shift B can exceed the
+  // block's own maximum for a merged right block)
+  double Astar = left_leaf ? -INFINITY : -logN, bmax = -INFINITY;
+  for (int m = threadIdx.x; m < N; m += kBlock) {
+    if (left_leaf) Astar = fmax(Astar, (double)alp[m]);
+    bmax = fmax(bmax, (double)colp[(size_t)m * (DX + 1) + DX]);
+  }
+  block_max2(Astar, bmax, red);
+  const int cons = nd.consumer;
+  const int gA = sd.base + nd.a, gB = sd.base + nd.b - 1;
+  if (ds == 0) {
+    if (threadIdx.x == 0) sd.zinc[c - 1] = __builtin_nan("");
+    if (sd.row_lse) {
+      double* rl = sd.row_lse + (size_t)(c - 1) * N;
+      for (int m = threadIdx.x; m < N; m += kBlock) rl[m] = __builtin_nan("");
+    }
+    if (cons >= 0 && nd.role == 1) {
+      for (int n = N + threadIdx.x; n < Npad; n += kBlock) put_col_pad<R, DX>(nb, (size_t)cons, Npad, n);
+      if (threadIdx.x == 0) nb.bcol[cons] = bmerged[gA];
     }
   }
+  // natural log of pair (i, j)'s weight relative to the rejection bound
+  auto logw = [&](int i, int j) -> double {
+    R v[DX], u[DX];
+#pragma unroll
+    for (int d = 0; d < DX; ++d) {
+      v[d] = rowp[(size_t)i * DX + d];
+      u[d] = colp[(size_t)j * (DX + 1) + d];
+    }
+    const double a = left_leaf ? (double)alp[i] : -logN;
+    return (a - Astar) +
+           kLn2 * ((double)pair_log2w<R, DX>(u, colp[(size_t)j * (DX + 1) + DX], v) - bmax);
+  };
+  const uint64_t purpose = (lazy == 1) ? kPurposeLazyMH : kPurposeLazyRS;
+  const int dper = (N + DS - 1) / DS;
+  const int n0 = ds * dper, n1 = min(N, n0 + dper);
+  int32_t* ancL = sd.anc + (size_t)(c - 1) * 2 * N;
+  int32_t* ancR = ancL + N;
+  int capped = 0, bad = 0;
+  for (int n = n0 + threadIdx.x; n < n1; n += kBlock) {
+    int l = n, r = n;
+    if (lazy == 1) {
+      double cur = logw(l, r);
+      for (int b = 0; b < param; ++b) {
+        const Words4 w = philox4x64_10((uint64_t)n, (uint64_t)c, purpose, (uint64_t)b, sd.seed, kKey1);
+        const int ip = min((int)(unif53(w.w0) * N), N - 1);
+        const int jp = min((int)(unif53(w.w1) * N), N - 1);
+        const double prop = logw(ip, jp);
+        if (unif53(w.w2) < exp(prop - cur)) {
+          l = ip;
+          r = jp;
+          cur = prop;
+        }
+      }
+      if (isnan(cur)) bad = 1;
+    } else {
+      bool done = false;
+      for (int k = 0; k < param && !done; ++k) {
+        const Words4 w = philox4x64_10((uint64_t)n, (uint64_t)c, purpose, (uint64_t)k, sd.seed, kKey1);
+        l = min((int)(unif53(w.w0) * N), N - 1);
+        r = min((int)(unif53(w.w1) * N), N - 1);
+        const double lw = logw(l, r);
+        if (isnan(lw)) bad = 1;
+        done = unif53(w.w2) < exp(lw);
+      }
+      if (!done) capped = 1;
+    }
+    if (n == 0 && sd.star != nullptr) {  // conditional combine: slot 0 keeps the star
+      l = 0;
+      r = 0;
+    }
+    record_draw<R, DX>(nb, nd, nodeid, N, Npad, n, l, r, ancL, ancR, gA, gB, logN, bmerged);
+  }
+  if (capped || bad) atomicOr(sd.status, (capped ? kFlagLazyCap : 0) | (bad ? kFlagNumeric : 0));
 }
 
 // =============================================================== output
@@ -1275,6 +1388,14 @@ static int launch_rows_t(const LevelLaunch& L, hipStream_t st) {
 
 template <typename R, int DX>
 static int launch_level_t(const LevelLaunch& L, hipStream_t st, Timer* tm) {
+  if (L.lazy) {  // no pair-row pass
+    tm->begin(2, st);
+    k_sample_lazy<R, DX><<<(unsigned)L.nodes * L.DS, kBlock, 0, st>>>(
+        L.d_nodes, L.d_series, L.node_list, L.node0, L.DS, L.N, L.Npad, L.lazy, L.lazy_param,
+        L.bmerged, L.nb);
+    tm->end(2, st);
+    return 0;
+  }
   tm->begin(1, st);
   if (launch_rows_t<R, DX>(L, st)) return -1;
   tm->end(1, st);

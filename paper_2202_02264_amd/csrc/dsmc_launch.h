@@ -61,6 +61,8 @@ struct LevelLaunch {
   int RPL, W, RB;       // rows kernel: rows per lane, waves per workgroup, row blocks per combine
   int CS, KC;           // rows kernel: column splits per combine, chunks per split
   int DS;               // sample kernel: workgroups per combine
+  int lazy;             // 0 exact draws; 1 Metropolis-Hastings, 2 rejection (no pair-row pass)
+  int lazy_param;       // MH steps, or the rejection proposal cap
   int totalK;
   const NodeDesc* d_nodes;
   const SeriesDesc* d_series;

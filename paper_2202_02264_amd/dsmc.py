@@ -21,7 +21,9 @@ LIB_PATH = os.path.join(_PKG, "libdsmc.so")
 DSMC_OK, DSMC_EINVAL, DSMC_ENOMEM, DSMC_EUNSUPPORTED = 0, -1, -2, -3
 DSMC_EAGAIN, DSMC_EDEGENERATE, DSMC_ENUMERIC, DSMC_EDEVICE, DSMC_ECANCELLED = -4, -5, -6, -8, -9
 DSMC_EDEADLINE = -10
-DSMC_FLAG_DEGENERATE, DSMC_FLAG_NUMERIC = 1, 2
+DSMC_FLAG_DEGENERATE, DSMC_FLAG_NUMERIC, DSMC_FLAG_LAZY_CAP = 1, 2, 4
+DSMC_RESAMPLE_EXACT, DSMC_RESAMPLE_MH, DSMC_RESAMPLE_RS = 0, 1, 2
+DSMC_MH_STEPS_DEFAULT, DSMC_RS_CAP_DEFAULT = 32, 1 << 20
 DSMC_OBS_LINEAR_GAUSSIAN, DSMC_OBS_STOCH_VOL = 0, 1
 DSMC_WEIGHT_LEAF_OBS, DSMC_WEIGHT_BOUNDARY_OBS = 0, 1
 DSMC_FP32, DSMC_FP64, DSMC_BF16 = 0, 1, 2
@@ -45,7 +47,8 @@ class dsmc_model_desc(C.Structure):
 
 class dsmc_plan_desc(C.Structure):
     _fields_ = [("N", C.c_int), ("d_x", C.c_int), ("max_K", C.c_int), ("max_total_K", C.c_int),
-                ("precision", C.c_int), ("flags", C.c_int), ("stream", C.c_void_p)]
+                ("precision", C.c_int), ("flags", C.c_int), ("stream", C.c_void_p),
+                ("resampling", C.c_int), ("lazy_param", C.c_int)]
 
 
 class dsmc_output(C.Structure):
@@ -77,6 +80,9 @@ class dsmc_profile(C.Structure):
 def _load() -> C.CDLL:
     if not os.path.exists(LIB_PATH):
         raise ImportError(f"{LIB_PATH} is not built; run __graft_entry__.build()")
+    # PyTorch ships its own copy of the HIP runtime; it must be loaded before
+    # this library's (the system one), or one of the two sees no GPU.
+    import torch  # noqa: F401
     lib = C.CDLL(LIB_PATH)
     vp, i, u64 = C.c_void_p, C.c_int, C.c_uint64
     sig = {
@@ -99,6 +105,7 @@ def _load() -> C.CDLL:
         "dsmc_schedule": (i, [i, i, C.POINTER(C.c_int32), C.POINTER(C.c_int32),
                               C.POINTER(C.c_int32), C.POINTER(C.c_int32)]),
         "dsmc_last_error": (C.c_char_p, []),
+        "dsmc_device_count": (i, [C.POINTER(i)]),
     }
     for name, (res, args) in sig.items():
         fn = getattr(lib, name)
@@ -175,7 +182,8 @@ class Plan:
 
     def __init__(self, N: int, d_x: int, max_K: int, max_total_K: int = 0,
                  precision: int = DSMC_FP32, profile: bool = False, autotune: bool = True,
-                 graph: bool = False, rescue_all: bool = False, stream=None):
+                 graph: bool = False, rescue_all: bool = False, stream=None,
+                 resampling: int = 0, lazy_param: int = 0):
         import torch
         if stream is None:
             stream = torch.cuda.current_stream()
@@ -185,6 +193,7 @@ class Plan:
         d.flags = ((DSMC_PLAN_PROFILE if profile else 0) | (DSMC_PLAN_AUTOTUNE if autotune else 0)
                    | (DSMC_PLAN_GRAPH if graph else 0) | (DSMC_PLAN_RESCUE_ALL if rescue_all else 0))
         d.stream = C.c_void_p(stream.cuda_stream)
+        d.resampling, d.lazy_param = resampling, lazy_param
         h = C.c_void_p()
         _check(_lib.dsmc_plan(C.byref(d), C.byref(h)), "dsmc_plan")
         self.handle = h

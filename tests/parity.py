@@ -186,3 +186,48 @@ def teacher_forced(spec, N: int, seed: int, g: dict, tol, select=None,
     total = float(g["leaf_logL"].sum() + g["logZ_inc"].sum())
     assert abs(float(g["log_Z"][0]) - total) <= 1e-9 * max(1.0, abs(total))
     return rep
+
+
+def lazy_teacher_forced(spec, N: int, seed: int, g: dict, scheme: str, param: int,
+                        band: float, conditional: bool = False) -> ParityReport:
+    """Teacher-forced parity of a lazy-resampling run (Algorithms 7 and 8): at
+    every node the oracle's lazy combine runs on the GPU's inputs of that
+    level.  A draw is near a boundary when one of its chain's accept/reject
+    decisions lies within ``band`` (relative to the log terms) of flipping;
+    indices must agree outside that band."""
+    K = spec.K
+    rep = ParityReport()
+    leaf_x = g["leaf_x"].astype(np.float64)
+    sig = np.tile(np.arange(N), (K, 1))
+    logN = np.log(N)
+    for level in D.schedule(K):
+        for (a, c, b) in level:
+            lg, rg = g["ancestry"][c - 1]
+            assert lg.min() >= 0 and lg.max() < N and rg.min() >= 0 and rg.max() < N
+            xL = leaf_x[:, c - 1, sig[c - 1]].T
+            xR = leaf_x[:, c, sig[c]].T
+            lwL = g["leaf_logw"][c - 1].astype(np.float64) if c - a == 1 else np.full(N, -logN)
+            lwR = g["leaf_logw"][c].astype(np.float64) if b - c == 1 else np.full(N, -logN)
+            res = D.lazy_combine(spec, c, xL, xR, lwL, lwR, seed, scheme, param, margins=True)
+            l, r = res.l.copy(), res.r.copy()
+            if conditional:
+                l[0] = r[0] = 0
+            assert np.isnan(g["logZ_inc"][c - 1])
+            rep.nodes += 1
+            for n in range(N):
+                near = bool(res.margin[n] < band)
+                ok = l[n] == lg[n] and r[n] == rg[n]
+                rep.draws += 1
+                rep.near += int(near)
+                if not ok:
+                    rep.mismatches += 1
+                    if not near:
+                        rep.mismatches_outside_band += 1
+                        rep.worst.append((c, n, int(l[n]), int(lg[n]), int(r[n]), int(rg[n]),
+                                          float(res.margin[n])))
+            sig[a:c] = sig[a:c][:, lg]
+            sig[c:b] = sig[c:b][:, rg]
+    np.testing.assert_array_equal(g["index"], sig)
+    gathered = np.take_along_axis(g["leaf_x"], sig[None, :, :], axis=2)
+    np.testing.assert_array_equal(g["traj"], gathered)
+    return rep

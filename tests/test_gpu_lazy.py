@@ -1,0 +1,107 @@
+"""GPU parity of lazy resampling (DSMC_RESAMPLE_MH / DSMC_RESAMPLE_RS; Section
+4.2, Algorithms 7 and 8) against the oracle's lazy combine.
+
+fp64 runs equal the oracle end to end (every index).  fp32 runs are compared
+level by level on the GPU's own inputs: indices must agree unless one of the
+draw's accept/reject decisions lies within 1e-5 (relative to its log terms)
+of flipping, the fp32 log-weight tolerance of the exact path.  Lazy plans
+estimate no increment: Z_c and log L^N are NaN.
+"""
+import math
+
+import numpy as np
+import pytest
+
+from oracle import dsmc as D
+from paper_2202_02264_amd import workloads as W
+
+from parity import check_leaves, lazy_teacher_forced, log, run_gpu, TOL32
+
+pytestmark = pytest.mark.gpu
+
+BAND = 1e-5
+SCHEMES = {"mh": 1, "rs": 2}
+
+
+def _plan(spec, N, scheme, param, precision):
+    from paper_2202_02264_amd import dsmc as G
+    prec = {"fp32": G.DSMC_FP32, "fp64": G.DSMC_FP64}[precision]
+    return G.Plan(N, spec.d_x, spec.K, precision=prec, resampling=SCHEMES[scheme],
+                  lazy_param=param)
+
+
+@pytest.mark.parametrize("scheme,param", [("mh", 16), ("rs", 1 << 20)])
+def test_fp64_lazy_end_to_end(scheme, param):
+    spec = W.c1_lg1d()
+    N, seed = 64, 7
+    g = run_gpu(spec, N, seed, precision="fp64", plan=_plan(spec, N, scheme, param, "fp64"))
+    ref = D.smooth_lazy(spec, N, seed, scheme, param)
+    assert g["status"][0] == 0
+    np.testing.assert_array_equal(g["ancestry"], ref.ancestry)
+    np.testing.assert_array_equal(g["index"], ref.idx)
+    np.testing.assert_allclose(g["traj"][0], ref.x[:, :, 0], rtol=1e-13, atol=1e-13)
+    assert np.all(np.isnan(g["logZ_inc"])) and math.isnan(g["log_Z"][0])
+
+
+# Metropolis-Hastings: any workload.  Rejection: workloads whose acceptance
+# rate (mean pair weight over the bound) is at least about 0.5 %, so that the
+# oracle's loop stays short; at d_x = 32 it is about 1e-25.
+MH_CASES = {
+    "sv_ragged": (lambda: W.sv(300, seed=11), 256),
+    "lg4d": (lambda: W.lg4d(40, seed=15), 128),
+    "sv_boundary_obs": (lambda: W.sv(65, seed=12, weighting="boundary_obs"), 96),
+    "lg32d": (lambda: W.lg_highdim(K=12, seed=19), 128),
+}
+RS_CASES = {
+    "lg1d_n100": (lambda: W.lg1d(64, seed=13), 100),
+    "sv_k40": (lambda: W.sv(40, seed=21), 64),
+}
+PARAMS = [("mh", c, 32) for c in sorted(MH_CASES)] + [("rs", c, 1 << 20) for c in sorted(RS_CASES)]
+
+
+@pytest.mark.parametrize("scheme,case,param", PARAMS)
+def test_lazy_teacher_forced_parity(scheme, case, param):
+    build, N = (MH_CASES if scheme == "mh" else RS_CASES)[case]
+    spec = build()
+    seed = 3000 + len(case)
+    g = run_gpu(spec, N, seed, plan=_plan(spec, N, scheme, param, "fp32"))
+    assert g["status"][0] == 0
+    check_leaves(spec, N, seed, g, TOL32)
+    rep = lazy_teacher_forced(spec, N, seed, g, scheme, param, BAND)
+    log(f"lazy {scheme} {case}: {rep.summary()}")
+    assert rep.mismatches_outside_band == 0, rep.worst[:5]
+
+
+def test_lazy_conditional_keeps_star():
+    from paper_2202_02264_amd import dsmc as G
+    spec = W.sv(40, seed=5)
+    N, seed = 64, 9
+    star = spec.x_true.astype(np.float32).astype(np.float64)
+    plan = G.Plan(N, 1, spec.K, resampling=G.DSMC_RESAMPLE_RS)
+    g = run_gpu(spec, N, seed, plan=plan, star=star)
+    np.testing.assert_array_equal(g["traj"][:, :, 0], star.T)
+    assert np.all(g["index"][:, 0] == 0)
+    rep = lazy_teacher_forced(spec, N, seed, g, "rs", G.DSMC_RS_CAP_DEFAULT, BAND,
+                              conditional=True)
+    assert rep.mismatches_outside_band == 0, rep.worst[:5]
+
+
+def test_rejection_cap_flagged():
+    """A cap of one proposal per draw: draws that reject it keep it and the run
+    is flagged; the indices still equal the oracle's."""
+    from paper_2202_02264_amd import dsmc as G
+    spec = W.sv(9, seed=6)
+    N, seed = 128, 4
+    g = run_gpu(spec, N, seed, precision="fp64", plan=_plan(spec, N, "rs", 1, "fp64"))
+    ref = D.smooth_lazy(spec, N, seed, "rs", 1)
+    assert ref.capped
+    assert g["status"][0] & G.DSMC_FLAG_LAZY_CAP
+    np.testing.assert_array_equal(g["ancestry"], ref.ancestry)
+
+
+def test_lazy_plan_rejects_bad_scheme():
+    from paper_2202_02264_amd import dsmc as G
+    with pytest.raises(RuntimeError):
+        G.Plan(64, 1, 8, resampling=3)
+    with pytest.raises(RuntimeError):
+        G.Plan(64, 1, 8, resampling=1, lazy_param=-1)
