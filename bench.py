@@ -43,6 +43,16 @@ BF16_MFMA_PEAK = 2.5e15
 # each scaled by the same counter's reading for a 256 MiB device copy (see
 # profiles/k_rows_sv_K4096_N1024.md).  Reset to None when k_rows changes.
 K_ROWS_SV_TRAFFIC_MIB = {"read": 21.89, "write": 89.85}
+# Lazy resampling kernel (k_sample_lazy<float, 1>): VALU instructions per
+# proposal in its Metropolis-Hastings loop, counted in the gfx950 assembly of
+# this source (one Philox4x64-10 block, pair weight, fp64 exponential); each is
+# priced at one issue slot, so the derived peak is an upper bound.
+LAZY_VALU_PER_PROPOSAL = 337
+# HBM traffic of one k_sample_lazy launch (MH, B = 32) of the default
+# workload: rocprofv3 FETCH_SIZE / WRITE_SIZE scaled by the copy calibration
+# (see profiles/k_sample_lazy_mh_sv_K4096_N1024.md).  Reset to None when
+# k_sample_lazy changes.
+LAZY_MH_SV_TRAFFIC_MIB = {"read": 12.44, "write": 8.01}
 
 
 def parse():
@@ -63,6 +73,8 @@ def parse():
                          "pgibbs: particle Gibbs sweeps of conditional dSMC on the sv series; "
                          "lazy: lazy resampling (MH, rejection) vs exact on the sv series")
     ap.add_argument("--B", type=int, default=512)
+    ap.add_argument("--schemes", type=str, default="exact,mh_B8,mh_B32,rs",
+                    help="lazy: which runs (exact, mh_B8, mh_B32, rs)")
     ap.add_argument("--jobs", type=int, default=600, help="serving: jobs per arrival run")
     ap.add_argument("--rates", type=str, default="0.25,0.5,0.75,0.9,1.1",
                     help="serving: Poisson arrival rates as fractions of the saturated rate")
@@ -436,10 +448,13 @@ def bench_lazy(args):
     spec = W.sv(K)
     model = G.Model(spec)
     runs = {}
+    wanted = set(args.schemes.split(","))
     for name, scheme, param, steps in (("exact", G.DSMC_RESAMPLE_EXACT, 0, args.steps),
                                        ("mh_B8", G.DSMC_RESAMPLE_MH, 8, args.steps),
                                        ("mh_B32", G.DSMC_RESAMPLE_MH, 32, args.steps),
                                        ("rs", G.DSMC_RESAMPLE_RS, 0, max(1, min(args.steps, 3)))):
+        if name not in wanted:
+            continue
         plan = G.Plan(N, 1, K, graph=True, resampling=scheme, lazy_param=param)
         out = G.alloc_output(plan, K)
         for s in range(2):
@@ -462,6 +477,31 @@ def bench_lazy(args):
            "config": {"workload": f"lazy resampling (Metropolis-Hastings, B=32), stochastic "
                                   f"volatility, K={K}, N={N}", "K": K, "N": N, "d_x": 1},
            "runs": runs}
+    if not args.no_kernel_events:
+        # the B = 32 run once more, eagerly, with HIP events around every launch
+        plan = G.Plan(N, 1, K, profile=True, resampling=G.DSMC_RESAMPLE_MH, lazy_param=32)
+        out = G.alloc_output(plan, K)
+        for s in range(2):
+            G.dsmc_smooth(plan, model, 1000 + s, out)
+        torch.cuda.synchronize()
+        G.dsmc_plan_profile(plan)
+        for s in range(args.steps):
+            G.dsmc_smooth(plan, model, s + 1, out)
+        prof = G.dsmc_plan_profile(plan)
+        launches = prof["launches"]["sample"]
+        ms = prof["ms"]["sample"]
+        proposals = args.steps * (K - 1) * N * 32
+        achieved = proposals / (ms * 1e-3)
+        peak = LANE_OPS_PER_S / LAZY_VALU_PER_PROPOSAL
+        traffic = None
+        if LAZY_MH_SV_TRAFFIC_MIB and (K, N) == (4096, 1024):
+            traffic = (LAZY_MH_SV_TRAFFIC_MIB["read"] + LAZY_MH_SV_TRAFFIC_MIB["write"]) * 2 ** 20
+        res["roofline"] = {"bound": "alu", "kernel": "k_sample_lazy<float,1>",
+                           "achieved": achieved / 1e9, "peak": peak / 1e9,
+                           "unit": "Gproposal/s", "frac": achieved / peak, "traffic": traffic,
+                           "avg_launch_ms": ms / max(1, launches),
+                           "proposals_per_launch": proposals / max(1, launches)}
+        res["kernel_ms_per_step"] = {k: v / args.steps for k, v in prof["ms"].items()}
     print(json.dumps(res))
 
 
