@@ -45,14 +45,15 @@ BF16_MFMA_PEAK = 2.5e15
 K_ROWS_SV_TRAFFIC_MIB = {"read": 21.89, "write": 89.85}
 # Lazy resampling kernel (k_sample_lazy<float, 1>): VALU instructions per
 # proposal in its Metropolis-Hastings loop, counted in the gfx950 assembly of
-# this source (one Philox4x64-10 block, pair weight, fp64 exponential); each is
-# priced at one issue slot, so the derived peak is an upper bound.
-LAZY_VALU_PER_PROPOSAL = 337
+# this source (half a Philox4x64-10 block, pair weight, fp64 exponential: 395
+# per loop trip of two proposals); each is priced at one issue slot, so the
+# derived peak is an upper bound.
+LAZY_VALU_PER_PROPOSAL = 198
 # HBM traffic of one k_sample_lazy launch (MH, B = 32) of the default
 # workload: rocprofv3 FETCH_SIZE / WRITE_SIZE scaled by the copy calibration
 # (see profiles/k_sample_lazy_mh_sv_K4096_N1024.md).  Reset to None when
 # k_sample_lazy changes.
-LAZY_MH_SV_TRAFFIC_MIB = {"read": 12.44, "write": 8.01}
+LAZY_MH_SV_TRAFFIC_MIB = {"read": 14.00, "write": 8.01}
 
 
 def parse():

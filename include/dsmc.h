@@ -186,8 +186,10 @@ typedef struct dsmc_plan_desc {
  *       (a bound of every pair weight of the combine); exact multinomial draws
  *       with random run time.  A draw still rejecting after `lazy_param`
  *       proposals keeps its last proposal and sets DSMC_FLAG_LAZY_CAP.
- * Proposal k of draw n at boundary c uses Philox block (n, c, 4 (MH) or
- * 5 (RS), k): I = floor(u0 N), J = floor(u1 N), acceptance uniform u2.
+ * Proposals 2j and 2j + 1 of draw n at boundary c use Philox block
+ * (n, c, 4 (MH) or 5 (RS), j): proposal 2j + h takes I = floor(lo32 N / 2^32)
+ * and J = floor(hi32 N / 2^32) from the 32-bit halves of word 2h and its
+ * acceptance uniform from word 2h + 1 (53 bits).
  * Lazy plans estimate no increment: logZ_inc, row_lse and log_Z are NaN.
  * Conditional runs keep slot 0 as in EXACT plans. */
 #define DSMC_RESAMPLE_EXACT 0

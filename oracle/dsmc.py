@@ -46,8 +46,8 @@ Readings of the paper this file takes:
   is "degenerate" and indices are drawn uniformly: l = floor(u1 N), r = floor(u2 N).
 * Lazy resampling targets the product-form weight W_c^{mn} (its log is the
   pair matrix S), which is Algorithms 7 and 8's omega_c when the block weights
-  are uniform.  Proposal k of chain n comes from Philox block
-  (n, c, 4 (MH) or 5 (RS), k).  The rejection bound is
+  are uniform.  Proposals 2j and 2j + 1 of chain n come from Philox block
+  (n, c, 4 (MH) or 5 (RS), j) (see philox.lazy_proposals).  The rejection bound is
   max_m a_m + max_n b_n + max log p_c, a bound of every realised pair weight.
   The rejection loop stops after `cap` proposals (the last one is kept and the
   run flagged).  No increment is estimated: Z_c is NaN.

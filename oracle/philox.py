@@ -105,11 +105,15 @@ def combine_uniforms(seed: int, c: int, N: int):
 
 
 def lazy_proposals(seed: int, c: int, N: int, purpose: int, step: int):
-    """Proposal `step` of the N lazy-resampling chains at boundary c: indices
-    I*, J* uniform on {0..N-1} (floor of a 53-bit uniform times N) from words
-    0 and 1 of block (n, c, purpose, step), and u in [0, 1) from word 2."""
+    """Proposal `step` of the N lazy-resampling chains at boundary c.  Block
+    (n, c, purpose, step // 2) serves proposals 2j and 2j + 1: proposal
+    2j + h takes its indices from word 2h, I* = floor(lo32 * N / 2^32) and
+    J* = floor(hi32 * N / 2^32) of its two 32-bit halves (uniform on
+    {0..N-1} up to N / 2^32), and u in [0, 1) from word 2h + 1 (53 bits)."""
     n = np.arange(N, dtype=np.uint64)
-    w = philox4x64_10((n, np.uint64(c), np.uint64(purpose), np.uint64(step)), key_of(seed))
-    I = np.minimum((to_uniform(w[0]) * N).astype(np.int64), N - 1)
-    J = np.minimum((to_uniform(w[1]) * N).astype(np.int64), N - 1)
-    return I, J, to_uniform(w[2])
+    w = philox4x64_10((n, np.uint64(c), np.uint64(purpose), np.uint64(step // 2)), key_of(seed))
+    h = step % 2
+    wi, wu = w[2 * h], w[2 * h + 1]
+    I = ((wi & _LO32) * np.uint64(N)) >> _S32
+    J = ((wi >> _S32) * np.uint64(N)) >> _S32
+    return I.astype(np.int64), J.astype(np.int64), to_uniform(wu)

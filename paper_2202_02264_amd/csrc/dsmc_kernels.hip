@@ -1239,32 +1239,45 @@ __global__ __launch_bounds__(kBlock) void k_sample_lazy(
   const int n0 = ds * dper, n1 = min(N, n0 + dper);
   int32_t* ancL = sd.anc + (size_t)(c - 1) * 2 * N;
   int32_t* ancR = ancL + N;
+  // proposal indices from the two 32-bit halves of one Philox word
+  auto index_lo = [N](uint64_t w) { return (int)(((w & 0xffffffffull) * (uint64_t)N) >> 32); };
+  auto index_hi = [N](uint64_t w) { return (int)(((w >> 32) * (uint64_t)N) >> 32); };
   int capped = 0, bad = 0;
   for (int n = n0 + threadIdx.x; n < n1; n += kBlock) {
     int l = n, r = n;
     if (lazy == 1) {
       double cur = logw(l, r);
-      for (int b = 0; b < param; ++b) {
-        const Words4 w = philox4x64_10((uint64_t)n, (uint64_t)c, purpose, (uint64_t)b, sd.seed, kKey1);
-        const int ip = min((int)(unif53(w.w0) * N), N - 1);
-        const int jp = min((int)(unif53(w.w1) * N), N - 1);
+      auto step = [&](uint64_t wi, uint64_t wu) {
+        const int ip = index_lo(wi), jp = index_hi(wi);
         const double prop = logw(ip, jp);
-        if (unif53(w.w2) < exp(prop - cur)) {
+        if (unif53(wu) < exp(prop - cur)) {
           l = ip;
           r = jp;
           cur = prop;
         }
+      };
+      // block j serves proposals 2j (words 0, 1) and 2j + 1 (words 2, 3)
+      for (int b = 0; b < param; b += 2) {
+        const Words4 w = philox4x64_10((uint64_t)n, (uint64_t)c, purpose, (uint64_t)(b >> 1),
+                                       sd.seed, kKey1);
+        step(w.w0, w.w1);
+        if (b + 1 < param) step(w.w2, w.w3);
       }
       if (isnan(cur)) bad = 1;
     } else {
       bool done = false;
-      for (int k = 0; k < param && !done; ++k) {
-        const Words4 w = philox4x64_10((uint64_t)n, (uint64_t)c, purpose, (uint64_t)k, sd.seed, kKey1);
-        l = min((int)(unif53(w.w0) * N), N - 1);
-        r = min((int)(unif53(w.w1) * N), N - 1);
+      auto trial = [&](uint64_t wi, uint64_t wu) {
+        l = index_lo(wi);
+        r = index_hi(wi);
         const double lw = logw(l, r);
         if (isnan(lw)) bad = 1;
-        done = unif53(w.w2) < exp(lw);
+        done = unif53(wu) < exp(lw);
+      };
+      for (int k = 0; k < param && !done; k += 2) {
+        const Words4 w = philox4x64_10((uint64_t)n, (uint64_t)c, purpose, (uint64_t)(k >> 1),
+                                       sd.seed, kKey1);
+        trial(w.w0, w.w1);
+        if (!done && k + 1 < param) trial(w.w2, w.w3);
       }
       if (!done) capped = 1;
     }
