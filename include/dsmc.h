@@ -21,6 +21,9 @@
  *            log L^N = sum_t log L_t + sum_c Z_c.
  *   conditional  (Section 3.1, Algorithm 4) the same with a given star
  *            trajectory kept in slot 0 throughout: dsmc_smooth_conditional.
+ *   lazy     (Section 4.2, Algorithms 7 and 8) the combine's multinomial draw
+ *            replaced by Metropolis-Hastings or rejection chains that evaluate
+ *            only the pairs they propose: dsmc_plan_desc.resampling.
  *
  * Time points are t = 0..K-1 (the paper's t = 0..T with K = T + 1).
  *
