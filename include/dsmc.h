@@ -194,7 +194,9 @@ typedef struct dsmc_plan_desc {
  * and J = floor(hi32 N / 2^32) from the 32-bit halves of word 2h and its
  * acceptance uniform from word 2h + 1 (53 bits).
  * Lazy plans estimate no increment: logZ_inc, row_lse and log_Z are NaN.
- * Conditional runs keep slot 0 as in EXACT plans. */
+ * Conditional runs keep slot 0 as in EXACT plans.  dsmc_plan rejects a lazy
+ * scheme with DSMC_BF16 (DSMC_EUNSUPPORTED), an unknown scheme or a negative
+ * lazy_param (DSMC_EINVAL). */
 #define DSMC_RESAMPLE_EXACT 0
 #define DSMC_RESAMPLE_MH 1
 #define DSMC_RESAMPLE_RS 2

@@ -296,6 +296,8 @@ extern "C" int dsmc_plan(const dsmc_plan_desc* d, dsmc_plan_t** out) {
       d->resampling != DSMC_RESAMPLE_RS)
     return fail(DSMC_EINVAL, "resampling %d not supported", d->resampling);
   if (d->lazy_param < 0) return fail(DSMC_EINVAL, "lazy_param must be >= 0");
+  if (d->precision == DSMC_BF16 && d->resampling != DSMC_RESAMPLE_EXACT)
+    return fail(DSMC_EUNSUPPORTED, "DSMC_BF16 selects the matrix-core pair rows, which lazy plans do not run");
   auto* p = new dsmc_plan_t;
   p->d = *d;
   if (p->d.max_total_K < p->d.max_K) p->d.max_total_K = p->d.max_K;

@@ -98,6 +98,13 @@ def test_invalid_arguments_rejected_on_host():
     p.precision, p.d_x = dsmc.DSMC_BF16, 8  # bf16 matrix-core rows need d_x >= 9
     assert lib.dsmc_plan(C.byref(p), C.byref(hp)) == dsmc.DSMC_EUNSUPPORTED
     p.precision, p.d_x = dsmc.DSMC_FP32, 1
+    p.resampling = 3                        # unknown resampling scheme
+    assert lib.dsmc_plan(C.byref(p), C.byref(hp)) == dsmc.DSMC_EINVAL
+    p.resampling, p.lazy_param = dsmc.DSMC_RESAMPLE_MH, -1
+    assert lib.dsmc_plan(C.byref(p), C.byref(hp)) == dsmc.DSMC_EINVAL
+    p.lazy_param, p.precision, p.d_x = 0, dsmc.DSMC_BF16, 32  # lazy plans run no matrix-core rows
+    assert lib.dsmc_plan(C.byref(p), C.byref(hp)) == dsmc.DSMC_EUNSUPPORTED
+    p.resampling, p.precision, p.d_x = dsmc.DSMC_RESAMPLE_EXACT, dsmc.DSMC_FP32, 1
     assert lib.dsmc_smooth(None, None, 0, None) == dsmc.DSMC_EINVAL
     assert lib.dsmc_smooth_conditional(None, None, 0, None, None) == dsmc.DSMC_EINVAL
     # serving entry points
