@@ -86,7 +86,15 @@ typedef enum dsmc_status {
 /* ---------------------------------------------------------------- model */
 
 enum { DSMC_OBS_LINEAR_GAUSSIAN = 0, /* y_t ~ N(H x_t + h, R)                  */
-       DSMC_OBS_STOCH_VOL = 1 };     /* y_t ~ N(0, exp(x_t)), needs d_x = d_y = 1 */
+       DSMC_OBS_STOCH_VOL = 1,       /* y_t ~ N(0, exp(x_t)), needs d_x = d_y = 1 */
+       DSMC_OBS_BOX = 2 };           /* h_t(x) = 1 if lo_t <= x <= hi_t else 0, with
+                                        y_t = (lo_t, hi_t), d_y = 2 d_x: the constrained
+                                        random walk of Section 5.3 */
+
+/* Proposal family: GAUSSIAN q_t = N(q_mean[t], q_chol[t] q_chol[t]^T);
+ * UNIFORM q_t uniform on the box q_mean[t] +- diag(q_chol[t]) (d_x <= 4; the
+ * uniform of coordinate i is word i % 4 of the leaf Philox block i / 4). */
+enum { DSMC_PROPOSAL_GAUSSIAN = 0, DSMC_PROPOSAL_UNIFORM = 1 };
 
 /* Choice of the auxiliary measures nu_t of Definition 2.1 (Section 2.1):
  *   LEAF_OBS      nu_t proportional to h_t q_t: leaf log-weight log h_t (t >= 1),
@@ -121,6 +129,7 @@ typedef struct dsmc_model_desc {
   const double *q_mean; /* [K][d_x] */
   const double *q_chol; /* [K][d_x][d_x] */
   int weighting;        /* DSMC_WEIGHT_* */
+  int proposal_kind;    /* DSMC_PROPOSAL_* (0 = Gaussian) */
 } dsmc_model_desc;
 
 typedef struct dsmc_model dsmc_model_t;
@@ -128,7 +137,8 @@ typedef struct dsmc_model dsmc_model_t;
 /* Validate the description, derive inverse Cholesky factors and log
  * normalisers on the host in fp64, and copy everything to device memory of
  * the current device (synchronously).  Errors: DSMC_EINVAL (bad sizes,
- * non-positive Cholesky diagonal, unknown kind, STOCH_VOL with d_x != 1),
+ * non-positive Cholesky diagonal, unknown kind, STOCH_VOL with d_x != 1,
+ * BOX with d_y != 2 d_x, UNIFORM proposals with d_x > 4),
  * DSMC_ENOMEM, DSMC_EDEVICE.  The model may be shared by many calls. */
 int dsmc_model_create(const dsmc_model_desc *desc, dsmc_model_t **out);
 void dsmc_model_destroy(dsmc_model_t *model);

@@ -115,6 +115,13 @@ def normalise(raw: np.ndarray):
     return raw - lse, lse - np.log(raw.shape[0])
 
 
+def _leaf_variates(spec, seed: int, t: int, N: int, d: int) -> np.ndarray:
+    """The proposal's base variates: normals, or uniforms for a uniform proposal."""
+    if getattr(spec, "proposal", "gaussian") == "uniform":
+        return philox.leaf_uniforms(seed, t, N, d)
+    return philox.leaf_normals(seed, t, N, d)
+
+
 def sample_leaves(spec, N: int, seed: int, x: np.ndarray | None = None) -> Leaves:
     """Algorithm 2.  If ``x`` (K, N, d_x) is given those particles are weighted
     instead of drawing new ones (used to feed the oracle another path's inputs)."""
@@ -122,7 +129,7 @@ def sample_leaves(spec, N: int, seed: int, x: np.ndarray | None = None) -> Leave
     if x is None:
         x = np.empty((K, N, d))
         for t in range(K):
-            x[t] = proposal_draw(spec, t, philox.leaf_normals(seed, t, N, d))
+            x[t] = proposal_draw(spec, t, _leaf_variates(spec, seed, t, N, d))
     x = np.asarray(x, dtype=np.float64)
     raw = np.empty((K, N))
     logw = np.empty((K, N))
@@ -296,7 +303,7 @@ def sample_leaves_conditional(spec, N: int, seed: int, star) -> Leaves:
     star = np.asarray(star, dtype=np.float64).reshape(K, d)
     x = np.empty((K, N, d))
     for t in range(K):
-        x[t] = proposal_draw(spec, t, philox.leaf_normals(seed, t, N, d))
+        x[t] = proposal_draw(spec, t, _leaf_variates(spec, seed, t, N, d))
     x[:, 0] = star
     return sample_leaves(spec, N, seed, x=x)
 

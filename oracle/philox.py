@@ -97,6 +97,20 @@ def leaf_normals(seed: int, t: int, N: int, d: int) -> np.ndarray:
     return z[:, :d]
 
 
+def leaf_uniforms(seed: int, t: int, N: int, d: int) -> np.ndarray:
+    """Uniforms in [0, 1) of the N particles drawn at time t, shape (N, d):
+    coordinate i from word i % 4 of block (n, t, 2, i // 4) (the blocks that
+    give a Gaussian proposal its normals)."""
+    n = np.arange(N, dtype=np.uint64)
+    u = np.empty((N, d))
+    for j in range((d + 3) // 4):
+        w = philox4x64_10((n, np.uint64(t), np.uint64(PURPOSE_LEAF), np.uint64(j)), key_of(seed))
+        for k in range(4):
+            if 4 * j + k < d:
+                u[:, 4 * j + k] = to_uniform(w[k])
+    return u
+
+
 def combine_uniforms(seed: int, c: int, N: int):
     """(u1, u2) of the N draws of the combine at boundary c, each shape (N,)."""
     n = np.arange(N, dtype=np.uint64)

@@ -33,8 +33,14 @@ def log_prior(spec, x: np.ndarray) -> np.ndarray:
 
 
 def log_potential(spec, t: int, x: np.ndarray) -> np.ndarray:
-    """log h_t(x) = log density of y_t given x_t = x."""
+    """log h_t(x) = log density of y_t given x_t = x; for the "box" kind the
+    indicator of lo <= x <= hi with y_t = (lo, hi) (the constrained random
+    walk of Section 5.3)."""
     y = spec.y[t]
+    if spec.obs == "box":
+        d = spec.d_x
+        inside = np.all((x >= y[:d]) & (x <= y[d:]), axis=-1)
+        return np.where(inside, 0.0, -np.inf)
     if spec.obs == "sv":
         v = x[..., 0]
         return -0.5 * LOG2PI - 0.5 * v - 0.5 * y[0] * y[0] * np.exp(-v)
@@ -42,13 +48,27 @@ def log_potential(spec, t: int, x: np.ndarray) -> np.ndarray:
     return gauss_logpdf(y, mean, spec.R_chol)
 
 
+def _half_widths(spec, t: int) -> np.ndarray:
+    return np.diag(spec.q_chol[t])
+
+
 def log_proposal(spec, t: int, x: np.ndarray) -> np.ndarray:
-    """log q_t(x)."""
+    """log q_t(x): Gaussian N(q_mean[t], q_chol[t] q_chol[t]^T), or for a
+    "uniform" proposal the uniform density on the box q_mean[t] +- the
+    diagonal of q_chol[t]."""
+    if getattr(spec, "proposal", "gaussian") == "uniform":
+        hw = _half_widths(spec, t)
+        inside = np.all(np.abs(x - spec.q_mean[t]) <= hw, axis=-1)
+        return np.where(inside, -np.sum(np.log(2.0 * hw)), -np.inf)
     return gauss_logpdf(x, spec.q_mean[t], spec.q_chol[t])
 
 
 def proposal_draw(spec, t: int, z: np.ndarray) -> np.ndarray:
-    """x = q_mean[t] + q_chol[t] z for standard normals z of shape (N, d_x)."""
+    """x = q_mean[t] + q_chol[t] z for standard normals z of shape (N, d_x)
+    (Gaussian proposals), or x = q_mean[t] + hw (2 z - 1) for uniforms z in
+    [0, 1) (uniform proposals, hw the box half-widths)."""
+    if getattr(spec, "proposal", "gaussian") == "uniform":
+        return spec.q_mean[t][None, :] + _half_widths(spec, t)[None, :] * (2.0 * z - 1.0)
     return spec.q_mean[t][None, :] + z @ spec.q_chol[t].T
 
 

@@ -75,11 +75,17 @@ extern "C" int dsmc_model_create(const dsmc_model_desc* d, dsmc_model_t** out) {
     if (dx != 1 || dy != 1) return fail(DSMC_EINVAL, "stochastic volatility needs d_x = d_y = 1");
   } else if (d->obs_kind == DSMC_OBS_LINEAR_GAUSSIAN) {
     if (!d->H || !d->h || !d->R_chol) return fail(DSMC_EINVAL, "missing observation array");
+  } else if (d->obs_kind == DSMC_OBS_BOX) {
+    if (dy != 2 * dx) return fail(DSMC_EINVAL, "box potential needs d_y = 2 d_x");
   } else {
     return fail(DSMC_EINVAL, "unknown obs_kind %d", d->obs_kind);
   }
   if (d->weighting != DSMC_WEIGHT_LEAF_OBS && d->weighting != DSMC_WEIGHT_BOUNDARY_OBS)
     return fail(DSMC_EINVAL, "unknown weighting %d", d->weighting);
+  if (d->proposal_kind != DSMC_PROPOSAL_GAUSSIAN && d->proposal_kind != DSMC_PROPOSAL_UNIFORM)
+    return fail(DSMC_EINVAL, "unknown proposal_kind %d", d->proposal_kind);
+  if (d->proposal_kind == DSMC_PROPOSAL_UNIFORM && dx > 4)
+    return fail(DSMC_EINVAL, "uniform proposals need d_x <= 4");
   const size_t dd = (size_t)dx * dx;
   if (!all_finite(d->m0, dx) || !all_finite(d->P0_chol, dd) || !all_finite(d->F, dd) ||
       !all_finite(d->f, dx) || !all_finite(d->Q_chol, dd) ||
@@ -97,6 +103,11 @@ extern "C" int dsmc_model_create(const dsmc_model_desc* d, dsmc_model_t** out) {
     if (!tri_inverse(d->q_chol + (size_t)t * dd, dx, qi.data() + (size_t)t * dd))
       return fail(DSMC_EINVAL, "bad q_chol at t=%d", t);
     qln[t] = log_norm(d->q_chol + (size_t)t * dd, dx);
+    if (d->proposal_kind == DSMC_PROPOSAL_UNIFORM) {  // box q_mean +- diag(q_chol)
+      double s = 0.0;
+      for (int i = 0; i < dx; ++i) s -= std::log(2.0 * d->q_chol[(size_t)t * dd + i * dx + i]);
+      qln[t] = s;
+    }
   }
   double obs_ln = 0.0;
   if (d->obs_kind == DSMC_OBS_LINEAR_GAUSSIAN) {
@@ -119,7 +130,7 @@ extern "C" int dsmc_model_create(const dsmc_model_desc* d, dsmc_model_t** out) {
       }
   } else {
     H.assign(1, 0.0);
-    y.assign(d->y, d->y + K);
+    y.assign(d->y, d->y + (size_t)K * dy);
   }
   // whitening: ||kappa Q^{-1/2} (x_R - F x_L - f)||^2 = (log2 e / 2) * quadratic form
   const double kappa = std::sqrt(0.5 / std::log(2.0));
@@ -161,6 +172,7 @@ extern "C" int dsmc_model_create(const dsmc_model_desc* d, dsmc_model_t** out) {
   hdr.dx = dx;
   hdr.dy = dy;
   hdr.obs_kind = d->obs_kind;
+  hdr.prop_kind = d->proposal_kind;
   hdr.weighting = d->weighting;
   auto P = [&](int i) { return (const double*)(base + offs[i]); };
   hdr.m0 = P(0);

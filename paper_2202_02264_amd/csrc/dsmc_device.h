@@ -146,6 +146,15 @@ __device__ __forceinline__ double log_prior(const DevModel& M, const double (&x)
 template <int DX>
 __device__ __forceinline__ double log_proposal(const DevModel& M, int t, const double (&x)[DX]) {
   const int dx = uniform(M.dx);
+  if (uniform(M.prop_kind) == 1) {  // uniform on the box q_mean +- diag(q_chol)
+    bool inside = true;
+#pragma unroll
+    for (int i = 0; i < DX; ++i)
+      if (i < dx)
+        inside = inside && fabs(x[i] - M.q_mean[(size_t)t * dx + i]) <=
+                               M.q_chol[((size_t)t * dx + i) * dx + i];
+    return inside ? M.q_lognorm[t] : -INFINITY;
+  }
   return neg_half_quad<DX>(M.q_inv + (size_t)t * dx * dx, M.q_mean + (size_t)t * dx, x, dx) +
          M.q_lognorm[t];
 }
@@ -154,6 +163,15 @@ __device__ __forceinline__ double log_proposal(const DevModel& M, int t, const d
 // (H <- R_inv H, y <- R_inv (y - h)), so the quadratic needs no temporaries.
 template <int DX>
 __device__ __forceinline__ double log_potential(const DevModel& M, int t, const double (&x)[DX]) {
+  if (uniform(M.obs_kind) == 2) {  // indicator of the box y_t = (lo, hi)
+    const int dx = uniform(M.dx);
+    const double* yt = M.y + (size_t)t * 2 * dx;
+    bool inside = true;
+#pragma unroll
+    for (int i = 0; i < DX; ++i)
+      if (i < dx) inside = inside && x[i] >= yt[i] && x[i] <= yt[dx + i];
+    return inside ? 0.0 : -INFINITY;
+  }
   if (uniform(M.obs_kind) == 1) {  // stochastic volatility: y ~ N(0, exp(x))
     const double y = M.y[t];
     return -0.9189385332046728 - 0.5 * x[0] - 0.5 * y * y * exp(-x[0]);

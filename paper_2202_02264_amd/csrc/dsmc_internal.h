@@ -13,7 +13,7 @@ constexpr int kChunk = 32;   // columns per chunk of the pair matrix
 // Inverse Cholesky factors and log normalisers are derived on the host in fp64.
 struct DevModel {
   int K, dx, dy, obs_kind, weighting;
-  int pad_;
+  int prop_kind;          // 0 Gaussian, 1 uniform on q_mean +- diag(q_chol)
   const double* m0;       // [dx]
   const double* P0_inv;   // [dx][dx] inverse of the prior Cholesky factor
   double prior_lognorm;   // -sum log diag(P0_chol) - dx/2 log(2 pi)
@@ -27,7 +27,7 @@ struct DevModel {
   const double* q_mean;   // [K][dx]
   const double* q_chol;   // [K][dx][dx]
   const double* q_inv;    // [K][dx][dx]
-  const double* q_lognorm;  // [K]
+  const double* q_lognorm;  // [K]  Gaussian: log normaliser; uniform: -sum log(2 half-width)
   const double* Wcol;     // [dx][dx] = kappa Q_inv          (column whitening)
   const double* Wrow;     // [dx][dx] = kappa Q_inv F        (row whitening)
   const double* wcol_off; // [dx]     = kappa Q_inv f

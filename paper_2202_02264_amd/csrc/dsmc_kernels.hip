@@ -353,13 +353,21 @@ __global__ __launch_bounds__(kBlock, 3) void k_leaves(
         x[i] = (double)xr;  // weights are those of the stored particle (0 past dx)
       }
     } else {
+      const bool unif = uniform(M.prop_kind) == 1;  // uniform proposal: uniforms, not normals
 #pragma unroll
       for (int j = 0; j < (DX + 3) / 4; ++j) {
         const Words4 w = philox4x64_10((uint64_t)n, (uint64_t)t, kPurposeLeaf, (uint64_t)j,
                                        sd.seed, kKey1);
         double z0, z1, z2, z3;
-        box_muller(w.w0, w.w1, z0, z1);
-        box_muller(w.w2, w.w3, z2, z3);
+        if (unif) {
+          z0 = unif53(w.w0);
+          z1 = unif53(w.w1);
+          z2 = unif53(w.w2);
+          z3 = unif53(w.w3);
+        } else {
+          box_muller(w.w0, w.w1, z0, z1);
+          box_muller(w.w2, w.w3, z2, z3);
+        }
         if (4 * j < DX) x[4 * j] = z0;
         if (4 * j + 1 < DX) x[4 * j + 1] = z1;
         if (4 * j + 2 < DX) x[4 * j + 2] = z2;
@@ -369,9 +377,13 @@ __global__ __launch_bounds__(kBlock, 3) void k_leaves(
       for (int i = DX - 1; i >= 0; --i) {
         double xi = 0.0;
         if (i < dx) {
-          xi = qm[i];
+          if (unif) {  // q_mean + half-width (2 u - 1)
+            xi = qm[i] + qc[i * dx + i] * (2.0 * x[i] - 1.0);
+          } else {
+            xi = qm[i];
 #pragma unroll
-          for (int j = 0; j <= i; ++j) xi += qc[i * dx + j] * x[j];
+            for (int j = 0; j <= i; ++j) xi += qc[i * dx + j] * x[j];
+          }
           const R xr = (R)xi;
           leafX[((size_t)i * totalK + g) * N + n] = xr;
           xi = (double)xr;  // weights are those of the stored particle

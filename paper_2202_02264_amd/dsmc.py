@@ -24,7 +24,8 @@ DSMC_EDEADLINE = -10
 DSMC_FLAG_DEGENERATE, DSMC_FLAG_NUMERIC, DSMC_FLAG_LAZY_CAP = 1, 2, 4
 DSMC_RESAMPLE_EXACT, DSMC_RESAMPLE_MH, DSMC_RESAMPLE_RS = 0, 1, 2
 DSMC_MH_STEPS_DEFAULT, DSMC_RS_CAP_DEFAULT = 32, 1 << 20
-DSMC_OBS_LINEAR_GAUSSIAN, DSMC_OBS_STOCH_VOL = 0, 1
+DSMC_OBS_LINEAR_GAUSSIAN, DSMC_OBS_STOCH_VOL, DSMC_OBS_BOX = 0, 1, 2
+DSMC_PROPOSAL_GAUSSIAN, DSMC_PROPOSAL_UNIFORM = 0, 1
 DSMC_WEIGHT_LEAF_OBS, DSMC_WEIGHT_BOUNDARY_OBS = 0, 1
 DSMC_FP32, DSMC_FP64, DSMC_BF16 = 0, 1, 2
 DSMC_PLAN_PROFILE = 1
@@ -42,7 +43,8 @@ class dsmc_model_desc(C.Structure):
     _fields_ = [("K", C.c_int), ("d_x", C.c_int), ("d_y", C.c_int),
                 ("m0", _dp), ("P0_chol", _dp), ("F", _dp), ("f", _dp), ("Q_chol", _dp),
                 ("obs_kind", C.c_int), ("H", _dp), ("h", _dp), ("R_chol", _dp), ("y", _dp),
-                ("q_mean", _dp), ("q_chol", _dp), ("weighting", C.c_int)]
+                ("q_mean", _dp), ("q_chol", _dp), ("weighting", C.c_int),
+                ("proposal_kind", C.c_int)]
 
 
 class dsmc_plan_desc(C.Structure):
@@ -150,8 +152,7 @@ class Model:
             "Q_chol": _f64(spec.Q_chol).reshape(dx, dx), "y": _f64(spec.y).reshape(K, dy),
             "q_mean": _f64(spec.q_mean).reshape(K, dx), "q_chol": _f64(spec.q_chol).reshape(K, dx, dx),
         }
-        sv = spec.obs == "sv"
-        if not sv:
+        if spec.obs == "lg":
             keep["H"] = _f64(spec.H).reshape(dy, dx)
             keep["h"] = _f64(spec.h).reshape(dy)
             keep["R_chol"] = _f64(spec.R_chol).reshape(dy, dy)
@@ -159,7 +160,10 @@ class Model:
         d.K, d.d_x, d.d_y = K, dx, dy
         for k, v in keep.items():
             setattr(d, k, _ptr(v))
-        d.obs_kind = DSMC_OBS_STOCH_VOL if sv else DSMC_OBS_LINEAR_GAUSSIAN
+        d.obs_kind = {"lg": DSMC_OBS_LINEAR_GAUSSIAN, "sv": DSMC_OBS_STOCH_VOL,
+                      "box": DSMC_OBS_BOX}[spec.obs]
+        d.proposal_kind = {"gaussian": DSMC_PROPOSAL_GAUSSIAN, "uniform": DSMC_PROPOSAL_UNIFORM}[
+            getattr(spec, "proposal", "gaussian")]
         d.weighting = {"leaf_obs": DSMC_WEIGHT_LEAF_OBS,
                        "boundary_obs": DSMC_WEIGHT_BOUNDARY_OBS}[spec.weighting]
         h = C.c_void_p()

@@ -50,6 +50,7 @@ class SSM:
     R_chol: Optional[np.ndarray] = None
     weighting: str = "leaf_obs"
     name: str = ""
+    proposal: str = "gaussian"   # or "uniform": q_t uniform on q_mean[t] +- diag(q_chol[t])
     x_true: Optional[np.ndarray] = field(default=None, repr=False)
 
     @property
@@ -291,3 +292,14 @@ def serving_jobs(J: int, seed: int = DATA_SEED, K_median: float = 512.0, sigma_l
         N = int(Ns[int(g.integers(len(Ns)))])
         jobs.append((base.truncated(K), N, 1 + j))
     return jobs
+
+
+def constrained_rw(K: int, sigma: float = 0.5, weighting: str = "boundary_obs") -> SSM:
+    """Constrained random walk (the lazy-resampling experiment, Section 5.3):
+    x_0 ~ N(0, 1), x_t = x_{t-1} + sigma eps_t, potential the indicator of
+    -1 <= x_t <= 1 (y_t holds the bounds), proposals q_t = U([-1, 1])."""
+    spec = SSM(d_x=1, d_y=2, m0=np.zeros(1), P0_chol=np.eye(1), F=np.eye(1), f=np.zeros(1),
+               Q_chol=np.array([[sigma]]), obs="box", y=np.tile([-1.0, 1.0], (K, 1)),
+               q_mean=np.zeros((K, 1)), q_chol=np.ones((K, 1, 1)), weighting=weighting,
+               name=f"crw(K={K},sigma={sigma})", proposal="uniform")
+    return spec

@@ -105,3 +105,38 @@ def test_lazy_plan_rejects_bad_scheme():
         G.Plan(64, 1, 8, resampling=3)
     with pytest.raises(RuntimeError):
         G.Plan(64, 1, 8, resampling=1, lazy_param=-1)
+
+
+def test_constrained_random_walk_fp64():
+    """The constrained random walk (uniform proposals, box potential): exact,
+    rejection and Metropolis-Hastings runs equal the oracle in every index."""
+    from paper_2202_02264_amd import dsmc as G
+    spec = W.constrained_rw(32, sigma=0.5)
+    N, seed = 64, 7
+    g = run_gpu(spec, N, seed, precision="fp64")
+    ref = D.smooth(spec, N, seed)
+    assert g["status"][0] == 0
+    np.testing.assert_array_equal(g["ancestry"], ref.ancestry)
+    assert abs(g["log_Z"][0] - ref.logZ) <= 1e-10 * max(1.0, abs(ref.logZ))
+    for scheme, param in (("rs", 1 << 20), ("mh", 16)):
+        g = run_gpu(spec, N, seed, precision="fp64", plan=_plan(spec, N, scheme, param, "fp64"))
+        ref = D.smooth_lazy(spec, N, seed, scheme, param)
+        assert g["status"][0] == 0
+        np.testing.assert_array_equal(g["ancestry"], ref.ancestry)
+
+
+@pytest.mark.parametrize("scheme", ["exact", "rs"])
+def test_constrained_random_walk_fp32_parity(scheme):
+    from parity import teacher_forced
+    spec = W.constrained_rw(64, sigma=0.3)
+    N, seed = 128, 11
+    plan = None if scheme == "exact" else _plan(spec, N, "rs", 1 << 20, "fp32")
+    g = run_gpu(spec, N, seed, plan=plan)
+    assert g["status"][0] == 0
+    check_leaves(spec, N, seed, g, TOL32)
+    if scheme == "exact":
+        rep = teacher_forced(spec, N, seed, g, TOL32)
+    else:
+        rep = lazy_teacher_forced(spec, N, seed, g, "rs", 1 << 20, BAND)
+    log(f"crw {scheme}: {rep.summary()}")
+    assert rep.mismatches_outside_band == 0, rep.worst[:5]
