@@ -140,3 +140,29 @@ def test_constrained_random_walk_fp32_parity(scheme):
         rep = lazy_teacher_forced(spec, N, seed, g, "rs", 1 << 20, BAND)
     log(f"crw {scheme}: {rep.summary()}")
     assert rep.mismatches_outside_band == 0, rep.worst[:5]
+
+
+@pytest.mark.parametrize("scheme", ["mh", "rs"])
+def test_lazy_batch_equals_single(scheme):
+    """A lazy plan's dsmc_smooth_batch (every level of every series in shared
+    launches, one hipGraph replay on the second call) equals each series'
+    own dsmc_smooth run bit for bit."""
+    import torch
+    from paper_2202_02264_amd import dsmc as G
+    specs = [W.constrained_rw(K, sigma=0.5) for K in (70, 1, 33, 128, 2)]
+    seeds = [21, 22, 23, 24, 25]
+    N = 128
+    res = SCHEMES[scheme]
+    plan = G.Plan(N, 1, max_K=128, max_total_K=sum(s.K for s in specs), graph=True,
+                  resampling=res, lazy_param=16 if scheme == "mh" else 0)
+    models = [G.Model(s) for s in specs]
+    outs = [G.alloc_output(plan, s.K, diagnostics=True) for s in specs]
+    log(f"gpu lazy {scheme} dsmc_smooth_batch of 5 series, twice")
+    for _ in range(2):                    # eager, then captured and replayed
+        G.dsmc_smooth_batch(plan, models, seeds, outs)
+        torch.cuda.synchronize()
+    single_plan = G.Plan(N, 1, max_K=128, resampling=res, lazy_param=16 if scheme == "mh" else 0)
+    for spec, m, o, seed in zip(specs, models, outs, seeds):
+        single = run_gpu(spec, N, seed, model=m, plan=single_plan)
+        for k in ("traj", "ancestry", "index", "leaf_x"):
+            np.testing.assert_array_equal(getattr(o, k).cpu().numpy(), single[k])
