@@ -274,6 +274,14 @@ int dsmc_smooth(dsmc_plan_t *plan, const dsmc_model_t *model, uint64_t seed,
 int dsmc_smooth_conditional(dsmc_plan_t *plan, const dsmc_model_t *model, uint64_t seed,
                             const void *star, const dsmc_output *out);
 
+/* B conditional runs (e.g. independent particle Gibbs chains) in packed
+ * launches, as dsmc_smooth_batch; stars[s] is series s's star trajectory
+ * (device, real [d_x][K_s]) or NULL for an unconditional run.  Results equal
+ * B separate dsmc_smooth_conditional / dsmc_smooth calls bit for bit. */
+int dsmc_smooth_batch_conditional(dsmc_plan_t *plan, int B, const dsmc_model_t *const *models,
+                                  const uint64_t *seeds, const void *const *stars,
+                                  const dsmc_output *outs);
+
 /* B independent series (each with its own model, K and seed) in packed
  * launches: every level's combines of all series run in the same kernels.
  * The results equal B separate dsmc_smooth calls bit for bit.

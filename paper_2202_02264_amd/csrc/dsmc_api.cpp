@@ -887,6 +887,14 @@ extern "C" int dsmc_smooth(dsmc_plan_t* p, const dsmc_model_t* model, uint64_t s
   return smooth_batch(p, 1, ms, &seed, nullptr, out);
 }
 
+extern "C" int dsmc_smooth_batch_conditional(dsmc_plan_t* p, int B,
+                                             const dsmc_model_t* const* models,
+                                             const uint64_t* seeds, const void* const* stars,
+                                             const dsmc_output* outs) {
+  if (!stars) return fail(DSMC_EINVAL, "null star list");
+  return smooth_batch(p, B, models, seeds, stars, outs);
+}
+
 extern "C" int dsmc_smooth_conditional(dsmc_plan_t* p, const dsmc_model_t* model, uint64_t seed,
                                        const void* star, const dsmc_output* out) {
   if (!star) return fail(DSMC_EINVAL, "null star trajectory");

@@ -96,6 +96,8 @@ def _load() -> C.CDLL:
         "dsmc_smooth": (i, [vp, vp, u64, C.POINTER(dsmc_output)]),
         "dsmc_smooth_batch": (i, [vp, i, C.POINTER(vp), C.POINTER(u64), C.POINTER(dsmc_output)]),
         "dsmc_smooth_conditional": (i, [vp, vp, u64, vp, C.POINTER(dsmc_output)]),
+        "dsmc_smooth_batch_conditional": (i, [vp, i, C.POINTER(vp), C.POINTER(u64),
+                                              C.POINTER(vp), C.POINTER(dsmc_output)]),
         "dsmc_plan_profile": (i, [vp, C.POINTER(dsmc_profile)]),
         "dsmc_server_create": (i, [C.POINTER(dsmc_server_desc), C.POINTER(vp)]),
         "dsmc_server_destroy": (None, [vp]),
@@ -276,6 +278,24 @@ def dsmc_smooth_conditional(plan: Plan, model: Model, seed: int, star, out: Outp
                                         C.c_uint64(seed & (2**64 - 1)),
                                         C.c_void_p(star.data_ptr()), C.byref(o)),
            "dsmc_smooth_conditional")
+
+
+def dsmc_smooth_batch_conditional(plan: Plan, models: Sequence[Model], seeds: Sequence[int],
+                                  stars: Sequence, outs: Sequence[Output]) -> None:
+    """B conditional runs in packed launches; stars[s] is a contiguous device
+    tensor [d_x][K_s] of the plan's real type, or None (unconditional)."""
+    B = len(models)
+    for st, m in zip(stars, models):
+        if st is not None and (not st.is_cuda or st.dtype != plan.dtype or not st.is_contiguous()
+                               or tuple(st.shape) != (plan.d_x, m.K)):
+            raise ValueError(f"each star must be a contiguous {plan.dtype} device tensor of "
+                             f"shape ({plan.d_x}, K)")
+    hs = (C.c_void_p * B)(*[m.handle.value for m in models])
+    ss = (C.c_uint64 * B)(*[int(s) & (2**64 - 1) for s in seeds])
+    ps = (C.c_void_p * B)(*[None if st is None else st.data_ptr() for st in stars])
+    os_ = (dsmc_output * B)(*[o.c_struct() for o in outs])
+    _check(_lib.dsmc_smooth_batch_conditional(plan.handle, B, hs, ss, ps, os_),
+           "dsmc_smooth_batch_conditional")
 
 
 def dsmc_smooth_batch(plan: Plan, models: Sequence[Model], seeds: Sequence[int],

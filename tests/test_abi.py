@@ -107,6 +107,7 @@ def test_invalid_arguments_rejected_on_host():
     p.resampling, p.precision, p.d_x = dsmc.DSMC_RESAMPLE_EXACT, dsmc.DSMC_FP32, 1
     assert lib.dsmc_smooth(None, None, 0, None) == dsmc.DSMC_EINVAL
     assert lib.dsmc_smooth_conditional(None, None, 0, None, None) == dsmc.DSMC_EINVAL
+    assert lib.dsmc_smooth_batch_conditional(None, 1, None, None, None, None) == dsmc.DSMC_EINVAL
     # serving entry points
     sd = dsmc.dsmc_server_desc()
     hs = C.c_void_p()

@@ -143,3 +143,26 @@ def test_star_argument_checked():
     with pytest.raises(ValueError):
         G.dsmc_smooth_conditional(plan, model, 1, torch.zeros((1, 8), dtype=torch.float64,
                                                               device="cuda"), out)
+
+
+def test_batch_conditional_equals_single():
+    """dsmc_smooth_batch_conditional: conditional and unconditional series in
+    one packed call equal their own single calls bit for bit."""
+    import torch
+    from paper_2202_02264_amd import dsmc as G
+    specs = [W.sv(K, seed=40 + K) for K in (70, 1, 33, 128)]
+    seeds = [31, 32, 33, 34]
+    N = 96
+    stars = [torch.tensor(_star(s, np.float32).T.copy(), dtype=torch.float32, device="cuda")
+             for s in specs]
+    stars[2] = None
+    plan = G.Plan(N, 1, max_K=128, max_total_K=sum(s.K for s in specs))
+    models = [G.Model(s) for s in specs]
+    outs = [G.alloc_output(plan, s.K, diagnostics=True) for s in specs]
+    G.dsmc_smooth_batch_conditional(plan, models, seeds, stars, outs)
+    torch.cuda.synchronize()
+    for spec, m, o, seed, st in zip(specs, models, outs, seeds, stars):
+        single = run_gpu(spec, N, seed, model=m,
+                         star=None if st is None else st.cpu().numpy().T.astype(np.float64))
+        for k in ("traj", "log_Z", "ancestry", "index", "leaf_x"):
+            np.testing.assert_array_equal(getattr(o, k).cpu().numpy(), single[k])
