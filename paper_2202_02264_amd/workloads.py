@@ -148,14 +148,18 @@ def sv(K: int, mu: float = -1.0, rho: float = 0.95, sigma: float = 0.3,
 
 def lg(K: int, F: np.ndarray, Q_chol: np.ndarray, H: np.ndarray, R_chol: np.ndarray,
        m0: np.ndarray, P0_chol: np.ndarray, seed: int = DATA_SEED,
-       proposal: str = "rts", weighting: str = "leaf_obs", name: str = "lg") -> SSM:
-    """General linear-Gaussian model; proposal "rts" = exact smoothing marginals
-    (the Gaussian-approximation proposals of Section 4.1, exact for this model),
-    "prior" = prior marginals."""
+       proposal: str = "rts", weighting: str = "leaf_obs", name: str = "lg",
+       f: Optional[np.ndarray] = None, h: Optional[np.ndarray] = None) -> SSM:
+    """General linear-Gaussian model x_t = F x_{t-1} + f + N(0, Q),
+    y_t = H x_t + h + N(0, R) (f, h default to zero); proposal "rts" = exact
+    smoothing marginals (the Gaussian-approximation proposals of Section 4.1,
+    exact for this model), "prior" = prior marginals."""
     dx, dy = F.shape[0], H.shape[0]
     spec = SSM(d_x=dx, d_y=dy, m0=np.asarray(m0, float), P0_chol=_as2(P0_chol),
-               F=_as2(F), f=np.zeros(dx), Q_chol=_as2(Q_chol), obs="lg", H=_as2(H),
-               h=np.zeros(dy), R_chol=_as2(R_chol), y=np.zeros((K, dy)),
+               F=_as2(F), f=np.zeros(dx) if f is None else np.asarray(f, float).reshape(dx),
+               Q_chol=_as2(Q_chol), obs="lg", H=_as2(H),
+               h=np.zeros(dy) if h is None else np.asarray(h, float).reshape(dy),
+               R_chol=_as2(R_chol), y=np.zeros((K, dy)),
                q_mean=np.zeros((K, dx)), q_chol=np.zeros((K, dx, dx)),
                weighting=weighting, name=name)
     _finish(spec, K, seed)
