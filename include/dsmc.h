@@ -69,6 +69,7 @@ typedef enum dsmc_status {
   DSMC_EAGAIN = -4,       /* dsmc_poll: the job has not finished */
   DSMC_EDEGENERATE = -5,  /* a combine had zero total weight */
   DSMC_ENUMERIC = -6,     /* a weight was NaN */
+  DSMC_ECALLBACK = -7,    /* a model callback returned nonzero */
   DSMC_EDEVICE = -8,      /* HIP runtime error */
   DSMC_ECANCELLED = -9,   /* job cancelled, or server shut down, before the job ran */
   DSMC_EDEADLINE = -10    /* serving: the job was still queued at its admission deadline */
@@ -85,7 +86,10 @@ typedef enum dsmc_status {
 
 /* ---------------------------------------------------------------- model */
 
-enum { DSMC_OBS_LINEAR_GAUSSIAN = 0, /* y_t ~ N(H x_t + h, R)                  */
+enum { DSMC_OBS_NONE = -1,           /* no parametric form: h_t is given by the
+                                        log_observation callback only, which the
+                                        device cannot run (DSMC_EUNSUPPORTED) */
+       DSMC_OBS_LINEAR_GAUSSIAN = 0, /* y_t ~ N(H x_t + h, R)                  */
        DSMC_OBS_STOCH_VOL = 1,       /* y_t ~ N(0, exp(x_t)), needs d_x = d_y = 1 */
        DSMC_OBS_BOX = 2 };           /* h_t(x) = 1 if lo_t <= x <= hi_t else 0, with
                                         y_t = (lo_t, hi_t), d_y = 2 d_x: the constrained
@@ -104,10 +108,35 @@ enum { DSMC_PROPOSAL_GAUSSIAN = 0, DSMC_PROPOSAL_UNIFORM = 1 };
  * Both target the same smoothing distribution. */
 enum { DSMC_WEIGHT_LEAF_OBS = 0, DSMC_WEIGHT_BOUNDARY_OBS = 1 };
 
+/* Host callbacks: the model as the problem statement of the paper's
+ * introduction gives it (prior P_0, transition densities p_t, potentials h_t)
+ * plus Algorithm 2's proposals q_t.  Each is vectorised over n points, fp64,
+ * row-major [n][d_x], and returns 0 on success (nonzero: DSMC_ECALLBACK).
+ * Callbacks must be deterministic; the library owns all randomness and hands
+ * the proposal its standard variates z.
+ *   log_prior        out[i] = log p_0(x_i)
+ *   log_transition   out[i] = log p_t(x_i | xp_i), t >= 1
+ *   log_observation  out[i] = log h_t(x_i)
+ *   proposal         x_out[i] = the draw of q_t made from z_i (standard normals
+ *                    for Gaussian proposals, uniforms on [0, 1) for uniform
+ *                    ones) and logq_out[i] = log q_t(x_out[i])
+ * The GPU cannot call host code, so the kernels evaluate the parametric
+ * (device) form of dsmc_model_desc; the callbacks define the model and
+ * dsmc_model_check / dsmc_model_create verify that the device form computes
+ * the same densities (see dsmc_model_check).  Any callback may be NULL
+ * (not checked). */
+typedef struct dsmc_model_callbacks {
+  void *ctx;
+  int (*log_prior)(void *ctx, int n, const double *x, double *out);
+  int (*log_transition)(void *ctx, int t, int n, const double *xp, const double *x, double *out);
+  int (*log_observation)(void *ctx, int t, int n, const double *x, double *out);
+  int (*proposal)(void *ctx, int t, int n, const double *z, double *x_out, double *logq_out);
+} dsmc_model_callbacks;
+
 /* The Feynman-Kac model of the paper's introduction: prior P_0, transitions
  * P_t with density p_t, potentials h_t, and the independent proposals q_t of
- * Algorithm 2.  The four components are given as parametric families (the
- * device cannot call host code); all are read in fp64. */
+ * Algorithm 2, given in the parametric (device) form below, read in fp64, and
+ * optionally also as host callbacks (dsmc_model_callbacks). */
 typedef struct dsmc_model_desc {
   int K;   /* time points t = 0..K-1, K >= 1 */
   int d_x; /* state dimension, 1..DSMC_MAX_DX */
@@ -130,16 +159,32 @@ typedef struct dsmc_model_desc {
   const double *q_chol; /* [K][d_x][d_x] */
   int weighting;        /* DSMC_WEIGHT_* */
   int proposal_kind;    /* DSMC_PROPOSAL_* (0 = Gaussian) */
+  const dsmc_model_callbacks *callbacks; /* optional host form of the model (NULL = none) */
 } dsmc_model_desc;
 
 typedef struct dsmc_model dsmc_model_t;
 
-/* Validate the description, derive inverse Cholesky factors and log
- * normalisers on the host in fp64, and copy everything to device memory of
- * the current device (synchronously).  Errors: DSMC_EINVAL (bad sizes,
- * non-positive Cholesky diagonal, unknown kind, STOCH_VOL with d_x != 1,
- * BOX with d_y != 2 d_x, UNIFORM proposals with d_x > 4),
- * DSMC_ENOMEM, DSMC_EDEVICE.  The model may be shared by many calls. */
+/* Host-only validation of a description, no device work.  Checks sizes, kinds
+ * and parameters (DSMC_EINVAL).  With callbacks it then evaluates the device
+ * form against them at 256 check points: 16 time points t spread over 0..K-1,
+ * 16 points each, x drawn from q_t (and x' from q_{t-1} for the transition)
+ * with variates of a fixed host generator.  Every log density must agree
+ * within |d| <= 1e-9 max(1, |callback value|) (both -inf counts as equal),
+ * and the proposal's x and log q likewise; otherwise DSMC_EINVAL, with the
+ * component, t and the two values in dsmc_last_error.  A callback returning
+ * nonzero gives DSMC_ECALLBACK.  Callbacks without a complete device form
+ * (obs_kind DSMC_OBS_NONE, or a missing prior, transition or proposal array)
+ * give DSMC_EUNSUPPORTED: the kernels have nothing to evaluate. */
+int dsmc_model_check(const dsmc_model_desc *desc);
+
+/* dsmc_model_check, then derive inverse Cholesky factors and log normalisers
+ * on the host in fp64 and copy the device form to device memory of the
+ * current device (synchronously).  Errors: those of dsmc_model_check
+ * (DSMC_EINVAL: bad sizes, non-positive Cholesky diagonal, unknown kind,
+ * STOCH_VOL with d_x != 1, BOX with d_y != 2 d_x, UNIFORM proposals with
+ * d_x > 4, device form disagreeing with the callbacks; DSMC_ECALLBACK;
+ * DSMC_EUNSUPPORTED), DSMC_ENOMEM, DSMC_EDEVICE.  Callbacks are not called
+ * after this returns.  The model may be shared by many calls. */
 int dsmc_model_create(const dsmc_model_desc *desc, dsmc_model_t **out);
 void dsmc_model_destroy(dsmc_model_t *model);
 int dsmc_model_K(const dsmc_model_t *model);
@@ -346,6 +391,12 @@ int dsmc_poll(dsmc_server_t *server, uint64_t job_id, int *state);
  * observed completion (0 while not reached). */
 int dsmc_job_times(dsmc_server_t *server, uint64_t job_id, double *t_submit, double *t_start,
                    double *t_done);
+/* Forget a finished job (DONE or FAILED): its record is freed and its id
+ * becomes unknown (DSMC_EINVAL from then on).  A long-running server keeps one
+ * record per submitted job until it is released or the server is destroyed.
+ * Returns DSMC_OK, DSMC_EAGAIN if the job is still queued or running,
+ * DSMC_EINVAL for an unknown id. */
+int dsmc_job_release(dsmc_server_t *server, uint64_t job_id);
 
 /* Kernel timings of a plan created with DSMC_PLAN_PROFILE, accumulated over
  * every dsmc_smooth / dsmc_smooth_batch since the previous dsmc_plan_profile

@@ -13,7 +13,9 @@ INCLUDE = os.path.join(ROOT, "include")
 LIB = os.path.join(PKG, "libdsmc.so")
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
 
-SOURCES = ["dsmc_kernels.hip", "dsmc_api.cpp", "dsmc_server.cpp"]
+SOURCES = ["dsmc_kernels.hip", "dsmc_kernels_dx1_8.hip", "dsmc_kernels_dx16.hip",
+           "dsmc_kernels_dx32_f32.hip", "dsmc_kernels_dx32_f64.hip", "dsmc_api.cpp",
+           "dsmc_server.cpp"]
 
 # Packed-fp32 instructions are disabled for all device code (the compiler
 # would otherwise form v_pk_* from plain float arithmetic).  Matrix-core
@@ -40,7 +42,7 @@ def _compile(src: str, objdir: str) -> str:
 def build(verbose: bool = True) -> str:
     objdir = os.path.join(PKG, "_build")
     os.makedirs(objdir, exist_ok=True)
-    with ThreadPoolExecutor(max_workers=len(SOURCES)) as ex:
+    with ThreadPoolExecutor(max_workers=min(len(SOURCES), 8)) as ex:
         objs = list(ex.map(lambda s: _compile(s, objdir), SOURCES))
     tmp = LIB + ".tmp"
     cmd = [HIPCC, "-shared", "-fPIC", "--offload-arch=gfx950", *objs, "-o", tmp]

@@ -1,5 +1,6 @@
-// Host side of the C ABI declared in include/dsmc.h: model upload, plans and
-// their device workspace, the Algorithm-5 schedule, and the launch sequence.
+// Host side of the C ABI declared in include/dsmc.h: model validation (with the
+// callback self-check) and upload, plans and their device workspace, the
+// Algorithm 6 schedule, and the launch sequence.
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
@@ -62,13 +63,19 @@ static bool all_finite(const double* p, size_t n) {
   return true;
 }
 
-extern "C" int dsmc_model_create(const dsmc_model_desc* d, dsmc_model_t** out) {
-  if (!d || !out) return fail(DSMC_EINVAL, "null argument");
-  *out = nullptr;
+// Sizes, kinds and parameters of a description (no callbacks, no device).
+static int validate_desc(const dsmc_model_desc* d) {
+  if (!d) return fail(DSMC_EINVAL, "null argument");
   const int K = d->K, dx = d->d_x, dy = d->d_y;
   if (K < 1) return fail(DSMC_EINVAL, "K must be >= 1 (got %d)", K);
   if (dx < 1 || dx > DSMC_MAX_DX) return fail(DSMC_EINVAL, "d_x must be in 1..%d", DSMC_MAX_DX);
   if (dy < 1) return fail(DSMC_EINVAL, "d_y must be >= 1");
+  const bool complete = d->m0 && d->P0_chol && d->F && d->f && d->Q_chol && d->y && d->q_mean &&
+                        d->q_chol && d->obs_kind != DSMC_OBS_NONE;
+  if (!complete && d->callbacks)
+    return fail(DSMC_EUNSUPPORTED,
+                "the model is given by callbacks without a complete parametric (device) form; "
+                "the GPU cannot run host callbacks");
   if (!d->m0 || !d->P0_chol || !d->F || !d->f || !d->Q_chol || !d->y || !d->q_mean || !d->q_chol)
     return fail(DSMC_EINVAL, "missing model array");
   if (d->obs_kind == DSMC_OBS_STOCH_VOL) {
@@ -91,6 +98,208 @@ extern "C" int dsmc_model_create(const dsmc_model_desc* d, dsmc_model_t** out) {
       !all_finite(d->f, dx) || !all_finite(d->Q_chol, dd) ||
       !all_finite(d->q_mean, (size_t)K * dx) || !all_finite(d->q_chol, (size_t)K * dd))
     return fail(DSMC_EINVAL, "non-finite model parameter");
+  return DSMC_OK;
+}
+
+// ---- host evaluation of the parametric form, for the callback self-check
+
+// -1/2 || Linv (v) ||^2 for lower-triangular Linv [d][d].
+static double neg_half_quad(const double* Linv, const double* v, int d) {
+  double q = 0.0;
+  for (int i = 0; i < d; ++i) {
+    double z = 0.0;
+    for (int j = 0; j <= i; ++j) z += Linv[i * d + j] * v[j];
+    q += z * z;
+  }
+  return -0.5 * q;
+}
+
+namespace {
+struct HostForm {
+  const dsmc_model_desc* d;
+  std::vector<double> P0i, Qi, Ri;
+  double prior_ln = 0, trans_ln = 0, obs_ln = 0;
+
+  bool init() {
+    const int dx = d->d_x, dy = d->d_y;
+    P0i.resize((size_t)dx * dx);
+    Qi.resize((size_t)dx * dx);
+    if (!tri_inverse(d->P0_chol, dx, P0i.data()) || !tri_inverse(d->Q_chol, dx, Qi.data()))
+      return false;
+    prior_ln = log_norm(d->P0_chol, dx);
+    trans_ln = log_norm(d->Q_chol, dx);
+    if (d->obs_kind == DSMC_OBS_LINEAR_GAUSSIAN) {
+      Ri.resize((size_t)dy * dy);
+      if (!tri_inverse(d->R_chol, dy, Ri.data())) return false;
+      obs_ln = log_norm(d->R_chol, dy);
+    }
+    return true;
+  }
+  double log_prior(const double* x) const {
+    const int dx = d->d_x;
+    std::vector<double> v(dx);
+    for (int i = 0; i < dx; ++i) v[i] = x[i] - d->m0[i];
+    return neg_half_quad(P0i.data(), v.data(), dx) + prior_ln;
+  }
+  double log_transition(const double* xp, const double* x) const {
+    const int dx = d->d_x;
+    std::vector<double> v(dx);
+    for (int i = 0; i < dx; ++i) {
+      double m = d->f[i];
+      for (int j = 0; j < dx; ++j) m += d->F[i * dx + j] * xp[j];
+      v[i] = x[i] - m;
+    }
+    return neg_half_quad(Qi.data(), v.data(), dx) + trans_ln;
+  }
+  double log_observation(int t, const double* x) const {
+    const int dx = d->d_x, dy = d->d_y;
+    const double* y = d->y + (size_t)t * dy;
+    if (d->obs_kind == DSMC_OBS_STOCH_VOL)
+      return -0.5 * std::log(2.0 * M_PI) - 0.5 * x[0] - 0.5 * y[0] * y[0] * std::exp(-x[0]);
+    if (d->obs_kind == DSMC_OBS_BOX) {
+      for (int i = 0; i < dx; ++i)
+        if (!(x[i] >= y[i] && x[i] <= y[dx + i])) return -INFINITY;
+      return 0.0;
+    }
+    std::vector<double> v(dy);
+    for (int i = 0; i < dy; ++i) {
+      double m = d->h[i];
+      for (int k = 0; k < dx; ++k) m += d->H[i * dx + k] * x[k];
+      v[i] = y[i] - m;
+    }
+    return neg_half_quad(Ri.data(), v.data(), dy) + obs_ln;
+  }
+  // x = the draw of q_t made from variates z; returns log q_t(x)
+  double proposal(int t, const double* z, double* x) const {
+    const int dx = d->d_x;
+    const double* qm = d->q_mean + (size_t)t * dx;
+    const double* qc = d->q_chol + (size_t)t * dx * dx;
+    if (d->proposal_kind == DSMC_PROPOSAL_UNIFORM) {
+      double ln = 0.0;
+      for (int i = 0; i < dx; ++i) {
+        const double hw = qc[i * dx + i];
+        x[i] = qm[i] + hw * (2.0 * z[i] - 1.0);
+        ln -= std::log(2.0 * hw);
+      }
+      return ln;
+    }
+    std::vector<double> qi((size_t)dx * dx), v(dx);
+    tri_inverse(qc, dx, qi.data());
+    for (int i = 0; i < dx; ++i) {
+      double s = qm[i];
+      for (int j = 0; j <= i; ++j) s += qc[i * dx + j] * z[j];
+      x[i] = s;
+      v[i] = s - qm[i];
+    }
+    return neg_half_quad(qi.data(), v.data(), dx) + log_norm(qc, dx);
+  }
+};
+
+// Fixed generator of the check points (splitmix64; any deterministic points do).
+struct CheckRng {
+  uint64_t s = 0x9E3779B97F4A7C15ull;
+  uint64_t next() {
+    uint64_t z = (s += 0x9E3779B97F4A7C15ull);
+    z = (z ^ (z >> 30)) * 0xBF58476D1CE4E5B9ull;
+    z = (z ^ (z >> 27)) * 0x94D049BB133111EBull;
+    return z ^ (z >> 31);
+  }
+  double unif() { return (double)(next() >> 11) * 0x1p-53; }
+  double normal() {
+    const double u1 = ((double)(next() >> 11) + 1.0) * 0x1p-53, u2 = unif();
+    return std::sqrt(-2.0 * std::log(u1)) * std::cos(2.0 * M_PI * u2);
+  }
+};
+
+bool close_enough(double got, double want) {
+  if (std::isinf(want) || std::isinf(got)) return got == want;
+  if (std::isnan(got) || std::isnan(want)) return false;
+  return std::fabs(got - want) <= 1e-9 * std::max(1.0, std::fabs(want));
+}
+}  // namespace
+
+// Evaluate the callbacks at 256 check points and compare with the parametric form.
+static int self_check(const dsmc_model_desc* d) {
+  const dsmc_model_callbacks* cb = d->callbacks;
+  HostForm hf{d};
+  if (!hf.init()) return fail(DSMC_EINVAL, "bad Cholesky factor");
+  const int K = d->K, dx = d->d_x;
+  constexpr int kTimes = 16, kPer = 16;
+  CheckRng rng;
+  const bool unif = d->proposal_kind == DSMC_PROPOSAL_UNIFORM;
+  std::vector<double> z(kPer * dx), zp(kPer * dx), x(kPer * dx), xp(kPer * dx), want(kPer),
+      got(kPer), gx(kPer * dx), lq(kPer);
+  for (int j = 0; j < kTimes; ++j) {
+    const int t = (int)(((long)j * (K - 1)) / (kTimes - 1));
+    for (auto& v : z) v = unif ? rng.unif() : rng.normal();
+    for (auto& v : zp) v = unif ? rng.unif() : rng.normal();
+    std::vector<double> lqw(kPer);
+    for (int i = 0; i < kPer; ++i) lqw[i] = hf.proposal(t, &z[i * dx], &x[i * dx]);
+    const int tp = t >= 1 ? t - 1 : 0;
+    for (int i = 0; i < kPer; ++i) hf.proposal(tp, &zp[i * dx], &xp[i * dx]);
+    auto mismatch = [&](const char* what, int i) {
+      return fail(DSMC_EINVAL,
+                  "device form disagrees with the %s callback at t=%d, point %d: %.17g (callback) "
+                  "vs %.17g (device form)",
+                  what, t, i, got[i], want[i]);
+    };
+    if (cb->proposal) {
+      if (cb->proposal(cb->ctx, t, kPer, z.data(), gx.data(), lq.data()))
+        return fail(DSMC_ECALLBACK, "proposal callback failed at t=%d", t);
+      for (int i = 0; i < kPer; ++i) {
+        for (int k = 0; k < dx; ++k)
+          if (!close_enough(gx[i * dx + k], x[i * dx + k]))
+            return fail(DSMC_EINVAL,
+                        "device form disagrees with the proposal callback at t=%d, point %d, "
+                        "coordinate %d: %.17g (callback) vs %.17g (device form)",
+                        t, i, k, gx[i * dx + k], x[i * dx + k]);
+        got[i] = lq[i];
+        want[i] = lqw[i];
+        if (!close_enough(got[i], want[i])) return mismatch("proposal density", i);
+      }
+    }
+    if (cb->log_prior && j == 0) {
+      if (cb->log_prior(cb->ctx, kPer, x.data(), got.data()))
+        return fail(DSMC_ECALLBACK, "log_prior callback failed");
+      for (int i = 0; i < kPer; ++i) {
+        want[i] = hf.log_prior(&x[i * dx]);
+        if (!close_enough(got[i], want[i])) return mismatch("log_prior", i);
+      }
+    }
+    if (cb->log_observation) {
+      if (cb->log_observation(cb->ctx, t, kPer, x.data(), got.data()))
+        return fail(DSMC_ECALLBACK, "log_observation callback failed at t=%d", t);
+      for (int i = 0; i < kPer; ++i) {
+        want[i] = hf.log_observation(t, &x[i * dx]);
+        if (!close_enough(got[i], want[i])) return mismatch("log_observation", i);
+      }
+    }
+    if (cb->log_transition && K >= 2 && t >= 1) {
+      if (cb->log_transition(cb->ctx, t, kPer, xp.data(), x.data(), got.data()))
+        return fail(DSMC_ECALLBACK, "log_transition callback failed at t=%d", t);
+      for (int i = 0; i < kPer; ++i) {
+        want[i] = hf.log_transition(&xp[i * dx], &x[i * dx]);
+        if (!close_enough(got[i], want[i])) return mismatch("log_transition", i);
+      }
+    }
+  }
+  return DSMC_OK;
+}
+
+extern "C" int dsmc_model_check(const dsmc_model_desc* d) {
+  int rc = validate_desc(d);
+  if (rc) return rc;
+  if (!d->callbacks) return DSMC_OK;
+  return self_check(d);
+}
+
+extern "C" int dsmc_model_create(const dsmc_model_desc* d, dsmc_model_t** out) {
+  if (!d || !out) return fail(DSMC_EINVAL, "null argument");
+  *out = nullptr;
+  int rc = dsmc_model_check(d);
+  if (rc) return rc;
+  const int K = d->K, dx = d->d_x, dy = d->d_y;
+  const size_t dd = (size_t)dx * dx;
 
   // host copies of every array the device needs
   std::vector<double> m0(d->m0, d->m0 + dx), P0i(dd), F(d->F, d->F + dd), f(d->f, d->f + dx),

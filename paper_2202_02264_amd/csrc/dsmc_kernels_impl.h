@@ -1,0 +1,1402 @@
+// Kernel templates of the dSMC combine tree for gfx950 (wave64, fp32/fp64
+// VALU, bf16 matrix cores), instantiated once per padded state dimension DX in
+// dsmc_kernels_dx*.hip so that the instantiations compile in parallel.
+//
+//   k_leaves   once per call, one workgroup per time point: Algorithm 2 (draw,
+//              weight, normalise), plus the data the time point's consumer
+//              combine needs (whitened coordinates and log-weights).
+//   k_rows     per level: the N x N pair-weight matrix of every combine, never
+//              stored.  Each lane owns RPL rows; all lanes walk the same
+//              columns, whose (u, beta) are wave-uniform and come through
+//              scalar registers.  Per pair: DX x (sub, fma) + exp2 + add.
+//              Output: 32-column chunk sums and fp64 row sums.
+//   k_sample   per level: per combine, the fp64 row-marginal CDF, N two-stage
+//              multinomial draws (Algorithm 1), the ancestry of the merged
+//              block's first and last times, and the data its consumer combine
+//              needs.  Several workgroups may share one combine's draws.
+//   k_output   once per call: each output entry follows the ancestry from the
+//              root combine down to its leaf (the gather of Algorithm 1, done
+//              once instead of per level).
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include <cmath>
+
+#include "dsmc.h"
+#include "dsmc_device.h"
+#include "dsmc_launch.h"
+
+namespace dsmc {
+
+// Row sums of combines with DX >= 8 are formed relative to a per-row shift
+// (see k_rows); below that the column bound alone keeps them in range.
+template <int DX>
+inline constexpr bool kRowShift = DX >= 8;
+
+// Whitened column coordinates of a right-block particle x at boundary c:
+// u = Wcol (x - q_mean[c]).
+template <int DX>
+__device__ __forceinline__ void col_coords(const DevModel& M, int c, const double (&x)[DX],
+                                           double (&u)[DX]) {
+  const int dx = uniform(M.dx);
+  const double* qm = M.q_mean + (size_t)c * dx;
+#pragma unroll
+  for (int i = 0; i < DX; ++i) {
+    double s = 0.0;
+    if (i < dx)
+      for (int j = 0; j < dx; ++j) s += M.Wcol[i * dx + j] * (x[j] - qm[j]);
+    u[i] = s;
+  }
+}
+
+// Whitened row coordinates of a left-block particle x at boundary c:
+// v = Wrow x + wcol_off - Wcol q_mean[c], so that
+// ||u - v||^2 = (log2 e / 2) ||Q^{-1/2} (x_R - F x_L - f)||^2.
+template <int DX>
+__device__ __forceinline__ void row_coords(const DevModel& M, int c, const double (&x)[DX],
+                                           double (&v)[DX]) {
+  const int dx = uniform(M.dx);
+  const double* qm = M.q_mean + (size_t)c * dx;
+#pragma unroll
+  for (int i = 0; i < DX; ++i) {
+    double s = 0.0;
+    if (i < dx) {
+      s = M.wcol_off[i];
+      for (int j = 0; j < dx; ++j) s += M.Wrow[i * dx + j] * x[j] - M.Wcol[i * dx + j] * qm[j];
+    }
+    v[i] = s;
+  }
+}
+
+template <typename R, int DX>
+__device__ __forceinline__ void load_particle(const R* __restrict__ leafX, int totalK, int N, int g,
+                                              int src, int dx, double (&x)[DX]) {
+#pragma unroll
+  for (int i = 0; i < DX; ++i)
+    x[i] = (i < dx) ? (double)leafX[((size_t)i * totalK + g) * N + src] : 0.0;
+}
+
+// bf16 bits of x, rounded to nearest even (NaN stays NaN).
+__device__ __forceinline__ uint32_t bf16_bits(float x) {
+  const uint32_t u = __float_as_uint(x);
+  if ((u & 0x7fffffffu) > 0x7f800000u) return 0x7fc0u;
+  return (u + 0x7fffu + ((u >> 16) & 1u)) >> 16;
+}
+__device__ __forceinline__ float bf16_float(uint32_t b) { return __uint_as_float(b << 16); }
+
+// Table entry of particle n of time row g for the combine at boundary t:
+// u (bf16 plans: rounded to bf16, plus the bits of 2u and ||u||^2).
+template <typename R, int DX>
+__device__ __forceinline__ void put_tcol(const NodeBufs& nb, size_t g, int N, int n,
+                                         const double (&u)[DX]) {
+  R* tp = (R*)nb.tcol + (g * N + n) * DX;
+  if constexpr (sizeof(R) == 4 && DX >= 16) {
+    if (nb.tcolh) {
+      uint32_t w[DX / 2];
+      double nrm = 0.0;
+#pragma unroll
+      for (int i = 0; i < DX; ++i) {
+        const float ur = bf16_float(bf16_bits((float)u[i]));
+        tp[i] = ur;
+        nrm += (double)ur * (double)ur;
+        const uint32_t b2 = bf16_bits(2.0f * ur);
+        w[i >> 1] = (i & 1) ? (w[i >> 1] | (b2 << 16)) : b2;
+      }
+      uint4* dst = (uint4*)(nb.tcolh + (g * N + n) * DX);
+#pragma unroll
+      for (int q = 0; q < DX / 8; ++q) dst[q] = make_uint4(w[4 * q], w[4 * q + 1], w[4 * q + 2], w[4 * q + 3]);
+      nb.tcoln[g * N + n] = (float)nrm;
+      return;
+    }
+  }
+#pragma unroll
+  for (int i = 0; i < DX; ++i) tp[i] = (R)u[i];
+}
+
+// Table entry of particle n of time row g for the combine at boundary t + 1:
+// v (bf16 plans: rounded, plus its bits and ||v||^2).
+template <typename R, int DX>
+__device__ __forceinline__ void put_trow(const NodeBufs& nb, size_t g, int N, int n,
+                                         const double (&v)[DX]) {
+  R* tp = (R*)nb.trow + (g * N + n) * DX;
+  if constexpr (sizeof(R) == 4 && DX >= 16) {
+    if (nb.trowh) {
+      uint32_t w[DX / 2];
+      double nrm = 0.0;
+#pragma unroll
+      for (int i = 0; i < DX; ++i) {
+        const uint32_t b = bf16_bits((float)v[i]);
+        const float vr = bf16_float(b);
+        tp[i] = vr;
+        nrm += (double)vr * (double)vr;
+        w[i >> 1] = (i & 1) ? (w[i >> 1] | (b << 16)) : b;
+      }
+      uint4* dst = (uint4*)(nb.trowh + (g * N + n) * DX);
+#pragma unroll
+      for (int q = 0; q < DX / 8; ++q) dst[q] = make_uint4(w[4 * q], w[4 * q + 1], w[4 * q + 2], w[4 * q + 3]);
+      nb.trown[g * N + n] = (float)nrm;
+      return;
+    }
+  }
+#pragma unroll
+  for (int i = 0; i < DX; ++i) tp[i] = (R)v[i];
+}
+
+// Column n of combine `node` := table entry (g, src) with log2 weight beta.
+template <typename R, int DX>
+__device__ __forceinline__ void copy_col(const NodeBufs& nb, size_t node, int Npad, int n, size_t g,
+                                         int N, int src, double beta) {
+  const R* tp = (const R*)nb.tcol + (g * N + src) * DX;
+  R* cp = (R*)nb.col + (node * Npad + n) * (DX + 1);
+#pragma unroll
+  for (int i = 0; i < DX; ++i) cp[i] = tp[i];
+  cp[DX] = (R)beta;
+  if constexpr (sizeof(R) == 4 && DX >= 16) {
+    if (nb.colh) {
+      const uint4* s4 = (const uint4*)(nb.tcolh + (g * N + src) * DX);
+      uint4* d4 = (uint4*)(nb.colh + (node * Npad + n) * DX);
+#pragma unroll
+      for (int q = 0; q < DX / 8; ++q) d4[q] = s4[q];
+      nb.colb[node * Npad + n] = (float)beta - nb.tcoln[g * N + src];
+    }
+  }
+}
+
+// Row m of combine `node` := table entry (g, src).
+template <typename R, int DX>
+__device__ __forceinline__ void copy_row(const NodeBufs& nb, size_t node, int Npad, int m, size_t g,
+                                         int N, int src) {
+  const R* tp = (const R*)nb.trow + (g * N + src) * DX;
+  R* rp = (R*)nb.row + (node * Npad + m) * DX;
+#pragma unroll
+  for (int i = 0; i < DX; ++i) rp[i] = tp[i];
+  if constexpr (sizeof(R) == 4 && DX >= 16) {
+    if (nb.rowh) {
+      const uint4* s4 = (const uint4*)(nb.trowh + (g * N + src) * DX);
+      uint4* d4 = (uint4*)(nb.rowh + (node * Npad + m) * DX);
+#pragma unroll
+      for (int q = 0; q < DX / 8; ++q) d4[q] = s4[q];
+      nb.rown[node * Npad + m] = nb.trown[g * N + src];
+    }
+  }
+}
+
+// Table entries for DX >= 8, written coordinate by coordinate (the matrix row
+// loop is not unrolled, so only x stays in registers); same values, order and
+// rounding as col_coords / row_coords followed by put_tcol / put_trow.
+// Wc, Wr: the whitening matrices; column table: qm = q_mean[t]; row table:
+// woff = kappa Q_inv f - Wcol q_mean[t + 1] (formed once per time); any
+// address space (the leaf kernel passes copies in LDS).
+template <typename R, int DX, bool kRow>
+__device__ __forceinline__ void stream_table(const NodeBufs& nb, const double* Wc, const double* Wr,
+                                             const double* woff, const double* qm, int, size_t g,
+                                             int N, int n, const double (&x)[DX]) {
+  constexpr int dx = DX;  // zero-padded matrices and vectors
+  R* tp = (R*)(kRow ? nb.trow : nb.tcol) + (g * N + n) * DX;
+  uint32_t* th = nullptr;
+  if constexpr (sizeof(R) == 4 && DX >= 16)
+    th = (uint32_t*)(kRow ? nb.trowh : nb.tcolh);
+  if (th) th += (g * N + n) * (DX / 2);
+  double nrm = 0.0;
+#pragma unroll 1
+  for (int i = 0; i < DX; i += 2) {
+    double s2[2];
+#pragma unroll
+    for (int k = 0; k < 2; ++k) {
+      const int ii = i + k;
+      double acc = 0.0;
+      if (ii < dx) {
+        if (kRow) {  // woff here holds kappa Q_inv f - Wcol q_mean[t + 1] (per time)
+          acc = woff[ii];
+#pragma unroll
+          for (int j = 0; j < DX; ++j)
+            if (j < dx) acc += Wr[ii * dx + j] * x[j];
+        } else {
+#pragma unroll
+          for (int j = 0; j < DX; ++j)
+            if (j < dx) acc += Wc[ii * dx + j] * (x[j] - qm[j]);
+        }
+      }
+      s2[k] = acc;
+    }
+    if (th) {
+      const float r0 = bf16_float(bf16_bits((float)s2[0]));
+      const float r1 = bf16_float(bf16_bits((float)s2[1]));
+      tp[i] = r0;
+      tp[i + 1] = r1;
+      nrm += (double)r0 * (double)r0;
+      nrm += (double)r1 * (double)r1;
+      const uint32_t b0 = bf16_bits(kRow ? r0 : 2.0f * r0), b1 = bf16_bits(kRow ? r1 : 2.0f * r1);
+      th[i >> 1] = b0 | (b1 << 16);
+    } else {
+      tp[i] = (R)s2[0];
+      tp[i + 1] = (R)s2[1];
+    }
+  }
+  if (th) (kRow ? nb.trown : nb.tcoln)[g * N + n] = (float)nrm;
+}
+
+// Padding column n (N <= n < Npad): weight zero.
+template <typename R, int DX>
+__device__ __forceinline__ void put_col_pad(const NodeBufs& nb, size_t node, int Npad, int n) {
+  R* cp = (R*)nb.col + (node * Npad + n) * (DX + 1);
+#pragma unroll
+  for (int i = 0; i < DX; ++i) cp[i] = (R)0;
+  cp[DX] = (R)(-INFINITY);
+  if constexpr (sizeof(R) == 4 && DX >= 16) {
+    if (nb.colh) {
+      uint4* dst = (uint4*)(nb.colh + (node * Npad + n) * DX);
+#pragma unroll
+      for (int q = 0; q < DX / 8; ++q) dst[q] = make_uint4(0u, 0u, 0u, 0u);
+      nb.colb[node * Npad + n] = -INFINITY;
+    }
+  }
+}
+
+// ================================================================ leaves
+// One workgroup per time row g of the packed time axis.
+template <typename R, int DX>
+__global__ __launch_bounds__(kBlock, 3) void k_leaves(
+    const SeriesDesc* __restrict__ series, const int32_t* __restrict__ series_of_t,
+    const int32_t* __restrict__ leaf_cons, const NodeDesc* __restrict__ nodes, int row0,
+    int totalK, int N, int Npad, R* __restrict__ leafX, R* __restrict__ leafW,
+    double* __restrict__ leafL, double* __restrict__ bmerged, NodeBufs nb) {
+  extern __shared__ double sh[];
+  const int g = row0 + blockIdx.x;
+  const SeriesDesc& sd = series[series_of_t[g]];
+  const DevModel& M = *sd.model;
+  const int t = uniform(g - sd.base);
+  const int dx = uniform(M.dx);
+  const int K = uniform(sd.K);
+  const int weighting = uniform(M.weighting);
+  // LDS: ell [N]; gq [N] (DX >= 8: gq lives in its table in global memory and
+  // LDS holds this time's matrices instead)
+  double* ell = sh;  // unnormalised leaf log-weights
+  double* gq = (DX >= 8) ? nb.tgq + (size_t)g * N : sh + N;  // -log q_t (+ log h_t, boundary weighting)
+  __shared__ double red[2 * kBlock / 64];
+  __shared__ int redi[2 * kBlock / 64];
+  const double logN = log((double)N);
+  int bad = 0;
+  const double* qm = M.q_mean + (size_t)t * dx;
+  const double* qc = M.q_chol + (size_t)t * dx * dx;
+  const double* qi = M.q_inv + (size_t)t * dx * dx;
+  const double* Wc = M.Wcol;
+  const double* Wr = M.Wrow;
+  const double* qm1 = (t + 1 < K) ? qm + dx : qm;  // q_mean[t + 1]
+  // DX >= 8: this time's matrices and vectors in LDS, zero-padded to DX x DX
+  // (triangular factors with zero upper triangles), so the particle loops
+  // below run without per-element bounds checks; the extra terms are exact
+  // zeros and leave every sum unchanged.
+  const bool lds_obs = uniform(M.obs_kind) == 0 && uniform(M.dy) <= DX;
+  double *Lc = nullptr, *Li = nullptr, *Hl = nullptr, *vy = nullptr, *vw = nullptr;
+  if constexpr (DX >= 8) {
+    const int dy = uniform(M.dy);
+    Lc = sh + N;
+    Li = Lc + DX * DX;
+    double* Wcl = Li + DX * DX;
+    double* Wrl = Wcl + DX * DX;
+    Hl = Wrl + DX * DX;
+    double* vq = Hl + DX * DX;
+    double* vq1 = vq + DX;
+    vw = vq1 + DX;
+    vy = vw + DX;
+    for (int e = threadIdx.x; e < DX * DX; e += kBlock) {
+      const int i = e / DX, j = e - (e / DX) * DX;
+      const bool in = i < dx && j < dx;
+      Lc[e] = (in && j <= i) ? qc[i * dx + j] : 0.0;
+      Li[e] = (in && j <= i) ? qi[i * dx + j] : 0.0;
+      Wcl[e] = in ? Wc[i * dx + j] : 0.0;
+      Wrl[e] = in ? Wr[i * dx + j] : 0.0;
+      Hl[e] = (lds_obs && i < dy && j < dx) ? M.H[i * dx + j] : 0.0;
+    }
+    for (int i = threadIdx.x; i < DX; i += kBlock) {
+      vq[i] = i < dx ? qm[i] : 0.0;
+      vq1[i] = i < dx ? qm1[i] : 0.0;
+      vy[i] = (lds_obs && i < dy) ? M.y[(size_t)t * dy + i] : 0.0;
+      double w = 0.0;  // the row coordinates' per-time offset
+      if (i < dx) {
+        w = M.wcol_off[i];
+        for (int j = 0; j < dx; ++j) w -= Wc[i * dx + j] * qm1[j];
+      }
+      vw[i] = w;
+    }
+    __syncthreads();
+    Wc = Wcl;
+    Wr = Wrl;
+    qm = vq;
+    qm1 = vq1;
+  }
+  for (int n = threadIdx.x; n < N; n += kBlock) {
+    // standard normals, four per Philox block, then x = q_mean + L z in place
+    // from the last coordinate down (x_i needs z_0 .. z_i)
+    double x[DX];
+    if constexpr (DX >= 8) {
+      // one Philox block (four normals) at a time, each added into every
+      // x_i it enters: the same terms in the same order as below, without
+      // holding all the normals
+#pragma unroll
+      for (int i = 0; i < DX; ++i) x[i] = qm[i];
+#pragma unroll 1
+      for (int j = 0; j < (DX + 3) / 4; ++j) {
+        const Words4 w = philox4x64_10((uint64_t)n, (uint64_t)t, kPurposeLeaf, (uint64_t)j,
+                                       sd.seed, kKey1);
+        double z[4];
+        box_muller(w.w0, w.w1, z[0], z[1]);
+        box_muller(w.w2, w.w3, z[2], z[3]);
+#pragma unroll
+        for (int i = 0; i < DX; ++i) {
+#pragma unroll
+          for (int k = 0; k < 4; ++k) x[i] += Lc[i * DX + 4 * j + k] * z[k];
+        }
+      }
+#pragma unroll
+      for (int i = 0; i < DX; ++i) {
+        const R xr = (R)x[i];
+        if (i < dx) leafX[((size_t)i * totalK + g) * N + n] = xr;
+        x[i] = (double)xr;  // weights are those of the stored particle (0 past dx)
+      }
+    } else {
+      const bool unif = uniform(M.prop_kind) == 1;  // uniform proposal: uniforms, not normals
+#pragma unroll
+      for (int j = 0; j < (DX + 3) / 4; ++j) {
+        const Words4 w = philox4x64_10((uint64_t)n, (uint64_t)t, kPurposeLeaf, (uint64_t)j,
+                                       sd.seed, kKey1);
+        double z0, z1, z2, z3;
+        if (unif) {
+          z0 = unif53(w.w0);
+          z1 = unif53(w.w1);
+          z2 = unif53(w.w2);
+          z3 = unif53(w.w3);
+        } else {
+          box_muller(w.w0, w.w1, z0, z1);
+          box_muller(w.w2, w.w3, z2, z3);
+        }
+        if (4 * j < DX) x[4 * j] = z0;
+        if (4 * j + 1 < DX) x[4 * j + 1] = z1;
+        if (4 * j + 2 < DX) x[4 * j + 2] = z2;
+        if (4 * j + 3 < DX) x[4 * j + 3] = z3;
+      }
+#pragma unroll
+      for (int i = DX - 1; i >= 0; --i) {
+        double xi = 0.0;
+        if (i < dx) {
+          if (unif) {  // q_mean + half-width (2 u - 1)
+            xi = qm[i] + qc[i * dx + i] * (2.0 * x[i] - 1.0);
+          } else {
+            xi = qm[i];
+#pragma unroll
+            for (int j = 0; j <= i; ++j) xi += qc[i * dx + j] * x[j];
+          }
+          const R xr = (R)xi;
+          leafX[((size_t)i * totalK + g) * N + n] = xr;
+          xi = (double)xr;  // weights are those of the stored particle
+        }
+        x[i] = xi;
+      }
+    }
+    if (n == 0 && sd.star != nullptr) {
+      // conditional run: slot 0 holds the star trajectory (its proposal draw
+      // above is discarded), weighted like every other particle
+      const R* st = (const R*)sd.star;
+#pragma unroll
+      for (int i = 0; i < DX; ++i) {
+        double xi = 0.0;
+        if (i < dx) {
+          const R xr = st[(size_t)i * K + t];
+          leafX[((size_t)i * totalK + g) * N + n] = xr;
+          xi = (double)xr;
+        }
+        x[i] = xi;
+      }
+    }
+    double lq, lh;  // log q_t(x), log h_t(x)
+    if constexpr (DX >= 8) {
+      double q = 0.0;
+#pragma unroll 1
+      for (int i = 0; i < DX; ++i) {
+        double zi = 0.0;
+#pragma unroll
+        for (int j = 0; j < DX; ++j) zi += Li[i * DX + j] * (x[j] - qm[j]);
+        q += zi * zi;
+      }
+      lq = -0.5 * q + M.q_lognorm[t];
+      if (lds_obs) {
+        double qh = 0.0;
+        const int dy = uniform(M.dy);
+#pragma unroll 1
+        for (int i = 0; i < dy; ++i) {
+          double r = vy[i];
+#pragma unroll
+          for (int k = 0; k < DX; ++k) r -= Hl[i * DX + k] * x[k];
+          qh += r * r;
+        }
+        lh = -0.5 * qh + M.obs_lognorm;
+      } else {
+        lh = log_potential<DX>(M, t, x);
+      }
+    } else {
+      lq = log_proposal<DX>(M, t, x);
+      lh = log_potential<DX>(M, t, x);
+    }
+    double l, gg = -lq;
+    if (t == 0) {
+      l = lh + log_prior<DX>(M, x) - lq;
+      if (weighting == 1) gg += lh;
+    } else if (weighting == 0) {
+      l = lh;
+    } else {
+      l = 0.0;
+      gg += lh;
+    }
+    if (isnan(l) || isnan(gg)) bad = kFlagNumeric;
+    ell[n] = l;
+    gq[n] = gg;
+  }
+  __syncthreads();
+  double mx = -INFINITY, gmx = -INFINITY;
+  for (int n = threadIdx.x; n < N; n += kBlock) {
+    mx = fmax(mx, ell[n]);
+    gmx = fmax(gmx, gq[n]);
+  }
+  block_max2(mx, gmx, red);
+  double s = 0.0;
+  if (mx > -INFINITY)
+    for (int n = threadIdx.x; n < N; n += kBlock) s += exp(ell[n] - mx);
+  s = block_sum(s, red);
+  const bool degenerate = !(mx > -INFINITY);
+  const double lse = mx + log(s);
+  double bmax = -INFINITY;  // max_n (lbar_n + gq_n): shift of a leaf right block
+  for (int n = threadIdx.x; n < N; n += kBlock) {
+    const double lbar = degenerate ? -logN : ell[n] - lse;
+    const R lr = (R)lbar;
+    leafW[(size_t)g * N + n] = lr;
+    ell[n] = (double)lr;  // the stored (rounded) weight is what every consumer sees
+    bmax = fmax(bmax, (double)lr + gq[n]);
+  }
+  block_max_or(bmax, bad, red, redi);
+  if (threadIdx.x == 0) {
+    leafL[g] = degenerate ? -INFINITY : lse - logN;
+    bmerged[g] = -logN + gmx;
+    const int flags = bad | (degenerate ? kFlagDegenerate : 0);
+    if (flags) atomicOr(sd.status, flags);
+  }
+  // Every particle's data for the combines at both boundaries of t (the
+  // tables merged blocks gather from), and the data of the combine that
+  // consumes this single-point block: its right block (c == t) or its left
+  // block (c == t + 1).
+  const int cons = leaf_cons[g];
+  const int P = cons >> 1, role = cons & 1;
+  for (int n = threadIdx.x; n < N; n += kBlock) {
+    double x[DX];
+    load_particle<R, DX>(leafX, totalK, N, g, n, dx, x);
+    if constexpr (DX < 8) nb.tgq[(size_t)g * N + n] = gq[n];
+    if (t >= 1) {
+      if constexpr (DX >= 8) {
+        stream_table<R, DX, false>(nb, Wc, Wr, vw, qm, DX, (size_t)g, N, n, x);
+      } else {
+        double u[DX];
+        col_coords<DX>(M, t, x, u);
+        put_tcol<R, DX>(nb, (size_t)g, N, n, u);
+      }
+      if (cons >= 0 && role == 1) {
+        const double beta = (bmax > -INFINITY) ? (ell[n] + gq[n] - bmax) * kLog2e : -INFINITY;
+        copy_col<R, DX>(nb, (size_t)P, Npad, n, (size_t)g, N, n, beta);
+      }
+    }
+    if (t + 1 < K) {
+      if constexpr (DX >= 8) {
+        stream_table<R, DX, true>(nb, Wc, Wr, vw, qm1, DX, (size_t)g, N, n, x);
+      } else {
+        double v[DX];
+        row_coords<DX>(M, t + 1, x, v);
+        put_trow<R, DX>(nb, (size_t)g, N, n, v);
+      }
+      if (cons >= 0 && role == 0) {
+        copy_row<R, DX>(nb, (size_t)P, Npad, n, (size_t)g, N, n);
+        ((R*)nb.alpha)[(size_t)P * N + n] = (R)ell[n];
+      }
+    }
+  }
+  if (cons >= 0 && role == 1) {
+    for (int n = N + threadIdx.x; n < Npad; n += kBlock) put_col_pad<R, DX>(nb, (size_t)P, Npad, n);
+    if (threadIdx.x == 0) nb.bcol[P] = bmax;
+  }
+}
+
+// ================================================================= rows
+// Tile = (combine, row block of RPL*64*W rows, column split of KC chunks, KC a
+// multiple of 4).  Lane owns rows base + lane + 64 r, r < RPL; lanes past N
+// recompute row N-1 and store the same values (no per-row branches).  Chunk
+// sums go to P[node][m][k] (row stride NcP = Nc rounded up to 4), four chunks
+// per vector store, so the sampler reads a row's sums as one contiguous run.
+// With one column split the tile also stores the row sum sum_k P[m][k] (fp64,
+// k ascending); otherwise the sampling kernel forms that same sum from P.
+template <typename R>
+__device__ __forceinline__ void store4(R* p, R a, R b, R c, R d);
+template <>
+__device__ __forceinline__ void store4<float>(float* p, float a, float b, float c, float d) {
+  *(float4*)p = make_float4(a, b, c, d);
+}
+template <>
+__device__ __forceinline__ void store4<double>(double* p, double a, double b, double c, double d) {
+  ((double2*)p)[0] = make_double2(a, b);
+  ((double2*)p)[1] = make_double2(c, d);
+}
+
+template <typename R, int DX, int RPL>
+__global__ __launch_bounds__(kBlock) void k_rows(const R* __restrict__ col,
+                                                 const R* __restrict__ row,
+                                                 R* __restrict__ P, double* __restrict__ Rsum,
+                                                 float* __restrict__ Rshift,
+                                                 const int32_t* __restrict__ node_list,
+                                                 int node0, int N, int Npad, int Nc, int NcP,
+                                                 int RB, int CS, int KC, int force_redo) {
+  const int W = blockDim.x >> 6;
+  const int tiles = RB * CS;
+  const int node_local = blockIdx.x / tiles;
+  const int tile = blockIdx.x - node_local * tiles;
+  const int rb = tile / CS, cs = tile - rb * CS;
+  const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
+  const int base = (rb * W + wave) * 64 * RPL;
+  if (base >= N) return;  // wave-uniform
+  const size_t nodeid = node_list ? (size_t)node_list[node_local] : (size_t)node0 + node_local;
+  const R* __restrict__ colp = col + nodeid * Npad * (DX + 1);
+  R v[RPL][DX];
+  int mrow[RPL];
+#pragma unroll
+  for (int r = 0; r < RPL; ++r) {
+    const int m = base + lane + 64 * r;
+    mrow[r] = m < N ? m : N - 1;
+#pragma unroll
+    for (int i = 0; i < DX; ++i) v[r][i] = row[(nodeid * Npad + mrow[r]) * DX + i];
+  }
+  // Row shift (DX >= 8): the row's largest log2 weight over its first chunk,
+  // so that row sums stay inside the fp32 range when every pair weight is far
+  // below the column bound.
+  R sft[RPL];
+#pragma unroll
+  for (int r = 0; r < RPL; ++r) sft[r] = (R)0;
+  if constexpr (kRowShift<DX>) {
+#pragma unroll
+    for (int r = 0; r < RPL; ++r) {
+      R mx = (R)(-INFINITY);
+      for (int jj = 0; jj < kChunk; ++jj) {
+        R u[DX];
+#pragma unroll
+        for (int i = 0; i < DX; ++i) u[i] = colp[jj * (DX + 1) + i];
+        mx = fmax(mx, pair_log2w<R, DX>(u, colp[jj * (DX + 1) + DX], v[r]));
+      }
+      // held at fp32 precision: the sampling kernel reads it back as fp32
+      sft[r] = (mx > (R)(-INFINITY) && mx < (R)INFINITY) ? (R)(float)mx : (R)0;
+    }
+  }
+  double Rm[RPL];
+  R* __restrict__ Pn = P + (size_t)node_local * N * NcP;
+  const int k0 = cs * KC, k1 = min(Nc, k0 + KC);
+  auto pass = [&]() {
+#pragma unroll
+    for (int r = 0; r < RPL; ++r) Rm[r] = 0.0;
+    for (int kg = k0; kg < k1; kg += 4) {
+      R acc[RPL][4];
+#pragma unroll
+      for (int q = 0; q < 4; ++q) {
+#pragma unroll
+        for (int r = 0; r < RPL; ++r) acc[r][q] = (R)0;
+        if (kg + q < k1) {  // uniform
+          const R* __restrict__ cp = colp + (size_t)(kg + q) * kChunk * (DX + 1);
+#pragma unroll
+          for (int jj = 0; jj < kChunk; ++jj) {
+            R u[DX];
+#pragma unroll
+            for (int i = 0; i < DX; ++i) u[i] = cp[jj * (DX + 1) + i];
+            const R beta = cp[jj * (DX + 1) + DX];
+#pragma unroll
+            for (int r = 0; r < RPL; ++r) {
+              if constexpr (kRowShift<DX>)
+                acc[r][q] += Real<R>::exp2(pair_log2w<R, DX>(u, beta, v[r]) - sft[r]);
+              else
+                acc[r][q] += Real<R>::exp2(pair_log2w<R, DX>(u, beta, v[r]));
+            }
+          }
+#pragma unroll
+          for (int r = 0; r < RPL; ++r) Rm[r] += (double)acc[r][q];
+        }
+      }
+#pragma unroll
+      for (int r = 0; r < RPL; ++r)
+        store4<R>(Pn + (size_t)mrow[r] * NcP + kg, acc[r][0], acc[r][1], acc[r][2], acc[r][3]);
+    }
+  };
+  pass();
+  if constexpr (kRowShift<DX>) {
+    // A row whose sum left the fp32 range (its largest weight far above the
+    // chunk-0 estimate, or every weight far below it) takes its exact maximum
+    // as shift and the wave redoes its rows; the other rows recompute the same
+    // values.  Rows are whole here (one column split for DX >= 8).
+    bool bad[RPL];
+    int any = 0;
+#pragma unroll
+    for (int r = 0; r < RPL; ++r) {
+      bad[r] = ((!(Rm[r] >= Real<R>::kTiny) || isinf(Rm[r])) && !isnan(Rm[r])) || force_redo;
+      any |= bad[r] ? 1 : 0;
+    }
+    if (__any(any)) {
+      R mx[RPL];
+#pragma unroll
+      for (int r = 0; r < RPL; ++r) mx[r] = (R)(-INFINITY);
+      for (int k = k0; k < k1; ++k) {
+        const R* __restrict__ cp = colp + (size_t)k * kChunk * (DX + 1);
+        for (int jj = 0; jj < kChunk; ++jj) {
+          R u[DX];
+#pragma unroll
+          for (int i = 0; i < DX; ++i) u[i] = cp[jj * (DX + 1) + i];
+          const R beta = cp[jj * (DX + 1) + DX];
+#pragma unroll
+          for (int r = 0; r < RPL; ++r) mx[r] = fmax(mx[r], pair_log2w<R, DX>(u, beta, v[r]));
+        }
+      }
+#pragma unroll
+      for (int r = 0; r < RPL; ++r)
+        if (bad[r]) sft[r] = (mx[r] > (R)(-INFINITY) && mx[r] < (R)INFINITY) ? (R)(float)mx[r] : (R)0;
+      pass();
+    }
+    if (cs == 0) {
+#pragma unroll
+      for (int r = 0; r < RPL; ++r) Rshift[(size_t)node_local * N + mrow[r]] = (float)sft[r];
+    }
+  }
+  if (CS == 1) {
+#pragma unroll
+    for (int r = 0; r < RPL; ++r) Rsum[(size_t)node_local * N + mrow[r]] = Rm[r];
+  }
+}
+
+// ============================================================ rows (bf16)
+// Matrix-core form of k_rows for bf16 plans (DX = 16 or 32).  With u, v
+// rounded to bf16, the pair's log2 weight beta_n - ||u_n - v_m||^2 equals
+// (beta_n - ||u_n||^2) - ||v_m||^2 + (2 u_n) . v_m.  A wave owns 32 MB rows;
+// for each 32-column chunk and each block of 32 rows, DX / 16
+// v_mfma_f32_32x32x16_bf16 add the 32 x 32 dot products (u on the
+// instruction's row side, v on its column side) onto accumulators that start
+// at the two fp32 norm terms, so each accumulator ends as the pair's log2
+// weight.  Lane (j, h) holds column j of the block (row m = block + j) for the
+// 16 chunk columns 8 (r / 4) + 4 h + r % 4, r < 16; the lanes j and j + 32
+// together hold the whole chunk.  Outputs as k_rows (chunk sums, and fp64 row
+// sums in chunk order with one column split).
+typedef __bf16 bf16x8_t __attribute__((ext_vector_type(8)));
+typedef float f32x16_t __attribute__((ext_vector_type(16)));
+
+template <int DX, int MB>
+__global__ __launch_bounds__(kBlock) void k_rows_mfma(
+    const uint16_t* __restrict__ colh, const float* __restrict__ colb,
+    const uint16_t* __restrict__ rowh, const float* __restrict__ rown, float* __restrict__ P,
+    double* __restrict__ Rsum, float* __restrict__ Rshift, const int32_t* __restrict__ node_list,
+    int node0, int N, int Npad, int Nc, int NcP, int RB, int CS, int KC, int force_redo) {
+  static_assert(DX == 16 || DX == 32, "bf16 rows need DX 16 or 32");
+  constexpr int KS = DX / 16;  // instructions per 32 x 32 block
+  const int W = blockDim.x >> 6;
+  const int tiles = RB * CS;
+  const int node_local = blockIdx.x / tiles;
+  const int tile = blockIdx.x - node_local * tiles;
+  const int rb = tile / CS, cs = tile - rb * CS;
+  const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
+  const int j32 = lane & 31, h = lane >> 5;
+  const int base = (rb * W + wave) * 32 * MB;
+  if (base >= N) return;  // wave-uniform
+  const size_t nodeid = node_list ? (size_t)node_list[node_local] : (size_t)node0 + node_local;
+  bf16x8_t vf[MB][KS];
+  float vv[MB];
+  int mrow[MB];
+#pragma unroll
+  for (int b = 0; b < MB; ++b) {
+    const int m = base + 32 * b + j32;
+    mrow[b] = m < N ? m : N - 1;
+    const uint16_t* rp = rowh + ((size_t)nodeid * Npad + mrow[b]) * DX + 8 * h;
+#pragma unroll
+    for (int s = 0; s < KS; ++s) vf[b][s] = *(const bf16x8_t*)(rp + 16 * s);
+    vv[b] = rown[(size_t)nodeid * Npad + mrow[b]];
+  }
+  const uint16_t* __restrict__ ch = colh + (size_t)nodeid * Npad * DX;
+  const float* __restrict__ cb = colb + (size_t)nodeid * Npad;
+  // Row shift: the row's largest log2 weight over chunk 0 (as k_rows), folded
+  // into the row norm term so the main loop pays nothing for it.
+  float vv0[MB], sft[MB];
+#pragma unroll
+  for (int b = 0; b < MB; ++b) vv0[b] = vv[b];
+  // log2 weights of chunk k for block b, into acc (row-norm term vv[b])
+  auto block = [&](int k, int b, f32x16_t& acc) {
+    const int n0 = k * kChunk;
+    bf16x8_t uf[KS];
+    const uint16_t* up = ch + (size_t)(n0 + j32) * DX + 8 * h;
+#pragma unroll
+    for (int s = 0; s < KS; ++s) uf[s] = *(const bf16x8_t*)(up + 16 * s);
+#pragma unroll
+    for (int g4 = 0; g4 < 4; ++g4) {
+      const float4 t4 = *(const float4*)(cb + n0 + 8 * g4 + 4 * h);
+      acc[4 * g4] = t4.x - vv[b];
+      acc[4 * g4 + 1] = t4.y - vv[b];
+      acc[4 * g4 + 2] = t4.z - vv[b];
+      acc[4 * g4 + 3] = t4.w - vv[b];
+    }
+#pragma unroll
+    for (int s = 0; s < KS; ++s)
+      acc = __builtin_amdgcn_mfma_f32_32x32x16_bf16(uf[s], vf[b][s], acc, 0, 0, 0);
+  };
+  // largest log2 weight of each row block over chunks [ka, kb)
+  auto row_max = [&](int ka, int kb, float (&mx)[MB]) {
+#pragma unroll
+    for (int b = 0; b < MB; ++b) mx[b] = -INFINITY;
+    for (int k = ka; k < kb; ++k) {
+#pragma unroll
+      for (int b = 0; b < MB; ++b) {
+        f32x16_t acc;
+        block(k, b, acc);
+#pragma unroll
+        for (int r = 0; r < 16; ++r) mx[b] = fmaxf(mx[b], acc[r]);
+      }
+    }
+#pragma unroll
+    for (int b = 0; b < MB; ++b) mx[b] = fmaxf(mx[b], __shfl_xor(mx[b], 32, 64));
+  };
+  {
+    float mx[MB];
+    row_max(0, 1, mx);
+#pragma unroll
+    for (int b = 0; b < MB; ++b) {
+      sft[b] = (mx[b] > -INFINITY && mx[b] < INFINITY) ? mx[b] : 0.0f;
+      vv[b] = vv0[b] + sft[b];
+    }
+  }
+  double Rm[MB];
+  float* __restrict__ Pn = P + (size_t)node_local * N * NcP;
+  const int k0 = cs * KC, k1 = min(Nc, k0 + KC);
+  auto pass = [&]() {
+#pragma unroll
+    for (int b = 0; b < MB; ++b) Rm[b] = 0.0;
+    for (int kg = k0; kg < k1; kg += 4) {
+      float c4[MB][4];
+#pragma unroll
+      for (int q = 0; q < 4; ++q) {
+#pragma unroll
+        for (int b = 0; b < MB; ++b) c4[b][q] = 0.0f;
+        if (kg + q < k1) {  // uniform
+#pragma unroll
+          for (int b = 0; b < MB; ++b) {
+            f32x16_t acc;
+            block(kg + q, b, acc);
+            float e = 0.0f;
+#pragma unroll
+            for (int r = 0; r < 16; ++r) e += Real<float>::exp2(acc[r]);
+            e += __shfl_xor(e, 32, 64);
+            c4[b][q] = e;
+            Rm[b] += (double)e;
+          }
+        }
+      }
+      if (h == 0) {
+#pragma unroll
+        for (int b = 0; b < MB; ++b)
+          store4<float>(Pn + (size_t)mrow[b] * NcP + kg, c4[b][0], c4[b][1], c4[b][2], c4[b][3]);
+      }
+    }
+  };
+  pass();
+  // As k_rows: a row whose sum left the fp32 range takes its exact maximum as
+  // shift and the wave redoes its rows (whole rows: one column split).
+  int any = 0;
+  bool bad[MB];
+#pragma unroll
+  for (int b = 0; b < MB; ++b) {
+    bad[b] = ((!(Rm[b] >= Real<float>::kTiny) || isinf(Rm[b])) && !isnan(Rm[b])) || force_redo;
+    any |= bad[b] ? 1 : 0;
+  }
+  if (__any(any)) {
+#pragma unroll
+    for (int b = 0; b < MB; ++b) vv[b] = vv0[b];
+    float mx[MB];
+    row_max(k0, k1, mx);
+#pragma unroll
+    for (int b = 0; b < MB; ++b) {
+      if (bad[b]) sft[b] = (mx[b] > -INFINITY && mx[b] < INFINITY) ? mx[b] : 0.0f;
+      vv[b] = vv0[b] + sft[b];
+    }
+    pass();
+  }
+  if (cs == 0 && h == 0) {
+#pragma unroll
+    for (int b = 0; b < MB; ++b) Rshift[(size_t)node_local * N + mrow[b]] = sft[b];
+  }
+  if (CS == 1 && h == 0) {
+#pragma unroll
+    for (int b = 0; b < MB; ++b) Rsum[(size_t)node_local * N + mrow[b]] = Rm[b];
+  }
+}
+
+// =============================================================== sample
+// Workgroup (combine, ds) of DS workgroups per combine; each builds the row
+// CDF of its combine and takes the draws n in [ds per, (ds+1) per).
+//   w_m = exp(a_m - A*) R_m  (fp64),  C_m = sum_{i<=m} w_i,
+//   Z_c = A* + B + trans_lognorm + ln C_{N-1}
+//   l_n = first m with C_m > u1 C_{N-1}
+//   r_n = first j with (chunk prefix + within-chunk prefix) > u2 R_l
+// Rows whose R_m leaves the fp32 range (underflow, or overflow when a row
+// shift estimated from one chunk is too low) are recomputed with their exact
+// maximum as shift: their chunk sums go to Pr, R_m carries a factor
+// 2^shift_m and the weights are formed in log space.
+// The combine's column data is staged in LDS when it fits (col_in_lds).
+template <typename R>
+__device__ __forceinline__ void load4(const R* p, R (&q)[4]);
+template <>
+__device__ __forceinline__ void load4<float>(const float* p, float (&q)[4]) {
+  const float4 v = *(const float4*)p;
+  q[0] = v.x; q[1] = v.y; q[2] = v.z; q[3] = v.w;
+}
+template <>
+__device__ __forceinline__ void load4<double>(const double* p, double (&q)[4]) {
+  const double2 a = ((const double2*)p)[0], b = ((const double2*)p)[1];
+  q[0] = a.x; q[1] = a.y; q[2] = b.x; q[3] = b.y;
+}
+
+// Draw n of combine `nodeid` is (l, r): its ancestry, the merged block's
+// first/last-time leaf indices, and the data the consuming combine reads.
+template <typename R, int DX>
+__device__ __forceinline__ void record_draw(const NodeBufs& nb, const NodeDesc& nd, int nodeid,
+                                            int N, int Npad, int n, int l, int r,
+                                            int32_t* ancL, int32_t* ancR, int gA, int gB,
+                                            double logN, const double* __restrict__ bmerged) {
+  ancL[n] = l;
+  ancR[n] = r;
+  const int sf = (nd.lchild < 0) ? l : nb.sfirst[(size_t)nd.lchild * N + l];
+  const int sl = (nd.rchild < 0) ? r : nb.slast[(size_t)nd.rchild * N + r];
+  nb.sfirst[(size_t)nodeid * N + n] = sf;
+  nb.slast[(size_t)nodeid * N + n] = sl;
+  const int cons = nd.consumer;
+  if (cons >= 0) {
+    if (nd.role == 1) {  // merged block is the right block of `cons` (boundary a)
+      const double b = -logN + nb.tgq[(size_t)gA * N + sf];
+      copy_col<R, DX>(nb, (size_t)cons, Npad, n, (size_t)gA, N, sf, (b - bmerged[gA]) * kLog2e);
+    } else {  // merged block is the left block of `cons` (boundary b)
+      copy_row<R, DX>(nb, (size_t)cons, Npad, n, (size_t)gB, N, sl);
+      ((R*)nb.alpha)[(size_t)cons * N + n] = (R)(-logN);
+    }
+  }
+}
+
+template <typename R, int DX>
+__global__ __launch_bounds__(kBlock) void k_sample(
+    const NodeDesc* __restrict__ nodes, const SeriesDesc* __restrict__ series,
+    const int32_t* __restrict__ node_list, int node0, int DS,
+    int N, int Npad, int Nc, int NcP, int rows_summed, int col_in_lds, int force_rescue,
+    const double* __restrict__ bmerged, const R* __restrict__ P, R* __restrict__ Pr,
+    const double* __restrict__ Rsum, const float* __restrict__ Rshift,
+    unsigned long long* __restrict__ rescue_count, NodeBufs nb) {
+  extern __shared__ double smem[];
+  double* cdf = smem;                        // [Npad]
+  double* rs = smem + Npad;                  // [Npad]
+  float* shift = (float*)(smem + 2 * Npad);  // [Npad]
+  R* lcol = (R*)(shift + Npad);              // [Npad][DX+1] when col_in_lds
+  __shared__ double red[2 * kBlock / 64];
+  __shared__ int redi[2 * kBlock / 64];
+  const int node_local = blockIdx.x / DS;
+  const int ds = blockIdx.x - node_local * DS;
+  const int nodeid = node_list ? node_list[node_local] : node0 + node_local;
+  const NodeDesc nd = nodes[nodeid];
+  const SeriesDesc& sd = series[nd.series];
+  const DevModel& M = *sd.model;
+  const int c = nd.c;
+  const bool left_leaf = nd.lchild < 0;
+  const double logN = log((double)N);
+  const R* __restrict__ gcol = (const R*)nb.col + (size_t)nodeid * Npad * (DX + 1);
+  const R* __restrict__ rowp = (const R*)nb.row + (size_t)nodeid * Npad * DX;
+  const R* __restrict__ Pn = P + (size_t)node_local * N * NcP;
+  R* __restrict__ Prn = Pr + (size_t)node_local * N * NcP;
+  const double* __restrict__ Rn = Rsum + (size_t)node_local * N;
+  const R* __restrict__ alp = (const R*)nb.alpha + (size_t)nodeid * N;
+  if (col_in_lds)
+    for (int i = threadIdx.x; i < Npad * (DX + 1); i += kBlock) lcol[i] = gcol[i];
+  const R* colp = col_in_lds ? lcol : gcol;
+  __syncthreads();
+
+  // ---- row sums (thread owns a contiguous segment of rows)
+  __shared__ unsigned need[DSMC_MAX_N / 32];  // rows still to rescue
+  __shared__ unsigned resc[DSMC_MAX_N / 32];  // rescued rows: their chunk sums are in Pr
+  __shared__ double csum[DSMC_MAX_N / kChunk];  // chunk sums of the row being rescued
+  __shared__ int rescue_list[kBlock];
+  __shared__ int n_rescue;
+  for (int i = threadIdx.x; i < DSMC_MAX_N / 32; i += kBlock) {
+    need[i] = 0u;
+    resc[i] = 0u;
+  }
+  __syncthreads();
+  const int per = (N + kBlock - 1) / kBlock;
+  const int m0 = threadIdx.x * per, m1 = min(N, m0 + per);
+  double amax = -INFINITY;
+  int rescued = 0, row_nan = 0;
+  for (int m = m0; m < m1; ++m) {
+    amax = fmax(amax, left_leaf ? (double)alp[m] : -logN);
+    double Rm;
+    if (rows_summed) {
+      Rm = Rn[m];
+    } else {  // the same sequential chunk-order sum the rows kernel forms
+      Rm = 0.0;
+      const R* Pm = Pn + (size_t)m * NcP;
+      for (int kb = 0; kb < NcP; kb += 4) {
+        R q[4];
+        load4<R>(Pm + kb, q);
+#pragma unroll
+        for (int i = 0; i < 4; ++i)
+          if (kb + i < Nc) Rm += (double)q[i];
+      }
+    }
+    if ((!(Rm >= Real<R>::kTiny) || isinf(Rm) || force_rescue) && !isnan(Rm)) {
+      atomicOr(&need[m >> 5], 1u << (m & 31));
+      atomicOr(&resc[m >> 5], 1u << (m & 31));
+      rescued = 1;
+    }
+    if (isnan(Rm)) row_nan = 1;
+    rs[m] = Rm;
+    if constexpr (kRowShift<DX>) shift[m] = Rshift[(size_t)node_local * N + m];
+    else shift[m] = 0.0f;
+  }
+  double Astar = amax;
+  block_max_or(Astar, rescued, red, redi);  // also orders the writes above
+  // Underflow rescue, one row at a time by the whole workgroup: exact row
+  // maximum as shift, then the fp64 sum of exp2(s - shift) over a fixed
+  // partition of the columns in a fixed reduction order.  Rows are taken in
+  // passes of at most kBlock.
+  bool first_pass = true;
+  while (rescued) {
+    if (threadIdx.x == 0) n_rescue = 0;
+    __syncthreads();
+    for (int wd = threadIdx.x; wd < Npad / 32; wd += kBlock) {
+      unsigned bits = need[wd];
+      while (bits) {
+        const int b = __ffs(bits) - 1;
+        bits &= bits - 1;
+        const int slot = atomicAdd(&n_rescue, 1);
+        if (slot < kBlock) {
+          rescue_list[slot] = wd * 32 + b;
+          atomicAnd(&need[wd], ~(1u << b));
+        }
+      }
+    }
+    __syncthreads();
+    const int total = n_rescue;
+    const int cnt = min(total, kBlock);
+    if (first_pass && rescue_count && ds == 0 && threadIdx.x == 0)
+      atomicAdd(rescue_count, (unsigned long long)total);
+    first_pass = false;
+    for (int i = 0; i < cnt; ++i) {
+      const int m = rescue_list[i];
+      R v[DX];
+#pragma unroll
+      for (int d = 0; d < DX; ++d) v[d] = rowp[(size_t)m * DX + d];
+      double smax = -INFINITY;
+      for (int j = threadIdx.x; j < N; j += kBlock) {
+        R u[DX];
+#pragma unroll
+        for (int d = 0; d < DX; ++d) u[d] = colp[(size_t)j * (DX + 1) + d];
+        smax = fmax(smax, (double)pair_log2w<R, DX>(u, colp[(size_t)j * (DX + 1) + DX], v));
+      }
+      smax = block_max(smax, red);
+      const R sh = (R)(float)smax;  // the shift is kept as fp32
+      // the row's chunk sums relative to sh, into Pr (thread k owns chunk k;
+      // the same terms in the same order as the draw's chunk recompute; every
+      // workgroup of the combine writes the same values), and their fp64 sum
+      // in chunk order
+      R* Pm = Prn + (size_t)m * NcP;
+      for (int k = threadIdx.x; k < Nc; k += kBlock) {
+        R acc = (R)0;
+        if (smax > -INFINITY) {
+          const R* cp = colp + (size_t)k * kChunk * (DX + 1);
+#pragma unroll 4
+          for (int jj = 0; jj < kChunk; ++jj) {
+            R u[DX];
+#pragma unroll
+            for (int d = 0; d < DX; ++d) u[d] = cp[jj * (DX + 1) + d];
+            acc += Real<R>::exp2(pair_log2w<R, DX>(u, cp[jj * (DX + 1) + DX], v) - sh);
+          }
+        }
+        Pm[k] = acc;
+        csum[k] = (double)acc;
+      }
+      __syncthreads();
+      if (threadIdx.x == 0) {
+        double tot = 0.0;
+        for (int k = 0; k < Nc; ++k) tot += csum[k];
+        rs[m] = (smax > -INFINITY) ? tot : 0.0;
+        shift[m] = (smax > -INFINITY) ? (float)sh : 0.0f;
+      }
+      __syncthreads();
+    }
+    if (total <= kBlock) break;
+  }
+
+  // ---- row weights: direct, or in log space when a row carries a shift
+  double G = 0.0;
+  if (rescued || kRowShift<DX>) {
+    double gmax = -INFINITY;
+    for (int m = m0; m < m1; ++m) {
+      const double a = left_leaf ? (double)alp[m] : -logN;
+      double rho = -INFINITY;
+      if (Astar > -INFINITY && rs[m] > 0.0) rho = a - Astar + (double)shift[m] * kLn2 + log(rs[m]);
+      cdf[m] = rho;
+      gmax = fmax(gmax, rho);
+    }
+    G = block_max(gmax, red);
+    for (int m = m0; m < m1; ++m) cdf[m] = (G > -INFINITY) ? exp(cdf[m] - G) : 0.0;
+  } else {
+    for (int m = m0; m < m1; ++m) {
+      double w = 0.0;
+      if (Astar > -INFINITY) w = (left_leaf ? exp((double)alp[m] - Astar) : 1.0) * rs[m];
+      cdf[m] = w;
+    }
+  }
+  double seg = 0.0;
+  int lastpos = -1;
+  for (int m = m0; m < m1; ++m) {
+    const double w = cdf[m];
+    if (w > 0.0) lastpos = m;
+    seg += w;
+    cdf[m] = seg;  // segment-local inclusive prefix for now
+  }
+  {  // workgroup scan of the segment totals
+    const int lane = threadIdx.x & 63, wid = threadIdx.x >> 6;
+    double incl = seg;
+#pragma unroll
+    for (int o = 1; o < 64; o <<= 1) {
+      const double y = __shfl_up(incl, o, 64);
+      if (lane >= o) incl += y;
+    }
+    __syncthreads();
+    if (lane == 63) red[wid] = incl;
+    __syncthreads();
+    double off = incl - seg;
+    for (int i = 0; i < wid; ++i) off += red[i];
+    for (int m = m0; m < m1; ++m) cdf[m] += off;
+  }
+  int any_nan = row_nan;
+  block_max_i_or(lastpos, any_nan, redi);
+  __syncthreads();
+  const double T = cdf[N - 1];
+  const bool degenerate = !(T > 0.0);
+  const double Bc = nb.bcol[nodeid];
+  if (ds == 0) {
+    if (threadIdx.x == 0) {
+      sd.zinc[c - 1] = degenerate ? -INFINITY : Astar + Bc + M.trans_lognorm + G + log(T);
+      const int flags = (degenerate ? kFlagDegenerate : 0) | ((isnan(T) || any_nan) ? kFlagNumeric : 0);
+      if (flags) atomicOr(sd.status, flags);
+    }
+    if (sd.row_lse) {
+      double* rl = sd.row_lse + (size_t)(c - 1) * N;
+      for (int m = threadIdx.x; m < N; m += kBlock) {
+        const double a = left_leaf ? (double)alp[m] : -logN;
+        rl[m] = a + Bc + M.trans_lognorm + log(rs[m]) + (double)shift[m] * kLn2;
+      }
+    }
+  }
+  // consumer of the merged block [a, b)
+  const int cons = nd.consumer;
+  const int crole = nd.role;
+  const int ca = nd.a, cb = nd.b;
+  const int gA = sd.base + ca, gB = sd.base + cb - 1;
+  if (cons >= 0 && crole == 1 && ds == 0) {
+    for (int n = N + threadIdx.x; n < Npad; n += kBlock) put_col_pad<R, DX>(nb, (size_t)cons, Npad, n);
+    if (threadIdx.x == 0) nb.bcol[cons] = bmerged[gA];
+  }
+  // ---- draws
+  const int dper = (N + DS - 1) / DS;
+  const int n0 = ds * dper, n1 = min(N, n0 + dper);
+  int32_t* ancL = sd.anc + (size_t)(c - 1) * 2 * N;
+  int32_t* ancR = ancL + N;
+  const bool star = sd.star != nullptr;
+  for (int n = n0 + threadIdx.x; n < n1; n += kBlock) {
+    const Words4 w = philox4x64_10((uint64_t)n, (uint64_t)c, kPurposeCombine, 0ull, sd.seed, kKey1);
+    const double u1 = unif53(w.w0), u2 = unif53(w.w1);
+    int l, r;
+    if (degenerate) {
+      l = min((int)(u1 * N), N - 1);
+      r = min((int)(u2 * N), N - 1);
+    } else {
+      const double target = u1 * T;
+      int lo = 0, hi = N;
+      while (lo < hi) {
+        const int mid = (lo + hi) >> 1;
+        if (cdf[mid] > target) hi = mid; else lo = mid + 1;
+      }
+      l = lo < N ? lo : (lastpos >= 0 ? lastpos : 0);
+      R v[DX];
+#pragma unroll
+      for (int i = 0; i < DX; ++i) v[i] = rowp[(size_t)l * DX + i];
+      const double target2 = u2 * rs[l];
+      const float sh = shift[l];
+      r = -1;
+      {
+        // chunk: first k with prefix_k > target2 (chunk sums read 16 at a time)
+        const R* Pl = (((resc[l >> 5] >> (l & 31)) & 1u) ? Prn : Pn) + (size_t)l * NcP;
+        double pref = 0.0, pref_last = 0.0;
+        int k = -1, klast = 0;
+        for (int kb = 0; kb < Nc && k < 0; kb += 16) {
+          R q[16];
+#pragma unroll
+          for (int g4 = 0; g4 < 4; ++g4) {
+            if (kb + 4 * g4 < NcP) {
+              R t4[4];
+              load4<R>(Pl + kb + 4 * g4, t4);
+#pragma unroll
+              for (int i = 0; i < 4; ++i) q[4 * g4 + i] = t4[i];
+            } else {
+#pragma unroll
+              for (int i = 0; i < 4; ++i) q[4 * g4 + i] = (R)0;
+            }
+          }
+#pragma unroll
+          for (int i = 0; i < 16; ++i) {
+            const int kk = kb + i;
+            if (k < 0 && kk < Nc) {
+              const double p = (double)q[i];
+              if (p > 0.0) { klast = kk; pref_last = pref; }
+              if (target2 < pref + p) k = kk; else pref += p;
+            }
+          }
+        }
+        if (k < 0) { k = klast; pref = pref_last; }
+        const double rem = target2 - pref;
+        // recompute chunk k of row l in the rows kernel's order
+        const R* cp = colp + (size_t)k * kChunk * (DX + 1);
+        R acc = (R)0;
+        int lastj = 0;
+#pragma unroll
+        for (int jj = 0; jj < kChunk; ++jj) {
+          R u[DX];
+#pragma unroll
+          for (int i = 0; i < DX; ++i) u[i] = cp[jj * (DX + 1) + i];
+          const R e = Real<R>::exp2(pair_log2w<R, DX>(u, cp[jj * (DX + 1) + DX], v) - (R)sh);
+          acc += e;
+          if (e > (R)0) lastj = jj;
+          if (r < 0 && rem < (double)acc) r = jj;
+        }
+        if (r < 0) r = lastj;
+        r += k * kChunk;
+      }
+      if (r >= N) r = N - 1;  // only reachable through NaN weights
+    }
+    if (n == 0 && star) {  // conditional combine: slot 0 keeps the star, (0, 0)
+      l = 0;
+      r = 0;
+    }
+    record_draw<R, DX>(nb, nd, nodeid, N, Npad, n, l, r, ancL, ancR, gA, gB, logN, bmerged);
+  }
+}
+
+
+// ========================================================= lazy sampling
+// Lazy resampling of one combine (Section 4.2): the N index pairs are drawn
+// without the pair-row pass, by N independent chains that evaluate only the
+// pairs they propose.  lazy == 1: Algorithm 7, `param` Metropolis-Hastings
+// steps from (n, n) with proposals uniform over the N^2 pairs; lazy == 2:
+// Algorithm 8, rejection from uniform proposals against the bound
+// max_m a_m + max_n b_n + max log p_c (at most `param` proposals per chain).
+// The target is the pair weight exp(a_m) 2^(beta_n - ||u_n - v_m||^2) relative
+// to that bound.  No increment is estimated (Z_c = NaN).
+template <typename R, int DX>
+__global__ __launch_bounds__(kBlock) void k_sample_lazy(
+    const NodeDesc* __restrict__ nodes, const SeriesDesc* __restrict__ series,
+    const int32_t* __restrict__ node_list, int node0, int DS, int N, int Npad, int lazy,
+    int param, const double* __restrict__ bmerged, NodeBufs nb) {
+  __shared__ double red[2 * kBlock / 64];
+  const int node_local = blockIdx.x / DS;
+  const int ds = blockIdx.x - node_local * DS;
+  const int nodeid = node_list ? node_list[node_local] : node0 + node_local;
+  const NodeDesc nd = nodes[nodeid];
+  const SeriesDesc& sd = series[nd.series];
+  const int c = nd.c;
+  const bool left_leaf = nd.lchild < 0;
+  const double logN = log((double)N);
+  const R* __restrict__ colp = (const R*)nb.col + (size_t)nodeid * Npad * (DX + 1);
+  const R* __restrict__ rowp = (const R*)nb.row + (size_t)nodeid * Npad * DX;
+  const R* __restrict__ alp = (const R*)nb.alpha + (size_t)nodeid * N;
+  // the bound: max_m a_m, and max_n beta_n (the column shift B can exceed the
+  // block's own maximum for a merged right block)
+  double Astar = left_leaf ? -INFINITY : -logN, bmax = -INFINITY;
+  for (int m = threadIdx.x; m < N; m += kBlock) {
+    if (left_leaf) Astar = fmax(Astar, (double)alp[m]);
+    bmax = fmax(bmax, (double)colp[(size_t)m * (DX + 1) + DX]);
+  }
+  block_max2(Astar, bmax, red);
+  const int cons = nd.consumer;
+  const int gA = sd.base + nd.a, gB = sd.base + nd.b - 1;
+  if (ds == 0) {
+    if (threadIdx.x == 0) sd.zinc[c - 1] = __builtin_nan("");
+    if (sd.row_lse) {
+      double* rl = sd.row_lse + (size_t)(c - 1) * N;
+      for (int m = threadIdx.x; m < N; m += kBlock) rl[m] = __builtin_nan("");
+    }
+    if (cons >= 0 && nd.role == 1) {
+      for (int n = N + threadIdx.x; n < Npad; n += kBlock) put_col_pad<R, DX>(nb, (size_t)cons, Npad, n);
+      if (threadIdx.x == 0) nb.bcol[cons] = bmerged[gA];
+    }
+  }
+  // natural log of pair (i, j)'s weight relative to the rejection bound
+  auto logw = [&](int i, int j) -> double {
+    R v[DX], u[DX];
+#pragma unroll
+    for (int d = 0; d < DX; ++d) {
+      v[d] = rowp[(size_t)i * DX + d];
+      u[d] = colp[(size_t)j * (DX + 1) + d];
+    }
+    const double a = left_leaf ? (double)alp[i] : -logN;
+    return (a - Astar) +
+           kLn2 * ((double)pair_log2w<R, DX>(u, colp[(size_t)j * (DX + 1) + DX], v) - bmax);
+  };
+  const uint64_t purpose = (lazy == 1) ? kPurposeLazyMH : kPurposeLazyRS;
+  const int dper = (N + DS - 1) / DS;
+  const int n0 = ds * dper, n1 = min(N, n0 + dper);
+  int32_t* ancL = sd.anc + (size_t)(c - 1) * 2 * N;
+  int32_t* ancR = ancL + N;
+  // proposal indices from the two 32-bit halves of one Philox word
+  auto index_lo = [N](uint64_t w) { return (int)(((w & 0xffffffffull) * (uint64_t)N) >> 32); };
+  auto index_hi = [N](uint64_t w) { return (int)(((w >> 32) * (uint64_t)N) >> 32); };
+  int capped = 0, bad = 0;
+  for (int n = n0 + threadIdx.x; n < n1; n += kBlock) {
+    int l = n, r = n;
+    if (lazy == 1) {
+      double cur = logw(l, r);
+      auto step = [&](uint64_t wi, uint64_t wu) {
+        const int ip = index_lo(wi), jp = index_hi(wi);
+        const double prop = logw(ip, jp);
+        if (unif53(wu) < exp(prop - cur)) {
+          l = ip;
+          r = jp;
+          cur = prop;
+        }
+      };
+      // block j serves proposals 2j (words 0, 1) and 2j + 1 (words 2, 3)
+      for (int b = 0; b < param; b += 2) {
+        const Words4 w = philox4x64_10((uint64_t)n, (uint64_t)c, purpose, (uint64_t)(b >> 1),
+                                       sd.seed, kKey1);
+        step(w.w0, w.w1);
+        if (b + 1 < param) step(w.w2, w.w3);
+      }
+      if (isnan(cur)) bad = 1;
+    } else {
+      bool done = false;
+      auto trial = [&](uint64_t wi, uint64_t wu) {
+        l = index_lo(wi);
+        r = index_hi(wi);
+        const double lw = logw(l, r);
+        if (isnan(lw)) bad = 1;
+        done = unif53(wu) < exp(lw);
+      };
+      for (int k = 0; k < param && !done; k += 2) {
+        const Words4 w = philox4x64_10((uint64_t)n, (uint64_t)c, purpose, (uint64_t)(k >> 1),
+                                       sd.seed, kKey1);
+        trial(w.w0, w.w1);
+        if (!done && k + 1 < param) trial(w.w2, w.w3);
+      }
+      if (!done) capped = 1;
+    }
+    if (n == 0 && sd.star != nullptr) {  // conditional combine: slot 0 keeps the star
+      l = 0;
+      r = 0;
+    }
+    record_draw<R, DX>(nb, nd, nodeid, N, Npad, n, l, r, ancL, ancR, gA, gB, logN, bmerged);
+  }
+  if (capped || bad) atomicOr(sd.status, (capped ? kFlagLazyCap : 0) | (bad ? kFlagNumeric : 0));
+}
+
+// ============================================================ launchers
+template <int DX, int MB>
+static void launch_rows_mfma(const LevelLaunch& L, hipStream_t st, unsigned grid, unsigned block) {
+  k_rows_mfma<DX, MB><<<grid, block, 0, st>>>(L.nb.colh, L.nb.colb, L.nb.rowh, L.nb.rown,
+                                              (float*)L.P, L.Rsum, L.Rshift, L.node_list, L.node0,
+                                              L.N, L.Npad, L.Nc, L.NcP, L.RB, L.CS, L.KC,
+                                              L.force_rescue ? 1 : 0);
+}
+
+template <typename R, int DX>
+static int launch_rows_t(const LevelLaunch& L, hipStream_t st) {
+  const unsigned grid = (unsigned)L.nodes * L.RB * L.CS;
+  const unsigned block = 64u * L.W;
+  if constexpr (sizeof(R) == 4 && DX >= 16) {
+    if (L.bf16) {  // 64 RPL rows per wave, as the fp32 kernel
+      switch (L.RPL) {
+        case 1: launch_rows_mfma<DX, 2>(L, st, grid, block); return 0;
+        case 2: launch_rows_mfma<DX, 4>(L, st, grid, block); return 0;
+        case 4: launch_rows_mfma<DX, 8>(L, st, grid, block); return 0;
+      }
+      return -1;
+    }
+  }
+  if (L.bf16) return -1;
+  switch (L.RPL) {
+    case 1:
+      k_rows<R, DX, 1><<<grid, block, 0, st>>>((const R*)L.nb.col, (const R*)L.nb.row, (R*)L.P,
+                                               L.Rsum, L.Rshift, L.node_list, L.node0, L.N, L.Npad, L.Nc,
+                                               L.NcP, L.RB, L.CS, L.KC,
+                                               L.force_rescue ? 1 : 0);
+      return 0;
+    case 2:
+      k_rows<R, DX, 2><<<grid, block, 0, st>>>((const R*)L.nb.col, (const R*)L.nb.row, (R*)L.P,
+                                               L.Rsum, L.Rshift, L.node_list, L.node0, L.N, L.Npad, L.Nc,
+                                               L.NcP, L.RB, L.CS, L.KC,
+                                               L.force_rescue ? 1 : 0);
+      return 0;
+    case 4:
+      k_rows<R, DX, 4><<<grid, block, 0, st>>>((const R*)L.nb.col, (const R*)L.nb.row, (R*)L.P,
+                                               L.Rsum, L.Rshift, L.node_list, L.node0, L.N, L.Npad, L.Nc,
+                                               L.NcP, L.RB, L.CS, L.KC,
+                                               L.force_rescue ? 1 : 0);
+      return 0;
+  }
+  return -1;
+}
+
+template <typename R, int DX>
+static int launch_level_t(const LevelLaunch& L, hipStream_t st, Timer* tm) {
+  if (L.lazy) {  // no pair-row pass
+    tm->begin(2, st);
+    k_sample_lazy<R, DX><<<(unsigned)L.nodes * L.DS, kBlock, 0, st>>>(
+        L.d_nodes, L.d_series, L.node_list, L.node0, L.DS, L.N, L.Npad, L.lazy, L.lazy_param,
+        L.bmerged, L.nb);
+    tm->end(2, st);
+    return 0;
+  }
+  tm->begin(1, st);
+  if (launch_rows_t<R, DX>(L, st)) return -1;
+  tm->end(1, st);
+  size_t lds_samp = (size_t)L.Npad * (2 * sizeof(double) + sizeof(float));
+  const size_t lds_col = (size_t)L.Npad * (DX + 1) * sizeof(R);
+  const int col_in_lds = (lds_samp + lds_col <= 96 * 1024) ? 1 : 0;
+  if (col_in_lds) lds_samp += lds_col;
+  tm->begin(2, st);
+  k_sample<R, DX><<<(unsigned)L.nodes * L.DS, kBlock, lds_samp, st>>>(
+      L.d_nodes, L.d_series, L.node_list, L.node0, L.DS, L.N, L.Npad, L.Nc, L.NcP,
+      L.CS == 1 ? 1 : 0, col_in_lds, L.force_rescue ? 1 : 0, L.bmerged, (const R*)L.P,
+      (R*)L.Pr, L.Rsum, L.Rshift, L.rescue_count, L.nb);
+  tm->end(2, st);
+  return 0;
+}
+
+template <typename R, int DX>
+static void launch_leaves_t(const LeafLaunch& L, hipStream_t st, Timer* tm) {
+  tm->begin(0, st);
+  const size_t lds = (DX >= 8 ? (size_t)L.N + 5 * DX * DX + 4 * DX : 2 * (size_t)L.N) * sizeof(double);
+  k_leaves<R, DX><<<L.rows, kBlock, lds, st>>>(
+      L.d_series, L.d_series_of_t, L.d_leaf_cons, L.d_nodes, L.row0, L.totalK, L.N, L.Npad,
+      (R*)L.leafX, (R*)L.leafW, L.leafL, L.bmerged, L.nb);
+  tm->end(0, st);
+}
+
+
+// Entry points of one (DX, real type) instantiation (dsmc_kernels_dx*.hip).
+#define DSMC_INSTANTIATE(DX, R, SUF)                                                    \
+  int launch_level_dx##DX##SUF(const LevelLaunch& L, hipStream_t st, Timer* tm) {       \
+    return launch_level_t<R, DX>(L, st, tm);                                            \
+  }                                                                                     \
+  void launch_leaves_dx##DX##SUF(const LeafLaunch& L, hipStream_t st, Timer* tm) {      \
+    launch_leaves_t<R, DX>(L, st, tm);                                                  \
+  }
+
+}  // namespace dsmc

@@ -574,3 +574,14 @@ extern "C" int dsmc_job_times(dsmc_server_t* s, uint64_t job_id, double* t_submi
   if (t_done) *t_done = j->t_done;
   return DSMC_OK;
 }
+
+extern "C" int dsmc_job_release(dsmc_server_t* s, uint64_t job_id) {
+  if (!s) return fail(DSMC_EINVAL, "null server");
+  std::lock_guard<std::mutex> lk(s->mu);
+  auto it = s->jobs.find(job_id);
+  if (it == s->jobs.end()) return fail(DSMC_EINVAL, "unknown job %llu", (unsigned long long)job_id);
+  const int st = it->second->state;
+  if (st != DSMC_JOB_DONE && st != DSMC_JOB_FAILED) return DSMC_EAGAIN;
+  s->jobs.erase(it);  // the scheduler holds no reference to a finished job
+  return DSMC_OK;
+}

@@ -20,11 +20,12 @@ LIB_PATH = os.path.join(_PKG, "libdsmc.so")
 
 DSMC_OK, DSMC_EINVAL, DSMC_ENOMEM, DSMC_EUNSUPPORTED = 0, -1, -2, -3
 DSMC_EAGAIN, DSMC_EDEGENERATE, DSMC_ENUMERIC, DSMC_EDEVICE, DSMC_ECANCELLED = -4, -5, -6, -8, -9
+DSMC_ECALLBACK = -7
 DSMC_EDEADLINE = -10
 DSMC_FLAG_DEGENERATE, DSMC_FLAG_NUMERIC, DSMC_FLAG_LAZY_CAP = 1, 2, 4
 DSMC_RESAMPLE_EXACT, DSMC_RESAMPLE_MH, DSMC_RESAMPLE_RS = 0, 1, 2
 DSMC_MH_STEPS_DEFAULT, DSMC_RS_CAP_DEFAULT = 32, 1 << 20
-DSMC_OBS_LINEAR_GAUSSIAN, DSMC_OBS_STOCH_VOL, DSMC_OBS_BOX = 0, 1, 2
+DSMC_OBS_NONE, DSMC_OBS_LINEAR_GAUSSIAN, DSMC_OBS_STOCH_VOL, DSMC_OBS_BOX = -1, 0, 1, 2
 DSMC_PROPOSAL_GAUSSIAN, DSMC_PROPOSAL_UNIFORM = 0, 1
 DSMC_WEIGHT_LEAF_OBS, DSMC_WEIGHT_BOUNDARY_OBS = 0, 1
 DSMC_FP32, DSMC_FP64, DSMC_BF16 = 0, 1, 2
@@ -39,12 +40,24 @@ KERNEL_CLASSES = ("leaves", "rows", "sample", "output")
 _dp = C.POINTER(C.c_double)
 
 
+LOG_PRIOR_FN = C.CFUNCTYPE(C.c_int, C.c_void_p, C.c_int, _dp, _dp)
+LOG_TRANSITION_FN = C.CFUNCTYPE(C.c_int, C.c_void_p, C.c_int, C.c_int, _dp, _dp, _dp)
+LOG_OBSERVATION_FN = C.CFUNCTYPE(C.c_int, C.c_void_p, C.c_int, C.c_int, _dp, _dp)
+PROPOSAL_FN = C.CFUNCTYPE(C.c_int, C.c_void_p, C.c_int, C.c_int, _dp, _dp, _dp)
+
+
+class dsmc_model_callbacks(C.Structure):
+    _fields_ = [("ctx", C.c_void_p), ("log_prior", LOG_PRIOR_FN),
+                ("log_transition", LOG_TRANSITION_FN), ("log_observation", LOG_OBSERVATION_FN),
+                ("proposal", PROPOSAL_FN)]
+
+
 class dsmc_model_desc(C.Structure):
     _fields_ = [("K", C.c_int), ("d_x", C.c_int), ("d_y", C.c_int),
                 ("m0", _dp), ("P0_chol", _dp), ("F", _dp), ("f", _dp), ("Q_chol", _dp),
                 ("obs_kind", C.c_int), ("H", _dp), ("h", _dp), ("R_chol", _dp), ("y", _dp),
                 ("q_mean", _dp), ("q_chol", _dp), ("weighting", C.c_int),
-                ("proposal_kind", C.c_int)]
+                ("proposal_kind", C.c_int), ("callbacks", C.POINTER(dsmc_model_callbacks))]
 
 
 class dsmc_plan_desc(C.Structure):
@@ -89,6 +102,7 @@ def _load() -> C.CDLL:
     vp, i, u64 = C.c_void_p, C.c_int, C.c_uint64
     sig = {
         "dsmc_model_create": (i, [C.POINTER(dsmc_model_desc), C.POINTER(vp)]),
+        "dsmc_model_check": (i, [C.POINTER(dsmc_model_desc)]),
         "dsmc_model_destroy": (None, [vp]),
         "dsmc_model_K": (i, [vp]),
         "dsmc_plan": (i, [C.POINTER(dsmc_plan_desc), C.POINTER(vp)]),
@@ -104,6 +118,7 @@ def _load() -> C.CDLL:
         "dsmc_submit": (i, [vp, C.POINTER(dsmc_job), C.POINTER(u64)]),
         "dsmc_poll": (i, [vp, u64, C.POINTER(i)]),
         "dsmc_cancel": (i, [vp, u64]),
+        "dsmc_job_release": (i, [vp, u64]),
         "dsmc_job_times": (i, [vp, u64, C.POINTER(C.c_double), C.POINTER(C.c_double),
                                C.POINTER(C.c_double)]),
         "dsmc_schedule": (i, [i, i, C.POINTER(C.c_int32), C.POINTER(C.c_int32),
@@ -143,33 +158,58 @@ def _f64(a) -> np.ndarray:
     return np.ascontiguousarray(np.asarray(a, dtype=np.float64))
 
 
-class Model:
-    """Device-resident model (dsmc_model_create)."""
+def model_desc(spec, callbacks: Optional[dsmc_model_callbacks] = None):
+    """(dsmc_model_desc, arrays it points into) for a model spec; the arrays
+    must outlive every use of the description."""
+    K, dx, dy = spec.K, spec.d_x, spec.d_y
+    keep = {
+        "m0": _f64(spec.m0).reshape(dx), "P0_chol": _f64(spec.P0_chol).reshape(dx, dx),
+        "F": _f64(spec.F).reshape(dx, dx), "f": _f64(spec.f).reshape(dx),
+        "Q_chol": _f64(spec.Q_chol).reshape(dx, dx), "y": _f64(spec.y).reshape(K, dy),
+        "q_mean": _f64(spec.q_mean).reshape(K, dx), "q_chol": _f64(spec.q_chol).reshape(K, dx, dx),
+    }
+    if spec.obs == "lg":
+        keep["H"] = _f64(spec.H).reshape(dy, dx)
+        keep["h"] = _f64(spec.h).reshape(dy)
+        keep["R_chol"] = _f64(spec.R_chol).reshape(dy, dy)
+    d = dsmc_model_desc()
+    d.K, d.d_x, d.d_y = K, dx, dy
+    for k, v in keep.items():
+        setattr(d, k, _ptr(v))
+    d.obs_kind = {"lg": DSMC_OBS_LINEAR_GAUSSIAN, "sv": DSMC_OBS_STOCH_VOL,
+                  "box": DSMC_OBS_BOX, "none": DSMC_OBS_NONE}[spec.obs]
+    d.proposal_kind = {"gaussian": DSMC_PROPOSAL_GAUSSIAN, "uniform": DSMC_PROPOSAL_UNIFORM}[
+        getattr(spec, "proposal", "gaussian")]
+    d.weighting = {"leaf_obs": DSMC_WEIGHT_LEAF_OBS,
+                   "boundary_obs": DSMC_WEIGHT_BOUNDARY_OBS}[spec.weighting]
+    if callbacks is not None:
+        d.callbacks = C.pointer(callbacks)
+        keep["callbacks"] = callbacks
+    return d, keep
 
-    def __init__(self, spec):
-        K, dx, dy = spec.K, spec.d_x, spec.d_y
-        keep = {
-            "m0": _f64(spec.m0).reshape(dx), "P0_chol": _f64(spec.P0_chol).reshape(dx, dx),
-            "F": _f64(spec.F).reshape(dx, dx), "f": _f64(spec.f).reshape(dx),
-            "Q_chol": _f64(spec.Q_chol).reshape(dx, dx), "y": _f64(spec.y).reshape(K, dy),
-            "q_mean": _f64(spec.q_mean).reshape(K, dx), "q_chol": _f64(spec.q_chol).reshape(K, dx, dx),
-        }
-        if spec.obs == "lg":
-            keep["H"] = _f64(spec.H).reshape(dy, dx)
-            keep["h"] = _f64(spec.h).reshape(dy)
-            keep["R_chol"] = _f64(spec.R_chol).reshape(dy, dy)
-        d = dsmc_model_desc()
-        d.K, d.d_x, d.d_y = K, dx, dy
-        for k, v in keep.items():
-            setattr(d, k, _ptr(v))
-        d.obs_kind = {"lg": DSMC_OBS_LINEAR_GAUSSIAN, "sv": DSMC_OBS_STOCH_VOL,
-                      "box": DSMC_OBS_BOX}[spec.obs]
-        d.proposal_kind = {"gaussian": DSMC_PROPOSAL_GAUSSIAN, "uniform": DSMC_PROPOSAL_UNIFORM}[
-            getattr(spec, "proposal", "gaussian")]
-        d.weighting = {"leaf_obs": DSMC_WEIGHT_LEAF_OBS,
-                       "boundary_obs": DSMC_WEIGHT_BOUNDARY_OBS}[spec.weighting]
+
+def dsmc_model_check(spec, callbacks: Optional[dsmc_model_callbacks] = None) -> int:
+    """Host-only validation (and callback self-check); returns the status code."""
+    d, keep = model_desc(spec, callbacks)
+    rc = _lib.dsmc_model_check(C.byref(d))
+    del keep
+    return rc
+
+
+def last_error() -> str:
+    return _lib.dsmc_last_error().decode()
+
+
+class Model:
+    """Device-resident model (dsmc_model_create), optionally with host callbacks
+    that dsmc_model_create checks the device form against."""
+
+    def __init__(self, spec, callbacks: Optional[dsmc_model_callbacks] = None):
+        K, dx = spec.K, spec.d_x
+        d, keep = model_desc(spec, callbacks)
         h = C.c_void_p()
         _check(_lib.dsmc_model_create(C.byref(d), C.byref(h)), "dsmc_model_create")
+        del keep
         self.handle = h
         self.K, self.d_x = K, dx
 
@@ -179,8 +219,8 @@ class Model:
             self.handle = None
 
 
-def dsmc_model_create(spec) -> Model:
-    return Model(spec)
+def dsmc_model_create(spec, callbacks: Optional[dsmc_model_callbacks] = None) -> Model:
+    return Model(spec, callbacks)
 
 
 class Plan:
@@ -403,6 +443,16 @@ def dsmc_poll(server: Server, job_id: int):
     if rc != DSMC_EAGAIN:
         server._keep.pop(job_id, None)
     return rc, st.value
+
+
+def dsmc_job_release(server: Server, job_id: int) -> int:
+    """Forget a finished job; DSMC_OK, or DSMC_EAGAIN while it is queued or running."""
+    rc = _lib.dsmc_job_release(server.handle, C.c_uint64(job_id))
+    if rc not in (DSMC_OK, DSMC_EAGAIN):
+        _check(rc, "dsmc_job_release")
+    if rc == DSMC_OK:
+        server._keep.pop(job_id, None)
+    return rc
 
 
 def dsmc_job_times(server: Server, job_id: int):

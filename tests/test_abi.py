@@ -42,7 +42,7 @@ def test_struct_layout_matches_header(tmp_path):
     from paper_2202_02264_amd import dsmc
     if shutil.which("gcc") is None:
         pytest.skip("gcc not available")
-    structs = [dsmc.dsmc_model_desc, dsmc.dsmc_plan_desc, dsmc.dsmc_output, dsmc.dsmc_profile,
+    structs = [dsmc.dsmc_model_callbacks, dsmc.dsmc_model_desc, dsmc.dsmc_plan_desc, dsmc.dsmc_output, dsmc.dsmc_profile,
                dsmc.dsmc_server_desc, dsmc.dsmc_job]
     lines = ["#include <stdio.h>", "#include <stddef.h>", '#include "dsmc.h"', "int main(void){"]
     for s in structs:

@@ -111,3 +111,31 @@ def test_cancel_and_admission_deadline():
     single = run_gpu(small, 4096, 4, model=ms)
     np.testing.assert_array_equal(oe.traj.cpu().numpy(), single["traj"])
     srv.close()
+
+
+def test_released_jobs_are_forgotten():
+    """dsmc_job_release frees a finished job's record (its id becomes unknown);
+    a job still queued or running is not released.  Many submit / poll /
+    release cycles leave no record behind."""
+    from paper_2202_02264_amd import dsmc as G
+    srv = G.Server(mem_budget=4 << 30, max_jobs=8, max_classes=2)
+    spec = W.sv(64, seed=3)
+    m = G.Model(spec)
+    outs = [G.alloc_job_output(256, 1, spec.K) for _ in range(16)]
+    log("serving: release cycles")
+    for wave in range(10):
+        ids = [G.dsmc_submit(srv, m, 256, 100 * wave + k, outs[k]) for k in range(16)]
+        codes = _wait(G, srv, ids)
+        assert all(c == 0 for c in codes.values()), codes
+        for i in ids:
+            assert G.dsmc_job_release(srv, i) == G.DSMC_OK
+            rc = G._lib.dsmc_poll(srv.handle, i, None)
+            assert rc == G.DSMC_EINVAL
+    big = W.sv(8192, seed=4)
+    mb = G.Model(big)
+    ob = G.alloc_job_output(4096, 1, big.K)
+    jb = G.dsmc_submit(srv, mb, 4096, 1, ob)
+    assert G.dsmc_job_release(srv, jb) == G.DSMC_EAGAIN  # queued or running
+    _wait(G, srv, [jb])
+    assert G.dsmc_job_release(srv, jb) == G.DSMC_OK
+    srv.close()
