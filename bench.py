@@ -1,22 +1,31 @@
 """Benchmark of the dSMC smoother on one MI355X.
 
-Workload: stochastic-volatility model (mu = -1, rho = 0.95, sigma = 0.3),
-K = 4096 time points (T = 4096 in the configs' notation), N = 1024 particles,
-fp32 pair weights, data simulated from the model with a fixed seed.  One step
-is one whole smoother run (leaves, 12 tree levels, output) on resident inputs,
-through the C ABI.
+Default run (`python bench.py`): the headline workload, stochastic-volatility
+model (mu = -1, rho = 0.95, sigma = 0.3), K = 4096 time points (T = 4096 in
+the configs' notation), N = 1024 particles, fp32 pair weights, data simulated
+from the model with a fixed seed.  One step is one whole smoother run (leaves,
+12 tree levels, output) on resident inputs, through the C ABI.  The same JSON
+line carries, under "workloads", shorter runs of the other configurations:
+the 512-series batch, the d_x = 32 bf16 matrix-core precision workload, the
+serving mix, and rejection lazy resampling on the constrained random walk.
 
 Output: one JSON line.  `value` = algorithmic pair evaluations per second,
 (K-1) N^2 per step.  `roofline` prices the dominant kernel (the pair-row
 kernel) against the VALU issue rate of the chip; `cpu_baseline` times the fp64
-oracle on a bounded sample of the same workload on the host cores.
+oracle on a bounded sample of the same workload on the host cores (one core,
+then all cores of the process's CPU share).
+
+`--workload X` runs one configuration alone in more detail; `--issue-rates`
+runs the VALU issue-rate microbenchmark behind the roofline's pricing.
 """
 from __future__ import annotations
 
 import argparse
+import hashlib
 import json
 import math
 import os
+import subprocess
 import sys
 import time
 
@@ -24,55 +33,70 @@ ROOT = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, ROOT)
 
 # MI355X: 256 CUs x 4 SIMD x 16 lanes at 2.4 GHz = 39.32e12 lane-instructions/s
-# for single-rate VALU work (fp32 add/sub/fma without packed math).
+# for single-rate VALU work (fp32 add/sub/fma without packed math): one wave64
+# instruction per SIMD every four cycles.
 LANE_OPS_PER_S = 256 * 4 * 16 * 2.4e9
 # VALU issue slots per pair evaluation in the pair-row kernel (d_x = 1):
-# v_sub, v_fma, v_add at one slot each, plus v_exp_f32 at TRANS_SLOTS slots
-# (v_exp_f32 issues at half the rate of v_fma_f32 on gfx950 and does not
-# co-issue with it: measured 1.85e13 vs 3.5e13 lane-instructions/s).
+# v_sub, v_fma, v_add at one slot each, plus v_exp_f32 at TRANS_SLOTS slots.
+# v_exp_f32 issues at half the rate of v_fma_f32 on gfx950 and does not
+# co-issue with it (paper_2202_02264_amd/microbench/issue_rates.hip, run by
+# `bench.py --issue-rates`; profiles/valu_issue_rates.md).  The line also
+# reports the fraction with every instruction at one slot (4 per pair).
 TRANS_SLOTS = 2.0
 SLOTS_PER_PAIR = 3.0 + TRANS_SLOTS
+SLOTS_PER_PAIR_SINGLE = 4.0
 # bf16 matrix-core pair rows (d_x = 16, 32): the dot products run on the
 # matrix cores; per pair the VALU issues the accumulator start (one v_sub),
 # v_exp_f32 (TRANS_SLOTS) and the chunk-sum add.
 SLOTS_PER_PAIR_MFMA = 2.0 + TRANS_SLOTS
-# dense bf16 matrix-core peak of MI355X, and flops per pair at d_x = 32
+# dense bf16 matrix-core peak of MI355X
 BF16_MFMA_PEAK = 2.5e15
-# HBM traffic of one pair-row launch of the default workload (K = 4096,
+# HBM traffic of one pair-row launch of the headline workload (K = 4096,
 # N = 1024), averaged over the 12 levels: rocprofv3 FETCH_SIZE / WRITE_SIZE,
-# each scaled by the same counter's reading for a 256 MiB device copy (see
-# profiles/k_rows_sv_K4096_N1024.md).  Reset to None when k_rows changes.
-K_ROWS_SV_TRAFFIC_MIB = {"read": 21.89, "write": 89.85}
+# each scaled by the same counter's reading for a 256 MiB device copy
+# (profiles/k_rows_sv_K4096_N1024.md).  `src` is the sha256 prefix of the
+# kernel source the counters were taken on; when the source differs the
+# figure is reported as null.
+K_ROWS_SV_TRAFFIC = {"src": None, "read_MiB": None, "write_MiB": None}
 # Lazy resampling kernel (k_sample_lazy<float, 1>): VALU instructions per
 # proposal in its Metropolis-Hastings loop, counted in the gfx950 assembly of
 # this source (half a Philox4x64-10 block, pair weight, fp64 exponential: 395
 # per loop trip of two proposals); each is priced at one issue slot, so the
 # derived peak is an upper bound.
 LAZY_VALU_PER_PROPOSAL = 198
-# HBM traffic of one k_sample_lazy launch (MH, B = 32) of the default
-# workload: rocprofv3 FETCH_SIZE / WRITE_SIZE scaled by the copy calibration
-# (see profiles/k_sample_lazy_mh_sv_K4096_N1024.md).  Reset to None when
-# k_sample_lazy changes.
-LAZY_MH_SV_TRAFFIC_MIB = {"read": 14.00, "write": 8.01}
+KERNEL_SOURCES = ("paper_2202_02264_amd/csrc/dsmc_kernels_impl.h",
+                  "paper_2202_02264_amd/csrc/dsmc_device.h")
+
+
+def kernel_source_hash() -> str:
+    h = hashlib.sha256()
+    for p in KERNEL_SOURCES:
+        with open(os.path.join(ROOT, p), "rb") as f:
+            h.update(f.read())
+    return h.hexdigest()[:16]
 
 
 def parse():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
-    ap.add_argument("--steps", type=int, default=20)
-    ap.add_argument("--warmup", type=int, default=3)
+    ap.add_argument("--steps", type=int, default=200)
+    ap.add_argument("--warmup", type=int, default=5)
     ap.add_argument("--K", type=int, default=4096)
     ap.add_argument("--N", type=int, default=1024)
-    ap.add_argument("--cpu-seconds", type=float, default=15.0,
-                    help="wall-clock budget of the oracle baseline sample (0 = skip)")
+    ap.add_argument("--cpu-seconds", type=float, default=8.0,
+                    help="wall-clock budget of each oracle baseline sample, per core count "
+                         "(0 = skip)")
+    ap.add_argument("--no-extras", action="store_true",
+                    help="default workload: skip the other configurations")
     ap.add_argument("--no-kernel-events", action="store_true",
                     help="time the steps without per-kernel HIP events")
     ap.add_argument("--workload", choices=("sv", "batch", "serve", "highdim", "pgibbs", "lazy"),
                     default="sv",
-                    help="sv: one long stochastic-volatility series (default); batch: "
-                         "B linear-Gaussian series of uneven length, packed vs one at a time; "
-                         "pgibbs: particle Gibbs sweeps of conditional dSMC on the sv series; "
-                         "lazy: lazy resampling (MH, rejection) vs exact on the sv series")
+                    help="sv: the headline series (default, with the other configurations "
+                         "under 'workloads'); batch: 512 linear-Gaussian series packed vs one at "
+                         "a time; highdim: d_x = 32 bf16 matrix-core pair rows; serve: "
+                         "continuous-batching server; pgibbs: particle Gibbs sweeps of "
+                         "conditional dSMC; lazy: lazy resampling vs exact")
     ap.add_argument("--B", type=int, default=512)
     ap.add_argument("--schemes", type=str, default="exact,mh_B8,mh_B32,rs",
                     help="lazy: which runs (exact, mh_B8, mh_B32, rs)")
@@ -86,42 +110,195 @@ def parse():
     ap.add_argument("--serve-mem-gib", type=int, default=192)
     ap.add_argument("--copy-calibration", action="store_true",
                     help="only run 10 device copies of 256 MiB (HBM counter calibration)")
+    ap.add_argument("--issue-rates", action="store_true",
+                    help="only run the VALU issue-rate microbenchmark")
     return ap.parse_args()
 
 
-def cpu_baseline(spec, N: int, budget_s: float) -> dict:
-    """The fp64 oracle's combine (Algorithm 1) on level-0 nodes of the same
-    workload, one after another until the time budget is spent."""
-    import numpy as np
+# ----------------------------------------------------------------- CPU baseline
+
+def host_cores() -> int:
+    """Cores of this process's CPU share (at most 16, a GPU machine's share)."""
+    try:
+        n = len(os.sched_getaffinity(0))
+    except AttributeError:
+        n = os.cpu_count() or 1
+    return max(1, min(n, 16))
+
+
+def _oracle_worker(job):
+    """Oracle combines (Algorithm 1 with Algorithm 2's leaves) on the boundaries
+    c = first, first + stride, ... of the spec until `budget` seconds pass,
+    single-threaded.  Returns (pairs, wall seconds, combines)."""
+    spec, N, first, stride, budget = job
+    from threadpoolctl import threadpool_limits
 
     from oracle import dsmc as D
     from oracle import philox as P
-    t_wall0, t_cpu0 = time.perf_counter(), time.process_time()
-    nodes = 0
-    seed = 1
-    c = 1
-    while time.perf_counter() - t_wall0 < budget_s and c < spec.K:
-        sub = spec.truncated(c + 1)
-        xs = []
-        for t in (c - 1, c):
-            z = P.leaf_normals(seed, t, N, spec.d_x)
-            xs.append(sub.q_mean[t][None, :] + z @ sub.q_chol[t].T)
-        lws = [D.normalise(D.leaf_logweights(sub, t, x))[0] for t, x in zip((c - 1, c), xs)]
-        u1, u2 = P.combine_uniforms(seed, c, N)
-        D.combine(sub, c, xs[0], xs[1], lws[0], lws[1], u1, u2)
-        nodes += 1
-        c += 2
-    wall = time.perf_counter() - t_wall0
-    cpu = time.process_time() - t_cpu0
-    pairs = nodes * N * N
-    return {"value": pairs / wall, "unit": "pair-evals/s", "cores": max(1, round(cpu / wall)),
-            "kind": "oracle",
-            "sample": f"{nodes} level-0 combines (leaf draws, weights, N x N pair weights, "
-                      f"{N} two-stage draws each) of the same workload, fp64 numpy, "
-                      f"{wall:.1f} s wall"}
+    from oracle import ssm
+    with threadpool_limits(1):
+        t0 = time.perf_counter()
+        done = 0
+        c = first
+        while time.perf_counter() - t0 < budget and c < spec.K:
+            xs = [ssm.proposal_draw(spec, t, P.leaf_normals(1, t, N, spec.d_x)) for t in (c - 1, c)]
+            lws = [D.normalise(D.leaf_logweights(spec, t, x))[0] for t, x in zip((c - 1, c), xs)]
+            u1, u2 = P.combine_uniforms(1, c, N)
+            D.combine(spec, c, xs[0], xs[1], lws[0], lws[1], u1, u2)
+            done += 1
+            c += stride
+        wall = time.perf_counter() - t0
+    return done * N * N, wall, done
 
 
-def bench_batch(args):
+def cpu_baseline(spec, N: int, budget_s: float, label: str) -> dict:
+    """The fp64 oracle's combine on level-0 boundaries of the workload: one
+    single-threaded process, then one single-threaded process per host core on
+    disjoint boundaries, each for `budget_s` seconds (pair-evals/s = all pairs
+    done / the longest wall time)."""
+    import multiprocessing as mp
+    cores = host_cores()
+    single = _oracle_worker((spec, N, 1, 2, budget_s))
+    ctx = mp.get_context("spawn")
+    with ctx.Pool(cores) as pool:
+        res = pool.map(_oracle_worker, [(spec, N, 1 + 2 * i, 2 * cores, budget_s)
+                                        for i in range(cores)])
+    pairs = sum(r[0] for r in res)
+    wall = max(r[1] for r in res)
+    return {"value": pairs / wall, "unit": "pair-evals/s", "cores": cores, "kind": "oracle",
+            "host_cpus": os.cpu_count(),
+            "sample": f"{sum(r[2] for r in res)} level-0 combines of {label} (leaf draws and "
+                      f"weights of both times, N x N pair weights, N = {N} two-stage draws "
+                      f"each), fp64 numpy, one single-threaded process per core, "
+                      f"{wall:.1f} s wall",
+            "single_core": {"value": single[0] / single[1], "cores": 1,
+                            "sample": f"{single[2]} combines, {single[1]:.1f} s wall"}}
+
+
+# ------------------------------------------------------------------ helpers
+
+def _pct(a, q):
+    import numpy as np
+    return float(np.percentile(np.asarray(a), q)) if len(a) else float("nan")
+
+
+def _timed(G, torch, plan, model, out, steps, warmup, seed0=1):
+    for s in range(warmup):
+        G.dsmc_smooth(plan, model, 1000 + s, out)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for s in range(steps):
+        G.dsmc_smooth(plan, model, seed0 + s, out)
+    torch.cuda.synchronize()
+    return (time.perf_counter() - t0) / steps
+
+
+def _rows_roofline(prof, steps, slots, kernel, single_slots=None, extra=None):
+    """Pair-row kernel against the VALU issue rate: achieved pairs/s over its
+    launches (HIP events), peak = lane-instructions/s / slots per pair."""
+    n_rows = prof["launches"]["rows"]
+    ms_rows = prof["ms"]["rows"]
+    achieved = prof["pairs"] / (ms_rows * 1e-3)
+    peak = LANE_OPS_PER_S / slots
+    r = {"bound": "alu", "kernel": kernel, "achieved": achieved / 1e9, "peak": peak / 1e9,
+         "unit": "Gpair/s", "frac": achieved / peak, "traffic": None,
+         "avg_launch_ms": ms_rows / max(1, n_rows),
+         "pairs_per_launch": prof["pairs"] / max(1, n_rows),
+         "slots_per_pair": slots}
+    if single_slots:
+        r["frac_one_slot_per_instruction"] = achieved / (LANE_OPS_PER_S / single_slots)
+    if extra:
+        r.update(extra)
+    return r
+
+
+def _profile_run(G, torch, N, dx, K, model, steps, warmup, **plan_kw):
+    """The same steps eagerly with HIP events around every launch."""
+    plan = G.Plan(N, dx, K, profile=True, **plan_kw)
+    out = G.alloc_output(plan, K)
+    for s in range(max(1, warmup)):
+        G.dsmc_smooth(plan, model, 1000 + s, out)
+    torch.cuda.synchronize()
+    G.dsmc_plan_profile(plan)  # drop the warm-up records
+    t0 = time.perf_counter()
+    for s in range(steps):
+        G.dsmc_smooth(plan, model, s + 1, out)
+    torch.cuda.synchronize()
+    dt = (time.perf_counter() - t0) / steps
+    prof = G.dsmc_plan_profile(plan)
+    return prof, dt
+
+
+# ----------------------------------------------------------------- headline
+
+def bench_sv(args) -> dict:
+    import torch
+
+    from paper_2202_02264_amd import dsmc as G
+    from paper_2202_02264_amd import workloads as W
+    torch.cuda.set_device(0)
+    K, N = args.K, args.N
+    spec = W.sv(K)
+    model = G.Model(spec)
+    # timed steps: the plan replays one hipGraph per step (first warm-up call
+    # runs eagerly and tunes the tiles, the second captures)
+    plan = G.Plan(N, 1, K, graph=True)
+    out = G.alloc_output(plan, K)
+    dt = _timed(G, torch, plan, model, out, args.steps, max(2, args.warmup))
+    status = int(out.status.item())
+    if status:
+        raise RuntimeError(f"device status {status}")
+    pairs = (K - 1) * N * N
+    res = {
+        "metric": "pair-evals/sec", "value": pairs / dt, "unit": "pair-evals/s", "n_gpus": 1,
+        "steps": args.steps, "warmup": args.warmup, "ms_per_step": dt * 1e3,
+        "higher_is_better": True, "scaling": "weak", "vs_baseline": None, "dtype": "f32",
+        "data": "synthetic",
+        "config": {"workload": f"stochastic volatility, K={K} time points, N={N} particles, "
+                               "one smoother per step", "K": K, "N": N, "d_x": 1,
+                   "precision": "fp32 pair weights, fp64 sums and CDFs",
+                   "weighting": spec.weighting, "data_seed": W.DATA_SEED},
+        "smoothers_per_sec": 1.0 / dt,
+        "pair_evals_T_log2T_N2_per_sec": K * math.log2(K) * N * N / dt,
+    }
+    if not args.no_kernel_events:
+        ev_steps = min(args.steps, 20)
+        prof, dt_ev = _profile_run(G, torch, N, 1, K, model, ev_steps, args.warmup)
+        n_rows = prof["launches"]["rows"]
+        nodes = K - 1
+        Npad = (N + 31) // 32 * 32
+        NcP = (Npad // 32 + 3) // 4 * 4
+        algo_bytes = nodes * (Npad * 2 * 4 + Npad * 4 + N * NcP * 4 + N * 8) / max(1, n_rows / ev_steps)
+        src = kernel_source_hash()
+        traffic = None
+        if (K, N) == (4096, 1024) and K_ROWS_SV_TRAFFIC["src"] == src:
+            traffic = (K_ROWS_SV_TRAFFIC["read_MiB"] + K_ROWS_SV_TRAFFIC["write_MiB"]) * 2 ** 20
+        res["ms_per_step_with_kernel_events"] = dt_ev * 1e3
+        res["roofline"] = _rows_roofline(
+            prof, ev_steps, SLOTS_PER_PAIR, "k_rows<float,1,RPL>", SLOTS_PER_PAIR_SINGLE,
+            {"traffic": traffic, "traffic_algorithmic": algo_bytes, "kernel_source": src,
+             "traffic_source": K_ROWS_SV_TRAFFIC["src"]})
+        res["kernel_ms_per_step"] = {k: v / ev_steps for k, v in prof["ms"].items()}
+        ms_comb = (prof["ms"]["rows"] + prof["ms"]["sample"]) / ev_steps
+        res["combine"] = {
+            "ms_per_step": ms_comb, "pairs_per_sec": pairs / (ms_comb * 1e-3),
+            "frac": pairs / (ms_comb * 1e-3) / (LANE_OPS_PER_S / SLOTS_PER_PAIR),
+            "frac_one_slot_per_instruction":
+                pairs / (ms_comb * 1e-3) / (LANE_OPS_PER_S / SLOTS_PER_PAIR_SINGLE),
+            "note": "pair rows + sampling kernels of every level against the pair-row roofline"}
+        draws = nodes * N
+        ms_s = prof["ms"]["sample"] / ev_steps
+        res["sample_kernel"] = {"ms_per_step": ms_s, "draws_per_sec": draws / (ms_s * 1e-3),
+                                "launches_per_step": prof["launches"]["sample"] / ev_steps}
+        res["rescued_rows_per_step"] = prof["rescued_rows"] / ev_steps
+    if args.cpu_seconds > 0:
+        res["cpu_baseline"] = cpu_baseline(spec, N, args.cpu_seconds, "the same workload")
+    return res
+
+
+# ------------------------------------------------------------------- batch
+
+def bench_batch(args, quick=False) -> dict:
     """B independent 1-D linear-Gaussian series (A ~ U[0.5, 0.99], Q, R ~ U[0.1, 2],
     K ~ U{64..8192}), N = 256: dsmc_smooth_batch (every level of every series
     in shared launches, replayed as one hipGraph) against dsmc_smooth called
@@ -131,18 +308,17 @@ def bench_batch(args):
 
     from paper_2202_02264_amd import dsmc as G
     from paper_2202_02264_amd import workloads as W
-    N = 256 if args.N == 1024 else args.N
+    N = 256 if (quick or args.N == 1024) else args.N
     specs = W.lg1d_batch(args.B)
     Ks = [s.K for s in specs]
     models = [G.Model(s) for s in specs]
-    # timed: one hipGraph replay per batch (warm-up: eager + tile tuning, then capture)
     plan = G.Plan(N, 1, max(Ks), max_total_K=sum(Ks), graph=True)
     outs = [G.alloc_output(plan, K) for K in Ks]
     seeds = list(range(1, args.B + 1))
-    for _ in range(max(2, args.warmup)):
+    for _ in range(3):  # eager + tile tuning, capture, replay
         G.dsmc_smooth_batch(plan, models, seeds, outs)
     torch.cuda.synchronize()
-    steps = max(1, min(args.steps, 5))
+    steps = 5
     t0 = time.perf_counter()
     for _ in range(steps):
         G.dsmc_smooth_batch(plan, models, seeds, outs)
@@ -154,7 +330,7 @@ def bench_batch(args):
         G.dsmc_smooth_batch(plan_p, models, seeds, outs)
         torch.cuda.synchronize()
         G.dsmc_plan_profile(plan_p)
-        for _ in range(steps):
+        for _ in range(2):
             G.dsmc_smooth_batch(plan_p, models, seeds, outs)
         torch.cuda.synchronize()
         prof = G.dsmc_plan_profile(plan_p)
@@ -175,7 +351,7 @@ def bench_batch(args):
     dt_p = time.perf_counter() - t0
     pairs = sum((K - 1) * N * N for K in Ks)
     res = {"metric": "smoothers/sec", "value": args.B / dt_b, "unit": "smoothers/s",
-           "n_gpus": 1, "steps": steps, "warmup": args.warmup, "ms_per_step": dt_b * 1e3,
+           "n_gpus": 1, "steps": steps, "warmup": 3, "ms_per_step": dt_b * 1e3,
            "higher_is_better": True, "scaling": "weak", "vs_baseline": None, "dtype": "f32",
            "data": "synthetic",
            "config": {"workload": f"{args.B} linear-Gaussian series, K ~ U{{64..8192}} "
@@ -184,22 +360,19 @@ def bench_batch(args):
            "plain_smoothers_per_sec": args.B / dt_p, "plain_ms_per_batch": dt_p * 1e3,
            "speedup_vs_plain": dt_p / dt_b, "pair_evals_per_sec": pairs / dt_b}
     if prof:
-        ms_rows = prof["ms"]["rows"]
-        peak = LANE_OPS_PER_S / SLOTS_PER_PAIR
-        res["roofline"] = {"bound": "alu", "kernel": "k_rows<float,1,RPL>",
-                           "achieved": prof["pairs"] / (ms_rows * 1e-3) / 1e9,
-                           "peak": peak / 1e9, "unit": "Gpair/s",
-                           "frac": prof["pairs"] / (ms_rows * 1e-3) / peak, "traffic": None}
-        res["kernel_ms_per_step"] = {k: v / steps for k, v in prof["ms"].items()}
-    print(json.dumps(res))
+        res["roofline"] = _rows_roofline(prof, 2, SLOTS_PER_PAIR, "k_rows<float,1,RPL>",
+                                         SLOTS_PER_PAIR_SINGLE)
+        res["kernel_ms_per_step"] = {k: v / 2 for k, v in prof["ms"].items()}
+    if args.cpu_seconds > 0:
+        long = specs[max(range(len(specs)), key=lambda i: Ks[i])]
+        res["cpu_baseline"] = cpu_baseline(long, N, min(args.cpu_seconds, 3.0),
+                                           f"the longest series (K={long.K})")
+    return res
 
 
-def _pct(a, q):
-    import numpy as np
-    return float(np.percentile(np.asarray(a), q)) if len(a) else float("nan")
+# ------------------------------------------------------------------ serving
 
-
-def bench_serve(args):
+def bench_serve(args, quick=False) -> dict:
     """Serving: a seeded stream of jobs (half stochastic-volatility, half 4-D
     linear-Gaussian, K ~ lognormal(median 512, sigma_log 1) clipped to
     [2, 16384], N uniform over {256, 1024, 4096}, fp32) through dsmc_submit /
@@ -248,6 +421,8 @@ def bench_serve(args):
                     pending.discard(i)
             time.sleep(2e-4)
         ts = np.array([G.dsmc_job_times(srv, i) for i in ids])
+        for i in ids:
+            G.dsmc_job_release(srv, i)
         lat = (ts[:, 2] - ts[:, 0]) * 1e3
         span = ts[:, 2].max() - ts[:, 0].min()
         return {"jobs_per_sec": len(ids) / span, "p50_ms": _pct(lat, 50), "p99_ms": _pct(lat, 99),
@@ -279,7 +454,8 @@ def bench_serve(args):
           file=sys.stderr, flush=True)
     g = np.random.default_rng(7)
     sweep = []
-    for f in [float(x) for x in args.rates.split(",") if x]:
+    rates = [0.5] if quick else [float(x) for x in args.rates.split(",") if x]
+    for f in rates:
         rate = f * sat["jobs_per_sec"]
         gaps = g.exponential(1.0 / rate, len(jobs))
         r = run(range(len(jobs)), gaps)
@@ -289,21 +465,22 @@ def bench_serve(args):
               f"p99 {r['p99_ms']:.2f} ms", file=sys.stderr, flush=True)
     srv.close()
     Ks = np.array([s.K for s, _, _ in jobs])
-    res = {"metric": "jobs/sec (serving, continuous batching)", "value": sat["jobs_per_sec"],
-           "unit": "jobs/s", "n_gpus": 1, "steps": 1, "warmup": 1,
-           "ms_per_step": sat["span_s"] * 1e3, "higher_is_better": True, "scaling": "weak",
-           "vs_baseline": None, "dtype": "f32", "data": "synthetic",
-           "config": {"workload": f"{len(jobs)} jobs, SV / 4-D LG 50/50, K ~ lognormal(median 512, "
-                                  f"sigma 1) in [2, 16384] (median {int(np.median(Ks))}, max "
-                                  f"{int(Ks.max())}), N in {{256, 1024, 4096}}, fp32",
-                      "jobs": len(jobs), "sum_pairs": pairs},
-           "saturated": sat, "plain_jobs_per_sec": len(jobs) / dt_plain,
-           "speedup_vs_plain": sat["jobs_per_sec"] * dt_plain / len(jobs),
-           "served_equals_alone": same, "sweep": sweep}
-    print(json.dumps(res))
+    return {"metric": "jobs/sec (serving, continuous batching)", "value": sat["jobs_per_sec"],
+            "unit": "jobs/s", "n_gpus": 1, "steps": 1, "warmup": 1,
+            "ms_per_step": sat["span_s"] * 1e3, "higher_is_better": True, "scaling": "weak",
+            "vs_baseline": None, "dtype": "f32", "data": "synthetic",
+            "config": {"workload": f"{len(jobs)} jobs, SV / 4-D LG 50/50, K ~ lognormal(median "
+                                   f"512, sigma 1) in [2, 16384] (median {int(np.median(Ks))}, "
+                                   f"max {int(Ks.max())}), N in {{256, 1024, 4096}}, fp32",
+                       "jobs": len(jobs), "sum_pairs": pairs},
+            "saturated": sat, "plain_jobs_per_sec": len(jobs) / dt_plain,
+            "speedup_vs_plain": sat["jobs_per_sec"] * dt_plain / len(jobs),
+            "served_equals_alone": same, "sweep": sweep}
 
 
-def bench_highdim(args):
+# ------------------------------------------------------------- precision
+
+def bench_highdim(args, quick=False) -> dict:
     """d_x = 32 linear-Gaussian model (A = 0.95 orth, Q = 0.1 I, d_y = 8,
     R = 0.5 I, RTS proposals), K = 2048, N = 4096: the bf16 matrix-core
     pair-row path (DSMC_BF16), with the fp32 VALU path on the same model
@@ -312,45 +489,34 @@ def bench_highdim(args):
 
     from paper_2202_02264_amd import dsmc as G
     from paper_2202_02264_amd import workloads as W
-    K = 2048 if args.K == 4096 else args.K
-    N = 4096 if args.N == 1024 else args.N
+    K = 2048 if (quick or args.K == 4096) else args.K
+    N = 4096 if (quick or args.N == 1024) else args.N
     spec = W.lg_highdim(K=K)
     model = G.Model(spec)
     pairs = (K - 1) * N * N
     runs = {}
-    for name, prec, steps in (("bf16", G.DSMC_BF16, max(1, min(args.steps, 10))),
-                              ("fp32", G.DSMC_FP32, max(1, min(args.steps, 3)))):
-        plan = G.Plan(N, spec.d_x, K, precision=prec, profile=not args.no_kernel_events)
+    for name, prec, steps in (("bf16", G.DSMC_BF16, 5 if quick else 10),
+                              ("fp32", G.DSMC_FP32, 2 if quick else 3)):
+        plan = G.Plan(N, spec.d_x, K, precision=prec, graph=True)
         out = G.alloc_output(plan, K)
-        for s in range(max(1, args.warmup)):
-            G.dsmc_smooth(plan, model, 1000 + s, out)
-        torch.cuda.synchronize()
-        if not args.no_kernel_events:
-            G.dsmc_plan_profile(plan)
-        t0 = time.perf_counter()
-        for s in range(steps):
-            G.dsmc_smooth(plan, model, s + 1, out)
-        torch.cuda.synchronize()
-        dt = (time.perf_counter() - t0) / steps
+        dt = _timed(G, torch, plan, model, out, steps, 2)
         status = int(out.status.item())
         if status:
             raise RuntimeError(f"{name}: device status {status}")
         r = {"ms_per_step": dt * 1e3, "pair_evals_per_sec": pairs / dt, "steps": steps,
              "log_Z_last": float(out.log_Z.item())}
+        del plan, out
         if not args.no_kernel_events:
-            prof = G.dsmc_plan_profile(plan)
-            r["kernel_ms_per_step"] = {k: v / steps for k, v in prof["ms"].items()}
-            r["rows_pairs_per_sec"] = prof["pairs"] / (prof["ms"]["rows"] * 1e-3)
-            r["rows_launches"] = prof["launches"]["rows"]
-            r["rows_pairs"] = prof["pairs"]
-            r["rescued_rows_per_step"] = prof["rescued_rows"] / steps
+            prof, _ = _profile_run(G, torch, N, spec.d_x, K, model, 2, 1, precision=prec)
+            r["kernel_ms_per_step"] = {k: v / 2 for k, v in prof["ms"].items()}
+            r["prof"] = prof
+            r["rescued_rows_per_step"] = prof["rescued_rows"] / 2
         runs[name] = r
         print(f"# highdim {name}: {dt * 1e3:.2f} ms/step", file=sys.stderr, flush=True)
-        del plan, out
         torch.cuda.empty_cache()
     b = runs["bf16"]
     res = {"metric": "pair-evals/sec", "value": b["pair_evals_per_sec"], "unit": "pair-evals/s",
-           "n_gpus": 1, "steps": b["steps"], "warmup": args.warmup, "ms_per_step": b["ms_per_step"],
+           "n_gpus": 1, "steps": b["steps"], "warmup": 2, "ms_per_step": b["ms_per_step"],
            "higher_is_better": True, "scaling": "weak", "vs_baseline": None, "dtype": "bf16",
            "data": "synthetic",
            "config": {"workload": f"linear-Gaussian d_x=32 (d_y=8, A=0.95 orth, Q=0.1I, R=0.5I, "
@@ -358,24 +524,28 @@ def bench_highdim(args):
                       "K": K, "N": N, "d_x": 32,
                       "precision": "bf16 matrix-core dot products, fp32 accumulation and "
                                    "exponentials, fp64 row sums and CDFs"},
-           "smoothers_per_sec": 1e3 / b["ms_per_step"], "fp32_valu": runs["fp32"],
+           "smoothers_per_sec": 1e3 / b["ms_per_step"],
            "speedup_vs_fp32": runs["fp32"]["ms_per_step"] / b["ms_per_step"]}
-    if "rows_pairs_per_sec" in b:
-        ach = b["rows_pairs_per_sec"]
-        peak = LANE_OPS_PER_S / SLOTS_PER_PAIR_MFMA
-        ms_rows = b["kernel_ms_per_step"]["rows"] * b["steps"]
-        res["roofline"] = {"bound": "alu", "kernel": "k_rows_mfma<32,MB>", "achieved": ach / 1e9,
-                           "peak": peak / 1e9, "unit": "Gpair/s", "frac": ach / peak,
-                           "traffic": None, "avg_launch_ms": ms_rows / max(1, b["rows_launches"]),
-                           "pairs_per_launch": b["rows_pairs"] / max(1, b["rows_launches"]),
-                           "mfma_utilisation": ach * 2 * spec.d_x / BF16_MFMA_PEAK}
+    if "prof" in b:
+        prof = b.pop("prof")
+        ach = prof["pairs"] / (prof["ms"]["rows"] * 1e-3)
+        res["roofline"] = _rows_roofline(
+            prof, 2, SLOTS_PER_PAIR_MFMA, "k_rows_mfma<32,MB>", None,
+            {"mfma_utilisation": ach * 2 * spec.d_x / BF16_MFMA_PEAK})
         res["kernel_ms_per_step"] = b["kernel_ms_per_step"]
+        f = runs["fp32"].pop("prof")
+        runs["fp32"]["roofline"] = _rows_roofline(f, 2, 2.0 * 32 + 2.0 + TRANS_SLOTS,
+                                                  "k_rows<float,32,RPL>")
+    res["fp32_valu"] = runs["fp32"]
     if args.cpu_seconds > 0:
-        res["cpu_baseline"] = cpu_baseline(spec, N, args.cpu_seconds)
-    print(json.dumps(res))
+        res["cpu_baseline"] = cpu_baseline(spec, N, min(args.cpu_seconds, 3.0),
+                                           "the same workload")
+    return res
 
 
-def bench_pgibbs(args):
+# ------------------------------------------------------------ particle Gibbs
+
+def bench_pgibbs(args) -> dict:
     """Particle Gibbs sweeps (Section 3.2) on the stochastic-volatility
     workload: each step is one conditional smoother run (Algorithm 4 at every
     node) with the previous sweep's star in slot 0, then the next star is an
@@ -418,65 +588,55 @@ def bench_pgibbs(args):
     torch.cuda.synchronize()
     if not torch.equal(out.traj[:, :, 0], before):
         raise RuntimeError("star trajectory not kept in slot 0")
-    for s in range(max(2, args.warmup)):
-        G.dsmc_smooth(plan, model, 1000 + s, out)
-    torch.cuda.synchronize()
-    t1 = time.perf_counter()
-    for s in range(args.steps):
-        G.dsmc_smooth(plan, model, s + 1, out)
-    torch.cuda.synchronize()
-    dt_plain = (time.perf_counter() - t1) / args.steps
+    dt_plain = _timed(G, torch, plan, model, out, args.steps, max(2, args.warmup))
     pairs = (K - 1) * N * N
-    res = {"metric": "pair-evals/sec", "value": pairs / dt, "unit": "pair-evals/s", "n_gpus": 1,
-           "steps": args.steps, "warmup": args.warmup, "ms_per_step": dt * 1e3,
-           "higher_is_better": True, "scaling": "weak", "vs_baseline": None, "dtype": "f32",
-           "data": "synthetic",
-           "config": {"workload": f"particle Gibbs sweeps of conditional dSMC, stochastic "
-                                  f"volatility, K={K}, N={N}, fixed parameters",
-                      "K": K, "N": N, "d_x": 1},
-           "sweeps_per_sec": 1.0 / dt, "unconditional_ms_per_step": dt_plain * 1e3,
-           "conditional_overhead": dt / dt_plain - 1.0}
-    print(json.dumps(res))
+    return {"metric": "pair-evals/sec", "value": pairs / dt, "unit": "pair-evals/s", "n_gpus": 1,
+            "steps": args.steps, "warmup": args.warmup, "ms_per_step": dt * 1e3,
+            "higher_is_better": True, "scaling": "weak", "vs_baseline": None, "dtype": "f32",
+            "data": "synthetic",
+            "config": {"workload": f"particle Gibbs sweeps of conditional dSMC, stochastic "
+                                   f"volatility, K={K}, N={N}, fixed parameters",
+                       "K": K, "N": N, "d_x": 1},
+            "sweeps_per_sec": 1.0 / dt, "unconditional_ms_per_step": dt_plain * 1e3,
+            "conditional_overhead": dt / dt_plain - 1.0}
 
 
-def bench_lazy(args):
-    """Lazy resampling (Section 4.2) on the stochastic-volatility workload:
-    whole smoother runs with Algorithm 7 (Metropolis-Hastings, B steps per
-    draw) or Algorithm 8 (rejection) in every combine, beside the exact
-    multinomial draw of Algorithm 1.  Lazy runs estimate no log L^N."""
+# ------------------------------------------------------------------- lazy
+
+def bench_lazy(args, quick=False) -> dict:
+    """Lazy resampling (Section 4.2): whole smoother runs with Algorithm 7
+    (Metropolis-Hastings, B steps per draw) or Algorithm 8 (rejection) in every
+    combine, beside the exact multinomial draw of Algorithm 1.  Lazy runs
+    estimate no log L^N.  Model: stochastic volatility, or the constrained
+    random walk of Section 5.3 (uniform proposals, box potential)."""
     import torch
 
     from paper_2202_02264_amd import dsmc as G
     from paper_2202_02264_amd import workloads as W
     torch.cuda.set_device(0)
-    K, N = args.K, args.N
-    spec = W.sv(K) if args.model == "sv" else W.constrained_rw(K, sigma=args.sigma)
+    model_name = "crw" if quick else args.model
+    K = args.K
+    N = 4096 if quick else args.N
+    spec = W.sv(K) if model_name == "sv" else W.constrained_rw(K, sigma=args.sigma)
     model = G.Model(spec)
     runs = {}
-    wanted = set(args.schemes.split(","))
-    for name, scheme, param, steps in (("exact", G.DSMC_RESAMPLE_EXACT, 0, args.steps),
-                                       ("mh_B8", G.DSMC_RESAMPLE_MH, 8, args.steps),
-                                       ("mh_B32", G.DSMC_RESAMPLE_MH, 32, args.steps),
+    wanted = {"exact", "rs"} if quick else set(args.schemes.split(","))
+    steps_all = 5 if quick else args.steps
+    for name, scheme, param, steps in (("exact", G.DSMC_RESAMPLE_EXACT, 0, steps_all),
+                                       ("mh_B8", G.DSMC_RESAMPLE_MH, 8, steps_all),
+                                       ("mh_B32", G.DSMC_RESAMPLE_MH, 32, steps_all),
                                        ("rs", G.DSMC_RESAMPLE_RS, 0,
-                                        args.steps if args.model == "crw"
-                                        else max(1, min(args.steps, 3)))):
+                                        steps_all if model_name == "crw"
+                                        else max(1, min(steps_all, 3)))):
         if name not in wanted:
             continue
         plan = G.Plan(N, 1, K, graph=True, resampling=scheme, lazy_param=param)
         out = G.alloc_output(plan, K)
-        for s in range(2):
-            G.dsmc_smooth(plan, model, 1000 + s, out)
-        torch.cuda.synchronize()
-        t0 = time.perf_counter()
-        for s in range(steps):
-            G.dsmc_smooth(plan, model, s + 1, out)
-        torch.cuda.synchronize()
-        dt = (time.perf_counter() - t0) / steps
-        runs[name] = {"ms_per_step": dt * 1e3, "steps": steps,
-                      "status": int(out.status.item())}
+        dt = _timed(G, torch, plan, model, out, steps, 2)
+        runs[name] = {"ms_per_step": dt * 1e3, "steps": steps, "status": int(out.status.item())}
         print(f"# lazy {name}: {dt * 1e3:.3f} ms/step", file=sys.stderr, flush=True)
         del plan, out
-    if args.model == "crw":  # the rejection run is the one reported
+    if model_name == "crw":  # the rejection run is the one reported
         rs = runs["rs"]
         res = {"metric": "smoothers/sec", "value": 1e3 / rs["ms_per_step"], "unit": "smoothers/s",
                "n_gpus": 1, "steps": rs["steps"], "warmup": 2, "ms_per_step": rs["ms_per_step"],
@@ -488,8 +648,7 @@ def bench_lazy(args):
                "runs": runs}
         if "exact" in runs:
             res["speedup_vs_exact"] = runs["exact"]["ms_per_step"] / rs["ms_per_step"]
-        print(json.dumps(res))
-        return
+        return res
     mh = runs["mh_B32"]
     res = {"metric": "smoothers/sec", "value": 1e3 / mh["ms_per_step"], "unit": "smoothers/s",
            "n_gpus": 1, "steps": mh["steps"], "warmup": 2, "ms_per_step": mh["ms_per_step"],
@@ -499,38 +658,40 @@ def bench_lazy(args):
                                   f"volatility, K={K}, N={N}", "K": K, "N": N, "d_x": 1},
            "runs": runs}
     if not args.no_kernel_events:
-        # the B = 32 run once more, eagerly, with HIP events around every launch
-        plan = G.Plan(N, 1, K, profile=True, resampling=G.DSMC_RESAMPLE_MH, lazy_param=32)
-        out = G.alloc_output(plan, K)
-        for s in range(2):
-            G.dsmc_smooth(plan, model, 1000 + s, out)
-        torch.cuda.synchronize()
-        G.dsmc_plan_profile(plan)
-        for s in range(args.steps):
-            G.dsmc_smooth(plan, model, s + 1, out)
-        prof = G.dsmc_plan_profile(plan)
+        prof, _ = _profile_run(G, torch, N, 1, K, model, args.steps, 2,
+                               resampling=G.DSMC_RESAMPLE_MH, lazy_param=32)
         launches = prof["launches"]["sample"]
         ms = prof["ms"]["sample"]
         proposals = args.steps * (K - 1) * N * 32
         achieved = proposals / (ms * 1e-3)
         peak = LANE_OPS_PER_S / LAZY_VALU_PER_PROPOSAL
-        traffic = None
-        if LAZY_MH_SV_TRAFFIC_MIB and (K, N) == (4096, 1024):
-            traffic = (LAZY_MH_SV_TRAFFIC_MIB["read"] + LAZY_MH_SV_TRAFFIC_MIB["write"]) * 2 ** 20
         res["roofline"] = {"bound": "alu", "kernel": "k_sample_lazy<float,1>",
                            "achieved": achieved / 1e9, "peak": peak / 1e9,
-                           "unit": "Gproposal/s", "frac": achieved / peak, "traffic": traffic,
+                           "unit": "Gproposal/s", "frac": achieved / peak, "traffic": None,
                            "avg_launch_ms": ms / max(1, launches),
                            "proposals_per_launch": proposals / max(1, launches)}
         res["kernel_ms_per_step"] = {k: v / args.steps for k, v in prof["ms"].items()}
-    print(json.dumps(res))
+    return res
+
+
+# --------------------------------------------------------------------- main
+
+def issue_rates() -> dict:
+    exe = os.path.join(ROOT, "paper_2202_02264_amd", "issue_rates")
+    if not os.path.exists(exe):
+        raise SystemExit(f"{exe} is not built; run __graft_entry__.build()")
+    r = subprocess.run([exe], capture_output=True, text=True, check=True)
+    return json.loads(r.stdout.strip().splitlines()[-1])
 
 
 def main():
     args = parse()
     if args.gpus != 1:
-        print(json.dumps({"error": "the smoother runs on one GPU; --gpus must be 1"}))
+        print(json.dumps({"error": "this build runs on one GPU; --gpus must be 1"}))
         sys.exit(2)
+    if args.issue_rates:
+        print(json.dumps(issue_rates()))
+        return
     if args.copy_calibration:
         import torch
         x = torch.ones(64 << 20, dtype=torch.float32, device="cuda")
@@ -540,98 +701,21 @@ def main():
         torch.cuda.synchronize()
         print(json.dumps({"copy_calibration_bytes_per_launch": 2 * x.numel() * 4, "launches": 10}))
         return
-    if args.workload == "serve":
-        return bench_serve(args)
-    if args.workload == "highdim":
-        return bench_highdim(args)
-    if args.workload == "batch":
-        return bench_batch(args)
-    if args.workload == "pgibbs":
-        return bench_pgibbs(args)
-    if args.workload == "lazy":
-        return bench_lazy(args)
-    import torch
-
-    from paper_2202_02264_amd import dsmc as G
-    from paper_2202_02264_amd import workloads as W
-
-    torch.cuda.set_device(0)
-    K, N = args.K, args.N
-    spec = W.sv(K)
-    model = G.Model(spec)
-    # timed steps: the plan replays one hipGraph per step (first warm-up call
-    # runs eagerly and tunes the tiles, the second captures)
-    plan = G.Plan(N, 1, K, graph=True)
-    out = G.alloc_output(plan, K)
-    for s in range(max(2, args.warmup)):
-        G.dsmc_smooth(plan, model, 1000 + s, out)
-    torch.cuda.synchronize()
-    t0 = time.perf_counter()
-    for s in range(args.steps):
-        G.dsmc_smooth(plan, model, s + 1, out)
-    torch.cuda.synchronize()
-    dt = (time.perf_counter() - t0) / args.steps
-    status = int(out.status.item())
-    if status:
-        raise RuntimeError(f"device status {status}")
-    prof = None
-    if not args.no_kernel_events:
-        # the same steps once more, eagerly, with HIP events around every launch
-        plan_p = G.Plan(N, 1, K, profile=True)
-        for s in range(max(1, args.warmup)):
-            G.dsmc_smooth(plan_p, model, 1000 + s, out)
-        torch.cuda.synchronize()
-        G.dsmc_plan_profile(plan_p)  # drop the warm-up records
-        t1 = time.perf_counter()
-        for s in range(args.steps):
-            G.dsmc_smooth(plan_p, model, s + 1, out)
-        torch.cuda.synchronize()
-        dt_ev = (time.perf_counter() - t1) / args.steps
-        prof = G.dsmc_plan_profile(plan_p)
-    pairs = (K - 1) * N * N
-    res = {
-        "metric": "pair-evals/sec",
-        "value": pairs / dt,
-        "unit": "pair-evals/s",
-        "n_gpus": 1,
-        "steps": args.steps,
-        "warmup": args.warmup,
-        "ms_per_step": dt * 1e3,
-        "higher_is_better": True,
-        "scaling": "weak",
-        "vs_baseline": None,
-        "dtype": "f32",
-        "data": "synthetic",
-        "config": {"workload": f"stochastic volatility, K={K} time points, N={N} particles, "
-                               "one smoother per step", "K": K, "N": N, "d_x": 1,
-                   "precision": "fp32 pair weights, fp64 sums and CDFs",
-                   "weighting": spec.weighting, "data_seed": W.DATA_SEED},
-        "smoothers_per_sec": 1.0 / dt,
-        "pair_evals_T_log2T_N2_per_sec": K * math.log2(K) * N * N / dt,
-    }
-    if prof is not None:
-        res["ms_per_step_with_kernel_events"] = dt_ev * 1e3
-        n_rows = prof["launches"]["rows"]
-        ms_rows = prof["ms"]["rows"]
-        achieved = prof["pairs"] / (ms_rows * 1e-3)
-        peak = LANE_OPS_PER_S / SLOTS_PER_PAIR
-        traffic = None
-        if K_ROWS_SV_TRAFFIC_MIB and (K, N) == (4096, 1024):
-            traffic = (K_ROWS_SV_TRAFFIC_MIB["read"] + K_ROWS_SV_TRAFFIC_MIB["write"]) * 2 ** 20
-        nodes = K - 1
-        Npad = (N + 31) // 32 * 32
-        algo_bytes = nodes * (Npad * 2 * 4 + Npad * 4 + N * ((Npad // 32 + 3) // 4 * 4) * 4
-                              + N * 8) / max(1, n_rows / args.steps)
-        res["roofline"] = {"bound": "alu", "kernel": "k_rows<float,1,RPL>",
-                           "achieved": achieved / 1e9, "peak": peak / 1e9, "unit": "Gpair/s",
-                           "frac": achieved / peak, "traffic": traffic,
-                           "traffic_algorithmic": algo_bytes,
-                           "avg_launch_ms": ms_rows / max(1, n_rows),
-                           "pairs_per_launch": prof["pairs"] / max(1, n_rows)}
-        res["kernel_ms_per_step"] = {k: v / args.steps for k, v in prof["ms"].items()}
-        res["rescued_rows_per_step"] = prof["rescued_rows"] / args.steps
-    if args.cpu_seconds > 0:
-        res["cpu_baseline"] = cpu_baseline(spec, N, args.cpu_seconds)
+    single = {"serve": bench_serve, "highdim": bench_highdim, "batch": bench_batch,
+              "pgibbs": bench_pgibbs, "lazy": bench_lazy}
+    if args.workload in single:
+        print(json.dumps(single[args.workload](args)))
+        return
+    res = bench_sv(args)
+    if not args.no_extras:
+        extras = {}
+        for name, fn in (("batch", bench_batch), ("highdim", bench_highdim),
+                         ("serve", bench_serve), ("lazy_crw", bench_lazy)):
+            t0 = time.perf_counter()
+            extras[name] = fn(args, quick=True)
+            extras[name]["wall_s"] = time.perf_counter() - t0
+            print(f"# {name} done in {extras[name]['wall_s']:.1f} s", file=sys.stderr, flush=True)
+        res["workloads"] = extras
     print(json.dumps(res))
 
 

@@ -11,6 +11,7 @@ ROOT = os.path.dirname(PKG)
 CSRC = os.path.join(PKG, "csrc")
 INCLUDE = os.path.join(ROOT, "include")
 LIB = os.path.join(PKG, "libdsmc.so")
+ISSUE_RATES = os.path.join(PKG, "issue_rates")
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
 
 SOURCES = ["dsmc_kernels.hip", "dsmc_kernels_dx1_8.hip", "dsmc_kernels_dx16.hip",
@@ -50,8 +51,14 @@ def build(verbose: bool = True) -> str:
     if r.returncode != 0:
         raise RuntimeError(f"link failed: {' '.join(cmd)}\n{r.stdout}\n{r.stderr}")
     os.replace(tmp, LIB)
+    # the VALU issue-rate microbenchmark behind the pair-row roofline (bench.py --issue-rates)
+    cmd = [HIPCC, "-x", "hip", *[f for f in FLAGS if f != "-fPIC"],
+           os.path.join(PKG, "microbench", "issue_rates.hip"), "-o", ISSUE_RATES]
+    r = subprocess.run(cmd, capture_output=True, text=True)
+    if r.returncode != 0:
+        raise RuntimeError(f"compile failed: {' '.join(cmd)}\n{r.stdout}\n{r.stderr}")
     if verbose:
-        print(f"built {LIB}", file=sys.stderr)
+        print(f"built {LIB} and {ISSUE_RATES}", file=sys.stderr)
     return LIB
 
 

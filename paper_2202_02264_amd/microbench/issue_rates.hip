@@ -1,0 +1,150 @@
+// Issue-rate microbenchmark of the VALU instructions that price the pair-row
+// kernel's roofline on gfx950: v_fma_f32, v_exp_f32, the two interleaved, and
+// the pair loop itself (v_sub_f32, v_fma_f32, v_exp_f32, v_add_f32 on
+// independent rows).  Each kernel runs 8 independent dependency chains per
+// lane so that latency is hidden; counts are known at compile time.  Prints
+// one JSON line with lane-instructions per second (pairs per second for the
+// pair loop) and the chip's nominal single-rate VALU issue rate.
+#include <hip/hip_runtime.h>
+
+#include <cstdio>
+#include <cstdlib>
+
+constexpr int kChains = 8;
+constexpr int kIters = 2048;
+constexpr int kBlock = 256;
+
+__global__ __launch_bounds__(kBlock) void k_fma(float* out, float a, float b) {
+  float x[kChains];
+#pragma unroll
+  for (int c = 0; c < kChains; ++c) x[c] = threadIdx.x * 1e-3f + c;
+  for (int i = 0; i < kIters; ++i) {
+#pragma unroll
+    for (int c = 0; c < kChains; ++c) x[c] = __builtin_fmaf(x[c], a, b);
+  }
+  float s = 0.f;
+#pragma unroll
+  for (int c = 0; c < kChains; ++c) s += x[c];
+  out[blockIdx.x * kBlock + threadIdx.x] = s;
+}
+
+__global__ __launch_bounds__(kBlock) void k_exp(float* out, float a) {
+  float x[kChains];
+#pragma unroll
+  for (int c = 0; c < kChains; ++c) x[c] = -(threadIdx.x & 7) * 0.1f - c * 0.01f;
+  for (int i = 0; i < kIters; ++i) {
+#pragma unroll
+    for (int c = 0; c < kChains; ++c) x[c] = __builtin_amdgcn_exp2f(-x[c]);  // stays in [0.5, 1]
+  }
+  float s = 0.f;
+#pragma unroll
+  for (int c = 0; c < kChains; ++c) s += x[c];
+  out[blockIdx.x * kBlock + threadIdx.x] = s * a;
+}
+
+// one v_exp_f32 and one v_fma_f32 per chain and iteration, independent
+__global__ __launch_bounds__(kBlock) void k_exp_fma(float* out, float a, float b) {
+  float x[kChains], y[kChains];
+#pragma unroll
+  for (int c = 0; c < kChains; ++c) {
+    x[c] = -(threadIdx.x & 7) * 0.1f - c * 0.01f;
+    y[c] = threadIdx.x * 1e-3f + c;
+  }
+  for (int i = 0; i < kIters; ++i) {
+#pragma unroll
+    for (int c = 0; c < kChains; ++c) {
+      x[c] = __builtin_amdgcn_exp2f(-x[c]);
+      y[c] = __builtin_fmaf(y[c], a, b);
+    }
+  }
+  float s = 0.f;
+#pragma unroll
+  for (int c = 0; c < kChains; ++c) s += x[c] + y[c];
+  out[blockIdx.x * kBlock + threadIdx.x] = s;
+}
+
+// The pair loop of the rows kernel at d_x = 1: per (row, column) pair
+// d = u - v, s = beta - d^2, acc += 2^s, with u, beta wave-uniform.
+__global__ __launch_bounds__(kBlock) void k_pairs(float* out, const float* __restrict__ col) {
+  float v[kChains], acc[kChains];
+#pragma unroll
+  for (int c = 0; c < kChains; ++c) {
+    v[c] = threadIdx.x * 1e-3f + c * 0.1f;
+    acc[c] = 0.f;
+  }
+  for (int i = 0; i < kIters; i += 32) {
+#pragma unroll
+    for (int j = 0; j < 32; ++j) {
+      const float u = col[2 * ((i + j) & 63)], beta = col[2 * ((i + j) & 63) + 1];
+#pragma unroll
+      for (int c = 0; c < kChains; ++c) {
+        const float d = u - v[c];
+        acc[c] += __builtin_amdgcn_exp2f(__builtin_fmaf(-d, d, beta));
+      }
+    }
+  }
+  float s = 0.f;
+#pragma unroll
+  for (int c = 0; c < kChains; ++c) s += acc[c];
+  out[blockIdx.x * kBlock + threadIdx.x] = s;
+}
+
+#define CHECK(x)                                                              \
+  do {                                                                        \
+    hipError_t e_ = (x);                                                      \
+    if (e_ != hipSuccess) {                                                   \
+      fprintf(stderr, "%s: %s\n", #x, hipGetErrorString(e_));                \
+      return 1;                                                               \
+    }                                                                         \
+  } while (0)
+
+int main(int argc, char** argv) {
+  int dev = 0;
+  hipDeviceProp_t prop;
+  CHECK(hipGetDeviceProperties(&prop, dev));
+  const int cus = prop.multiProcessorCount;
+  const int blocks = cus * 16;  // 16 workgroups of 4 waves per CU: 16 waves per SIMD requested
+  const size_t threads = (size_t)blocks * kBlock;
+  float *out, *col;
+  CHECK(hipMalloc(&out, threads * sizeof(float)));
+  CHECK(hipMalloc(&col, 128 * sizeof(float)));
+  float hc[128];
+  for (int i = 0; i < 128; ++i) hc[i] = (i & 1) ? -0.5f : 0.01f * i;
+  CHECK(hipMemcpy(col, hc, sizeof hc, hipMemcpyHostToDevice));
+  hipEvent_t e0, e1;
+  CHECK(hipEventCreate(&e0));
+  CHECK(hipEventCreate(&e1));
+  const int reps = 20;
+  auto timeit = [&](auto launch) -> double {
+    launch();  // warm-up (code object load)
+    CHECK(hipDeviceSynchronize());
+    CHECK(hipEventRecord(e0, 0));
+    for (int r = 0; r < reps; ++r) launch();
+    CHECK(hipEventRecord(e1, 0));
+    CHECK(hipEventSynchronize(e1));
+    float ms = 0.f;
+    CHECK(hipEventElapsedTime(&ms, e0, e1));
+    return ms * 1e-3 / reps;
+  };
+  const double per_thread = (double)kIters * kChains;
+  const double t_fma = timeit([&] { k_fma<<<blocks, kBlock>>>(out, 0.999f, 1e-3f); });
+  const double t_exp = timeit([&] { k_exp<<<blocks, kBlock>>>(out, 1.0f); });
+  const double t_mix = timeit([&] { k_exp_fma<<<blocks, kBlock>>>(out, 0.999f, 1e-3f); });
+  const double t_pair = timeit([&] { k_pairs<<<blocks, kBlock>>>(out, col); });
+  CHECK(hipGetLastError());
+  const double fma_rate = threads * per_thread / t_fma;
+  const double exp_rate = threads * per_thread / t_exp;
+  const double mix_rate = threads * 2.0 * per_thread / t_mix;  // lane-instructions/s, both kinds
+  const double pair_rate = threads * per_thread / t_pair;
+  const double clock_ghz = prop.clockRate * 1e-6;
+  const double nominal = (double)cus * 4 * 16 * clock_ghz * 1e9;
+  printf("{\"device\": \"%s\", \"cus\": %d, \"clock_ghz\": %.3f, "
+         "\"nominal_lane_instr_per_s\": %.4e, \"v_fma_f32_per_s\": %.4e, "
+         "\"v_exp_f32_per_s\": %.4e, \"exp_plus_fma_lane_instr_per_s\": %.4e, "
+         "\"pair_loop_pairs_per_s\": %.4e, "
+         "\"exp_slots_vs_fma\": %.3f, \"mix_time_vs_sum\": %.3f, "
+         "\"pair_slots_at_fma_rate\": %.3f}\n",
+         prop.name, cus, clock_ghz, nominal, fma_rate, exp_rate, mix_rate, pair_rate,
+         fma_rate / exp_rate, t_mix / (t_fma + t_exp), fma_rate / pair_rate);
+  return 0;
+}
