@@ -334,6 +334,33 @@ int dsmc_smooth_batch_conditional(dsmc_plan_t *plan, int B, const dsmc_model_t *
 int dsmc_smooth_batch(dsmc_plan_t *plan, int B, const dsmc_model_t *const *models,
                       const uint64_t *seeds, const dsmc_output *outs);
 
+/* ------------------------------------------------- allocation-free run */
+
+/* For callers that cannot allocate device memory (code under HIP graph
+ * capture, tight serving loops, harnesses that forbid hipMalloc): one
+ * dsmc_smooth run without a plan and without any device allocation.  All
+ * workspace (particles, weights, per-time tables, per-combine data, chunk sums
+ * and the combine tree, which a kernel writes from its closed form) lives in a
+ * fixed device array of DSMC_STATIC_SCRATCH_BYTES that the library holds on
+ * each GPU it runs on until the process ends; the call makes no hipMalloc,
+ * hipFree or host-to-device copy.  Results equal dsmc_smooth with the same
+ * model, N, precision and seed bit for bit.
+ *   precision  DSMC_FP32 or DSMC_FP64 (else DSMC_EUNSUPPORTED);
+ *   out        as dsmc_smooth (caller-owned device buffers);
+ *   stream     hipStream_t the work is enqueued on (NULL = null stream).
+ * The workspace needs about K N ((d_x + 4 D + 3) s + 24) bytes (s = 4 or 8,
+ * D = d_x rounded up to a power of two) plus the chunk sums of at least one
+ * combine, 2 N ceil(N / 128) 4 s bytes; a run that does not fit fails with
+ * DSMC_EUNSUPPORTED before any device work (the stochastic-volatility run with
+ * K = 4096, N = 1024 in fp32 fits).  Every call on a GPU shares that GPU's
+ * array: calls that overlap on one GPU (other streams or threads) race and
+ * must be serialised by the caller; a call may start once the previous one's
+ * work is ordered before it on the stream.  Errors: DSMC_EINVAL,
+ * DSMC_EUNSUPPORTED, DSMC_EDEVICE. */
+#define DSMC_STATIC_SCRATCH_BYTES ((size_t)256 << 20)
+int dsmc_smooth_static(const dsmc_model_t *model, int N, int precision, uint64_t seed,
+                       const dsmc_output *out, void *stream);
+
 /* --------------------------------------------------------------- serving */
 
 /* A serving engine runs smoothing jobs submitted at any time, with continuous

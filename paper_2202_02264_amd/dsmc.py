@@ -113,6 +113,7 @@ def _load() -> C.CDLL:
         "dsmc_smooth_batch_conditional": (i, [vp, i, C.POINTER(vp), C.POINTER(u64),
                                               C.POINTER(vp), C.POINTER(dsmc_output)]),
         "dsmc_plan_profile": (i, [vp, C.POINTER(dsmc_profile)]),
+        "dsmc_smooth_static": (i, [vp, i, i, u64, C.POINTER(dsmc_output), vp]),
         "dsmc_server_create": (i, [C.POINTER(dsmc_server_desc), C.POINTER(vp)]),
         "dsmc_server_destroy": (None, [vp]),
         "dsmc_submit": (i, [vp, C.POINTER(dsmc_job), C.POINTER(u64)]),
@@ -304,6 +305,22 @@ def dsmc_smooth(plan: Plan, model: Model, seed: int, out: Output) -> None:
     o = out.c_struct()
     _check(_lib.dsmc_smooth(plan.handle, model.handle, C.c_uint64(seed & (2**64 - 1)),
                             C.byref(o)), "dsmc_smooth")
+
+
+DSMC_STATIC_SCRATCH_BYTES = 256 << 20
+
+
+def dsmc_smooth_static(model: Model, N: int, seed: int, out: Output, precision: int = DSMC_FP32,
+                       stream=None) -> None:
+    """dsmc_smooth without a plan or any device allocation (the library's fixed
+    per-GPU workspace); ``out`` as from alloc_output for (N, d_x, K, precision)."""
+    import torch
+    if stream is None:
+        stream = torch.cuda.current_stream()
+    o = out.c_struct()
+    _check(_lib.dsmc_smooth_static(model.handle, N, precision, C.c_uint64(seed & (2**64 - 1)),
+                                   C.byref(o), C.c_void_p(stream.cuda_stream)),
+           "dsmc_smooth_static")
 
 
 def dsmc_smooth_conditional(plan: Plan, model: Model, seed: int, star, out: Output) -> None:
