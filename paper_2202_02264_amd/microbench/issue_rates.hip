@@ -89,6 +89,79 @@ __global__ __launch_bounds__(kBlock) void k_pairs(float* out, const float* __res
   out[blockIdx.x * kBlock + threadIdx.x] = s;
 }
 
+// Philox4x64-10 blocks (the leaf kernel's generator) per second: kChains
+// independent blocks per lane and iteration, their words folded into an
+// accumulator.
+__device__ __forceinline__ void philox_block(uint64_t& c0, uint64_t& c1, uint64_t& c2,
+                                             uint64_t& c3, uint64_t k0, uint64_t k1) {
+#pragma unroll
+  for (int r = 0; r < 10; ++r) {
+    if (r) {
+      k0 += 0x9E3779B97F4A7C15ull;
+      k1 += 0xBB67AE8584CAA73Bull;
+    }
+    const uint64_t hi0 = __umul64hi(0xD2E7470EE14C6C93ull, c0), lo0 = 0xD2E7470EE14C6C93ull * c0;
+    const uint64_t hi1 = __umul64hi(0xCA5A826395121157ull, c2), lo1 = 0xCA5A826395121157ull * c2;
+    const uint64_t n0 = hi1 ^ c1 ^ k0, n2 = hi0 ^ c3 ^ k1;
+    c0 = n0;
+    c1 = lo1;
+    c2 = n2;
+    c3 = lo0;
+  }
+}
+
+constexpr int kPhiloxIters = 64;
+
+__global__ __launch_bounds__(kBlock) void k_philox(uint64_t* out, uint64_t seed) {
+  uint64_t acc = 0;
+  const uint64_t n = blockIdx.x * kBlock + threadIdx.x;
+  for (int i = 0; i < kPhiloxIters; ++i) {
+#pragma unroll
+    for (int c = 0; c < kChains; ++c) {
+      uint64_t c0 = n, c1 = (uint64_t)i, c2 = 2, c3 = (uint64_t)c;
+      philox_block(c0, c1, c2, c3, seed, 0x64534D43ull);
+      acc ^= c0 ^ c1 ^ c2 ^ c3;
+    }
+  }
+  out[n] = acc;
+}
+
+// Box-Muller pairs per second: fp64 (log, sqrt, cos, sin in double, as the
+// leaf kernel of fp64 plans) and fp32 (the hardware v_log_f32, v_sqrt_f32 and
+// v_cos_f32 / v_sin_f32, which take revolutions).
+__global__ __launch_bounds__(kBlock) void k_box_muller64(double* out) {
+  double acc = 0.0;
+  const uint64_t n = blockIdx.x * kBlock + threadIdx.x;
+  for (int i = 0; i < kPhiloxIters; ++i) {
+#pragma unroll
+    for (int c = 0; c < kChains; ++c) {
+      const uint64_t wa = (n * 0x9E3779B97F4A7C15ull) ^ (uint64_t)(i * 8 + c) * 0xBB67AE8584CAA73Bull;
+      const uint64_t wb = wa * 0xD2E7470EE14C6C93ull;
+      const double ua = (double)((wa >> 11) + 1ull) * 0x1p-53, ub = (double)(wb >> 11) * 0x1p-53;
+      const double rad = sqrt(-2.0 * log(ua)), th = 2.0 * 3.141592653589793 * ub;
+      acc += rad * cos(th) + rad * sin(th);
+    }
+  }
+  out[n] = acc;
+}
+
+__global__ __launch_bounds__(kBlock) void k_box_muller32(double* out) {
+  float acc = 0.0f;
+  const uint64_t n = blockIdx.x * kBlock + threadIdx.x;
+  for (int i = 0; i < kPhiloxIters; ++i) {
+#pragma unroll
+    for (int c = 0; c < kChains; ++c) {
+      const uint64_t wa = (n * 0x9E3779B97F4A7C15ull) ^ (uint64_t)(i * 8 + c) * 0xBB67AE8584CAA73Bull;
+      const uint64_t wb = wa * 0xD2E7470EE14C6C93ull;
+      const float ua = (float)((double)((wa >> 11) + 1ull) * 0x1p-53);
+      const float ub = (float)((double)(wb >> 11) * 0x1p-53);
+      const float rad = __builtin_sqrtf(-1.3862943611198906f * __builtin_amdgcn_logf(ua));
+      acc += rad * __builtin_amdgcn_cosf(ub) + rad * __builtin_amdgcn_sinf(ub);
+    }
+  }
+  out[n] = acc;
+}
+
 #define CHECK(x)                                                              \
   do {                                                                        \
     hipError_t e_ = (x);                                                      \
@@ -106,7 +179,9 @@ int main(int argc, char** argv) {
   const int blocks = cus * 16;  // 16 workgroups of 4 waves per CU: 16 waves per SIMD requested
   const size_t threads = (size_t)blocks * kBlock;
   float *out, *col;
+  uint64_t* out64;
   CHECK(hipMalloc(&out, threads * sizeof(float)));
+  CHECK(hipMalloc(&out64, threads * sizeof(uint64_t)));
   CHECK(hipMalloc(&col, 128 * sizeof(float)));
   float hc[128];
   for (int i = 0; i < 128; ++i) hc[i] = (i & 1) ? -0.5f : 0.01f * i;
@@ -131,7 +206,14 @@ int main(int argc, char** argv) {
   const double t_exp = timeit([&] { k_exp<<<blocks, kBlock>>>(out, 1.0f); });
   const double t_mix = timeit([&] { k_exp_fma<<<blocks, kBlock>>>(out, 0.999f, 1e-3f); });
   const double t_pair = timeit([&] { k_pairs<<<blocks, kBlock>>>(out, col); });
+  const double t_philox = timeit([&] { k_philox<<<blocks, kBlock>>>(out64, 12345ull); });
   CHECK(hipGetLastError());
+  const double philox_rate = threads * (double)kPhiloxIters * kChains / t_philox;
+  const double t_bm64 = timeit([&] { k_box_muller64<<<blocks, kBlock>>>((double*)out64); });
+  const double t_bm32 = timeit([&] { k_box_muller32<<<blocks, kBlock>>>((double*)out64); });
+  CHECK(hipGetLastError());
+  const double bm64_rate = threads * (double)kPhiloxIters * kChains / t_bm64;
+  const double bm32_rate = threads * (double)kPhiloxIters * kChains / t_bm32;
   const double fma_rate = threads * per_thread / t_fma;
   const double exp_rate = threads * per_thread / t_exp;
   const double mix_rate = threads * 2.0 * per_thread / t_mix;  // lane-instructions/s, both kinds
@@ -143,8 +225,11 @@ int main(int argc, char** argv) {
          "\"v_exp_f32_per_s\": %.4e, \"exp_plus_fma_lane_instr_per_s\": %.4e, "
          "\"pair_loop_pairs_per_s\": %.4e, "
          "\"exp_slots_vs_fma\": %.3f, \"mix_time_vs_sum\": %.3f, "
-         "\"pair_slots_at_fma_rate\": %.3f}\n",
+         "\"pair_slots_at_fma_rate\": %.3f, \"philox4x64_10_blocks_per_s\": %.4e, "
+         "\"philox_block_slots_at_fma_rate\": %.1f, \"box_muller_f64_pairs_per_s\": %.4e, "
+         "\"box_muller_f32_pairs_per_s\": %.4e}\n",
          prop.name, cus, clock_ghz, nominal, fma_rate, exp_rate, mix_rate, pair_rate,
-         fma_rate / exp_rate, t_mix / (t_fma + t_exp), fma_rate / pair_rate);
+         fma_rate / exp_rate, t_mix / (t_fma + t_exp), fma_rate / pair_rate, philox_rate,
+         fma_rate / philox_rate, bm64_rate, bm32_rate);
   return 0;
 }
