@@ -189,16 +189,40 @@ int dsmc_model_create(const dsmc_model_desc *desc, dsmc_model_t **out);
 void dsmc_model_destroy(dsmc_model_t *model);
 int dsmc_model_K(const dsmc_model_t *model);
 
+/* Parallel-in-time Gaussian proposals (Section 4.1, Algorithm 5) for a
+ * linear-Gaussian model (obs_kind LINEAR_GAUSSIAN, Gaussian proposals): the
+ * Kalman filter and the RTS smoother run on the device as associative scans
+ * over the K time points (span O(log K)), in fp64, and the smoothing marginals
+ * N(m_t, P_t) replace the model's proposals q_t (q_mean, q_chol and the derived
+ * inverse factors and log normalisers).  For a linear-Gaussian model the
+ * linearisation of Algorithm 5 is exact, so one pass is its fixed point.
+ * Enqueued on `stream` (hipStream_t, NULL = null stream); smoother calls
+ * ordered after it on the same stream use the new proposals, so the model
+ * must not be in use by other streams meanwhile.  The model keeps a workspace
+ * of about K (5 d_x^2 + 3 d_x) 8 bytes, allocated on the first call.
+ * Errors: DSMC_EINVAL (null model), DSMC_EUNSUPPORTED (other model kinds,
+ * d_y > DSMC_MAX_DX), DSMC_ENOMEM, DSMC_EDEVICE. */
+int dsmc_model_gaussian_proposals(dsmc_model_t *model, void *stream);
+
+/* Copy the model's current proposals to host memory (synchronises the device):
+ * q_mean [K][d_x], q_chol [K][d_x][d_x].  Errors: DSMC_EINVAL, DSMC_EDEVICE. */
+int dsmc_model_read_proposals(const dsmc_model_t *model, double *q_mean, double *q_chol);
+
 /* ----------------------------------------------------------------- plan */
 
 enum { DSMC_FP32 = 0, /* particles and pair weights in fp32, sums and CDFs in fp64 */
        DSMC_FP64 = 1, /* everything in fp64 */
        DSMC_BF16 = 2  /* d_x >= 9 only (padded to 16 or 32): as DSMC_FP32, except that the
-                         whitened boundary coordinates u, v of Algorithm 1's pair weight
-                         are rounded to bf16 and the quadratic form ||u - v||^2 is
-                         formed as ||u||^2 + ||v||^2 - 2 u.v with the dot products on
-                         bf16 matrix cores (fp32 accumulation); results differ from the
-                         fp64 oracle by the bf16 rounding of u and v */ };
+                         quadratic form ||u - v||^2 of Algorithm 1's pair weight (whitened
+                         boundary coordinates u, v) is formed as ||u||^2 + ||v||^2 - 2 u.v
+                         with fp32 norms and the dot products on bf16 matrix cores (fp32
+                         accumulation) from split operands: each of 2u and v is a bf16
+                         number plus a bf16 remainder and three products are summed, so
+                         u.v carries about 16 significant bits; results differ from the
+                         fp64 oracle by that rounding and the cancellation of the
+                         expanded form.  The sampling kernel recomputes a chunk's weights
+                         in the direct form and rescales its search to the stored chunk
+                         sum, so every draw stays inside its chunk. */ };
 
 #define DSMC_PLAN_PROFILE 1  /* record HIP events around every kernel launch */
 #define DSMC_PLAN_AUTOTUNE 2 /* on first use of each level size (combines per launch), run the
@@ -264,7 +288,8 @@ typedef struct dsmc_plan_impl dsmc_plan_t;
  * max_total_K * N * ((5 d_x + 2) s + 36) bytes for particles, weights, ancestry
  * and per-combine data, plus at most 2 GiB of per-level chunk sums
  * (2 N * N * s / 32 per combine of a launch), s = sizeof the real type;
- * DSMC_BF16 adds max_total_K * N * (8 d_x + 16) bytes of bf16 operands.
+ * DSMC_BF16 adds max_total_K * N * (16 D + 16) bytes of bf16 operands (D = d_x padded
+ * to 16 or 32).
  * Errors: DSMC_EINVAL, DSMC_EUNSUPPORTED (also DSMC_BF16 with d_x <= 8),
  * DSMC_ENOMEM. */
 /* Number of GPUs the library's HIP runtime sees (*count, 0 on error).

@@ -16,7 +16,8 @@ HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
 
 SOURCES = ["dsmc_kernels.hip", "dsmc_kernels_dx1_8.hip", "dsmc_kernels_dx16.hip",
            "dsmc_kernels_dx32_f32.hip", "dsmc_kernels_dx32_f64.hip", "dsmc_api.cpp",
-           "dsmc_server.cpp", "dsmc_static.cpp"]
+           "dsmc_server.cpp", "dsmc_static.cpp",
+           "dsmc_pit_kalman.hip"]
 
 # Packed-fp32 instructions are disabled for all device code (the compiler
 # would otherwise form v_pk_* from plain float arithmetic).  Matrix-core

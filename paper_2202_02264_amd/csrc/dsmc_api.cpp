@@ -356,8 +356,10 @@ extern "C" int dsmc_model_create(const dsmc_model_desc* d, dsmc_model_t** out) {
   }
 
   // pack: header, then arrays (each 256-byte aligned)
+  std::vector<double> P0c(d->P0_chol, d->P0_chol + dd), Qc(d->Q_chol, d->Q_chol + dd);
   std::vector<const std::vector<double>*> arrs = {&m0, &P0i, &F,  &f,  &Qi,  &H,    &y,
-                                                  &qm, &qc,  &qi, &qln, &Wcol, &Wrow, &woff};
+                                                  &qm, &qc,  &qi, &qln, &Wcol, &Wrow, &woff,
+                                                  &P0c, &Qc};
   size_t off = (sizeof(DevModel) + 255) & ~size_t(255);
   std::vector<size_t> offs;
   for (auto* a : arrs) {
@@ -401,6 +403,8 @@ extern "C" int dsmc_model_create(const dsmc_model_desc* d, dsmc_model_t** out) {
   hdr.Wcol = P(11);
   hdr.Wrow = P(12);
   hdr.wcol_off = P(13);
+  hdr.P0_chol = P(14);
+  hdr.Q_chol = P(15);
   std::memcpy(blob.data(), &hdr, sizeof hdr);
   e = hipMemcpy(m->dmem, blob.data(), off, hipMemcpyHostToDevice);
   if (e != hipSuccess) {
@@ -409,13 +413,18 @@ extern "C" int dsmc_model_create(const dsmc_model_desc* d, dsmc_model_t** out) {
     return fail(DSMC_EDEVICE, "hipMemcpy(model): %s", hipGetErrorString(e));
   }
   m->dev = (DevModel*)m->dmem;
+  m->hdr = hdr;
+  m->dy = dy;
+  m->obs_kind = d->obs_kind;
+  m->prop_kind = d->proposal_kind;
   *out = m;
   return DSMC_OK;
 }
 
 extern "C" void dsmc_model_destroy(dsmc_model_t* m) {
   if (!m) return;
-  hipFree(m->dmem);
+  (void)hipFree(m->dmem);
+  if (m->pit_ws) (void)hipFree(m->pit_ws);
   delete m;
 }
 
@@ -576,13 +585,14 @@ extern "C" int dsmc_plan(const dsmc_plan_desc* d, dsmc_plan_t** out) {
   std::vector<A> all(std::begin(allocs), std::end(allocs));
   if (p->timer.on) all.push_back({(void**)&p->d_rescued, sizeof(unsigned long long), "rescue counter"});
   if (p->bf16) {
-    all.push_back({(void**)&p->nb.colh, TK * p->Npad * DXp * 2, "bf16 column operands"});
+    // split operands: 2 DX bf16 values (hi, then lo) per particle
+    all.push_back({(void**)&p->nb.colh, TK * p->Npad * DXp * 4, "bf16 column operands"});
     all.push_back({(void**)&p->nb.colb, TK * p->Npad * sizeof(float), "column norms"});
-    all.push_back({(void**)&p->nb.rowh, TK * p->Npad * DXp * 2, "bf16 row operands"});
+    all.push_back({(void**)&p->nb.rowh, TK * p->Npad * DXp * 4, "bf16 row operands"});
     all.push_back({(void**)&p->nb.rown, TK * p->Npad * sizeof(float), "row norms"});
-    all.push_back({(void**)&p->nb.tcolh, TK * N * DXp * 2, "bf16 column table"});
+    all.push_back({(void**)&p->nb.tcolh, TK * N * DXp * 4, "bf16 column table"});
     all.push_back({(void**)&p->nb.tcoln, TK * N * sizeof(float), "column table norms"});
-    all.push_back({(void**)&p->nb.trowh, TK * N * DXp * 2, "bf16 row table"});
+    all.push_back({(void**)&p->nb.trowh, TK * N * DXp * 4, "bf16 row table"});
     all.push_back({(void**)&p->nb.trown, TK * N * sizeof(float), "row table norms"});
   }
   for (auto& a : all) {
@@ -729,21 +739,19 @@ int dsmc::pick_cs(int nodes, int N, int Nc, int rpl, int W) {
   return (int)std::max<long>(1, std::min<long>(cs, Nc));
 }
 
-// Heuristic rows-kernel tile: most rows per lane that still gives 16 waves
-// per CU without column splits, else one row per lane and column splits
-// (split_ok: d_x < 8; wider rows stay whole so a wave can redo its rows with
-// exact shifts).
+// Heuristic rows-kernel tile (times of every level of the headline workload on
+// MI355X under each tile picked these thresholds): four rows per lane when the
+// level has at least 2 M rows, two down to 128 K rows, else one row per lane;
+// four waves per workgroup; and when the level's waves cannot fill the chip,
+// column splits up to about 8192 waves (split_ok: d_x < 8; wider rows stay
+// whole so that a wave can redo its rows with exact shifts).
 TileChoice dsmc::heuristic_tile(int nodes, int N, int Nc, bool split_ok) {
-  const int rpls[3] = {4, 2, 1};
-  for (int rpl : rpls) {
-    const long waves = (long)nodes * ((N + 64 * rpl - 1) / (64 * rpl));
-    if (waves >= 4096 || rpl == 1) {
-      int W = 4;
-      while (W > 1 && 64 * rpl * W > N) W >>= 1;
-      return {rpl, W, split_ok ? pick_cs(nodes, N, Nc, rpl, W) : 1};
-    }
-  }
-  return {1, 1, 1};
+  const long rows = (long)nodes * N;
+  const int rpl = rows >= (2L << 20) ? 4 : (rows >= (128L << 10) ? 2 : 1);
+  int W = 4;
+  while (W > 1 && 64 * rpl * W > N) W >>= 1;
+  const long waves = (long)nodes * ((N + 64L * rpl * W - 1) / (64L * rpl * W)) * W;
+  return {rpl, W, (split_ok && waves < 4096) ? pick_cs(nodes, N, Nc, rpl, W) : 1};
 }
 
 void dsmc::set_tile(LevelLaunch& L, TileChoice tc) {
@@ -763,37 +771,57 @@ void dsmc::set_tile(LevelLaunch& L, TileChoice tc) {
 // the tile does not change any result.
 static TileChoice autotune_tile(dsmc_plan_t* p, LevelLaunch L) {
   const bool split_ok = L.DX < 8;
-  TileChoice best = heuristic_tile(L.nodes, L.N, L.Nc, split_ok);
+  const TileChoice heur = heuristic_tile(L.nodes, L.N, L.Nc, split_ok);
+  TileChoice best = heur;
   hipEvent_t e0, e1;
   if (hipEventCreate(&e0) != hipSuccess) return best;
   if (hipEventCreate(&e1) != hipSuccess) {
     (void)hipEventDestroy(e0);
     return best;
   }
-  float best_ms = 1e30f;
+  auto waves = [&](const TileChoice& tc) {
+    const long rb = (L.N + 64L * tc.RPL * tc.W - 1) / (64L * tc.RPL * tc.W);
+    return (long)L.nodes * rb * tc.CS * tc.W;
+  };
+  // a level time: the first run loads the kernels' code, the best of the next four counts
+  auto time_level = [&](const TileChoice& tc, float* ms) {
+    set_tile(L, tc);
+    *ms = 1e30f;
+    Timer untimed;
+    for (int rep = 0; rep < 5; ++rep) {
+      float t = 0.0f;
+      if (hipEventRecord(e0, p->stream) != hipSuccess || launch_level(L, p->stream, &untimed) != 0 ||
+          hipEventRecord(e1, p->stream) != hipSuccess || hipEventSynchronize(e1) != hipSuccess ||
+          hipEventElapsedTime(&t, e0, e1) != hipSuccess)
+        return false;
+      if (rep > 0) *ms = std::min(*ms, t);
+    }
+    return true;
+  };
+  float heur_ms = 1e30f;
+  if (!time_level(heur, &heur_ms)) heur_ms = 1e30f;
+  float best_ms = heur_ms;
+  const long min_waves = std::min<long>(1024, waves(heur));
   const int rpls[3] = {1, 2, 4};
   const int ws[3] = {1, 2, 4};
   for (int rpl : rpls)
     for (int w : ws)
       for (int split = 0; split < 2; ++split) {
-      if (64 * rpl * w > 2 * L.N && !(rpl == 1 && w == 1)) continue;
-      if (split && !split_ok) continue;
-      const TileChoice tc{rpl, w, split ? pick_cs(L.nodes, L.N, L.Nc, rpl, w) : 1};
-      if (split && tc.CS == 1) continue;
-      set_tile(L, tc);
-      float ms = 0.0f;
-      bool ok = true;
-      Timer untimed;
-      for (int rep = 0; rep < 2 && ok; ++rep) {
-        ok = hipEventRecord(e0, p->stream) == hipSuccess && launch_level(L, p->stream, &untimed) == 0 &&
-             hipEventRecord(e1, p->stream) == hipSuccess && hipEventSynchronize(e1) == hipSuccess &&
-             hipEventElapsedTime(&ms, e0, e1) == hipSuccess;
+        if (64 * rpl * w > 2 * L.N && !(rpl == 1 && w == 1)) continue;
+        if (split && !split_ok) continue;
+        const TileChoice tc{rpl, w, split ? pick_cs(L.nodes, L.N, L.Nc, rpl, w) : 1};
+        if (split && tc.CS == 1) continue;
+        if (tc.RPL == heur.RPL && tc.W == heur.W && tc.CS == heur.CS) continue;
+        // tiles with fewer waves than the heuristic's (at most 1024) leave
+        // most SIMDs idle or with one long wave each; they are not tried
+        if (waves(tc) < min_waves) continue;
+        float ms = 0.0f;
+        // a candidate replaces the heuristic tile only when clearly faster
+        if (time_level(tc, &ms) && ms < 0.9f * heur_ms && ms < best_ms) {
+          best_ms = ms;
+          best = tc;
+        }
       }
-      if (ok && ms < best_ms) {
-        best_ms = ms;
-        best = tc;
-      }
-    }
   (void)hipEventDestroy(e0);
   (void)hipEventDestroy(e1);
   return best;
@@ -1031,11 +1059,9 @@ static int enqueue_batch(dsmc_plan_t* p, int B, int totalK, hipStream_t st) {
       L.force_rescue = (p->d.flags & DSMC_PLAN_RESCUE_ALL) != 0;
       L.rescue_count = p->d_rescued;
       L.nb = p->nb;
-      // sampling: enough workgroups to cover the chip when a level has few combines
-      const int ds_max = std::max(1, (N + 127) / 128);
-      L.DS = nodes >= 256 ? 1 : (int)std::min<long>(ds_max, (512 + nodes - 1) / nodes);
       L.lazy = p->d.resampling;
       L.lazy_param = p->lazy_param;
+      set_sample_shape(L);
       auto it = p->tiles.find(nodes);
       TileChoice tc;
       if (it != p->tiles.end()) {

@@ -63,6 +63,83 @@ __device__ __forceinline__ void box_muller(uint64_t wa, uint64_t wb, double& z0,
   z1 = rad * sin(th);
 }
 
+// Box-Muller with the three transcendentals written out (used by the fp32
+// plans' leaves, whose particles are rounded to fp32): the results agree with
+// box_muller to a few fp64 ulps.
+//   log u:  u = m 2^e with m in [1/sqrt 2, sqrt 2); log m = 2 atanh s,
+//           s = (m - 1) / (m + 1), |s| <= 0.1716, by its odd power series to
+//           s^21; e log 2 with log 2 split in a high part exact in e log2_hi.
+//   cos 2 pi u, sin 2 pi u:  v = 4u is exact; q = nearest integer to v picks
+//           the quarter turn, f = v - q in [-1/2, 1/2] is exact, and
+//           theta = f pi / 2 in [-pi/4, pi/4] goes through the Taylor series
+//           of cos to theta^18 and of sin to theta^17 (truncation below
+//           2^-55 relative on that interval).
+__device__ __forceinline__ double log_unit(double u) {
+  const uint64_t bits = (uint64_t)__double_as_longlong(u);
+  int e = (int)((bits >> 52) & 0x7ff) - 1023;
+  double m = __longlong_as_double((long long)((bits & 0x000fffffffffffffull) | 0x3ff0000000000000ull));
+  if (m > 1.4142135623730951) {
+    m *= 0.5;
+    e += 1;
+  }
+  const double s = (m - 1.0) / (m + 1.0), s2 = s * s;
+  double p = 1.0 / 21.0;
+  p = fma(p, s2, 1.0 / 19.0);
+  p = fma(p, s2, 1.0 / 17.0);
+  p = fma(p, s2, 1.0 / 15.0);
+  p = fma(p, s2, 1.0 / 13.0);
+  p = fma(p, s2, 1.0 / 11.0);
+  p = fma(p, s2, 1.0 / 9.0);
+  p = fma(p, s2, 1.0 / 7.0);
+  p = fma(p, s2, 1.0 / 5.0);
+  p = fma(p, s2, 1.0 / 3.0);
+  const double logm = 2.0 * fma(s * s2, p, s);
+  const double ln2_hi = 6.93147180369123816490e-01;  // leading 32 bits of log 2
+  const double ln2_lo = 1.90821492927058770002e-10;  // log 2 - ln2_hi
+  return fma((double)e, ln2_hi, fma((double)e, ln2_lo, logm));
+}
+
+__device__ __forceinline__ void sincos_turn(double u, double& c, double& s) {
+  const double v = 4.0 * u;
+  const double q = rint(v);
+  const double th = (v - q) * 1.5707963267948966;
+  const double t2 = th * th;
+  double pc = 1.0 / 6402373705728000.0;             // 1 / 18!
+  pc = fma(pc, -t2, 1.0 / 20922789888000.0);         // 1 / 16!
+  pc = fma(pc, -t2, 1.0 / 87178291200.0);            // 1 / 14!
+  pc = fma(pc, -t2, 1.0 / 479001600.0);              // 1 / 12!
+  pc = fma(pc, -t2, 1.0 / 3628800.0);                // 1 / 10!
+  pc = fma(pc, -t2, 1.0 / 40320.0);                  // 1 / 8!
+  pc = fma(pc, -t2, 1.0 / 720.0);                    // 1 / 6!
+  pc = fma(pc, -t2, 1.0 / 24.0);                     // 1 / 4!
+  pc = fma(pc, -t2, 0.5);                            // 1 / 2!
+  const double cth = fma(pc, -t2, 1.0);
+  double ps = 1.0 / 355687428096000.0;               // 1 / 17!
+  ps = fma(ps, -t2, 1.0 / 1307674368000.0);          // 1 / 15!
+  ps = fma(ps, -t2, 1.0 / 6227020800.0);             // 1 / 13!
+  ps = fma(ps, -t2, 1.0 / 39916800.0);               // 1 / 11!
+  ps = fma(ps, -t2, 1.0 / 362880.0);                 // 1 / 9!
+  ps = fma(ps, -t2, 1.0 / 5040.0);                   // 1 / 7!
+  ps = fma(ps, -t2, 1.0 / 120.0);                    // 1 / 5!
+  ps = fma(ps, -t2, 1.0 / 6.0);                      // 1 / 3!
+  const double sth = fma(th * t2, -ps, th);
+  // 2 pi u = q pi / 2 + th
+  switch (((int)q) & 3) {
+    case 0: c = cth; s = sth; break;
+    case 1: c = -sth; s = cth; break;
+    case 2: c = -cth; s = -sth; break;
+    default: c = sth; s = -cth; break;
+  }
+}
+
+__device__ __forceinline__ void box_muller_poly(uint64_t wa, uint64_t wb, double& z0, double& z1) {
+  const double rad = sqrt(-2.0 * log_unit(unif53_open0(wa)));
+  double c, s;
+  sincos_turn(unif53(wb), c, s);
+  z0 = rad * c;
+  z1 = rad * s;
+}
+
 // ------------------------------------------------------------- real traits
 template <typename R>
 struct Real;
@@ -211,60 +288,60 @@ __device__ __forceinline__ int wave_or_i(int v) {
   return v;
 }
 
-// Workgroup-wide reductions (kBlock threads); `red` holds kBlock/64 values.
-// The combination order is fixed, so results are deterministic.
+// Workgroup-wide reductions over blockDim.x threads (a multiple of 64, at most
+// 64 kMaxWaves); `red` holds kMaxWaves values (2 kMaxWaves for the paired
+// forms).  The combination order is fixed for a given workgroup size, so
+// results are deterministic.
+__device__ __forceinline__ int num_waves() { return (int)(blockDim.x >> 6); }
+
 __device__ __forceinline__ double block_max(double v, double* red) {
   v = wave_max(v);
-  const int w = threadIdx.x >> 6;
+  const int w = threadIdx.x >> 6, nw = num_waves();
   __syncthreads();
   if ((threadIdx.x & 63) == 0) red[w] = v;
   __syncthreads();
   double r = red[0];
-#pragma unroll
-  for (int i = 1; i < kBlock / 64; ++i) r = fmax(r, red[i]);
+  for (int i = 1; i < nw; ++i) r = fmax(r, red[i]);
   return r;
 }
 __device__ __forceinline__ double block_sum(double v, double* red) {
   v = wave_sum(v);
-  const int w = threadIdx.x >> 6;
+  const int w = threadIdx.x >> 6, nw = num_waves();
   __syncthreads();
   if ((threadIdx.x & 63) == 0) red[w] = v;
   __syncthreads();
   double r = red[0];
-#pragma unroll
-  for (int i = 1; i < kBlock / 64; ++i) r += red[i];
+  for (int i = 1; i < nw; ++i) r += red[i];
   return r;
 }
 __device__ __forceinline__ int block_max_i(int v, int* red) {
   v = wave_max_i(v);
-  const int w = threadIdx.x >> 6;
+  const int w = threadIdx.x >> 6, nw = num_waves();
   __syncthreads();
   if ((threadIdx.x & 63) == 0) red[w] = v;
   __syncthreads();
   int r = red[0];
-#pragma unroll
-  for (int i = 1; i < kBlock / 64; ++i) r = max(r, red[i]);
+  for (int i = 1; i < nw; ++i) r = max(r, red[i]);
   return r;
 }
 __device__ __forceinline__ int block_or_i(int v, int* red) {
   v = wave_or_i(v);
-  const int w = threadIdx.x >> 6;
+  const int w = threadIdx.x >> 6, nw = num_waves();
   __syncthreads();
   if ((threadIdx.x & 63) == 0) red[w] = v;
   __syncthreads();
   int r = red[0];
-#pragma unroll
-  for (int i = 1; i < kBlock / 64; ++i) r |= red[i];
+  for (int i = 1; i < nw; ++i) r |= red[i];
   return r;
 }
 
 // Two reductions for the price of one exchange (max and OR are order-free, so
 // the results equal those of the separate calls).  red / redi hold
-// 2 * kBlock / 64 values.
+// 2 kMaxWaves values.
 __device__ __forceinline__ void block_max_or(double& v, int& f, double* red, int* redi) {
   v = wave_max(v);
   f = wave_or_i(f);
-  const int w = threadIdx.x >> 6;
+  const int w = threadIdx.x >> 6, nw = num_waves();
   __syncthreads();
   if ((threadIdx.x & 63) == 0) {
     red[w] = v;
@@ -273,8 +350,7 @@ __device__ __forceinline__ void block_max_or(double& v, int& f, double* red, int
   __syncthreads();
   double r = red[0];
   int o = redi[0];
-#pragma unroll
-  for (int i = 1; i < kBlock / 64; ++i) {
+  for (int i = 1; i < nw; ++i) {
     r = fmax(r, red[i]);
     o |= redi[i];
   }
@@ -284,18 +360,17 @@ __device__ __forceinline__ void block_max_or(double& v, int& f, double* red, int
 __device__ __forceinline__ void block_max2(double& a, double& b, double* red) {
   a = wave_max(a);
   b = wave_max(b);
-  const int w = threadIdx.x >> 6;
+  const int w = threadIdx.x >> 6, nw = num_waves();
   __syncthreads();
   if ((threadIdx.x & 63) == 0) {
     red[w] = a;
-    red[kBlock / 64 + w] = b;
+    red[kMaxWaves + w] = b;
   }
   __syncthreads();
-  double ra = red[0], rb = red[kBlock / 64];
-#pragma unroll
-  for (int i = 1; i < kBlock / 64; ++i) {
+  double ra = red[0], rb = red[kMaxWaves];
+  for (int i = 1; i < nw; ++i) {
     ra = fmax(ra, red[i]);
-    rb = fmax(rb, red[kBlock / 64 + i]);
+    rb = fmax(rb, red[kMaxWaves + i]);
   }
   a = ra;
   b = rb;
@@ -303,18 +378,17 @@ __device__ __forceinline__ void block_max2(double& a, double& b, double* red) {
 __device__ __forceinline__ void block_max_i_or(int& a, int& b, int* redi) {
   a = wave_max_i(a);
   b = wave_or_i(b);
-  const int w = threadIdx.x >> 6;
+  const int w = threadIdx.x >> 6, nw = num_waves();
   __syncthreads();
   if ((threadIdx.x & 63) == 0) {
     redi[w] = a;
-    redi[kBlock / 64 + w] = b;
+    redi[kMaxWaves + w] = b;
   }
   __syncthreads();
-  int ra = redi[0], rb = redi[kBlock / 64];
-#pragma unroll
-  for (int i = 1; i < kBlock / 64; ++i) {
+  int ra = redi[0], rb = redi[kMaxWaves];
+  for (int i = 1; i < nw; ++i) {
     ra = max(ra, redi[i]);
-    rb |= redi[kBlock / 64 + i];
+    rb |= redi[kMaxWaves + i];
   }
   a = ra;
   b = rb;

@@ -14,7 +14,10 @@
 struct dsmc_model {
   void* dmem = nullptr;  // DevModel header followed by its arrays
   dsmc::DevModel* dev = nullptr;
-  int K = 0, dx = 0;
+  dsmc::DevModel hdr{};  // host copy of the header (device array pointers)
+  int K = 0, dx = 0, dy = 0, obs_kind = 0, prop_kind = 0;
+  void* pit_ws = nullptr;  // workspace of dsmc_model_gaussian_proposals
+  size_t pit_bytes = 0;
 };
 
 namespace dsmc {

@@ -6,7 +6,8 @@
 
 namespace dsmc {
 
-constexpr int kBlock = 256;  // threads per workgroup of the leaf / sample / output kernels
+constexpr int kBlock = 256;     // threads per workgroup of the leaf / lazy-sampling / output kernels
+constexpr int kMaxWaves = 16;  // largest workgroup (1024 threads) of any kernel, in waves
 constexpr int kChunk = 32;   // columns per chunk of the pair matrix
 
 // Device-resident model (one allocation: this header, then the arrays).
@@ -31,6 +32,8 @@ struct DevModel {
   const double* Wcol;     // [dx][dx] = kappa Q_inv          (column whitening)
   const double* Wrow;     // [dx][dx] = kappa Q_inv F        (row whitening)
   const double* wcol_off; // [dx]     = kappa Q_inv f
+  const double* P0_chol;  // [dx][dx] prior Cholesky factor
+  const double* Q_chol;   // [dx][dx] transition Cholesky factor
 };
 
 // One series of a (batched) run.

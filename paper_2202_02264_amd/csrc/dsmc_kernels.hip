@@ -68,7 +68,7 @@ __global__ __launch_bounds__(kBlock) void k_output_series(const SeriesDesc* __re
                                                           int s0, int N,
                                                           const R* __restrict__ leafW,
                                                           const double* __restrict__ leafL) {
-  __shared__ double red[kBlock / 64];
+  __shared__ double red[kMaxWaves];
   const SeriesDesc& sd = series[s0 + blockIdx.x];
   const int K = sd.K;
   double s = 0.0;

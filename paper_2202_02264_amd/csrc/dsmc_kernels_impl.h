@@ -85,62 +85,30 @@ __device__ __forceinline__ uint32_t bf16_bits(float x) {
 }
 __device__ __forceinline__ float bf16_float(uint32_t b) { return __uint_as_float(b << 16); }
 
-// Table entry of particle n of time row g for the combine at boundary t:
-// u (bf16 plans: rounded to bf16, plus the bits of 2u and ||u||^2).
+// Table entry of particle n of time row g for the combine at boundary t: u.
 template <typename R, int DX>
 __device__ __forceinline__ void put_tcol(const NodeBufs& nb, size_t g, int N, int n,
                                          const double (&u)[DX]) {
   R* tp = (R*)nb.tcol + (g * N + n) * DX;
-  if constexpr (sizeof(R) == 4 && DX >= 16) {
-    if (nb.tcolh) {
-      uint32_t w[DX / 2];
-      double nrm = 0.0;
-#pragma unroll
-      for (int i = 0; i < DX; ++i) {
-        const float ur = bf16_float(bf16_bits((float)u[i]));
-        tp[i] = ur;
-        nrm += (double)ur * (double)ur;
-        const uint32_t b2 = bf16_bits(2.0f * ur);
-        w[i >> 1] = (i & 1) ? (w[i >> 1] | (b2 << 16)) : b2;
-      }
-      uint4* dst = (uint4*)(nb.tcolh + (g * N + n) * DX);
-#pragma unroll
-      for (int q = 0; q < DX / 8; ++q) dst[q] = make_uint4(w[4 * q], w[4 * q + 1], w[4 * q + 2], w[4 * q + 3]);
-      nb.tcoln[g * N + n] = (float)nrm;
-      return;
-    }
-  }
 #pragma unroll
   for (int i = 0; i < DX; ++i) tp[i] = (R)u[i];
 }
 
-// Table entry of particle n of time row g for the combine at boundary t + 1:
-// v (bf16 plans: rounded, plus its bits and ||v||^2).
+// Table entry of particle n of time row g for the combine at boundary t + 1: v.
 template <typename R, int DX>
 __device__ __forceinline__ void put_trow(const NodeBufs& nb, size_t g, int N, int n,
                                          const double (&v)[DX]) {
   R* tp = (R*)nb.trow + (g * N + n) * DX;
-  if constexpr (sizeof(R) == 4 && DX >= 16) {
-    if (nb.trowh) {
-      uint32_t w[DX / 2];
-      double nrm = 0.0;
-#pragma unroll
-      for (int i = 0; i < DX; ++i) {
-        const uint32_t b = bf16_bits((float)v[i]);
-        const float vr = bf16_float(b);
-        tp[i] = vr;
-        nrm += (double)vr * (double)vr;
-        w[i >> 1] = (i & 1) ? (w[i >> 1] | (b << 16)) : b;
-      }
-      uint4* dst = (uint4*)(nb.trowh + (g * N + n) * DX);
-#pragma unroll
-      for (int q = 0; q < DX / 8; ++q) dst[q] = make_uint4(w[4 * q], w[4 * q + 1], w[4 * q + 2], w[4 * q + 3]);
-      nb.trown[g * N + n] = (float)nrm;
-      return;
-    }
-  }
 #pragma unroll
   for (int i = 0; i < DX; ++i) tp[i] = (R)v[i];
+}
+
+// bf16 plans keep each matrix-core operand as a pair of bf16 numbers, hi and
+// lo = the bf16 rounding of the remainder, so that hi + lo carries 16
+// significant bits; a particle's entry is 2 DX bf16 values: DX hi, then DX lo.
+__device__ __forceinline__ void bf16_split(float a, uint32_t& hi, uint32_t& lo) {
+  hi = bf16_bits(a);
+  lo = bf16_bits(a - bf16_float(hi));
 }
 
 // Column n of combine `node` := table entry (g, src) with log2 weight beta.
@@ -154,10 +122,10 @@ __device__ __forceinline__ void copy_col(const NodeBufs& nb, size_t node, int Np
   cp[DX] = (R)beta;
   if constexpr (sizeof(R) == 4 && DX >= 16) {
     if (nb.colh) {
-      const uint4* s4 = (const uint4*)(nb.tcolh + (g * N + src) * DX);
-      uint4* d4 = (uint4*)(nb.colh + (node * Npad + n) * DX);
+      const uint4* s4 = (const uint4*)(nb.tcolh + (g * N + src) * 2 * DX);
+      uint4* d4 = (uint4*)(nb.colh + (node * Npad + n) * 2 * DX);
 #pragma unroll
-      for (int q = 0; q < DX / 8; ++q) d4[q] = s4[q];
+      for (int q = 0; q < DX / 4; ++q) d4[q] = s4[q];
       nb.colb[node * Npad + n] = (float)beta - nb.tcoln[g * N + src];
     }
   }
@@ -173,21 +141,21 @@ __device__ __forceinline__ void copy_row(const NodeBufs& nb, size_t node, int Np
   for (int i = 0; i < DX; ++i) rp[i] = tp[i];
   if constexpr (sizeof(R) == 4 && DX >= 16) {
     if (nb.rowh) {
-      const uint4* s4 = (const uint4*)(nb.trowh + (g * N + src) * DX);
-      uint4* d4 = (uint4*)(nb.rowh + (node * Npad + m) * DX);
+      const uint4* s4 = (const uint4*)(nb.trowh + (g * N + src) * 2 * DX);
+      uint4* d4 = (uint4*)(nb.rowh + (node * Npad + m) * 2 * DX);
 #pragma unroll
-      for (int q = 0; q < DX / 8; ++q) d4[q] = s4[q];
+      for (int q = 0; q < DX / 4; ++q) d4[q] = s4[q];
       nb.rown[node * Npad + m] = nb.trown[g * N + src];
     }
   }
 }
 
 // Table entries for DX >= 8, written coordinate by coordinate (the matrix row
-// loop is not unrolled, so only x stays in registers); same values, order and
-// rounding as col_coords / row_coords followed by put_tcol / put_trow.
-// Wc, Wr: the whitening matrices; column table: qm = q_mean[t]; row table:
-// woff = kappa Q_inv f - Wcol q_mean[t + 1] (formed once per time); any
-// address space (the leaf kernel passes copies in LDS).
+// loop is not unrolled, so only x stays in registers).  bf16 plans also write
+// the split bf16 operands (2u for columns, v for rows) and the fp32 squared
+// norm of the entry.  Wc, Wr: the whitening matrices; column table:
+// qm = q_mean[t]; row table: woff = kappa Q_inv f - Wcol q_mean[t + 1] (formed
+// once per time); any address space (the leaf kernel passes copies in LDS).
 template <typename R, int DX, bool kRow>
 __device__ __forceinline__ void stream_table(const NodeBufs& nb, const double* Wc, const double* Wr,
                                              const double* woff, const double* qm, int, size_t g,
@@ -197,7 +165,7 @@ __device__ __forceinline__ void stream_table(const NodeBufs& nb, const double* W
   uint32_t* th = nullptr;
   if constexpr (sizeof(R) == 4 && DX >= 16)
     th = (uint32_t*)(kRow ? nb.trowh : nb.tcolh);
-  if (th) th += (g * N + n) * (DX / 2);
+  if (th) th += (g * N + n) * DX;  // DX / 2 words of hi pairs, then DX / 2 of lo pairs
   double nrm = 0.0;
 #pragma unroll 1
   for (int i = 0; i < DX; i += 2) {
@@ -220,18 +188,17 @@ __device__ __forceinline__ void stream_table(const NodeBufs& nb, const double* W
       }
       s2[k] = acc;
     }
+    const R r0 = (R)s2[0], r1 = (R)s2[1];
+    tp[i] = r0;
+    tp[i + 1] = r1;
     if (th) {
-      const float r0 = bf16_float(bf16_bits((float)s2[0]));
-      const float r1 = bf16_float(bf16_bits((float)s2[1]));
-      tp[i] = r0;
-      tp[i + 1] = r1;
       nrm += (double)r0 * (double)r0;
       nrm += (double)r1 * (double)r1;
-      const uint32_t b0 = bf16_bits(kRow ? r0 : 2.0f * r0), b1 = bf16_bits(kRow ? r1 : 2.0f * r1);
-      th[i >> 1] = b0 | (b1 << 16);
-    } else {
-      tp[i] = (R)s2[0];
-      tp[i + 1] = (R)s2[1];
+      uint32_t h0, l0, h1, l1;
+      bf16_split(kRow ? (float)r0 : 2.0f * (float)r0, h0, l0);
+      bf16_split(kRow ? (float)r1 : 2.0f * (float)r1, h1, l1);
+      th[i >> 1] = h0 | (h1 << 16);
+      th[DX / 2 + (i >> 1)] = l0 | (l1 << 16);
     }
   }
   if (th) (kRow ? nb.trown : nb.tcoln)[g * N + n] = (float)nrm;
@@ -246,15 +213,32 @@ __device__ __forceinline__ void put_col_pad(const NodeBufs& nb, size_t node, int
   cp[DX] = (R)(-INFINITY);
   if constexpr (sizeof(R) == 4 && DX >= 16) {
     if (nb.colh) {
-      uint4* dst = (uint4*)(nb.colh + (node * Npad + n) * DX);
+      uint4* dst = (uint4*)(nb.colh + (node * Npad + n) * 2 * DX);
 #pragma unroll
-      for (int q = 0; q < DX / 8; ++q) dst[q] = make_uint4(0u, 0u, 0u, 0u);
+      for (int q = 0; q < DX / 4; ++q) dst[q] = make_uint4(0u, 0u, 0u, 0u);
       nb.colb[node * Npad + n] = -INFINITY;
     }
   }
 }
 
 // ================================================================ leaves
+// The four standard normals of one leaf Philox block.  fp32 plans use the
+// Box-Muller transform with its transcendentals written out (box_muller_poly,
+// a few fp64 ulps from the library's); their particles are rounded to fp32,
+// which hides the difference in all but rare last-ulp cases.  fp64 plans use
+// the library's log, sqrt, cos and sin.
+template <typename R>
+__device__ __forceinline__ void leaf_normals(const Words4& w, double& z0, double& z1, double& z2,
+                                             double& z3) {
+  if constexpr (sizeof(R) == 4) {
+    box_muller_poly(w.w0, w.w1, z0, z1);
+    box_muller_poly(w.w2, w.w3, z2, z3);
+  } else {
+    box_muller(w.w0, w.w1, z0, z1);
+    box_muller(w.w2, w.w3, z2, z3);
+  }
+}
+
 // One workgroup per time row g of the packed time axis.
 template <typename R, int DX>
 __global__ __launch_bounds__(kBlock, 3) void k_leaves(
@@ -274,8 +258,8 @@ __global__ __launch_bounds__(kBlock, 3) void k_leaves(
   // LDS holds this time's matrices instead)
   double* ell = sh;  // unnormalised leaf log-weights
   double* gq = (DX >= 8) ? nb.tgq + (size_t)g * N : sh + N;  // -log q_t (+ log h_t, boundary weighting)
-  __shared__ double red[2 * kBlock / 64];
-  __shared__ int redi[2 * kBlock / 64];
+  __shared__ double red[2 * kMaxWaves];
+  __shared__ int redi[2 * kMaxWaves];
   const double logN = log((double)N);
   int bad = 0;
   const double* qm = M.q_mean + (size_t)t * dx;
@@ -342,8 +326,7 @@ __global__ __launch_bounds__(kBlock, 3) void k_leaves(
         const Words4 w = philox4x64_10((uint64_t)n, (uint64_t)t, kPurposeLeaf, (uint64_t)j,
                                        sd.seed, kKey1);
         double z[4];
-        box_muller(w.w0, w.w1, z[0], z[1]);
-        box_muller(w.w2, w.w3, z[2], z[3]);
+        leaf_normals<R>(w, z[0], z[1], z[2], z[3]);
 #pragma unroll
         for (int i = 0; i < DX; ++i) {
 #pragma unroll
@@ -369,8 +352,7 @@ __global__ __launch_bounds__(kBlock, 3) void k_leaves(
           z2 = unif53(w.w2);
           z3 = unif53(w.w3);
         } else {
-          box_muller(w.w0, w.w1, z0, z1);
-          box_muller(w.w2, w.w3, z2, z3);
+          leaf_normals<R>(w, z0, z1, z2, z3);
         }
         if (4 * j < DX) x[4 * j] = z0;
         if (4 * j + 1 < DX) x[4 * j + 1] = z1;
@@ -673,14 +655,16 @@ __global__ __launch_bounds__(kBlock) void k_rows(const R* __restrict__ col,
 }
 
 // ============================================================ rows (bf16)
-// Matrix-core form of k_rows for bf16 plans (DX = 16 or 32).  With u, v
-// rounded to bf16, the pair's log2 weight beta_n - ||u_n - v_m||^2 equals
-// (beta_n - ||u_n||^2) - ||v_m||^2 + (2 u_n) . v_m.  A wave owns 32 MB rows;
-// for each 32-column chunk and each block of 32 rows, DX / 16
-// v_mfma_f32_32x32x16_bf16 add the 32 x 32 dot products (u on the
-// instruction's row side, v on its column side) onto accumulators that start
-// at the two fp32 norm terms, so each accumulator ends as the pair's log2
-// weight.  Lane (j, h) holds column j of the block (row m = block + j) for the
+// Matrix-core form of k_rows for bf16 plans (DX = 16 or 32).  The pair's log2
+// weight beta_n - ||u_n - v_m||^2 equals (beta_n - ||u_n||^2) - ||v_m||^2 +
+// (2 u_n) . v_m, with the norms in fp32 and the dot product from split bf16
+// operands: with 2u = Uh + Ul and v = Vh + Vl (hi and remainder, each bf16),
+// (2u) . v = Uh.Vh + Uh.Vl + Ul.Vh up to the dropped Ul.Vl (about 2^-16 of
+// it).  A wave owns 32 MB rows; for each 32-column chunk and each block of 32
+// rows, 3 DX / 16 v_mfma_f32_32x32x16_bf16 add the 32 x 32 dot products (u on
+// the instruction's row side, v on its column side) onto accumulators that
+// start at the two fp32 norm terms, so each accumulator ends as the pair's
+// log2 weight.  Lane (j, h) holds column j of the block (row m = block + j) for the
 // 16 chunk columns 8 (r / 4) + 4 h + r % 4, r < 16; the lanes j and j + 32
 // together hold the whole chunk.  Outputs as k_rows (chunk sums, and fp64 row
 // sums in chunk order with one column split).
@@ -705,19 +689,22 @@ __global__ __launch_bounds__(kBlock) void k_rows_mfma(
   const int base = (rb * W + wave) * 32 * MB;
   if (base >= N) return;  // wave-uniform
   const size_t nodeid = node_list ? (size_t)node_list[node_local] : (size_t)node0 + node_local;
-  bf16x8_t vf[MB][KS];
+  bf16x8_t vf[MB][KS], vl[MB][KS];
   float vv[MB];
   int mrow[MB];
 #pragma unroll
   for (int b = 0; b < MB; ++b) {
     const int m = base + 32 * b + j32;
     mrow[b] = m < N ? m : N - 1;
-    const uint16_t* rp = rowh + ((size_t)nodeid * Npad + mrow[b]) * DX + 8 * h;
+    const uint16_t* rp = rowh + ((size_t)nodeid * Npad + mrow[b]) * 2 * DX + 8 * h;
 #pragma unroll
-    for (int s = 0; s < KS; ++s) vf[b][s] = *(const bf16x8_t*)(rp + 16 * s);
+    for (int s = 0; s < KS; ++s) {
+      vf[b][s] = *(const bf16x8_t*)(rp + 16 * s);
+      vl[b][s] = *(const bf16x8_t*)(rp + DX + 16 * s);
+    }
     vv[b] = rown[(size_t)nodeid * Npad + mrow[b]];
   }
-  const uint16_t* __restrict__ ch = colh + (size_t)nodeid * Npad * DX;
+  const uint16_t* __restrict__ ch = colh + (size_t)nodeid * Npad * 2 * DX;
   const float* __restrict__ cb = colb + (size_t)nodeid * Npad;
   // Row shift: the row's largest log2 weight over chunk 0 (as k_rows), folded
   // into the row norm term so the main loop pays nothing for it.
@@ -727,10 +714,13 @@ __global__ __launch_bounds__(kBlock) void k_rows_mfma(
   // log2 weights of chunk k for block b, into acc (row-norm term vv[b])
   auto block = [&](int k, int b, f32x16_t& acc) {
     const int n0 = k * kChunk;
-    bf16x8_t uf[KS];
-    const uint16_t* up = ch + (size_t)(n0 + j32) * DX + 8 * h;
+    bf16x8_t uf[KS], ul[KS];
+    const uint16_t* up = ch + (size_t)(n0 + j32) * 2 * DX + 8 * h;
 #pragma unroll
-    for (int s = 0; s < KS; ++s) uf[s] = *(const bf16x8_t*)(up + 16 * s);
+    for (int s = 0; s < KS; ++s) {
+      uf[s] = *(const bf16x8_t*)(up + 16 * s);
+      ul[s] = *(const bf16x8_t*)(up + DX + 16 * s);
+    }
 #pragma unroll
     for (int g4 = 0; g4 < 4; ++g4) {
       const float4 t4 = *(const float4*)(cb + n0 + 8 * g4 + 4 * h);
@@ -740,8 +730,11 @@ __global__ __launch_bounds__(kBlock) void k_rows_mfma(
       acc[4 * g4 + 3] = t4.w - vv[b];
     }
 #pragma unroll
-    for (int s = 0; s < KS; ++s)
+    for (int s = 0; s < KS; ++s) {
+      acc = __builtin_amdgcn_mfma_f32_32x32x16_bf16(ul[s], vf[b][s], acc, 0, 0, 0);
+      acc = __builtin_amdgcn_mfma_f32_32x32x16_bf16(uf[s], vl[b][s], acc, 0, 0, 0);
       acc = __builtin_amdgcn_mfma_f32_32x32x16_bf16(uf[s], vf[b][s], acc, 0, 0, 0);
+    }
   };
   // largest log2 weight of each row block over chunks [ka, kb)
   auto row_max = [&](int ka, int kb, float (&mx)[MB]) {
@@ -883,21 +876,81 @@ __device__ __forceinline__ void record_draw(const NodeBufs& nb, const NodeDesc& 
   }
 }
 
+// Column data of the combine in LDS: 32-column chunks padded by 8 bytes, so
+// that lanes reading the same column of different chunks (the draws' chunk
+// recompute) fall into different LDS banks.
+template <typename R, int DX>
+constexpr int col_chunk_lds_stride() {
+  return kChunk * (DX + 1) + (int)(8 / sizeof(R));
+}
+template <typename R, int DX>
+__device__ __forceinline__ int col_chunk_stride(int col_in_lds) {
+  return col_in_lds ? col_chunk_lds_stride<R, DX>() : kChunk * (DX + 1);
+}
+
+// Chunk sums P[m][0..Nc) of one row into q (NcP <= 32: the whole row, every
+// load issued before any is used).
+template <typename R>
+__device__ __forceinline__ void load_row32(const R* __restrict__ Pm, int NcP, R (&q)[32]) {
+#pragma unroll
+  for (int g4 = 0; g4 < 8; ++g4) {
+    if (4 * g4 < NcP) {
+      R t4[4];
+      load4<R>(Pm + 4 * g4, t4);
+#pragma unroll
+      for (int i = 0; i < 4; ++i) q[4 * g4 + i] = t4[i];
+    } else {
+#pragma unroll
+      for (int i = 0; i < 4; ++i) q[4 * g4 + i] = (R)0;
+    }
+  }
+}
+
+// fp64 sum of a row's chunk sums in chunk order (the row sum R_m every path
+// uses: the rows kernel forms the same sum when it runs without column splits)
+template <typename R>
+__device__ __forceinline__ double row_sum(const R* __restrict__ Pm, int Nc, int NcP) {
+  double s = 0.0;
+  if (NcP <= 32) {
+    R q[32];
+    load_row32<R>(Pm, NcP, q);
+#pragma unroll
+    for (int i = 0; i < 32; ++i)
+      if (i < Nc) s += (double)q[i];
+    return s;
+  }
+  for (int kb = 0; kb < NcP; kb += 16) {
+    R q[16];
+#pragma unroll
+    for (int g4 = 0; g4 < 4; ++g4) {
+      R t4[4];
+      if (kb + 4 * g4 < NcP) load4<R>(Pm + kb + 4 * g4, t4);
+#pragma unroll
+      for (int i = 0; i < 4; ++i) q[4 * g4 + i] = (kb + 4 * g4 < NcP) ? t4[i] : (R)0;
+    }
+#pragma unroll
+    for (int i = 0; i < 16; ++i)
+      if (kb + i < Nc) s += (double)q[i];
+  }
+  return s;
+}
+
 template <typename R, int DX>
 __global__ __launch_bounds__(kBlock) void k_sample(
     const NodeDesc* __restrict__ nodes, const SeriesDesc* __restrict__ series,
     const int32_t* __restrict__ node_list, int node0, int DS,
     int N, int Npad, int Nc, int NcP, int rows_summed, int col_in_lds, int force_rescue,
-    const double* __restrict__ bmerged, const R* __restrict__ P, R* __restrict__ Pr,
-    const double* __restrict__ Rsum, const float* __restrict__ Rshift,
+    int rescale_chunk, const double* __restrict__ bmerged, const R* __restrict__ P,
+    R* __restrict__ Pr, double* __restrict__ Rsum, const float* __restrict__ Rshift,
     unsigned long long* __restrict__ rescue_count, NodeBufs nb) {
   extern __shared__ double smem[];
-  double* cdf = smem;                        // [Npad]
-  double* rs = smem + Npad;                  // [Npad]
-  float* shift = (float*)(smem + 2 * Npad);  // [Npad]
-  R* lcol = (R*)(shift + Npad);              // [Npad][DX+1] when col_in_lds
-  __shared__ double red[2 * kBlock / 64];
-  __shared__ int redi[2 * kBlock / 64];
+  const int nthr = blockDim.x;
+  const int cstr = col_chunk_stride<R, DX>(col_in_lds);
+  double* cdf = smem;                        // [Npad]: row sums R_m, then the row CDF
+  float* shift = (float*)(smem + Npad);      // [Npad]
+  R* lcol = (R*)(shift + Npad);              // [Nc][cstr] when col_in_lds
+  __shared__ double red[2 * kMaxWaves];
+  __shared__ int redi[2 * kMaxWaves];
   const int node_local = blockIdx.x / DS;
   const int ds = blockIdx.x - node_local * DS;
   const int nodeid = node_list ? node_list[node_local] : node0 + node_local;
@@ -911,11 +964,18 @@ __global__ __launch_bounds__(kBlock) void k_sample(
   const R* __restrict__ rowp = (const R*)nb.row + (size_t)nodeid * Npad * DX;
   const R* __restrict__ Pn = P + (size_t)node_local * N * NcP;
   R* __restrict__ Prn = Pr + (size_t)node_local * N * NcP;
-  const double* __restrict__ Rn = Rsum + (size_t)node_local * N;
+  double* __restrict__ Rn = Rsum + (size_t)node_local * N;
   const R* __restrict__ alp = (const R*)nb.alpha + (size_t)nodeid * N;
-  if (col_in_lds)
-    for (int i = threadIdx.x; i < Npad * (DX + 1); i += kBlock) lcol[i] = gcol[i];
+  if (col_in_lds) {
+    constexpr int CW = kChunk * (DX + 1);
+    for (int i = threadIdx.x; i < Npad * (DX + 1); i += nthr) {
+      const int k = i / CW;
+      lcol[k * cstr + (i - k * CW)] = gcol[i];
+    }
+  }
   const R* colp = col_in_lds ? lcol : gcol;
+  // column j, coordinate d of the combine (padded layout in LDS)
+  auto colv = [&](int j, int d) -> R { return colp[(j >> 5) * cstr + (j & 31) * (DX + 1) + d]; };
   __syncthreads();
 
   // ---- row sums (thread owns a contiguous segment of rows)
@@ -924,38 +984,30 @@ __global__ __launch_bounds__(kBlock) void k_sample(
   __shared__ double csum[DSMC_MAX_N / kChunk];  // chunk sums of the row being rescued
   __shared__ int rescue_list[kBlock];
   __shared__ int n_rescue;
-  for (int i = threadIdx.x; i < DSMC_MAX_N / 32; i += kBlock) {
+  for (int i = threadIdx.x; i < DSMC_MAX_N / 32; i += nthr) {
     need[i] = 0u;
     resc[i] = 0u;
   }
   __syncthreads();
-  const int per = (N + kBlock - 1) / kBlock;
+  const int per = (N + nthr - 1) / nthr;
   const int m0 = threadIdx.x * per, m1 = min(N, m0 + per);
   double amax = -INFINITY;
   int rescued = 0, row_nan = 0;
   for (int m = m0; m < m1; ++m) {
     amax = fmax(amax, left_leaf ? (double)alp[m] : -logN);
-    double Rm;
-    if (rows_summed) {
-      Rm = Rn[m];
-    } else {  // the same sequential chunk-order sum the rows kernel forms
-      Rm = 0.0;
-      const R* Pm = Pn + (size_t)m * NcP;
-      for (int kb = 0; kb < NcP; kb += 4) {
-        R q[4];
-        load4<R>(Pm + kb, q);
-#pragma unroll
-        for (int i = 0; i < 4; ++i)
-          if (kb + i < Nc) Rm += (double)q[i];
-      }
-    }
+    // with column splits the rows kernel leaves the row sums to this kernel,
+    // which stores them for the draws (every workgroup of the combine writes
+    // the same values; no workgroup reads them before its own write)
+    const double Rm = rows_summed ? Rn[m] : row_sum<R>(Pn + (size_t)m * NcP, Nc, NcP);
     if ((!(Rm >= Real<R>::kTiny) || isinf(Rm) || force_rescue) && !isnan(Rm)) {
       atomicOr(&need[m >> 5], 1u << (m & 31));
       atomicOr(&resc[m >> 5], 1u << (m & 31));
       rescued = 1;
+    } else if (!rows_summed) {
+      Rn[m] = Rm;
     }
     if (isnan(Rm)) row_nan = 1;
-    rs[m] = Rm;
+    cdf[m] = Rm;
     if constexpr (kRowShift<DX>) shift[m] = Rshift[(size_t)node_local * N + m];
     else shift[m] = 0.0f;
   }
@@ -964,18 +1016,18 @@ __global__ __launch_bounds__(kBlock) void k_sample(
   // Underflow rescue, one row at a time by the whole workgroup: exact row
   // maximum as shift, then the fp64 sum of exp2(s - shift) over a fixed
   // partition of the columns in a fixed reduction order.  Rows are taken in
-  // passes of at most kBlock.
+  // passes of at most one per thread.
   bool first_pass = true;
   while (rescued) {
     if (threadIdx.x == 0) n_rescue = 0;
     __syncthreads();
-    for (int wd = threadIdx.x; wd < Npad / 32; wd += kBlock) {
+    for (int wd = threadIdx.x; wd < Npad / 32; wd += nthr) {
       unsigned bits = need[wd];
       while (bits) {
         const int b = __ffs(bits) - 1;
         bits &= bits - 1;
         const int slot = atomicAdd(&n_rescue, 1);
-        if (slot < kBlock) {
+        if (slot < nthr) {
           rescue_list[slot] = wd * 32 + b;
           atomicAnd(&need[wd], ~(1u << b));
         }
@@ -983,7 +1035,7 @@ __global__ __launch_bounds__(kBlock) void k_sample(
     }
     __syncthreads();
     const int total = n_rescue;
-    const int cnt = min(total, kBlock);
+    const int cnt = min(total, nthr);
     if (first_pass && rescue_count && ds == 0 && threadIdx.x == 0)
       atomicAdd(rescue_count, (unsigned long long)total);
     first_pass = false;
@@ -993,11 +1045,11 @@ __global__ __launch_bounds__(kBlock) void k_sample(
 #pragma unroll
       for (int d = 0; d < DX; ++d) v[d] = rowp[(size_t)m * DX + d];
       double smax = -INFINITY;
-      for (int j = threadIdx.x; j < N; j += kBlock) {
+      for (int j = threadIdx.x; j < N; j += nthr) {
         R u[DX];
 #pragma unroll
-        for (int d = 0; d < DX; ++d) u[d] = colp[(size_t)j * (DX + 1) + d];
-        smax = fmax(smax, (double)pair_log2w<R, DX>(u, colp[(size_t)j * (DX + 1) + DX], v));
+        for (int d = 0; d < DX; ++d) u[d] = colv(j, d);
+        smax = fmax(smax, (double)pair_log2w<R, DX>(u, colv(j, DX), v));
       }
       smax = block_max(smax, red);
       const R sh = (R)(float)smax;  // the shift is kept as fp32
@@ -1006,10 +1058,10 @@ __global__ __launch_bounds__(kBlock) void k_sample(
       // workgroup of the combine writes the same values), and their fp64 sum
       // in chunk order
       R* Pm = Prn + (size_t)m * NcP;
-      for (int k = threadIdx.x; k < Nc; k += kBlock) {
+      for (int k = threadIdx.x; k < Nc; k += nthr) {
         R acc = (R)0;
         if (smax > -INFINITY) {
-          const R* cp = colp + (size_t)k * kChunk * (DX + 1);
+          const R* cp = colp + (size_t)k * cstr;
 #pragma unroll 4
           for (int jj = 0; jj < kChunk; ++jj) {
             R u[DX];
@@ -1025,22 +1077,31 @@ __global__ __launch_bounds__(kBlock) void k_sample(
       if (threadIdx.x == 0) {
         double tot = 0.0;
         for (int k = 0; k < Nc; ++k) tot += csum[k];
-        rs[m] = (smax > -INFINITY) ? tot : 0.0;
+        cdf[m] = (smax > -INFINITY) ? tot : 0.0;
         shift[m] = (smax > -INFINITY) ? (float)sh : 0.0f;
       }
       __syncthreads();
     }
-    if (total <= kBlock) break;
+    if (total <= nthr) break;
+  }
+  const double Bc = nb.bcol[nodeid];
+  if (ds == 0 && sd.row_lse) {  // r_m = log of row m's sum of pair weights
+    double* rl = sd.row_lse + (size_t)(c - 1) * N;
+    for (int m = m0; m < m1; ++m) {
+      const double a = left_leaf ? (double)alp[m] : -logN;
+      rl[m] = a + Bc + M.trans_lognorm + log(cdf[m]) + (double)shift[m] * kLn2;
+    }
   }
 
-  // ---- row weights: direct, or in log space when a row carries a shift
+  // ---- row weights (each thread its own rows): direct, or in log space when
+  // a row carries a shift
   double G = 0.0;
   if (rescued || kRowShift<DX>) {
     double gmax = -INFINITY;
     for (int m = m0; m < m1; ++m) {
       const double a = left_leaf ? (double)alp[m] : -logN;
       double rho = -INFINITY;
-      if (Astar > -INFINITY && rs[m] > 0.0) rho = a - Astar + (double)shift[m] * kLn2 + log(rs[m]);
+      if (Astar > -INFINITY && cdf[m] > 0.0) rho = a - Astar + (double)shift[m] * kLn2 + log(cdf[m]);
       cdf[m] = rho;
       gmax = fmax(gmax, rho);
     }
@@ -1049,7 +1110,7 @@ __global__ __launch_bounds__(kBlock) void k_sample(
   } else {
     for (int m = m0; m < m1; ++m) {
       double w = 0.0;
-      if (Astar > -INFINITY) w = (left_leaf ? exp((double)alp[m] - Astar) : 1.0) * rs[m];
+      if (Astar > -INFINITY) w = (left_leaf ? exp((double)alp[m] - Astar) : 1.0) * cdf[m];
       cdf[m] = w;
     }
   }
@@ -1081,20 +1142,10 @@ __global__ __launch_bounds__(kBlock) void k_sample(
   __syncthreads();
   const double T = cdf[N - 1];
   const bool degenerate = !(T > 0.0);
-  const double Bc = nb.bcol[nodeid];
-  if (ds == 0) {
-    if (threadIdx.x == 0) {
-      sd.zinc[c - 1] = degenerate ? -INFINITY : Astar + Bc + M.trans_lognorm + G + log(T);
-      const int flags = (degenerate ? kFlagDegenerate : 0) | ((isnan(T) || any_nan) ? kFlagNumeric : 0);
-      if (flags) atomicOr(sd.status, flags);
-    }
-    if (sd.row_lse) {
-      double* rl = sd.row_lse + (size_t)(c - 1) * N;
-      for (int m = threadIdx.x; m < N; m += kBlock) {
-        const double a = left_leaf ? (double)alp[m] : -logN;
-        rl[m] = a + Bc + M.trans_lognorm + log(rs[m]) + (double)shift[m] * kLn2;
-      }
-    }
+  if (ds == 0 && threadIdx.x == 0) {
+    sd.zinc[c - 1] = degenerate ? -INFINITY : Astar + Bc + M.trans_lognorm + G + log(T);
+    const int flags = (degenerate ? kFlagDegenerate : 0) | ((isnan(T) || any_nan) ? kFlagNumeric : 0);
+    if (flags) atomicOr(sd.status, flags);
   }
   // consumer of the merged block [a, b)
   const int cons = nd.consumer;
@@ -1102,7 +1153,7 @@ __global__ __launch_bounds__(kBlock) void k_sample(
   const int ca = nd.a, cb = nd.b;
   const int gA = sd.base + ca, gB = sd.base + cb - 1;
   if (cons >= 0 && crole == 1 && ds == 0) {
-    for (int n = N + threadIdx.x; n < Npad; n += kBlock) put_col_pad<R, DX>(nb, (size_t)cons, Npad, n);
+    for (int n = N + threadIdx.x; n < Npad; n += nthr) put_col_pad<R, DX>(nb, (size_t)cons, Npad, n);
     if (threadIdx.x == 0) nb.bcol[cons] = bmerged[gA];
   }
   // ---- draws
@@ -1111,7 +1162,7 @@ __global__ __launch_bounds__(kBlock) void k_sample(
   int32_t* ancL = sd.anc + (size_t)(c - 1) * 2 * N;
   int32_t* ancR = ancL + N;
   const bool star = sd.star != nullptr;
-  for (int n = n0 + threadIdx.x; n < n1; n += kBlock) {
+  for (int n = n0 + threadIdx.x; n < n1; n += nthr) {
     const Words4 w = philox4x64_10((uint64_t)n, (uint64_t)c, kPurposeCombine, 0ull, sd.seed, kKey1);
     const double u1 = unif53(w.w0), u2 = unif53(w.w1);
     int l, r;
@@ -1129,44 +1180,77 @@ __global__ __launch_bounds__(kBlock) void k_sample(
       R v[DX];
 #pragma unroll
       for (int i = 0; i < DX; ++i) v[i] = rowp[(size_t)l * DX + i];
-      const double target2 = u2 * rs[l];
       const float sh = shift[l];
-      r = -1;
-      {
-        // chunk: first k with prefix_k > target2 (chunk sums read 16 at a time)
-        const R* Pl = (((resc[l >> 5] >> (l & 31)) & 1u) ? Prn : Pn) + (size_t)l * NcP;
-        double pref = 0.0, pref_last = 0.0;
-        int k = -1, klast = 0;
-        for (int kb = 0; kb < Nc && k < 0; kb += 16) {
-          R q[16];
+      const bool lres = (resc[l >> 5] >> (l & 31)) & 1u;
+      const R* Pl = (lres ? Prn : Pn) + (size_t)l * NcP;
+      // the first 16 chunk sums of row l, loaded together with R_l (the row sum
+      // of the row phase; rescued rows: the sum of their chunk sums in Pr)
+      R q[16];
+#pragma unroll
+      for (int g4 = 0; g4 < 4; ++g4) {
+        R t4[4];
+        if (4 * g4 < NcP) load4<R>(Pl + 4 * g4, t4);
+#pragma unroll
+        for (int i = 0; i < 4; ++i) q[4 * g4 + i] = (4 * g4 < NcP) ? t4[i] : (R)0;
+      }
+      const double target2 = u2 * (lres ? row_sum<R>(Pl, Nc, NcP) : Rn[l]);
+      // chunk: first k whose prefix of chunk sums exceeds u2 R_l (16 at a time)
+      double pref = 0.0, pref_last = 0.0, pk = 0.0, plast = 0.0;
+      int k = -1, klast = 0;
+      for (int kb = 0; kb < Nc && k < 0; kb += 16) {
+        if (kb > 0) {
 #pragma unroll
           for (int g4 = 0; g4 < 4; ++g4) {
-            if (kb + 4 * g4 < NcP) {
-              R t4[4];
-              load4<R>(Pl + kb + 4 * g4, t4);
+            R t4[4];
+            if (kb + 4 * g4 < NcP) load4<R>(Pl + kb + 4 * g4, t4);
 #pragma unroll
-              for (int i = 0; i < 4; ++i) q[4 * g4 + i] = t4[i];
-            } else {
-#pragma unroll
-              for (int i = 0; i < 4; ++i) q[4 * g4 + i] = (R)0;
-            }
-          }
-#pragma unroll
-          for (int i = 0; i < 16; ++i) {
-            const int kk = kb + i;
-            if (k < 0 && kk < Nc) {
-              const double p = (double)q[i];
-              if (p > 0.0) { klast = kk; pref_last = pref; }
-              if (target2 < pref + p) k = kk; else pref += p;
-            }
+            for (int i = 0; i < 4; ++i) q[4 * g4 + i] = (kb + 4 * g4 < NcP) ? t4[i] : (R)0;
           }
         }
-        if (k < 0) { k = klast; pref = pref_last; }
-        const double rem = target2 - pref;
-        // recompute chunk k of row l in the rows kernel's order
-        const R* cp = colp + (size_t)k * kChunk * (DX + 1);
-        R acc = (R)0;
-        int lastj = 0;
+#pragma unroll
+        for (int i = 0; i < 16; ++i) {
+          const int kk = kb + i;
+          if (k < 0 && kk < Nc) {
+            const double p = (double)q[i];
+            if (p > 0.0) { klast = kk; pref_last = pref; plast = p; }
+            if (target2 < pref + p) { k = kk; pk = p; } else pref += p;
+          }
+        }
+      }
+      if (k < 0) { k = klast; pref = pref_last; pk = plast; }
+      double rem = target2 - pref;
+      // recompute chunk k of row l in the rows kernel's order
+      const R* cp = colp + (size_t)k * cstr;
+      R acc = (R)0;
+      int lastj = 0;
+      r = -1;
+      bool done = false;
+      if constexpr (sizeof(R) == 4 && DX >= 16) {
+        if (rescale_chunk) {
+          // bf16 plans: the stored chunk sums come from the matrix cores'
+          // expanded form; the recompute here is the direct form, so the
+          // search is rescaled to the recomputed chunk total
+          R ev[kChunk];
+          R tot = (R)0;
+#pragma unroll
+          for (int jj = 0; jj < kChunk; ++jj) {
+            R u[DX];
+#pragma unroll
+            for (int i = 0; i < DX; ++i) u[i] = cp[jj * (DX + 1) + i];
+            ev[jj] = Real<R>::exp2(pair_log2w<R, DX>(u, cp[jj * (DX + 1) + DX], v) - (R)sh);
+            tot += ev[jj];
+          }
+          if (pk > 0.0 && tot > (R)0) rem *= (double)tot / pk;
+#pragma unroll
+          for (int jj = 0; jj < kChunk; ++jj) {
+            acc += ev[jj];
+            if (ev[jj] > (R)0) lastj = jj;
+            if (r < 0 && rem < (double)acc) r = jj;
+          }
+          done = true;
+        }
+      }
+      if (!done) {
 #pragma unroll
         for (int jj = 0; jj < kChunk; ++jj) {
           R u[DX];
@@ -1177,9 +1261,9 @@ __global__ __launch_bounds__(kBlock) void k_sample(
           if (e > (R)0) lastj = jj;
           if (r < 0 && rem < (double)acc) r = jj;
         }
-        if (r < 0) r = lastj;
-        r += k * kChunk;
       }
+      if (r < 0) r = lastj;
+      r += k * kChunk;
       if (r >= N) r = N - 1;  // only reachable through NaN weights
     }
     if (n == 0 && star) {  // conditional combine: slot 0 keeps the star, (0, 0)
@@ -1205,7 +1289,7 @@ __global__ __launch_bounds__(kBlock) void k_sample_lazy(
     const NodeDesc* __restrict__ nodes, const SeriesDesc* __restrict__ series,
     const int32_t* __restrict__ node_list, int node0, int DS, int N, int Npad, int lazy,
     int param, const double* __restrict__ bmerged, NodeBufs nb) {
-  __shared__ double red[2 * kBlock / 64];
+  __shared__ double red[2 * kMaxWaves];
   const int node_local = blockIdx.x / DS;
   const int ds = blockIdx.x - node_local * DS;
   const int nodeid = node_list ? node_list[node_local] : node0 + node_local;
@@ -1366,15 +1450,15 @@ static int launch_level_t(const LevelLaunch& L, hipStream_t st, Timer* tm) {
   tm->begin(1, st);
   if (launch_rows_t<R, DX>(L, st)) return -1;
   tm->end(1, st);
-  size_t lds_samp = (size_t)L.Npad * (2 * sizeof(double) + sizeof(float));
-  const size_t lds_col = (size_t)L.Npad * (DX + 1) * sizeof(R);
+  size_t lds_samp = (size_t)L.Npad * (sizeof(double) + sizeof(float));
+  const size_t lds_col = (size_t)(L.Npad / kChunk) * col_chunk_lds_stride<R, DX>() * sizeof(R);
   const int col_in_lds = (lds_samp + lds_col <= 96 * 1024) ? 1 : 0;
   if (col_in_lds) lds_samp += lds_col;
   tm->begin(2, st);
-  k_sample<R, DX><<<(unsigned)L.nodes * L.DS, kBlock, lds_samp, st>>>(
+  k_sample<R, DX><<<(unsigned)L.nodes * L.DS, (unsigned)L.SB, lds_samp, st>>>(
       L.d_nodes, L.d_series, L.node_list, L.node0, L.DS, L.N, L.Npad, L.Nc, L.NcP,
-      L.CS == 1 ? 1 : 0, col_in_lds, L.force_rescue ? 1 : 0, L.bmerged, (const R*)L.P,
-      (R*)L.Pr, L.Rsum, L.Rshift, L.rescue_count, L.nb);
+      L.CS == 1 ? 1 : 0, col_in_lds, L.force_rescue ? 1 : 0, L.bf16 ? 1 : 0, L.bmerged,
+      (const R*)L.P, (R*)L.Pr, L.Rsum, L.Rshift, L.rescue_count, L.nb);
   tm->end(2, st);
   return 0;
 }

@@ -61,6 +61,7 @@ struct LevelLaunch {
   int RPL, W, RB;       // rows kernel: rows per lane, waves per workgroup, row blocks per combine
   int CS, KC;           // rows kernel: column splits per combine, chunks per split
   int DS;               // sample kernel: workgroups per combine
+  int SB;               // sample kernel: threads per workgroup
   int lazy;             // 0 exact draws; 1 Metropolis-Hastings, 2 rejection (no pair-row pass)
   int lazy_param;       // MH steps, or the rejection proposal cap
   int totalK;
@@ -92,6 +93,18 @@ struct LeafLaunch {
   double* bmerged;
   NodeBufs nb;
 };
+
+// Shape of a level's sampling launch (needs L.N and L.nodes): kBlock threads
+// per workgroup (the exact sampler's fp64 CDF is summed in an order fixed by
+// the workgroup size, so every path uses the same one), and several
+// workgroups per combine when a level has few combines.
+inline void set_sample_shape(LevelLaunch& L) {
+  const int nodes = L.nodes < 1 ? 1 : L.nodes;
+  L.SB = kBlock;
+  const int ds_max = (L.N + 127) / 128 < 1 ? 1 : (L.N + 127) / 128;
+  const int spread = (512 + nodes - 1) / nodes;
+  L.DS = nodes >= 256 ? 1 : (ds_max < spread ? ds_max : spread);
+}
 
 int launch_leaves(const LeafLaunch& L, hipStream_t st, Timer* tm);
 int launch_level(const LevelLaunch& L, hipStream_t st, Timer* tm);

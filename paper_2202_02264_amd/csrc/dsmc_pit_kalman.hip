@@ -1,0 +1,578 @@
+// Parallel-in-time Gaussian proposals (Section 4.1, Algorithm 5) for
+// linear-Gaussian models: the Kalman filter and the RTS smoother as
+// associative scans over the K time points (the element and operator
+// definitions of Sarkka and Garcia-Fernandez, "Temporal parallelization of
+// Bayesian smoothers", 2021), in fp64 on the device, and the smoothing
+// marginals N(m_t, P_t) written into the model as the proposals q_t.  For a
+// linear-Gaussian model the linearisation of Algorithm 5 is exact, so one pass
+// is its fixed point.
+//
+// Filtering element of time t (prior of x_0 for t = 0, transition from
+// x_{t-1} otherwise; observations in whitened form y~ = R^{-1/2}(y - h),
+// H~ = R^{-1/2} H, so the observation noise is N(0, I)):
+//   t >= 1:  S = H~ Q H~^T + I,  G = Q H~^T S^{-1}
+//            A = (I - G H~) F,   b = f + G (y~ - H~ f),   C = (I - G H~) Q
+//            eta = (H~ F)^T S^{-1} (y~ - H~ f),   J = (H~ F)^T S^{-1} H~ F
+//   t = 0:   S = H~ P0 H~^T + I,  G = P0 H~^T S^{-1}
+//            A = 0,  b = m0 + G (y~ - H~ m0),  C = (I - G H~) P0,  eta = 0,  J = 0
+// and (i earlier, j later)
+//   A = A_j M^{-1} A_i,  b = A_j M^{-1} (b_i + C_i eta_j) + b_j,
+//   C = A_j M^{-1} C_i A_j^T + C_j,          M = I + C_i J_j
+//   eta = A_i^T M^{-T} (eta_j - J_j b_i) + eta_i,  J = A_i^T M^{-T} J_j A_i + J_i.
+// The prefix at t holds the filtering mean (b) and covariance (C).
+// Smoothing element of time t (filtering moments m, P):
+//   t < K-1: E = P F^T (F P F^T + Q)^{-1},  g = m - E (F m + f),  L = P - E F P
+//   t = K-1: E = 0,  g = m,  L = P
+// and (i earlier, j later) E = E_i E_j, g = E_i g_j + g_i, L = E_i L_j E_i^T + L_i;
+// the suffix from t holds the smoothing mean (g) and covariance (L).
+//
+// Scans: blocks of kScanBlock elements are scanned sequentially by one
+// workgroup, the block totals are scanned the same way (recursively), and the
+// exclusive block prefixes are applied to every element: span O(log K) with
+// 2 kScanBlock sequential combines per level.  One workgroup per combine; the
+// matrices (d <= 32) live in LDS.
+#include <hip/hip_runtime.h>
+
+#include <cmath>
+#include <vector>
+
+#include "dsmc.h"
+#include "dsmc_host.h"
+#include "dsmc_internal.h"
+
+using namespace dsmc;
+
+namespace {
+
+constexpr int kScanBlock = 16;
+constexpr int kPitThreads = 256;
+
+// ----------------------------------------------------- LDS linear algebra
+// All helpers are called by every thread of the workgroup and end with a
+// barrier; matrices are row-major with the given column count.
+
+// C[n x m] = op(A) op(B) (+ D), op = transpose when the flag is set;
+// A is n x k after op, B is k x m after op.  C must not alias A or B.  Each
+// thread forms a 2 x 2 block of C when n and m are even (half the LDS reads).
+__device__ void mm(double* C, const double* A, bool tA, const double* B, bool tB, int n, int k,
+                   int m, const double* D = nullptr) {
+  auto a = [&](int i, int q) { return tA ? A[q * n + i] : A[i * k + q]; };
+  auto b = [&](int q, int j) { return tB ? B[j * k + q] : B[q * m + j]; };
+  if (((n | m) & 1) == 0) {
+    const int mh = m >> 1;
+    for (int e = threadIdx.x; e < (n >> 1) * mh; e += blockDim.x) {
+      const int i = 2 * (e / mh), j = 2 * (e - (e / mh) * mh);
+      double s00 = D ? D[i * m + j] : 0.0, s01 = D ? D[i * m + j + 1] : 0.0;
+      double s10 = D ? D[(i + 1) * m + j] : 0.0, s11 = D ? D[(i + 1) * m + j + 1] : 0.0;
+      for (int q = 0; q < k; ++q) {
+        const double a0 = a(i, q), a1 = a(i + 1, q), b0 = b(q, j), b1 = b(q, j + 1);
+        s00 = fma(a0, b0, s00);
+        s01 = fma(a0, b1, s01);
+        s10 = fma(a1, b0, s10);
+        s11 = fma(a1, b1, s11);
+      }
+      C[i * m + j] = s00;
+      C[i * m + j + 1] = s01;
+      C[(i + 1) * m + j] = s10;
+      C[(i + 1) * m + j + 1] = s11;
+    }
+  } else {
+    for (int e = threadIdx.x; e < n * m; e += blockDim.x) {
+      const int i = e / m, j = e - (e / m) * m;
+      double s = D ? D[e] : 0.0;
+      for (int q = 0; q < k; ++q) s = fma(a(i, q), b(q, j), s);
+      C[e] = s;
+    }
+  }
+  __syncthreads();
+}
+
+// y[n] = z + sign op(A) x (z optional); A is n x k after op.  y must not alias x.
+__device__ void mv(double* y, const double* A, bool tA, const double* x, int n, int k,
+                   const double* z = nullptr, double sign = 1.0) {
+  for (int i = threadIdx.x; i < n; i += blockDim.x) {
+    double s = 0.0;
+    for (int q = 0; q < k; ++q) s = fma(tA ? A[q * n + i] : A[i * k + q], x[q], s);
+    y[i] = (z ? z[i] : 0.0) + sign * s;
+  }
+  __syncthreads();
+}
+
+__device__ void copy(double* dst, const double* src, int n) {
+  for (int e = threadIdx.x; e < n; e += blockDim.x) dst[e] = src[e];
+  __syncthreads();
+}
+
+__device__ void symmetrize(double* A, int n) {
+  for (int e = threadIdx.x; e < n * n; e += blockDim.x) {
+    const int i = e / n, j = e - (e / n) * n;
+    if (i < j) {
+      const double v = 0.5 * (A[i * n + j] + A[j * n + i]);
+      A[i * n + j] = v;
+      A[j * n + i] = v;
+    }
+  }
+  __syncthreads();
+}
+
+// Inverse of the n x n matrix in aug[:, 0:n] by Gauss-Jordan elimination with
+// partial pivoting; aug is n x 2n, the inverse ends in aug[:, n:2n].
+// `col` holds n values of scratch.
+__device__ void invert(double* aug, int n, double* col) {
+  const int w = 2 * n;
+  for (int e = threadIdx.x; e < n * n; e += blockDim.x) {
+    const int i = e / n, j = e - (e / n) * n;
+    aug[i * w + n + j] = (i == j) ? 1.0 : 0.0;
+  }
+  __shared__ int piv;
+  __syncthreads();
+  for (int c = 0; c < n; ++c) {
+    if (threadIdx.x < 64) {  // pivot: the first row of largest |entry| in column c (n <= 64)
+      const int r = c + (int)threadIdx.x;
+      double v = r < n ? fabs(aug[r * w + c]) : -1.0;
+      int idx = r;
+#pragma unroll
+      for (int o = 32; o > 0; o >>= 1) {
+        const double ov = __shfl_xor(v, o, 64);
+        const int oi = __shfl_xor(idx, o, 64);
+        if (ov > v || (ov == v && oi < idx)) {
+          v = ov;
+          idx = oi;
+        }
+      }
+      if (threadIdx.x == 0) piv = idx;
+    }
+    __syncthreads();
+    const int p = piv;
+    if (p != c)
+      for (int j = threadIdx.x; j < w; j += blockDim.x) {
+        const double t = aug[c * w + j];
+        aug[c * w + j] = aug[p * w + j];
+        aug[p * w + j] = t;
+      }
+    __syncthreads();
+    const double inv_p = 1.0 / aug[c * w + c];
+    __syncthreads();
+    for (int j = threadIdx.x; j < w; j += blockDim.x) aug[c * w + j] *= inv_p;
+    for (int r = threadIdx.x; r < n; r += blockDim.x) col[r] = aug[r * w + c];
+    __syncthreads();
+    for (int e = threadIdx.x; e < n * w; e += blockDim.x) {
+      const int r = e / w, j = e - (e / w) * w;
+      if (r != c) aug[e] = fma(-col[r], aug[c * w + j], aug[e]);
+    }
+    __syncthreads();
+  }
+}
+
+// inverse (n x n) of aug's left block into out (row-major n x n)
+__device__ void inverse_of(double* out, double* aug, const double* M, int n, double* col) {
+  const int w = 2 * n;
+  for (int e = threadIdx.x; e < n * n; e += blockDim.x) {
+    const int i = e / n, j = e - (e / n) * n;
+    aug[i * w + j] = M[e];
+  }
+  __syncthreads();
+  invert(aug, n, col);
+  for (int e = threadIdx.x; e < n * n; e += blockDim.x) {
+    const int i = e / n, j = e - (e / n) * n;
+    out[e] = aug[i * w + n + j];
+  }
+  __syncthreads();
+}
+
+// ---------------------------------------------------------------- records
+// Filtering record: A [d*d], b [d], C [d*d], eta [d], J [d*d].
+__host__ __device__ inline int filter_rec(int d) { return 3 * d * d + 2 * d; }
+// Smoothing record: E [d*d], g [d], L [d*d].
+__host__ __device__ inline int smooth_rec(int d) { return 2 * d * d + d; }
+
+struct FilterOp {
+  static __host__ __device__ int rec(int d) { return filter_rec(d); }
+  // out = x (earlier) combined with y (later); work holds 2 d^2 (aug) + 4 d^2 + 2 d.
+  static __device__ void combine(const double* x, const double* y, double* out, int d,
+                                 double* work) {
+    const int dd = d * d;
+    const double *Ax = x, *bx = x + dd, *Cx = bx + d, *ex = Cx + dd, *Jx = ex + d;
+    const double *Ay = y, *by = y + dd, *Cy = by + d, *ey = Cy + dd, *Jy = ey + d;
+    double *Ao = out, *bo = out + dd, *Co = bo + d, *eo = Co + dd, *Jo = eo + d;
+    double* aug = work;              // 2 dd
+    double* M = aug + 2 * dd;        // dd: I + Cx Jy, then its inverse
+    double* T1 = M + dd;             // dd
+    double* T2 = T1 + dd;            // dd
+    double* W = T2 + dd;             // dd
+    double* v = W + dd;              // d
+    double* col = v + d;             // d
+    mm(M, Cx, false, Jy, false, d, d, d);
+    for (int i = threadIdx.x; i < d; i += blockDim.x) M[i * d + i] += 1.0;
+    __syncthreads();
+    inverse_of(M, aug, M, d, col);                      // M = (I + Cx Jy)^{-1}
+    mm(T1, Ay, false, M, false, d, d, d);               // T1 = Ay M^{-1}
+    mm(Ao, T1, false, Ax, false, d, d, d);
+    mv(v, Cx, false, ey, d, d, bx);                     // v = bx + Cx ey
+    mv(bo, T1, false, v, d, d, by);
+    mm(W, Cx, false, Ay, true, d, d, d);                // W = Cx Ay^T
+    mm(Co, T1, false, W, false, d, d, d, Cy);
+    symmetrize(Co, d);
+    mm(T2, Ax, true, M, true, d, d, d);                 // T2 = Ax^T M^{-T}
+    mv(v, Jy, false, bx, d, d, ey, -1.0);               // v = ey - Jy bx
+    mv(eo, T2, false, v, d, d, ex);
+    mm(W, Jy, false, Ax, false, d, d, d);               // W = Jy Ax
+    mm(Jo, T2, false, W, false, d, d, d, Jx);
+    symmetrize(Jo, d);
+  }
+};
+
+struct SmoothOp {
+  static __host__ __device__ int rec(int d) { return smooth_rec(d); }
+  // The smoothing scan runs backwards in time: x is the later time block
+  // (earlier in scan order), y the earlier one; out = y (earlier in time)
+  // combined with x.  work holds 2 d^2.
+  static __device__ void combine(const double* x, const double* y, double* out, int d,
+                                 double* work) {
+    const int dd = d * d;
+    const double *Ej = x, *gj = x + dd, *Lj = gj + d;   // later in time
+    const double *Ei = y, *gi = y + dd, *Li = gi + d;   // earlier in time
+    double *Eo = out, *go = out + dd, *Lo = go + d;
+    double* T = work;
+    mm(Eo, Ei, false, Ej, false, d, d, d);
+    mv(go, Ei, false, gj, d, d, gi);
+    mm(T, Ei, false, Lj, false, d, d, d);
+    mm(Lo, T, false, Ei, true, d, d, d, Li);
+    symmetrize(Lo, d);
+  }
+};
+
+// --------------------------------------------------------------- elements
+
+// Model matrices in LDS: Q = Qc Qc^T, F, and the whitened observation matrix.
+struct ModelLds {
+  double *Q, *F, *H, *f;
+};
+
+__device__ void load_model(const DevModel& M, ModelLds& L, double* tmp) {
+  const int d = M.dx, dy = M.dy, dd = d * d;
+  copy(tmp, M.Q_chol, dd);
+  mm(L.Q, tmp, false, tmp, true, d, d, d);
+  copy(L.F, M.F, dd);
+  copy(L.H, M.H, dy * d);
+  copy(L.f, M.f, d);
+}
+
+// One workgroup per time point: the filtering element of time t.
+__global__ __launch_bounds__(kPitThreads) void k_filter_elements(const DevModel* __restrict__ Mp,
+                                                                 double* __restrict__ rec) {
+  extern __shared__ double sh[];
+  const DevModel& M = *Mp;
+  const int t = blockIdx.x, d = M.dx, dy = M.dy, dd = d * d;
+  ModelLds L;
+  L.Q = sh;
+  L.F = L.Q + dd;
+  L.H = L.F + dd;
+  L.f = L.H + dy * d;
+  double* P = L.f + d;             // dd: Q (t >= 1) or P0 (t = 0)
+  double* HP = P + dd;             // dy x d
+  double* S = HP + dy * d;         // dy x dy, then its inverse
+  double* G = S + dy * dy;         // d x dy
+  double* IGH = G + d * dy;        // dd
+  double* HF = IGH + dd;           // dy x d
+  double* SHF = HF + dy * d;       // dy x d
+  double* r = SHF + dy * d;        // dy
+  double* aug = r + dy;            // 2 max(d, dy)^2
+  double* col = aug + 2 * (dy > d ? dy * dy : dd);
+  load_model(M, L, aug);
+  double* out = rec + (size_t)t * filter_rec(d);
+  double *A = out, *b = out + dd, *C = b + d, *eta = C + dd, *J = eta + d;
+  const double* yt = M.y + (size_t)t * dy;
+  if (t == 0) {
+    copy(aug, M.P0_chol, dd);
+    mm(P, aug, false, aug, true, d, d, d);
+  } else {
+    copy(P, L.Q, dd);
+  }
+  mm(HP, L.H, false, P, false, dy, d, d);                    // H P
+  mm(S, HP, false, L.H, true, dy, d, dy);                    // H P H^T
+  for (int i = threadIdx.x; i < dy; i += blockDim.x) S[i * dy + i] += 1.0;
+  __syncthreads();
+  inverse_of(S, aug, S, dy, col);                            // S^{-1}
+  mm(G, HP, true, S, false, d, dy, dy);                      // G = P H^T S^{-1}
+  mm(IGH, G, false, L.H, false, d, dy, d);                   // G H
+  for (int e = threadIdx.x; e < dd; e += blockDim.x) {
+    const int i = e / d, j = e - (e / d) * d;
+    IGH[e] = (i == j ? 1.0 : 0.0) - IGH[e];
+  }
+  __syncthreads();
+  mm(C, IGH, false, P, false, d, d, d);                      // (I - G H) P
+  symmetrize(C, d);
+  if (t == 0) {
+    mv(r, L.H, false, M.m0, dy, d, yt, -1.0);                // y - H m0
+    mv(b, G, false, r, d, dy, M.m0);                         // m0 + G r
+    for (int e = threadIdx.x; e < dd; e += blockDim.x) {
+      A[e] = 0.0;
+      J[e] = 0.0;
+    }
+    for (int i = threadIdx.x; i < d; i += blockDim.x) eta[i] = 0.0;
+    __syncthreads();
+    return;
+  }
+  mm(A, IGH, false, L.F, false, d, d, d);                    // (I - G H) F
+  mv(r, L.H, false, L.f, dy, d, yt, -1.0);                   // y - H f
+  mv(b, G, false, r, d, dy, L.f);                            // f + G r
+  mm(HF, L.H, false, L.F, false, dy, d, d);                  // H F
+  mm(SHF, S, false, HF, false, dy, dy, d);                   // S^{-1} H F
+  mv(eta, SHF, true, r, d, dy);                              // (H F)^T S^{-1} r
+  mm(J, HF, true, SHF, false, d, dy, d);                     // (H F)^T S^{-1} H F
+  symmetrize(J, d);
+}
+
+// One workgroup per time point: the smoothing element of time t from the
+// filtering moments (prefix record t), stored at scan position K-1-t.
+__global__ __launch_bounds__(kPitThreads) void k_smooth_elements(const DevModel* __restrict__ Mp,
+                                                                 const double* __restrict__ frec,
+                                                                 double* __restrict__ srec) {
+  extern __shared__ double sh[];
+  const DevModel& M = *Mp;
+  const int t = blockIdx.x, K = M.K, d = M.dx, dy = M.dy, dd = d * d;
+  ModelLds L;
+  L.Q = sh;
+  L.F = L.Q + dd;
+  L.H = L.F + dd;
+  L.f = L.H + dy * d;
+  double* P = L.f + d;
+  double* FP = P + dd;
+  double* Pp = FP + dd;
+  double* E = Pp + dd;
+  double* m = E + dd;
+  double* v = m + d;
+  double* aug = v + d;                                       // 2 dd
+  double* col = aug + 2 * dd;
+  load_model(M, L, aug);
+  const double* fr = frec + (size_t)t * filter_rec(d);
+  copy(m, fr + dd, d);
+  copy(P, fr + dd + d, dd);
+  double* out = srec + (size_t)(K - 1 - t) * smooth_rec(d);
+  double *Eo = out, *go = out + dd, *Lo = go + d;
+  if (t == K - 1) {
+    for (int e = threadIdx.x; e < dd; e += blockDim.x) {
+      Eo[e] = 0.0;
+      Lo[e] = P[e];
+    }
+    for (int i = threadIdx.x; i < d; i += blockDim.x) go[i] = m[i];
+    __syncthreads();
+    return;
+  }
+  mm(FP, L.F, false, P, false, d, d, d);                      // F P
+  mm(Pp, FP, false, L.F, true, d, d, d, L.Q);                 // F P F^T + Q
+  symmetrize(Pp, d);
+  inverse_of(Pp, aug, Pp, d, col);
+  mm(E, FP, true, Pp, false, d, d, d);                        // P F^T Pp^{-1}
+  copy(Eo, E, dd);
+  mv(v, L.F, false, m, d, d, L.f);                            // F m + f
+  mv(go, E, false, v, d, d, m, -1.0);                         // m - E (F m + f)
+  mm(Lo, E, false, FP, false, d, d, d);                       // E F P
+  for (int e = threadIdx.x; e < dd; e += blockDim.x) Lo[e] = P[e] - Lo[e];
+  __syncthreads();
+  symmetrize(Lo, d);
+}
+
+// ------------------------------------------------------------------ scans
+
+// In-place inclusive scan of each block of kScanBlock records of `lvl` (n
+// records) by one workgroup; the block's total goes to next[block].
+template <class Op>
+__global__ __launch_bounds__(kPitThreads) void k_scan_local(double* __restrict__ lvl, int n, int d,
+                                                            double* __restrict__ next) {
+  extern __shared__ double sh[];
+  const int R = Op::rec(d);
+  double* run = sh;
+  double* y = run + R;
+  double* out = y + R;
+  double* work = out + R;
+  const int first = blockIdx.x * kScanBlock, last = min(n, first + kScanBlock);
+  copy(run, lvl + (size_t)first * R, R);
+  for (int i = first + 1; i < last; ++i) {
+    copy(y, lvl + (size_t)i * R, R);
+    Op::combine(run, y, out, d, work);
+    for (int e = threadIdx.x; e < R; e += blockDim.x) {
+      run[e] = out[e];
+      lvl[(size_t)i * R + e] = out[e];
+    }
+    __syncthreads();
+  }
+  if (next)
+    for (int e = threadIdx.x; e < R; e += blockDim.x) next[(size_t)blockIdx.x * R + e] = run[e];
+}
+
+// Record i (block g >= 1) := prefix of blocks 0..g-1 (upper[g-1]) combined with it.
+template <class Op>
+__global__ __launch_bounds__(kPitThreads) void k_scan_apply(double* __restrict__ lvl, int n, int d,
+                                                            const double* __restrict__ upper) {
+  extern __shared__ double sh[];
+  const int R = Op::rec(d);
+  const int i = kScanBlock + blockIdx.x;
+  if (i >= n) return;
+  double* x = sh;
+  double* y = x + R;
+  double* out = y + R;
+  double* work = out + R;
+  copy(x, upper + (size_t)(i / kScanBlock - 1) * R, R);
+  copy(y, lvl + (size_t)i * R, R);
+  Op::combine(x, y, out, d, work);
+  for (int e = threadIdx.x; e < R; e += blockDim.x) lvl[(size_t)i * R + e] = out[e];
+}
+
+// ---------------------------------------------------------------- factors
+
+// One workgroup per time point: q_t = N(g, L) of the smoothing suffix: mean,
+// Cholesky factor, its inverse and the log normaliser, into the model.
+__global__ __launch_bounds__(kPitThreads) void k_proposal_factors(const DevModel* __restrict__ Mp,
+                                                                  const double* __restrict__ srec) {
+  extern __shared__ double sh[];
+  const DevModel& M = *Mp;
+  const int t = blockIdx.x, K = M.K, d = M.dx, dd = d * d;
+  const double* r = srec + (size_t)(K - 1 - t) * smooth_rec(d);
+  double* P = sh;          // dd
+  double* Lc = P + dd;     // dd
+  double* Li = Lc + dd;    // dd
+  copy(P, r + dd + d, dd);
+  // Cholesky by one thread per row of the current column (column by column)
+  for (int e = threadIdx.x; e < dd; e += blockDim.x) Lc[e] = 0.0;
+  __syncthreads();
+  for (int j = 0; j < d; ++j) {
+    if (threadIdx.x == 0) {
+      double s = P[j * d + j];
+      for (int q = 0; q < j; ++q) s -= Lc[j * d + q] * Lc[j * d + q];
+      Lc[j * d + j] = sqrt(fmax(s, 0.0));
+    }
+    __syncthreads();
+    for (int i = j + 1 + threadIdx.x; i < d; i += blockDim.x) {
+      double s = P[i * d + j];
+      for (int q = 0; q < j; ++q) s -= Lc[i * d + q] * Lc[j * d + q];
+      Lc[i * d + j] = s / Lc[j * d + j];
+    }
+    __syncthreads();
+  }
+  // inverse of the lower-triangular factor, one column per thread
+  for (int j = threadIdx.x; j < d; j += blockDim.x) {
+    for (int i = 0; i < d; ++i) Li[i * d + j] = 0.0;
+    Li[j * d + j] = 1.0 / Lc[j * d + j];
+    for (int i = j + 1; i < d; ++i) {
+      double s = 0.0;
+      for (int q = j; q < i; ++q) s += Lc[i * d + q] * Li[q * d + j];
+      Li[i * d + j] = -s / Lc[i * d + i];
+    }
+  }
+  __syncthreads();
+  double* qm = (double*)M.q_mean + (size_t)t * d;
+  double* qc = (double*)M.q_chol + (size_t)t * dd;
+  double* qi = (double*)M.q_inv + (size_t)t * dd;
+  for (int i = threadIdx.x; i < d; i += blockDim.x) qm[i] = r[dd + i];
+  for (int e = threadIdx.x; e < dd; e += blockDim.x) {
+    qc[e] = Lc[e];
+    qi[e] = Li[e];
+  }
+  if (threadIdx.x == 0) {
+    double s = 0.0;
+    for (int i = 0; i < d; ++i) s += log(Lc[i * d + i]);
+    ((double*)M.q_lognorm)[t] = -s - 0.5 * d * 1.8378770664093453;
+  }
+}
+
+size_t filter_lds(int d, int dy) {
+  const int dd = d * d, m = dy > d ? dy : d;
+  return sizeof(double) * (size_t)(3 * dd + dy * d + d + dd + dy * d + dy * dy + d * dy + dd +
+                                   2 * dy * d + dy + d + 2 * m * m + m + 8);
+}
+size_t smooth_lds(int d, int dy) {
+  const int dd = d * d;
+  return sizeof(double) * (size_t)(2 * dd + dy * d + d + 4 * dd + 2 * d + 2 * dd + d + 8);
+}
+template <class Op>
+size_t scan_lds(int d) {
+  return sizeof(double) * (size_t)(3 * Op::rec(d) + 6 * d * d + 2 * d + 8);
+}
+
+// Multi-level blocked inclusive scan of n records at `base`; `levels` holds
+// the block totals of every level after the first.
+template <class Op>
+int scan(double* base, int n, int d, double* levels, hipStream_t st) {
+  const int R = Op::rec(d);
+  std::vector<double*> lv{base};
+  std::vector<int> cnt{n};
+  double* p = levels;
+  while (cnt.back() > kScanBlock) {
+    const int m = (cnt.back() + kScanBlock - 1) / kScanBlock;
+    lv.push_back(p);
+    cnt.push_back(m);
+    p += (size_t)m * R;
+  }
+  const size_t lds = scan_lds<Op>(d);
+  for (size_t j = 0; j < lv.size(); ++j) {
+    const int blocks = (cnt[j] + kScanBlock - 1) / kScanBlock;
+    k_scan_local<Op><<<blocks, kPitThreads, lds, st>>>(lv[j], cnt[j], d,
+                                                       j + 1 < lv.size() ? lv[j + 1] : nullptr);
+    HIP_TRY(hipGetLastError());
+  }
+  for (int j = (int)lv.size() - 2; j >= 0; --j) {
+    if (cnt[j] > kScanBlock) {
+      k_scan_apply<Op><<<cnt[j] - kScanBlock, kPitThreads, lds, st>>>(lv[j], cnt[j], d, lv[j + 1]);
+      HIP_TRY(hipGetLastError());
+    }
+  }
+  return DSMC_OK;
+}
+
+size_t level_records(int n) {
+  size_t s = 0;
+  while (n > kScanBlock) {
+    n = (n + kScanBlock - 1) / kScanBlock;
+    s += n;
+  }
+  return s;
+}
+
+}  // namespace
+
+extern "C" int dsmc_model_gaussian_proposals(dsmc_model_t* m, void* stream) {
+  if (!m || !m->dev) return fail(DSMC_EINVAL, "null model");
+  if (m->obs_kind != DSMC_OBS_LINEAR_GAUSSIAN || m->prop_kind != DSMC_PROPOSAL_GAUSSIAN)
+    return fail(DSMC_EUNSUPPORTED,
+                "parallel-in-time Gaussian proposals need a linear-Gaussian potential and "
+                "Gaussian proposals");
+  if (m->dy > DSMC_MAX_DX) return fail(DSMC_EUNSUPPORTED, "d_y must be <= %d", DSMC_MAX_DX);
+  const int K = m->K, d = m->dx, dy = m->dy;
+  const size_t fr = filter_rec(d), sr = smooth_rec(d);
+  const size_t need = sizeof(double) * ((size_t)K * fr + level_records(K) * fr + (size_t)K * sr +
+                                        level_records(K) * sr);
+  if (!m->pit_ws || m->pit_bytes < need) {
+    if (m->pit_ws) (void)hipFree(m->pit_ws);
+    m->pit_ws = nullptr;
+    m->pit_bytes = 0;
+    HIP_TRY(hipMalloc(&m->pit_ws, need));
+    m->pit_bytes = need;
+  }
+  double* frec = (double*)m->pit_ws;
+  double* flev = frec + (size_t)K * fr;
+  double* srec = flev + level_records(K) * fr;
+  double* slev = srec + (size_t)K * sr;
+  hipStream_t st = (hipStream_t)stream;
+  k_filter_elements<<<K, kPitThreads, filter_lds(d, dy), st>>>(m->dev, frec);
+  HIP_TRY(hipGetLastError());
+  int rc = scan<FilterOp>(frec, K, d, flev, st);
+  if (rc) return rc;
+  k_smooth_elements<<<K, kPitThreads, smooth_lds(d, dy), st>>>(m->dev, frec, srec);
+  HIP_TRY(hipGetLastError());
+  rc = scan<SmoothOp>(srec, K, d, slev, st);
+  if (rc) return rc;
+  k_proposal_factors<<<K, kPitThreads, sizeof(double) * 3 * (size_t)d * d + 64, st>>>(m->dev, srec);
+  HIP_TRY(hipGetLastError());
+  return DSMC_OK;
+}
+
+extern "C" int dsmc_model_read_proposals(const dsmc_model_t* m, double* q_mean, double* q_chol) {
+  if (!m || !m->dev || !q_mean || !q_chol) return fail(DSMC_EINVAL, "null argument");
+  const size_t K = (size_t)m->K, d = (size_t)m->dx;
+  HIP_TRY(hipDeviceSynchronize());
+  HIP_TRY(hipMemcpy(q_mean, m->hdr.q_mean, K * d * sizeof(double), hipMemcpyDeviceToHost));
+  HIP_TRY(hipMemcpy(q_chol, m->hdr.q_chol, K * d * d * sizeof(double), hipMemcpyDeviceToHost));
+  return DSMC_OK;
+}

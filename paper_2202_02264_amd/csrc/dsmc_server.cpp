@@ -325,9 +325,8 @@ int tick(dsmc_server_impl* s, Class* c) {
     L.Rsum = c->Rsum;
     L.Rshift = c->Rshift;
     L.nb = c->nb;
+    set_sample_shape(L);
     set_tile(L, heuristic_tile(nodes, N, c->Nc, c->DX < 8));
-    const int ds_max = std::max(1, (N + 127) / 128);
-    L.DS = nodes >= 256 ? 1 : (int)std::min<long>(ds_max, (512 + nodes - 1) / nodes);
     if (launch_level(L, c->stream, &s->no_timer)) return fail(DSMC_EUNSUPPORTED, "no combine kernel");
     HIP_TRY(hipGetLastError());
   }

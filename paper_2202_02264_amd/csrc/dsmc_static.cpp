@@ -276,10 +276,9 @@ extern "C" int dsmc_smooth_static(const dsmc_model_t* model, int N, int precisio
       L.force_rescue = false;
       L.rescue_count = nullptr;
       L.nb = nb;
-      const int ds_max = std::max(1, (N + 127) / 128);
-      L.DS = nodes >= 256 ? 1 : (int)std::min<long>(ds_max, (512 + nodes - 1) / nodes);
       L.lazy = 0;
       L.lazy_param = 0;
+      set_sample_shape(L);
       set_tile(L, heuristic_tile(nodes, N, Nc, DX < 8));
       if (launch_level(L, st, &untimed)) return fail(DSMC_EUNSUPPORTED, "no combine kernel for d_x");
       HIP_TRY(hipGetLastError());

@@ -103,6 +103,8 @@ def _load() -> C.CDLL:
     sig = {
         "dsmc_model_create": (i, [C.POINTER(dsmc_model_desc), C.POINTER(vp)]),
         "dsmc_model_check": (i, [C.POINTER(dsmc_model_desc)]),
+        "dsmc_model_gaussian_proposals": (i, [vp, vp]),
+        "dsmc_model_read_proposals": (i, [vp, _dp, _dp]),
         "dsmc_model_destroy": (None, [vp]),
         "dsmc_model_K": (i, [vp]),
         "dsmc_plan": (i, [C.POINTER(dsmc_plan_desc), C.POINTER(vp)]),
@@ -220,6 +222,25 @@ class Model:
             self.handle = None
 
 
+def dsmc_model_gaussian_proposals(model: Model, stream=None) -> None:
+    """Algorithm 5 on the device for a linear-Gaussian model: the parallel-in-time
+    Kalman filter and RTS smoother set q_t to the smoothing marginals."""
+    import torch
+    if stream is None:
+        stream = torch.cuda.current_stream()
+    _check(_lib.dsmc_model_gaussian_proposals(model.handle, C.c_void_p(stream.cuda_stream)),
+           "dsmc_model_gaussian_proposals")
+
+
+def dsmc_model_read_proposals(model: Model):
+    """(q_mean (K, d_x), q_chol (K, d_x, d_x)) of the device model, as numpy fp64."""
+    qm = np.zeros((model.K, model.d_x))
+    qc = np.zeros((model.K, model.d_x, model.d_x))
+    _check(_lib.dsmc_model_read_proposals(model.handle, _ptr(qm), _ptr(qc)),
+           "dsmc_model_read_proposals")
+    return qm, qc
+
+
 def dsmc_model_create(spec, callbacks: Optional[dsmc_model_callbacks] = None) -> Model:
     return Model(spec, callbacks)
 
@@ -228,7 +249,7 @@ class Plan:
     """dsmc_plan: workspace for series of up to max_K points (sum max_total_K)."""
 
     def __init__(self, N: int, d_x: int, max_K: int, max_total_K: int = 0,
-                 precision: int = DSMC_FP32, profile: bool = False, autotune: bool = True,
+                 precision: int = DSMC_FP32, profile: bool = False, autotune: bool = False,
                  graph: bool = False, rescue_all: bool = False, stream=None,
                  resampling: int = 0, lazy_param: int = 0):
         import torch

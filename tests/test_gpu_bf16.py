@@ -1,12 +1,15 @@
 """GPU: the bf16 matrix-core pair-row path (DSMC_BF16, d_x = 16 and 32).
 
 Its results are not expected to equal the fp64 oracle to fp32 tolerance: the
-whitened boundary coordinates are rounded to bf16 (8-bit significand), which
-moves each pair's log weight by about 2 ||u - v|| ||du - dv||, a few hundredths
-of a unit at these models' scales.  The tests state the errors (row log-sums,
-increments, index agreement; teacher-forced against the oracle) and bound
-them; everything that does not depend on the pair weights (leaves, gather,
-ancestry bookkeeping, log L = sum of the parts) is checked exactly.
+pair weight's quadratic form is formed as ||u||^2 + ||v||^2 - 2 u.v with the
+dot product from split bf16 operands (hi + remainder, about 16 significant
+bits) and fp32 accumulation, so each pair's log weight moves by the dropped
+remainder product and the cancellation of the expanded form.  The tests state
+the errors (row log-sums, increments, index agreement; teacher-forced against
+the oracle) and bound them: median row log-sum error at most 0.005 and maximum
+at most 0.03 (natural log), at least 97 % of the index draws equal; everything
+that does not depend on the pair weights (leaves, gather, ancestry
+bookkeeping, log L = sum of the parts) is checked exactly.
 """
 import numpy as np
 import pytest
@@ -37,17 +40,17 @@ def _errors(spec, N, seed, select=None, leaves=True):
 def test_bf16_dx32_errors_vs_oracle():
     """d_x = 32 (the precision workload's model, K = 64, N = 512)."""
     er, ez, agree = _errors(W.lg_highdim(K=64, seed=31), 512, 5)
-    assert np.median(er) < 0.1 and er.max() < 1.0
-    assert ez.max() < 0.5
-    assert agree > 0.5
+    assert np.median(er) <= 0.005 and er.max() <= 0.03
+    assert ez.max() <= 0.03
+    assert agree >= 0.97
 
 
 def test_bf16_dx16_errors_vs_oracle():
     """d_x = 12, padded to 16 (one matrix-core instruction per 32 x 32 block)."""
     er, ez, agree = _errors(W.lg_highdim(K=40, d_x=12, d_y=4, seed=32), 256, 6)
-    assert np.median(er) < 0.1 and er.max() < 1.0
-    assert ez.max() < 0.5
-    assert agree > 0.5
+    assert np.median(er) <= 0.005 and er.max() <= 0.03
+    assert ez.max() <= 0.03
+    assert agree >= 0.97
 
 
 def test_bf16_smoothed_means_vs_rts():
@@ -82,8 +85,9 @@ def test_bf16_precision_workload_sampled():
     spec = W.lg_highdim()
     chosen = {1, 32 * 33, 1024}
     er, ez, agree = _errors(spec, 4096, 1, select=lambda a, c, b: c in chosen, leaves=False)
-    assert np.median(er) < 0.1 and er.max() < 1.0
-    assert ez.max() < 0.5
+    assert np.median(er) <= 0.005 and er.max() <= 0.03
+    assert ez.max() <= 0.03
+    assert agree >= 0.97
 
 
 def test_bf16_rescue_paths():
@@ -96,4 +100,4 @@ def test_bf16_rescue_paths():
     rep = teacher_forced(spec, 256, 8, g, None)
     er = np.concatenate(rep.abs_err_row)
     log(f"bf16 rescue-all: |d row_lse| median {np.median(er):.3g} max {er.max():.3g}")
-    assert np.median(er) < 0.1 and er.max() < 1.0
+    assert np.median(er) <= 0.005 and er.max() <= 0.03
