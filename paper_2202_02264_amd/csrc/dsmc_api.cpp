@@ -357,9 +357,11 @@ extern "C" int dsmc_model_create(const dsmc_model_desc* d, dsmc_model_t** out) {
 
   // pack: header, then arrays (each 256-byte aligned)
   std::vector<double> P0c(d->P0_chol, d->P0_chol + dd), Qc(d->Q_chol, d->Q_chol + dd);
+  const int DXp = padded_dx(dx);
+  std::vector<double> lrec(DXp >= 8 ? leafrec_size(K, DXp) : 0, 0.0);  // filled on the device
   std::vector<const std::vector<double>*> arrs = {&m0, &P0i, &F,  &f,  &Qi,  &H,    &y,
                                                   &qm, &qc,  &qi, &qln, &Wcol, &Wrow, &woff,
-                                                  &P0c, &Qc};
+                                                  &P0c, &Qc, &lrec};
   size_t off = (sizeof(DevModel) + 255) & ~size_t(255);
   std::vector<size_t> offs;
   for (auto* a : arrs) {
@@ -405,6 +407,7 @@ extern "C" int dsmc_model_create(const dsmc_model_desc* d, dsmc_model_t** out) {
   hdr.wcol_off = P(13);
   hdr.P0_chol = P(14);
   hdr.Q_chol = P(15);
+  hdr.leafrec = lrec.empty() ? nullptr : P(16);
   std::memcpy(blob.data(), &hdr, sizeof hdr);
   e = hipMemcpy(m->dmem, blob.data(), off, hipMemcpyHostToDevice);
   if (e != hipSuccess) {
@@ -414,6 +417,16 @@ extern "C" int dsmc_model_create(const dsmc_model_desc* d, dsmc_model_t** out) {
   }
   m->dev = (DevModel*)m->dmem;
   m->hdr = hdr;
+  if (hdr.leafrec) {
+    launch_leaf_records(m->dev, (double*)hdr.leafrec, K, DXp, nullptr);
+    e = hipGetLastError();
+    if (e == hipSuccess) e = hipStreamSynchronize(nullptr);
+    if (e != hipSuccess) {
+      hipFree(m->dmem);
+      delete m;
+      return fail(DSMC_EDEVICE, "leaf records: %s", hipGetErrorString(e));
+    }
+  }
   m->dy = dy;
   m->obs_kind = d->obs_kind;
   m->prop_kind = d->proposal_kind;

@@ -34,7 +34,22 @@ struct DevModel {
   const double* wcol_off; // [dx]     = kappa Q_inv f
   const double* P0_chol;  // [dx][dx] prior Cholesky factor
   const double* Q_chol;   // [dx][dx] transition Cholesky factor
+  const double* leafrec;  // leaf records (padded d_x >= 8; leafrec_stride), else null
 };
+
+// Leaf records of a model whose padded state dimension DX is at least 8: at
+// t * leafrec_stride(DX), q_chol[t] and its inverse (DX x DX, zero padded,
+// lower triangular), then q_mean[t], the row offset of boundary t + 1
+// (kappa Q^{-1/2} f - Wcol q_mean[t + 1] + Wrow q_mean[t]) and the whitened
+// y_t - H q_mean[t] (DX each, zero padded); after the K records, Wcol, Wrow and
+// the whitened H (DX x DX each, zero padded).  Built on the device from the
+// model's arrays whenever those change.
+__host__ __device__ constexpr int leafrec_stride(int DX) {
+  return (2 * DX * DX + 3 * DX + 31) / 32 * 32;
+}
+inline size_t leafrec_size(int K, int DX) {
+  return (size_t)K * leafrec_stride(DX) + 3 * (size_t)DX * DX;
+}
 
 // One series of a (batched) run.
 struct SeriesDesc {

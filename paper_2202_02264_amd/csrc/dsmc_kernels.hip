@@ -114,6 +114,61 @@ int launch_leaves(const LeafLaunch& L, hipStream_t st, Timer* tm) {
   return -1;
 }
 
+// Leaf records (layout at leafrec_stride) of one model: one workgroup per time
+// t, and workgroup K for the time-invariant matrices.
+__global__ __launch_bounds__(kBlock) void k_leaf_records(const DevModel* __restrict__ Mp,
+                                                         double* __restrict__ rec, int DX) {
+  const DevModel& M = *Mp;
+  const int K = M.K, dx = M.dx, dy = M.dy, t = blockIdx.x;
+  const int S = leafrec_stride(DX);
+  const bool lg_obs = M.obs_kind == 0 && dy <= DX;
+  if (t == K) {
+    double* inv = rec + (size_t)K * S;
+    for (int e = threadIdx.x; e < DX * DX; e += blockDim.x) {
+      const int i = e / DX, j = e - (e / DX) * DX;
+      const bool in = i < dx && j < dx;
+      inv[e] = (in && j <= i) ? M.Wcol[i * dx + j] : 0.0;
+      inv[DX * DX + e] = in ? M.Wrow[i * dx + j] : 0.0;
+      inv[2 * DX * DX + e] = (lg_obs && i < dy && j < dx) ? M.H[i * dx + j] : 0.0;
+    }
+    return;
+  }
+  double* r = rec + (size_t)t * S;
+  const double* qc = M.q_chol + (size_t)t * dx * dx;
+  const double* qi = M.q_inv + (size_t)t * dx * dx;
+  const double* qm = M.q_mean + (size_t)t * dx;
+  for (int e = threadIdx.x; e < DX * DX; e += blockDim.x) {
+    const int i = e / DX, j = e - (e / DX) * DX;
+    const bool in = i < dx && j <= i;
+    r[e] = in ? qc[i * dx + j] : 0.0;
+    r[DX * DX + e] = in ? qi[i * dx + j] : 0.0;
+  }
+  for (int i = threadIdx.x; i < S - 2 * DX * DX; i += blockDim.x) {
+    double v = 0.0;
+    if (i < DX) {  // q_mean[t]
+      v = i < dx ? qm[i] : 0.0;
+    } else if (i < 2 * DX) {  // row offset of boundary t + 1
+      const int k = i - DX;
+      if (k < dx && t + 1 < K) {
+        v = M.wcol_off[k];
+        for (int j = 0; j < dx; ++j)
+          v += M.Wrow[k * dx + j] * qm[j] - M.Wcol[k * dx + j] * qm[dx + j];
+      }
+    } else if (i < 3 * DX) {  // whitened y_t - H q_mean[t]
+      const int k = i - 2 * DX;
+      if (lg_obs && k < dy) {
+        v = M.y[(size_t)t * dy + k];
+        for (int j = 0; j < dx; ++j) v -= M.H[k * dx + j] * qm[j];
+      }
+    }
+    r[2 * DX * DX + i] = v;
+  }
+}
+
+void launch_leaf_records(const DevModel* dev, double* rec, int K, int DX, hipStream_t st) {
+  k_leaf_records<<<K + 1, kBlock, 0, st>>>(dev, rec, DX);
+}
+
 void launch_clear_status(const SeriesDesc* d_series, int s0, int B, hipStream_t st) {
   k_clear_status<<<(B + kBlock - 1) / kBlock, kBlock, 0, st>>>(d_series, s0, B);
 }

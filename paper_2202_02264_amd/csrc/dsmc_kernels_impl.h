@@ -34,6 +34,19 @@ namespace dsmc {
 template <int DX>
 inline constexpr bool kRowShift = DX >= 8;
 
+// Four consecutive values, one 16-byte (fp32) or two (fp64) vector stores.
+template <typename R>
+__device__ __forceinline__ void store4(R* p, R a, R b, R c, R d);
+template <>
+__device__ __forceinline__ void store4<float>(float* p, float a, float b, float c, float d) {
+  *(float4*)p = make_float4(a, b, c, d);
+}
+template <>
+__device__ __forceinline__ void store4<double>(double* p, double a, double b, double c, double d) {
+  ((double2*)p)[0] = make_double2(a, b);
+  ((double2*)p)[1] = make_double2(c, d);
+}
+
 // Whitened column coordinates of a right-block particle x at boundary c:
 // u = Wcol (x - q_mean[c]).
 template <int DX>
@@ -150,58 +163,69 @@ __device__ __forceinline__ void copy_row(const NodeBufs& nb, size_t node, int Np
   }
 }
 
-// Table entries for DX >= 8, written coordinate by coordinate (the matrix row
-// loop is not unrolled, so only x stays in registers).  bf16 plans also write
-// the split bf16 operands (2u for columns, v for rows) and the fp32 squared
-// norm of the entry.  Wc, Wr: the whitening matrices; column table:
-// qm = q_mean[t]; row table: woff = kappa Q_inv f - Wcol q_mean[t + 1] (formed
-// once per time); any address space (the leaf kernel passes copies in LDS).
+// Matrix operands of the leaf kernel for DX >= 8: the model's per-time leaf
+// records (zero-padded to DX x DX, laid out by leafrec_stride) read through the
+// constant address space, so that every entry, being wave-uniform, reaches the
+// FMAs through scalar registers instead of LDS or vector loads.
+typedef const __attribute__((address_space(4))) double cdouble;
+
+// p, opaque to the optimiser: loads through it stay where they are written
+// instead of being hoisted out of the particle loop (which would hold every
+// matrix entry in registers at once).
+__device__ __forceinline__ cdouble* opaque(cdouble* p) {
+  asm volatile("" : "+s"(p));
+  return p;
+}
+
+// A wave-uniform pointer, held in scalar registers.
+__device__ __forceinline__ cdouble* uniform_ptr(const double* p) {
+  const uint64_t v = (uint64_t)p;
+  const uint64_t lo = (uint32_t)__builtin_amdgcn_readfirstlane((int)(uint32_t)v);
+  const uint64_t hi = (uint32_t)__builtin_amdgcn_readfirstlane((int)(uint32_t)(v >> 32));
+  return (cdouble*)((hi << 32) | lo);
+}
+
+// Whitened coordinates of one particle for one boundary, from d = x - q_mean[t]
+// (zero past d_x): columns u = Wcol d (Wcol lower triangular), rows
+// v = Wrow d + off.  Stores the R-rounded coordinates at dst (16-byte vector
+// stores where `aligned`), and in bf16 plans (dsth non-null) the split operands
+// (2u for columns, v for rows; DX/2 words of hi pairs, then DX/2 of lo pairs)
+// and the fp32 squared norm of the rounded entry at *dstn.
 template <typename R, int DX, bool kRow>
-__device__ __forceinline__ void stream_table(const NodeBufs& nb, const double* Wc, const double* Wr,
-                                             const double* woff, const double* qm, int, size_t g,
-                                             int N, int n, const double (&x)[DX]) {
-  constexpr int dx = DX;  // zero-padded matrices and vectors
-  R* tp = (R*)(kRow ? nb.trow : nb.tcol) + (g * N + n) * DX;
-  uint32_t* th = nullptr;
-  if constexpr (sizeof(R) == 4 && DX >= 16)
-    th = (uint32_t*)(kRow ? nb.trowh : nb.tcolh);
-  if (th) th += (g * N + n) * DX;  // DX / 2 words of hi pairs, then DX / 2 of lo pairs
+__device__ __forceinline__ void emit_coords(cdouble* Wm, cdouble* off, const double (&d)[DX],
+                                            R* dst, bool aligned, uint32_t* dsth, float* dstn) {
   double nrm = 0.0;
-#pragma unroll 1
-  for (int i = 0; i < DX; i += 2) {
-    double s2[2];
 #pragma unroll
-    for (int k = 0; k < 2; ++k) {
-      const int ii = i + k;
-      double acc = 0.0;
-      if (ii < dx) {
-        if (kRow) {  // woff here holds kappa Q_inv f - Wcol q_mean[t + 1] (per time)
-          acc = woff[ii];
+  for (int i0 = 0; i0 < DX; i0 += 4) {
+    R r4[4];
 #pragma unroll
-          for (int j = 0; j < DX; ++j)
-            if (j < dx) acc += Wr[ii * dx + j] * x[j];
-        } else {
+    for (int k = 0; k < 4; ++k) {
+      const int i = i0 + k;
+      double acc = kRow ? off[i] : 0.0;
 #pragma unroll
-          for (int j = 0; j < DX; ++j)
-            if (j < dx) acc += Wc[ii * dx + j] * (x[j] - qm[j]);
-        }
-      }
-      s2[k] = acc;
+      for (int j = 0; j < (kRow ? DX : i + 1); ++j) acc = fma(Wm[i * DX + j], d[j], acc);
+      r4[k] = (R)acc;
     }
-    const R r0 = (R)s2[0], r1 = (R)s2[1];
-    tp[i] = r0;
-    tp[i + 1] = r1;
-    if (th) {
-      nrm += (double)r0 * (double)r0;
-      nrm += (double)r1 * (double)r1;
-      uint32_t h0, l0, h1, l1;
-      bf16_split(kRow ? (float)r0 : 2.0f * (float)r0, h0, l0);
-      bf16_split(kRow ? (float)r1 : 2.0f * (float)r1, h1, l1);
-      th[i >> 1] = h0 | (h1 << 16);
-      th[DX / 2 + (i >> 1)] = l0 | (l1 << 16);
+    if (aligned) {
+      store4<R>(dst + i0, r4[0], r4[1], r4[2], r4[3]);
+    } else {
+#pragma unroll
+      for (int k = 0; k < 4; ++k) dst[i0 + k] = r4[k];
+    }
+    if constexpr (sizeof(R) == 4 && DX >= 16) {
+      if (dsth) {
+        uint32_t h[4], l[4];
+#pragma unroll
+        for (int k = 0; k < 4; ++k) {
+          nrm += (double)r4[k] * (double)r4[k];
+          bf16_split(kRow ? (float)r4[k] : 2.0f * (float)r4[k], h[k], l[k]);
+        }
+        *(uint2*)(dsth + (i0 >> 1)) = make_uint2(h[0] | (h[1] << 16), h[2] | (h[3] << 16));
+        *(uint2*)(dsth + DX / 2 + (i0 >> 1)) = make_uint2(l[0] | (l[1] << 16), l[2] | (l[3] << 16));
+      }
     }
   }
-  if (th) (kRow ? nb.trown : nb.tcoln)[g * N + n] = (float)nrm;
+  if (dsth) *dstn = (float)nrm;
 }
 
 // Padding column n (N <= n < Npad): weight zero.
@@ -239,202 +263,18 @@ __device__ __forceinline__ void leaf_normals(const Words4& w, double& z0, double
   }
 }
 
-// One workgroup per time row g of the packed time axis.
-template <typename R, int DX>
-__global__ __launch_bounds__(kBlock, 3) void k_leaves(
-    const SeriesDesc* __restrict__ series, const int32_t* __restrict__ series_of_t,
-    const int32_t* __restrict__ leaf_cons, const NodeDesc* __restrict__ nodes, int row0,
-    int totalK, int N, int Npad, R* __restrict__ leafX, R* __restrict__ leafW,
-    double* __restrict__ leafL, double* __restrict__ bmerged, NodeBufs nb) {
-  extern __shared__ double sh[];
-  const int g = row0 + blockIdx.x;
-  const SeriesDesc& sd = series[series_of_t[g]];
-  const DevModel& M = *sd.model;
-  const int t = uniform(g - sd.base);
-  const int dx = uniform(M.dx);
-  const int K = uniform(sd.K);
-  const int weighting = uniform(M.weighting);
-  // LDS: ell [N]; gq [N] (DX >= 8: gq lives in its table in global memory and
-  // LDS holds this time's matrices instead)
-  double* ell = sh;  // unnormalised leaf log-weights
-  double* gq = (DX >= 8) ? nb.tgq + (size_t)g * N : sh + N;  // -log q_t (+ log h_t, boundary weighting)
+// Leaf weights of one time row once every particle's unnormalised log weight
+// ell[n] and -log q (+ log h) gq[n] are known: normalise (rounded to R, the
+// value every consumer sees), write leafW, leafL and the block's shift, and
+// return max_n (lbar_n + gq_n) (every thread of the block).
+template <typename R>
+__device__ __forceinline__ double leaf_normalise(double* ell, const double* gq, int g, int N,
+                                                 int bad, const SeriesDesc& sd,
+                                                 R* __restrict__ leafW, double* __restrict__ leafL,
+                                                 double* __restrict__ bmerged) {
   __shared__ double red[2 * kMaxWaves];
   __shared__ int redi[2 * kMaxWaves];
   const double logN = log((double)N);
-  int bad = 0;
-  const double* qm = M.q_mean + (size_t)t * dx;
-  const double* qc = M.q_chol + (size_t)t * dx * dx;
-  const double* qi = M.q_inv + (size_t)t * dx * dx;
-  const double* Wc = M.Wcol;
-  const double* Wr = M.Wrow;
-  const double* qm1 = (t + 1 < K) ? qm + dx : qm;  // q_mean[t + 1]
-  // DX >= 8: this time's matrices and vectors in LDS, zero-padded to DX x DX
-  // (triangular factors with zero upper triangles), so the particle loops
-  // below run without per-element bounds checks; the extra terms are exact
-  // zeros and leave every sum unchanged.
-  const bool lds_obs = uniform(M.obs_kind) == 0 && uniform(M.dy) <= DX;
-  double *Lc = nullptr, *Li = nullptr, *Hl = nullptr, *vy = nullptr, *vw = nullptr;
-  if constexpr (DX >= 8) {
-    const int dy = uniform(M.dy);
-    Lc = sh + N;
-    Li = Lc + DX * DX;
-    double* Wcl = Li + DX * DX;
-    double* Wrl = Wcl + DX * DX;
-    Hl = Wrl + DX * DX;
-    double* vq = Hl + DX * DX;
-    double* vq1 = vq + DX;
-    vw = vq1 + DX;
-    vy = vw + DX;
-    for (int e = threadIdx.x; e < DX * DX; e += kBlock) {
-      const int i = e / DX, j = e - (e / DX) * DX;
-      const bool in = i < dx && j < dx;
-      Lc[e] = (in && j <= i) ? qc[i * dx + j] : 0.0;
-      Li[e] = (in && j <= i) ? qi[i * dx + j] : 0.0;
-      Wcl[e] = in ? Wc[i * dx + j] : 0.0;
-      Wrl[e] = in ? Wr[i * dx + j] : 0.0;
-      Hl[e] = (lds_obs && i < dy && j < dx) ? M.H[i * dx + j] : 0.0;
-    }
-    for (int i = threadIdx.x; i < DX; i += kBlock) {
-      vq[i] = i < dx ? qm[i] : 0.0;
-      vq1[i] = i < dx ? qm1[i] : 0.0;
-      vy[i] = (lds_obs && i < dy) ? M.y[(size_t)t * dy + i] : 0.0;
-      double w = 0.0;  // the row coordinates' per-time offset
-      if (i < dx) {
-        w = M.wcol_off[i];
-        for (int j = 0; j < dx; ++j) w -= Wc[i * dx + j] * qm1[j];
-      }
-      vw[i] = w;
-    }
-    __syncthreads();
-    Wc = Wcl;
-    Wr = Wrl;
-    qm = vq;
-    qm1 = vq1;
-  }
-  for (int n = threadIdx.x; n < N; n += kBlock) {
-    // standard normals, four per Philox block, then x = q_mean + L z in place
-    // from the last coordinate down (x_i needs z_0 .. z_i)
-    double x[DX];
-    if constexpr (DX >= 8) {
-      // one Philox block (four normals) at a time, each added into every
-      // x_i it enters: the same terms in the same order as below, without
-      // holding all the normals
-#pragma unroll
-      for (int i = 0; i < DX; ++i) x[i] = qm[i];
-#pragma unroll 1
-      for (int j = 0; j < (DX + 3) / 4; ++j) {
-        const Words4 w = philox4x64_10((uint64_t)n, (uint64_t)t, kPurposeLeaf, (uint64_t)j,
-                                       sd.seed, kKey1);
-        double z[4];
-        leaf_normals<R>(w, z[0], z[1], z[2], z[3]);
-#pragma unroll
-        for (int i = 0; i < DX; ++i) {
-#pragma unroll
-          for (int k = 0; k < 4; ++k) x[i] += Lc[i * DX + 4 * j + k] * z[k];
-        }
-      }
-#pragma unroll
-      for (int i = 0; i < DX; ++i) {
-        const R xr = (R)x[i];
-        if (i < dx) leafX[((size_t)i * totalK + g) * N + n] = xr;
-        x[i] = (double)xr;  // weights are those of the stored particle (0 past dx)
-      }
-    } else {
-      const bool unif = uniform(M.prop_kind) == 1;  // uniform proposal: uniforms, not normals
-#pragma unroll
-      for (int j = 0; j < (DX + 3) / 4; ++j) {
-        const Words4 w = philox4x64_10((uint64_t)n, (uint64_t)t, kPurposeLeaf, (uint64_t)j,
-                                       sd.seed, kKey1);
-        double z0, z1, z2, z3;
-        if (unif) {
-          z0 = unif53(w.w0);
-          z1 = unif53(w.w1);
-          z2 = unif53(w.w2);
-          z3 = unif53(w.w3);
-        } else {
-          leaf_normals<R>(w, z0, z1, z2, z3);
-        }
-        if (4 * j < DX) x[4 * j] = z0;
-        if (4 * j + 1 < DX) x[4 * j + 1] = z1;
-        if (4 * j + 2 < DX) x[4 * j + 2] = z2;
-        if (4 * j + 3 < DX) x[4 * j + 3] = z3;
-      }
-#pragma unroll
-      for (int i = DX - 1; i >= 0; --i) {
-        double xi = 0.0;
-        if (i < dx) {
-          if (unif) {  // q_mean + half-width (2 u - 1)
-            xi = qm[i] + qc[i * dx + i] * (2.0 * x[i] - 1.0);
-          } else {
-            xi = qm[i];
-#pragma unroll
-            for (int j = 0; j <= i; ++j) xi += qc[i * dx + j] * x[j];
-          }
-          const R xr = (R)xi;
-          leafX[((size_t)i * totalK + g) * N + n] = xr;
-          xi = (double)xr;  // weights are those of the stored particle
-        }
-        x[i] = xi;
-      }
-    }
-    if (n == 0 && sd.star != nullptr) {
-      // conditional run: slot 0 holds the star trajectory (its proposal draw
-      // above is discarded), weighted like every other particle
-      const R* st = (const R*)sd.star;
-#pragma unroll
-      for (int i = 0; i < DX; ++i) {
-        double xi = 0.0;
-        if (i < dx) {
-          const R xr = st[(size_t)i * K + t];
-          leafX[((size_t)i * totalK + g) * N + n] = xr;
-          xi = (double)xr;
-        }
-        x[i] = xi;
-      }
-    }
-    double lq, lh;  // log q_t(x), log h_t(x)
-    if constexpr (DX >= 8) {
-      double q = 0.0;
-#pragma unroll 1
-      for (int i = 0; i < DX; ++i) {
-        double zi = 0.0;
-#pragma unroll
-        for (int j = 0; j < DX; ++j) zi += Li[i * DX + j] * (x[j] - qm[j]);
-        q += zi * zi;
-      }
-      lq = -0.5 * q + M.q_lognorm[t];
-      if (lds_obs) {
-        double qh = 0.0;
-        const int dy = uniform(M.dy);
-#pragma unroll 1
-        for (int i = 0; i < dy; ++i) {
-          double r = vy[i];
-#pragma unroll
-          for (int k = 0; k < DX; ++k) r -= Hl[i * DX + k] * x[k];
-          qh += r * r;
-        }
-        lh = -0.5 * qh + M.obs_lognorm;
-      } else {
-        lh = log_potential<DX>(M, t, x);
-      }
-    } else {
-      lq = log_proposal<DX>(M, t, x);
-      lh = log_potential<DX>(M, t, x);
-    }
-    double l, gg = -lq;
-    if (t == 0) {
-      l = lh + log_prior<DX>(M, x) - lq;
-      if (weighting == 1) gg += lh;
-    } else if (weighting == 0) {
-      l = lh;
-    } else {
-      l = 0.0;
-      gg += lh;
-    }
-    if (isnan(l) || isnan(gg)) bad = kFlagNumeric;
-    ell[n] = l;
-    gq[n] = gg;
-  }
   __syncthreads();
   double mx = -INFINITY, gmx = -INFINITY;
   for (int n = threadIdx.x; n < N; n += kBlock) {
@@ -463,6 +303,110 @@ __global__ __launch_bounds__(kBlock, 3) void k_leaves(
     const int flags = bad | (degenerate ? kFlagDegenerate : 0);
     if (flags) atomicOr(sd.status, flags);
   }
+  return bmax;
+}
+
+// Unnormalised leaf log weight l and gq = -log q_t(x) (+ log h_t(x) under
+// boundary weighting) from log q, log h and (t = 0) the prior.
+__device__ __forceinline__ void leaf_logw(int t, int weighting, double lq, double lh,
+                                          double lprior, double& l, double& gg) {
+  gg = -lq;
+  if (t == 0) {
+    l = lh + lprior - lq;
+    if (weighting == 1) gg += lh;
+  } else if (weighting == 0) {
+    l = lh;
+  } else {
+    l = 0.0;
+    gg += lh;
+  }
+}
+
+// DX < 8.  One workgroup per time row g of the packed time axis.
+template <typename R, int DX>
+__global__ __launch_bounds__(kBlock, 3) void k_leaves(
+    const SeriesDesc* __restrict__ series, const int32_t* __restrict__ series_of_t,
+    const int32_t* __restrict__ leaf_cons, int row0, int totalK, int N, int Npad,
+    R* __restrict__ leafX, R* __restrict__ leafW, double* __restrict__ leafL,
+    double* __restrict__ bmerged, NodeBufs nb) {
+  static_assert(DX < 8, "DX >= 8 uses k_leaves_mat");
+  extern __shared__ double sh[];
+  const int g = row0 + blockIdx.x;
+  const SeriesDesc& sd = series[series_of_t[g]];
+  const DevModel& M = *sd.model;
+  const int t = uniform(g - sd.base);
+  const int dx = uniform(M.dx);
+  const int K = uniform(sd.K);
+  const int weighting = uniform(M.weighting);
+  double* ell = sh;     // [N] unnormalised leaf log-weights
+  double* gq = sh + N;  // [N] -log q_t (+ log h_t, boundary weighting)
+  int bad = 0;
+  const double* qm = M.q_mean + (size_t)t * dx;
+  const double* qc = M.q_chol + (size_t)t * dx * dx;
+  const bool unif = uniform(M.prop_kind) == 1;  // uniform proposal: uniforms, not normals
+  for (int n = threadIdx.x; n < N; n += kBlock) {
+    // standard normals (or uniforms), four per Philox block, then
+    // x = q_mean + L z in place from the last coordinate down (x_i needs z_0 .. z_i)
+    double x[DX];
+#pragma unroll
+    for (int j = 0; j < (DX + 3) / 4; ++j) {
+      const Words4 w = philox4x64_10((uint64_t)n, (uint64_t)t, kPurposeLeaf, (uint64_t)j,
+                                     sd.seed, kKey1);
+      double z0, z1, z2, z3;
+      if (unif) {
+        z0 = unif53(w.w0);
+        z1 = unif53(w.w1);
+        z2 = unif53(w.w2);
+        z3 = unif53(w.w3);
+      } else {
+        leaf_normals<R>(w, z0, z1, z2, z3);
+      }
+      if (4 * j < DX) x[4 * j] = z0;
+      if (4 * j + 1 < DX) x[4 * j + 1] = z1;
+      if (4 * j + 2 < DX) x[4 * j + 2] = z2;
+      if (4 * j + 3 < DX) x[4 * j + 3] = z3;
+    }
+#pragma unroll
+    for (int i = DX - 1; i >= 0; --i) {
+      double xi = 0.0;
+      if (i < dx) {
+        if (unif) {  // q_mean + half-width (2 u - 1)
+          xi = qm[i] + qc[i * dx + i] * (2.0 * x[i] - 1.0);
+        } else {
+          xi = qm[i];
+#pragma unroll
+          for (int j = 0; j <= i; ++j) xi += qc[i * dx + j] * x[j];
+        }
+        const R xr = (R)xi;
+        leafX[((size_t)i * totalK + g) * N + n] = xr;
+        xi = (double)xr;  // weights are those of the stored particle
+      }
+      x[i] = xi;
+    }
+    if (n == 0 && sd.star != nullptr) {
+      // conditional run: slot 0 holds the star trajectory (its proposal draw
+      // above is discarded), weighted like every other particle
+      const R* st = (const R*)sd.star;
+#pragma unroll
+      for (int i = 0; i < DX; ++i) {
+        double xi = 0.0;
+        if (i < dx) {
+          const R xr = st[(size_t)i * K + t];
+          leafX[((size_t)i * totalK + g) * N + n] = xr;
+          xi = (double)xr;
+        }
+        x[i] = xi;
+      }
+    }
+    const double lq = log_proposal<DX>(M, t, x);
+    const double lh = log_potential<DX>(M, t, x);
+    double l, gg;
+    leaf_logw(t, weighting, lq, lh, t == 0 ? log_prior<DX>(M, x) : 0.0, l, gg);
+    if (isnan(l) || isnan(gg)) bad = kFlagNumeric;
+    ell[n] = l;
+    gq[n] = gg;
+  }
+  const double bmax = leaf_normalise<R>(ell, gq, g, N, bad, sd, leafW, leafL, bmerged);
   // Every particle's data for the combines at both boundaries of t (the
   // tables merged blocks gather from), and the data of the combine that
   // consumes this single-point block: its right block (c == t) or its left
@@ -472,28 +416,20 @@ __global__ __launch_bounds__(kBlock, 3) void k_leaves(
   for (int n = threadIdx.x; n < N; n += kBlock) {
     double x[DX];
     load_particle<R, DX>(leafX, totalK, N, g, n, dx, x);
-    if constexpr (DX < 8) nb.tgq[(size_t)g * N + n] = gq[n];
+    nb.tgq[(size_t)g * N + n] = gq[n];
     if (t >= 1) {
-      if constexpr (DX >= 8) {
-        stream_table<R, DX, false>(nb, Wc, Wr, vw, qm, DX, (size_t)g, N, n, x);
-      } else {
-        double u[DX];
-        col_coords<DX>(M, t, x, u);
-        put_tcol<R, DX>(nb, (size_t)g, N, n, u);
-      }
+      double u[DX];
+      col_coords<DX>(M, t, x, u);
+      put_tcol<R, DX>(nb, (size_t)g, N, n, u);
       if (cons >= 0 && role == 1) {
         const double beta = (bmax > -INFINITY) ? (ell[n] + gq[n] - bmax) * kLog2e : -INFINITY;
         copy_col<R, DX>(nb, (size_t)P, Npad, n, (size_t)g, N, n, beta);
       }
     }
     if (t + 1 < K) {
-      if constexpr (DX >= 8) {
-        stream_table<R, DX, true>(nb, Wc, Wr, vw, qm1, DX, (size_t)g, N, n, x);
-      } else {
-        double v[DX];
-        row_coords<DX>(M, t + 1, x, v);
-        put_trow<R, DX>(nb, (size_t)g, N, n, v);
-      }
+      double v[DX];
+      row_coords<DX>(M, t + 1, x, v);
+      put_trow<R, DX>(nb, (size_t)g, N, n, v);
       if (cons >= 0 && role == 0) {
         copy_row<R, DX>(nb, (size_t)P, Npad, n, (size_t)g, N, n);
         ((R*)nb.alpha)[(size_t)P * N + n] = (R)ell[n];
@@ -506,6 +442,157 @@ __global__ __launch_bounds__(kBlock, 3) void k_leaves(
   }
 }
 
+// DX >= 8.  One workgroup per time row g; each particle's whole leaf step in
+// registers: the normals, x = q_mean + L z, log q from L^{-1} (x - q_mean),
+// the linear-Gaussian log h from the whitened residual, and the whitened
+// coordinates for both boundaries of t, every matrix entry a scalar operand
+// (the model's leaf records).  A boundary consumed by this leaf's level-0
+// combine is written straight into that combine's buffers (no table entry:
+// no other combine reads it); the other boundary goes to its table.
+template <typename R, int DX>
+__global__ __launch_bounds__(kBlock, 3) void k_leaves_mat(
+    const SeriesDesc* __restrict__ series, const int32_t* __restrict__ series_of_t,
+    const int32_t* __restrict__ leaf_cons, int row0, int totalK, int N, int Npad,
+    R* __restrict__ leafX, R* __restrict__ leafW, double* __restrict__ leafL,
+    double* __restrict__ bmerged, NodeBufs nb) {
+  static_assert(DX >= 8 && DX % 4 == 0, "k_leaves_mat: DX >= 8, a multiple of 4");
+  extern __shared__ double sh[];
+  double* ell = sh;  // [N] leaf log-weights, unnormalised then normalised
+  const int g = row0 + blockIdx.x;
+  const SeriesDesc& sd = series[series_of_t[g]];
+  const DevModel& M = *sd.model;
+  const int t = uniform(g - sd.base);
+  const int dx = uniform(M.dx);
+  const int dy = uniform(M.dy);
+  const int K = uniform(sd.K);
+  const int weighting = uniform(M.weighting);
+  constexpr int S = leafrec_stride(DX);
+  cdouble* const rec0 = uniform_ptr(M.leafrec + (size_t)t * S);
+  cdouble* const inv0 = uniform_ptr(M.leafrec + (size_t)uniform(M.K) * S);
+  const bool lg_obs = uniform(M.obs_kind) == 0 && dy <= DX;
+  const double qln = M.q_lognorm[t];
+  const int cons = leaf_cons[g];
+  const int P = cons >> 1, role = cons & 1;
+  const bool col_direct = cons >= 0 && role == 1;  // boundary t belongs to combine P
+  const bool row_direct = cons >= 0 && role == 0;  // boundary t + 1 belongs to combine P
+  const bool split = sizeof(R) == 4 && DX >= 16 && nb.colh != nullptr;
+  int bad = 0;
+  auto reload = [&](int n, double (&x)[DX]) { load_particle<R, DX>(leafX, totalK, N, g, n, dx, x); };
+  for (int n = threadIdx.x; n < N; n += kBlock) {
+    cdouble* rec = opaque(rec0);
+    cdouble* Lc = rec;                // q_chol[t]
+    cdouble* Li = rec + DX * DX;      // q_chol[t]^{-1}
+    cdouble* qm = rec + 2 * DX * DX;  // q_mean[t]
+    cdouble* ro = qm + DX;            // row offset for boundary t + 1
+    cdouble* yo = ro + DX;            // whitened y_t - H q_mean[t]
+    cdouble* inv = opaque(inv0);
+    cdouble* Wc = inv;                // Wcol (lower triangular)
+    cdouble* Wr = inv + DX * DX;      // Wrow
+    cdouble* Hw = inv + 2 * DX * DX;  // whitened H, dy rows
+    double d[DX];  // x - q_mean[t] of the stored particle (zero past d_x)
+    {
+      double x[DX];
+#pragma unroll
+      for (int i = 0; i < DX; ++i) x[i] = qm[i];
+      // one Philox block (four normals) at a time, each added into every x_i
+      // it enters (x_i needs z_0 .. z_i)
+#pragma unroll
+      for (int j = 0; j < DX / 4; ++j) {
+        const Words4 w = philox4x64_10((uint64_t)n, (uint64_t)t, kPurposeLeaf, (uint64_t)j,
+                                       sd.seed, kKey1);
+        double z[4];
+        leaf_normals<R>(w, z[0], z[1], z[2], z[3]);
+#pragma unroll
+        for (int i = 4 * j; i < DX; ++i) {
+#pragma unroll
+          for (int k = 0; k < 4; ++k)
+            if (4 * j + k <= i) x[i] = fma(Lc[i * DX + 4 * j + k], z[k], x[i]);
+        }
+      }
+      if (n == 0 && sd.star != nullptr) {
+        // conditional run: slot 0 holds the star trajectory (its proposal
+        // draw above is discarded), weighted like every other particle
+        const R* st = (const R*)sd.star;
+#pragma unroll
+        for (int i = 0; i < DX; ++i) x[i] = (i < dx) ? (double)st[(size_t)i * K + t] : 0.0;
+      }
+#pragma unroll
+      for (int i = 0; i < DX; ++i) {
+        double xi = 0.0;
+        if (i < dx) {
+          const R xr = (R)x[i];
+          leafX[((size_t)i * totalK + g) * N + n] = xr;
+          xi = (double)xr;  // weights are those of the stored particle
+        }
+        d[i] = xi - qm[i];
+      }
+    }
+    // log q_t(x) = -||L^{-1} (x - q_mean)||^2 / 2 + log normaliser
+    double qq = 0.0;
+#pragma unroll
+    for (int i = 0; i < DX; ++i) {
+      double zi = 0.0;
+#pragma unroll
+      for (int j = 0; j <= i; ++j) zi = fma(Li[i * DX + j], d[j], zi);
+      qq = fma(zi, zi, qq);
+    }
+    const double lq = -0.5 * qq + qln;
+    double lh, lprior = 0.0;
+    if (lg_obs) {  // whitened residual y_t - H x = yo - H d
+      double qh = 0.0;
+#pragma unroll 1
+      for (int i = 0; i < dy; ++i) {
+        double r = yo[i];
+#pragma unroll
+        for (int k = 0; k < DX; ++k) r = fma(-Hw[i * DX + k], d[k], r);
+        qh = fma(r, r, qh);
+      }
+      lh = -0.5 * qh + M.obs_lognorm;
+    } else {
+      double x[DX];
+      reload(n, x);
+      lh = log_potential<DX>(M, t, x);
+    }
+    if (t == 0) {
+      double x[DX];
+      reload(n, x);
+      lprior = log_prior<DX>(M, x);
+    }
+    double l, gg;
+    leaf_logw(t, weighting, lq, lh, lprior, l, gg);
+    if (isnan(l) || isnan(gg)) bad = kFlagNumeric;
+    ell[n] = l;
+    nb.tgq[(size_t)g * N + n] = gg;
+    if (t >= 1) {  // u for boundary t
+      const size_t e = col_direct ? (size_t)P * Npad + n : (size_t)g * N + n;
+      R* dst = col_direct ? (R*)nb.col + e * (DX + 1) : (R*)nb.tcol + e * DX;
+      uint32_t* dh = split ? (uint32_t*)(col_direct ? nb.colh : nb.tcolh) + e * DX : nullptr;
+      emit_coords<R, DX, false>(Wc, nullptr, d, dst, !col_direct, dh, nb.tcoln + (size_t)g * N + n);
+    }
+    if (t + 1 < K) {  // v for boundary t + 1
+      const size_t e = row_direct ? (size_t)P * Npad + n : (size_t)g * N + n;
+      R* dst = (R*)(row_direct ? nb.row : nb.trow) + e * DX;
+      uint32_t* dh = split ? (uint32_t*)(row_direct ? nb.rowh : nb.trowh) + e * DX : nullptr;
+      emit_coords<R, DX, true>(Wr, ro, d, dst, true, dh,
+                               split ? (row_direct ? nb.rown : nb.trown) + e : nullptr);
+    }
+  }
+  const double* gq = nb.tgq + (size_t)g * N;  // this thread's own entries, read back
+  const double bmax = leaf_normalise<R>(ell, gq, g, N, bad, sd, leafW, leafL, bmerged);
+  if (col_direct) {
+    for (int n = threadIdx.x; n < N; n += kBlock) {
+      const double beta = (bmax > -INFINITY) ? (ell[n] + gq[n] - bmax) * kLog2e : -INFINITY;
+      const size_t e = (size_t)P * Npad + n;
+      ((R*)nb.col)[e * (DX + 1) + DX] = (R)beta;
+      if (split) nb.colb[e] = (float)beta - nb.tcoln[(size_t)g * N + n];
+    }
+    for (int n = N + threadIdx.x; n < Npad; n += kBlock) put_col_pad<R, DX>(nb, (size_t)P, Npad, n);
+    if (threadIdx.x == 0) nb.bcol[P] = bmax;
+  }
+  if (row_direct)
+    for (int n = threadIdx.x; n < N; n += kBlock) ((R*)nb.alpha)[(size_t)P * N + n] = (R)ell[n];
+}
+
 // ================================================================= rows
 // Tile = (combine, row block of RPL*64*W rows, column split of KC chunks, KC a
 // multiple of 4).  Lane owns rows base + lane + 64 r, r < RPL; lanes past N
@@ -514,17 +601,6 @@ __global__ __launch_bounds__(kBlock, 3) void k_leaves(
 // per vector store, so the sampler reads a row's sums as one contiguous run.
 // With one column split the tile also stores the row sum sum_k P[m][k] (fp64,
 // k ascending); otherwise the sampling kernel forms that same sum from P.
-template <typename R>
-__device__ __forceinline__ void store4(R* p, R a, R b, R c, R d);
-template <>
-__device__ __forceinline__ void store4<float>(float* p, float a, float b, float c, float d) {
-  *(float4*)p = make_float4(a, b, c, d);
-}
-template <>
-__device__ __forceinline__ void store4<double>(double* p, double a, double b, double c, double d) {
-  ((double2*)p)[0] = make_double2(a, b);
-  ((double2*)p)[1] = make_double2(c, d);
-}
 
 template <typename R, int DX, int RPL>
 __global__ __launch_bounds__(kBlock) void k_rows(const R* __restrict__ col,
@@ -1466,10 +1542,15 @@ static int launch_level_t(const LevelLaunch& L, hipStream_t st, Timer* tm) {
 template <typename R, int DX>
 static void launch_leaves_t(const LeafLaunch& L, hipStream_t st, Timer* tm) {
   tm->begin(0, st);
-  const size_t lds = (DX >= 8 ? (size_t)L.N + 5 * DX * DX + 4 * DX : 2 * (size_t)L.N) * sizeof(double);
-  k_leaves<R, DX><<<L.rows, kBlock, lds, st>>>(
-      L.d_series, L.d_series_of_t, L.d_leaf_cons, L.d_nodes, L.row0, L.totalK, L.N, L.Npad,
-      (R*)L.leafX, (R*)L.leafW, L.leafL, L.bmerged, L.nb);
+  if constexpr (DX >= 8) {
+    k_leaves_mat<R, DX><<<L.rows, kBlock, (size_t)L.N * sizeof(double), st>>>(
+        L.d_series, L.d_series_of_t, L.d_leaf_cons, L.row0, L.totalK, L.N, L.Npad, (R*)L.leafX,
+        (R*)L.leafW, L.leafL, L.bmerged, L.nb);
+  } else {
+    k_leaves<R, DX><<<L.rows, kBlock, 2 * (size_t)L.N * sizeof(double), st>>>(
+        L.d_series, L.d_series_of_t, L.d_leaf_cons, L.row0, L.totalK, L.N, L.Npad, (R*)L.leafX,
+        (R*)L.leafW, L.leafL, L.bmerged, L.nb);
+  }
   tm->end(0, st);
 }
 

@@ -110,5 +110,7 @@ int launch_leaves(const LeafLaunch& L, hipStream_t st, Timer* tm);
 int launch_level(const LevelLaunch& L, hipStream_t st, Timer* tm);
 void launch_output(const LeafLaunch& L, int s0, int B, int dx, hipStream_t st, Timer* tm);
 void launch_clear_status(const SeriesDesc* d_series, int s0, int B, hipStream_t st);
+// Fills a model's leaf records (rec = its leafrec array, padded dimension DX).
+void launch_leaf_records(const DevModel* dev, double* rec, int K, int DX, hipStream_t st);
 
 }  // namespace dsmc

@@ -565,6 +565,10 @@ extern "C" int dsmc_model_gaussian_proposals(dsmc_model_t* m, void* stream) {
   if (rc) return rc;
   k_proposal_factors<<<K, kPitThreads, sizeof(double) * 3 * (size_t)d * d + 64, st>>>(m->dev, srec);
   HIP_TRY(hipGetLastError());
+  if (m->hdr.leafrec) {  // the leaf kernel's padded copies of the new proposals
+    launch_leaf_records(m->dev, (double*)m->hdr.leafrec, K, padded_dx(d), st);
+    HIP_TRY(hipGetLastError());
+  }
   return DSMC_OK;
 }
 
