@@ -267,7 +267,7 @@ def bench_sv(args) -> dict:
         n_rows = prof["launches"]["rows"]
         nodes = K - 1
         Npad = (N + 31) // 32 * 32
-        NcP = (Npad // 32 + 3) // 4 * 4
+        NcP = (Npad // 32 + 7) // 8 * 8
         algo_bytes = nodes * (Npad * 2 * 4 + Npad * 4 + N * NcP * 4 + N * 8) / max(1, n_rows / ev_steps)
         src = kernel_source_hash()
         traffic = None

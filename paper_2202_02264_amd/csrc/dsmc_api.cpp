@@ -470,6 +470,7 @@ struct dsmc_plan_impl {
   void* Pr = nullptr;
   double* Rsum = nullptr;
   float* Rshift = nullptr;
+  double* Gs = nullptr;                      // chunk-group sums of rows under column splits
   unsigned long long* d_rescued = nullptr;  // profiling: rescued-row counter
   // schedule
   NodeDesc* d_nodes = nullptr;
@@ -507,9 +508,9 @@ static void plan_free(dsmc_plan_t* p) {
   void* dev[] = {p->leafX, p->leafW, p->leafL, p->bmerged, p->anc, p->zinc, p->nb.col, p->nb.row,
                  p->nb.alpha, p->nb.bcol, p->nb.sfirst, p->nb.slast, p->nb.colh, p->nb.colb,
                  p->nb.rowh, p->nb.rown, p->nb.tcol, p->nb.tgq, p->nb.trow, p->nb.tcolh,
-                 p->nb.tcoln, p->nb.trowh, p->nb.trown, p->P, p->Pr, p->Rsum, p->Rshift, p->d_rescued, p->d_nodes,
-                 p->d_series_of_t,
-                 p->d_leaf_cons, p->d_series};
+                 p->nb.tcoln, p->nb.trowh, p->nb.trown, p->P, p->Pr, p->Rsum, p->Rshift,
+                 p->Gs, p->d_rescued, p->d_nodes, p->d_series_of_t, p->d_leaf_cons,
+                 p->d_series};
   for (void* q : dev) (void)hipFree(q);
   void* host[] = {p->h_nodes, p->h_series_of_t, p->h_leaf_cons, p->h_series};
   for (void* q : host) (void)hipHostFree(q);
@@ -558,7 +559,7 @@ extern "C" int dsmc_plan(const dsmc_plan_desc* d, dsmc_plan_t** out) {
   const int N = d->N;
   p->Npad = (N + kChunk - 1) / kChunk * kChunk;
   p->Nc = p->Npad / kChunk;
-  p->NcP = (p->Nc + 3) / 4 * 4;
+  p->NcP = (p->Nc + kGroup - 1) / kGroup * kGroup;
   const size_t TK = (size_t)p->d.max_total_K;
   const size_t max_nodes = std::max<size_t>(1, TK / 2);
   const size_t per_node_P = 2 * (size_t)N * p->NcP * p->rsz + (size_t)N * (sizeof(double) + sizeof(float));
@@ -591,6 +592,7 @@ extern "C" int dsmc_plan(const dsmc_plan_desc* d, dsmc_plan_t** out) {
       {&p->Pr, nc * N * p->NcP * R, "rescued chunk sums"},
       {(void**)&p->Rsum, nc * N * sizeof(double), "row sums"},
       {(void**)&p->Rshift, nc * N * sizeof(float), "row shifts"},
+      {(void**)&p->Gs, nc * N * group_stride(p->NcP) * sizeof(double), "chunk-group sums"},
       {(void**)&p->d_nodes, TK * sizeof(NodeDesc), "schedule"},
       {(void**)&p->d_series_of_t, TK * sizeof(int32_t), "series map"},
       {(void**)&p->d_leaf_cons, TK * sizeof(int32_t), "leaf consumers"},
@@ -771,7 +773,7 @@ void dsmc::set_tile(LevelLaunch& L, TileChoice tc) {
   L.RPL = tc.RPL;
   L.W = tc.W;
   L.RB = (L.N + 64 * tc.RPL * tc.W - 1) / (64 * tc.RPL * tc.W);
-  L.KC = ((L.Nc + tc.CS - 1) / tc.CS + 3) / 4 * 4;  // whole groups of four chunks
+  L.KC = ((L.Nc + tc.CS - 1) / tc.CS + kGroup - 1) / kGroup * kGroup;  // whole chunk groups
   L.CS = (L.Nc + L.KC - 1) / L.KC;
 }
 
@@ -897,7 +899,7 @@ void dsmc::build_series_schedule(int K, int series, int node_base, std::vector<N
 
 PoolSizes dsmc::pool_sizes(int N, int DX, int dx_alloc, size_t rsz) {
   const size_t Npad = (size_t)(N + kChunk - 1) / kChunk * kChunk;
-  const size_t Nc = Npad / kChunk, NcP = (Nc + 3) / 4 * 4;
+  const size_t Nc = Npad / kChunk, NcP = (Nc + kGroup - 1) / kGroup * kGroup;
   PoolSizes ps;
   ps.per_row = (size_t)dx_alloc * N * rsz + N * rsz + 2 * sizeof(double)  // particles, weights, log L, bound
                + 2 * N * sizeof(int32_t) + sizeof(double)                // ancestry, increment
@@ -1069,6 +1071,7 @@ static int enqueue_batch(dsmc_plan_t* p, int B, int totalK, hipStream_t st) {
       L.Pr = p->Pr;
       L.Rsum = p->Rsum;
       L.Rshift = p->Rshift;
+      L.Gs = p->Gs;
       L.force_rescue = (p->d.flags & DSMC_PLAN_RESCUE_ALL) != 0;
       L.rescue_count = p->d_rescued;
       L.nb = p->nb;

@@ -9,6 +9,8 @@ namespace dsmc {
 constexpr int kBlock = 256;     // threads per workgroup of the leaf / lazy-sampling / output kernels
 constexpr int kMaxWaves = 16;  // largest workgroup (1024 threads) of any kernel, in waves
 constexpr int kChunk = 32;   // columns per chunk of the pair matrix
+constexpr int kGroup = 8;    // chunk sums per store group (a 32-byte sector in fp32); row
+                             // stride of the chunk sums and column splits are multiples
 
 // Device-resident model (one allocation: this header, then the arrays).
 // Inverse Cholesky factors and log normalisers are derived on the host in fp64.

@@ -34,6 +34,20 @@ namespace dsmc {
 template <int DX>
 inline constexpr bool kRowShift = DX >= 8;
 
+// Four consecutive values, one 16-byte (fp32) or two (fp64) vector loads.
+template <typename R>
+__device__ __forceinline__ void load4(const R* p, R (&q)[4]);
+template <>
+__device__ __forceinline__ void load4<float>(const float* p, float (&q)[4]) {
+  const float4 v = *(const float4*)p;
+  q[0] = v.x; q[1] = v.y; q[2] = v.z; q[3] = v.w;
+}
+template <>
+__device__ __forceinline__ void load4<double>(const double* p, double (&q)[4]) {
+  const double2 a = ((const double2*)p)[0], b = ((const double2*)p)[1];
+  q[0] = a.x; q[1] = a.y; q[2] = b.x; q[3] = b.y;
+}
+
 // Four consecutive values, one 16-byte (fp32) or two (fp64) vector stores.
 template <typename R>
 __device__ __forceinline__ void store4(R* p, R a, R b, R c, R d);
@@ -90,11 +104,9 @@ __device__ __forceinline__ void load_particle(const R* __restrict__ leafX, int t
     x[i] = (i < dx) ? (double)leafX[((size_t)i * totalK + g) * N + src] : 0.0;
 }
 
-// bf16 bits of x, rounded to nearest even (NaN stays NaN).
+// bf16 bits of x, rounded to nearest even (the hardware conversion).
 __device__ __forceinline__ uint32_t bf16_bits(float x) {
-  const uint32_t u = __float_as_uint(x);
-  if ((u & 0x7fffffffu) > 0x7f800000u) return 0x7fc0u;
-  return (u + 0x7fffu + ((u >> 16) & 1u)) >> 16;
+  return __builtin_bit_cast(uint16_t, (__bf16)x);
 }
 __device__ __forceinline__ float bf16_float(uint32_t b) { return __uint_as_float(b << 16); }
 
@@ -188,10 +200,10 @@ __device__ __forceinline__ cdouble* uniform_ptr(const double* p) {
 // Whitened coordinates of one particle for one boundary, from d = x - q_mean[t]
 // (zero past d_x): columns u = Wcol d (Wcol lower triangular), rows
 // v = Wrow d + off.  Stores the R-rounded coordinates at dst (16-byte vector
-// stores where `aligned`), and in bf16 plans (dsth non-null) the split operands
-// (2u for columns, v for rows; DX/2 words of hi pairs, then DX/2 of lo pairs)
-// and the fp32 squared norm of the rounded entry at *dstn.
-template <typename R, int DX, bool kRow>
+// stores where `aligned`), and in bf16 plans (kSplit) the split operands (2u
+// for columns, v for rows; DX/2 words of hi pairs, then DX/2 of lo pairs) at
+// dsth and the fp32 squared norm of the rounded entry at *dstn.
+template <typename R, int DX, bool kRow, bool kSplit>
 __device__ __forceinline__ void emit_coords(cdouble* Wm, cdouble* off, const double (&d)[DX],
                                             R* dst, bool aligned, uint32_t* dsth, float* dstn) {
   double nrm = 0.0;
@@ -212,20 +224,18 @@ __device__ __forceinline__ void emit_coords(cdouble* Wm, cdouble* off, const dou
 #pragma unroll
       for (int k = 0; k < 4; ++k) dst[i0 + k] = r4[k];
     }
-    if constexpr (sizeof(R) == 4 && DX >= 16) {
-      if (dsth) {
-        uint32_t h[4], l[4];
+    if constexpr (kSplit) {
+      uint32_t h[4], l[4];
 #pragma unroll
-        for (int k = 0; k < 4; ++k) {
-          nrm += (double)r4[k] * (double)r4[k];
-          bf16_split(kRow ? (float)r4[k] : 2.0f * (float)r4[k], h[k], l[k]);
-        }
-        *(uint2*)(dsth + (i0 >> 1)) = make_uint2(h[0] | (h[1] << 16), h[2] | (h[3] << 16));
-        *(uint2*)(dsth + DX / 2 + (i0 >> 1)) = make_uint2(l[0] | (l[1] << 16), l[2] | (l[3] << 16));
+      for (int k = 0; k < 4; ++k) {
+        nrm += (double)r4[k] * (double)r4[k];
+        bf16_split(kRow ? (float)r4[k] : 2.0f * (float)r4[k], h[k], l[k]);
       }
+      *(uint2*)(dsth + (i0 >> 1)) = make_uint2(h[0] | (h[1] << 16), h[2] | (h[3] << 16));
+      *(uint2*)(dsth + DX / 2 + (i0 >> 1)) = make_uint2(l[0] | (l[1] << 16), l[2] | (l[3] << 16));
     }
   }
-  if (dsth) *dstn = (float)nrm;
+  if constexpr (kSplit) *dstn = (float)nrm;
 }
 
 // Padding column n (N <= n < Npad): weight zero.
@@ -449,7 +459,7 @@ __global__ __launch_bounds__(kBlock, 3) void k_leaves(
 // (the model's leaf records).  A boundary consumed by this leaf's level-0
 // combine is written straight into that combine's buffers (no table entry:
 // no other combine reads it); the other boundary goes to its table.
-template <typename R, int DX>
+template <typename R, int DX, bool kSplit>
 __global__ __launch_bounds__(kBlock, 3) void k_leaves_mat(
     const SeriesDesc* __restrict__ series, const int32_t* __restrict__ series_of_t,
     const int32_t* __restrict__ leaf_cons, int row0, int totalK, int N, int Npad,
@@ -475,7 +485,6 @@ __global__ __launch_bounds__(kBlock, 3) void k_leaves_mat(
   const int P = cons >> 1, role = cons & 1;
   const bool col_direct = cons >= 0 && role == 1;  // boundary t belongs to combine P
   const bool row_direct = cons >= 0 && role == 0;  // boundary t + 1 belongs to combine P
-  const bool split = sizeof(R) == 4 && DX >= 16 && nb.colh != nullptr;
   int bad = 0;
   auto reload = [&](int n, double (&x)[DX]) { load_particle<R, DX>(leafX, totalK, N, g, n, dx, x); };
   for (int n = threadIdx.x; n < N; n += kBlock) {
@@ -566,15 +575,16 @@ __global__ __launch_bounds__(kBlock, 3) void k_leaves_mat(
     if (t >= 1) {  // u for boundary t
       const size_t e = col_direct ? (size_t)P * Npad + n : (size_t)g * N + n;
       R* dst = col_direct ? (R*)nb.col + e * (DX + 1) : (R*)nb.tcol + e * DX;
-      uint32_t* dh = split ? (uint32_t*)(col_direct ? nb.colh : nb.tcolh) + e * DX : nullptr;
-      emit_coords<R, DX, false>(Wc, nullptr, d, dst, !col_direct, dh, nb.tcoln + (size_t)g * N + n);
+      uint32_t* dh = kSplit ? (uint32_t*)(col_direct ? nb.colh : nb.tcolh) + e * DX : nullptr;
+      float* dn = kSplit ? nb.tcoln + (size_t)g * N + n : nullptr;  // read back for the weight
+      emit_coords<R, DX, false, kSplit>(Wc, nullptr, d, dst, !col_direct, dh, dn);
     }
     if (t + 1 < K) {  // v for boundary t + 1
       const size_t e = row_direct ? (size_t)P * Npad + n : (size_t)g * N + n;
       R* dst = (R*)(row_direct ? nb.row : nb.trow) + e * DX;
-      uint32_t* dh = split ? (uint32_t*)(row_direct ? nb.rowh : nb.trowh) + e * DX : nullptr;
-      emit_coords<R, DX, true>(Wr, ro, d, dst, true, dh,
-                               split ? (row_direct ? nb.rown : nb.trown) + e : nullptr);
+      uint32_t* dh = kSplit ? (uint32_t*)(row_direct ? nb.rowh : nb.trowh) + e * DX : nullptr;
+      float* dn = kSplit ? (row_direct ? nb.rown : nb.trown) + e : nullptr;
+      emit_coords<R, DX, true, kSplit>(Wr, ro, d, dst, true, dh, dn);
     }
   }
   const double* gq = nb.tgq + (size_t)g * N;  // this thread's own entries, read back
@@ -584,7 +594,7 @@ __global__ __launch_bounds__(kBlock, 3) void k_leaves_mat(
       const double beta = (bmax > -INFINITY) ? (ell[n] + gq[n] - bmax) * kLog2e : -INFINITY;
       const size_t e = (size_t)P * Npad + n;
       ((R*)nb.col)[e * (DX + 1) + DX] = (R)beta;
-      if (split) nb.colb[e] = (float)beta - nb.tcoln[(size_t)g * N + n];
+      if constexpr (kSplit) nb.colb[e] = (float)beta - nb.tcoln[(size_t)g * N + n];
     }
     for (int n = N + threadIdx.x; n < Npad; n += kBlock) put_col_pad<R, DX>(nb, (size_t)P, Npad, n);
     if (threadIdx.x == 0) nb.bcol[P] = bmax;
@@ -595,21 +605,25 @@ __global__ __launch_bounds__(kBlock, 3) void k_leaves_mat(
 
 // ================================================================= rows
 // Tile = (combine, row block of RPL*64*W rows, column split of KC chunks, KC a
-// multiple of 4).  Lane owns rows base + lane + 64 r, r < RPL; lanes past N
+// multiple of 8).  Lane owns rows base + lane + 64 r, r < RPL; lanes past N
 // recompute row N-1 and store the same values (no per-row branches).  Chunk
-// sums go to P[node][m][k] (row stride NcP = Nc rounded up to 4), four chunks
-// per vector store, so the sampler reads a row's sums as one contiguous run.
-// With one column split the tile also stores the row sum sum_k P[m][k] (fp64,
-// k ascending); otherwise the sampling kernel forms that same sum from P.
+// sums go to P[node][m][k] (row stride NcP = Nc rounded up to 8), eight chunks
+// (one aligned 32-byte sector) per pair of vector stores, so that no sector is
+// written in part, and the sampler reads a row's sums as one contiguous run.
+// The fp64 row sum is the sum, in group order, of the fp64 sums of its groups
+// of kGroup chunks (each in chunk order), whatever the tile: with one column
+// split the tile stores it; with more, every split stores its groups' sums
+// (Gs) and the sampling kernel adds them.
 
 template <typename R, int DX, int RPL>
 __global__ __launch_bounds__(kBlock) void k_rows(const R* __restrict__ col,
                                                  const R* __restrict__ row,
                                                  R* __restrict__ P, double* __restrict__ Rsum,
                                                  float* __restrict__ Rshift,
+                                                 double* __restrict__ Gs,
                                                  const int32_t* __restrict__ node_list,
                                                  int node0, int N, int Npad, int Nc, int NcP,
-                                                 int RB, int CS, int KC, int force_redo) {
+                                                 int NGS, int RB, int CS, int KC, int force_redo) {
   const int W = blockDim.x >> 6;
   const int tiles = RB * CS;
   const int node_local = blockIdx.x / tiles;
@@ -655,10 +669,13 @@ __global__ __launch_bounds__(kBlock) void k_rows(const R* __restrict__ col,
   auto pass = [&]() {
 #pragma unroll
     for (int r = 0; r < RPL; ++r) Rm[r] = 0.0;
-    for (int kg = k0; kg < k1; kg += 4) {
-      R acc[RPL][4];
+    for (int kg = k0; kg < k1; kg += kGroup) {
+      R acc[RPL][kGroup];
+      double G[RPL];  // the group's sum
 #pragma unroll
-      for (int q = 0; q < 4; ++q) {
+      for (int r = 0; r < RPL; ++r) G[r] = 0.0;
+#pragma unroll
+      for (int q = 0; q < kGroup; ++q) {
 #pragma unroll
         for (int r = 0; r < RPL; ++r) acc[r][q] = (R)0;
         if (kg + q < k1) {  // uniform
@@ -678,12 +695,17 @@ __global__ __launch_bounds__(kBlock) void k_rows(const R* __restrict__ col,
             }
           }
 #pragma unroll
-          for (int r = 0; r < RPL; ++r) Rm[r] += (double)acc[r][q];
+          for (int r = 0; r < RPL; ++r) G[r] += (double)acc[r][q];
         }
       }
 #pragma unroll
-      for (int r = 0; r < RPL; ++r)
-        store4<R>(Pn + (size_t)mrow[r] * NcP + kg, acc[r][0], acc[r][1], acc[r][2], acc[r][3]);
+      for (int r = 0; r < RPL; ++r) {
+        Rm[r] += G[r];
+        R* pm = Pn + (size_t)mrow[r] * NcP + kg;
+        store4<R>(pm, acc[r][0], acc[r][1], acc[r][2], acc[r][3]);
+        store4<R>(pm + 4, acc[r][4], acc[r][5], acc[r][6], acc[r][7]);
+        if (CS > 1) Gs[((size_t)node_local * N + mrow[r]) * NGS + kg / kGroup] = G[r];
+      }
     }
   };
   pass();
@@ -843,10 +865,13 @@ __global__ __launch_bounds__(kBlock) void k_rows_mfma(
   auto pass = [&]() {
 #pragma unroll
     for (int b = 0; b < MB; ++b) Rm[b] = 0.0;
-    for (int kg = k0; kg < k1; kg += 4) {
-      float c4[MB][4];
+    for (int kg = k0; kg < k1; kg += kGroup) {
+      float c4[MB][kGroup];
+      double G[MB];  // the group's sum
 #pragma unroll
-      for (int q = 0; q < 4; ++q) {
+      for (int b = 0; b < MB; ++b) G[b] = 0.0;
+#pragma unroll
+      for (int q = 0; q < kGroup; ++q) {
 #pragma unroll
         for (int b = 0; b < MB; ++b) c4[b][q] = 0.0f;
         if (kg + q < k1) {  // uniform
@@ -859,14 +884,19 @@ __global__ __launch_bounds__(kBlock) void k_rows_mfma(
             for (int r = 0; r < 16; ++r) e += Real<float>::exp2(acc[r]);
             e += __shfl_xor(e, 32, 64);
             c4[b][q] = e;
-            Rm[b] += (double)e;
+            G[b] += (double)e;
           }
         }
       }
+#pragma unroll
+      for (int b = 0; b < MB; ++b) Rm[b] += G[b];
       if (h == 0) {
 #pragma unroll
-        for (int b = 0; b < MB; ++b)
-          store4<float>(Pn + (size_t)mrow[b] * NcP + kg, c4[b][0], c4[b][1], c4[b][2], c4[b][3]);
+        for (int b = 0; b < MB; ++b) {
+          float* pm = Pn + (size_t)mrow[b] * NcP + kg;
+          store4<float>(pm, c4[b][0], c4[b][1], c4[b][2], c4[b][3]);
+          store4<float>(pm + 4, c4[b][4], c4[b][5], c4[b][6], c4[b][7]);
+        }
       }
     }
   };
@@ -914,30 +944,23 @@ __global__ __launch_bounds__(kBlock) void k_rows_mfma(
 // maximum as shift: their chunk sums go to Pr, R_m carries a factor
 // 2^shift_m and the weights are formed in log space.
 // The combine's column data is staged in LDS when it fits (col_in_lds).
-template <typename R>
-__device__ __forceinline__ void load4(const R* p, R (&q)[4]);
-template <>
-__device__ __forceinline__ void load4<float>(const float* p, float (&q)[4]) {
-  const float4 v = *(const float4*)p;
-  q[0] = v.x; q[1] = v.y; q[2] = v.z; q[3] = v.w;
-}
-template <>
-__device__ __forceinline__ void load4<double>(const double* p, double (&q)[4]) {
-  const double2 a = ((const double2*)p)[0], b = ((const double2*)p)[1];
-  q[0] = a.x; q[1] = a.y; q[2] = b.x; q[3] = b.y;
-}
 
 // Draw n of combine `nodeid` is (l, r): its ancestry, the merged block's
 // first/last-time leaf indices, and the data the consuming combine reads.
+// The leaf indices of draw (l, r) at the merged block's first and last times.
+__device__ __forceinline__ void draw_sources(const NodeBufs& nb, const NodeDesc& nd, int N, int l,
+                                             int r, int& sf, int& sl) {
+  sf = (nd.lchild < 0) ? l : nb.sfirst[(size_t)nd.lchild * N + l];
+  sl = (nd.rchild < 0) ? r : nb.slast[(size_t)nd.rchild * N + r];
+}
+
 template <typename R, int DX>
 __device__ __forceinline__ void record_draw(const NodeBufs& nb, const NodeDesc& nd, int nodeid,
-                                            int N, int Npad, int n, int l, int r,
+                                            int N, int Npad, int n, int l, int r, int sf, int sl,
                                             int32_t* ancL, int32_t* ancR, int gA, int gB,
                                             double logN, const double* __restrict__ bmerged) {
   ancL[n] = l;
   ancR[n] = r;
-  const int sf = (nd.lchild < 0) ? l : nb.sfirst[(size_t)nd.lchild * N + l];
-  const int sl = (nd.rchild < 0) ? r : nb.slast[(size_t)nd.rchild * N + r];
   nb.sfirst[(size_t)nodeid * N + n] = sf;
   nb.slast[(size_t)nodeid * N + n] = sl;
   const int cons = nd.consumer;
@@ -982,8 +1005,8 @@ __device__ __forceinline__ void load_row32(const R* __restrict__ Pm, int NcP, R 
   }
 }
 
-// fp64 sum of a row's chunk sums in chunk order (the row sum R_m every path
-// uses: the rows kernel forms the same sum when it runs without column splits)
+// fp64 sum of a rescued row's chunk sums (in Pr) in chunk order: the sum the
+// rescue forms for the row's CDF weight
 template <typename R>
 __device__ __forceinline__ double row_sum(const R* __restrict__ Pm, int Nc, int NcP) {
   double s = 0.0;
@@ -1015,16 +1038,18 @@ template <typename R, int DX>
 __global__ __launch_bounds__(kBlock) void k_sample(
     const NodeDesc* __restrict__ nodes, const SeriesDesc* __restrict__ series,
     const int32_t* __restrict__ node_list, int node0, int DS,
-    int N, int Npad, int Nc, int NcP, int rows_summed, int col_in_lds, int force_rescue,
-    int rescale_chunk, const double* __restrict__ bmerged, const R* __restrict__ P,
-    R* __restrict__ Pr, double* __restrict__ Rsum, const float* __restrict__ Rshift,
+    int N, int Npad, int Nc, int NcP, int rows_summed, int NGS, int col_in_lds,
+    int force_rescue, int rescale_chunk, const double* __restrict__ bmerged,
+    const R* __restrict__ P, R* __restrict__ Pr, double* __restrict__ Rsum,
+    const double* __restrict__ Gs, const float* __restrict__ Rshift,
     unsigned long long* __restrict__ rescue_count, NodeBufs nb) {
   extern __shared__ double smem[];
   const int nthr = blockDim.x;
   const int cstr = col_chunk_stride<R, DX>(col_in_lds);
   double* cdf = smem;                        // [Npad]: row sums R_m, then the row CDF
   float* shift = (float*)(smem + Npad);      // [Npad]
-  R* lcol = (R*)(shift + Npad);              // [Nc][cstr] when col_in_lds
+  R* aw = (R*)(shift + Npad);                // [Npad]: row weights alpha_m (left leaf)
+  R* lcol = aw + Npad;                       // [Nc][cstr] when col_in_lds
   __shared__ double red[2 * kMaxWaves];
   __shared__ int redi[2 * kMaxWaves];
   const int node_local = blockIdx.x / DS;
@@ -1042,11 +1067,21 @@ __global__ __launch_bounds__(kBlock) void k_sample(
   R* __restrict__ Prn = Pr + (size_t)node_local * N * NcP;
   double* __restrict__ Rn = Rsum + (size_t)node_local * N;
   const R* __restrict__ alp = (const R*)nb.alpha + (size_t)nodeid * N;
-  if (col_in_lds) {
+  if (col_in_lds) {  // four loads in flight per thread
     constexpr int CW = kChunk * (DX + 1);
-    for (int i = threadIdx.x; i < Npad * (DX + 1); i += nthr) {
-      const int k = i / CW;
-      lcol[k * cstr + (i - k * CW)] = gcol[i];
+    const int tot = Npad * (DX + 1);
+    for (int i0 = threadIdx.x; i0 < tot; i0 += 4 * nthr) {
+      R cv[4];
+#pragma unroll
+      for (int b = 0; b < 4; ++b) cv[b] = gcol[min(i0 + b * nthr, tot - 1)];
+#pragma unroll
+      for (int b = 0; b < 4; ++b) {
+        const int i = i0 + b * nthr;
+        if (i < tot) {
+          const int k = i / CW;
+          lcol[k * cstr + (i - k * CW)] = cv[b];
+        }
+      }
     }
   }
   const R* colp = col_in_lds ? lcol : gcol;
@@ -1069,23 +1104,57 @@ __global__ __launch_bounds__(kBlock) void k_sample(
   const int m0 = threadIdx.x * per, m1 = min(N, m0 + per);
   double amax = -INFINITY;
   int rescued = 0, row_nan = 0;
-  for (int m = m0; m < m1; ++m) {
-    amax = fmax(amax, left_leaf ? (double)alp[m] : -logN);
-    // with column splits the rows kernel leaves the row sums to this kernel,
-    // which stores them for the draws (every workgroup of the combine writes
-    // the same values; no workgroup reads them before its own write)
-    const double Rm = rows_summed ? Rn[m] : row_sum<R>(Pn + (size_t)m * NcP, Nc, NcP);
-    if ((!(Rm >= Real<R>::kTiny) || isinf(Rm) || force_rescue) && !isnan(Rm)) {
-      atomicOr(&need[m >> 5], 1u << (m & 31));
-      atomicOr(&resc[m >> 5], 1u << (m & 31));
-      rescued = 1;
-    } else if (!rows_summed) {
-      Rn[m] = Rm;
+  for (int mb = m0; mb < m1; mb += 4) {
+    double Rv[4];
+    R av[4];
+    float sv[4];
+#pragma unroll
+    for (int i = 0; i < 4; ++i) {  // the loads of four rows issued together
+      const int m = min(mb + i, m1 - 1);
+      if (rows_summed) {
+        Rv[i] = Rn[m];
+      } else {
+        // column splits: the rows kernel left the sums of the row's groups of
+        // kGroup chunks; their sum in group order is the row sum of one split
+        const double* gp = Gs + ((size_t)node_local * N + m) * NGS;
+        const int NG = NcP / kGroup;
+        double t;
+        if (NGS == 4) {
+          const double2 g01 = ((const double2*)gp)[0], g23 = ((const double2*)gp)[1];
+          t = g01.x;
+          if (NG > 1) t += g01.y;
+          if (NG > 2) t += g23.x;
+          if (NG > 3) t += g23.y;
+        } else {
+          t = gp[0];
+          for (int g = 1; g < NG; ++g) t += gp[g];
+        }
+        Rv[i] = t;
+      }
+      av[i] = left_leaf ? alp[m] : (R)0;
+      sv[i] = kRowShift<DX> ? Rshift[(size_t)node_local * N + m] : 0.0f;
     }
-    if (isnan(Rm)) row_nan = 1;
-    cdf[m] = Rm;
-    if constexpr (kRowShift<DX>) shift[m] = Rshift[(size_t)node_local * N + m];
-    else shift[m] = 0.0f;
+#pragma unroll
+    for (int i = 0; i < 4; ++i) {
+      const int m = mb + i;
+      if (m < m1) {
+        amax = fmax(amax, left_leaf ? (double)av[i] : -logN);
+        const double Rm = Rv[i];
+        if ((!(Rm >= Real<R>::kTiny) || isinf(Rm) || force_rescue) && !isnan(Rm)) {
+          atomicOr(&need[m >> 5], 1u << (m & 31));
+          atomicOr(&resc[m >> 5], 1u << (m & 31));
+          rescued = 1;
+        } else if (!rows_summed) {
+          // stored for the draws: every workgroup of the combine writes the
+          // same values, and none reads them before its own write
+          Rn[m] = Rm;
+        }
+        if (isnan(Rm)) row_nan = 1;
+        cdf[m] = Rm;
+        shift[m] = sv[i];
+        aw[m] = av[i];
+      }
+    }
   }
   double Astar = amax;
   block_max_or(Astar, rescued, red, redi);  // also orders the writes above
@@ -1164,7 +1233,7 @@ __global__ __launch_bounds__(kBlock) void k_sample(
   if (ds == 0 && sd.row_lse) {  // r_m = log of row m's sum of pair weights
     double* rl = sd.row_lse + (size_t)(c - 1) * N;
     for (int m = m0; m < m1; ++m) {
-      const double a = left_leaf ? (double)alp[m] : -logN;
+      const double a = left_leaf ? (double)aw[m] : -logN;
       rl[m] = a + Bc + M.trans_lognorm + log(cdf[m]) + (double)shift[m] * kLn2;
     }
   }
@@ -1175,7 +1244,7 @@ __global__ __launch_bounds__(kBlock) void k_sample(
   if (rescued || kRowShift<DX>) {
     double gmax = -INFINITY;
     for (int m = m0; m < m1; ++m) {
-      const double a = left_leaf ? (double)alp[m] : -logN;
+      const double a = left_leaf ? (double)aw[m] : -logN;
       double rho = -INFINITY;
       if (Astar > -INFINITY && cdf[m] > 0.0) rho = a - Astar + (double)shift[m] * kLn2 + log(cdf[m]);
       cdf[m] = rho;
@@ -1186,7 +1255,7 @@ __global__ __launch_bounds__(kBlock) void k_sample(
   } else {
     for (int m = m0; m < m1; ++m) {
       double w = 0.0;
-      if (Astar > -INFINITY) w = (left_leaf ? exp((double)alp[m] - Astar) : 1.0) * cdf[m];
+      if (Astar > -INFINITY) w = (left_leaf ? exp((double)aw[m] - Astar) : 1.0) * cdf[m];
       cdf[m] = w;
     }
   }
@@ -1232,121 +1301,156 @@ __global__ __launch_bounds__(kBlock) void k_sample(
     for (int n = N + threadIdx.x; n < Npad; n += nthr) put_col_pad<R, DX>(nb, (size_t)cons, Npad, n);
     if (threadIdx.x == 0) nb.bcol[cons] = bmerged[gA];
   }
-  // ---- draws
+  // ---- draws, DB per thread at a time (each step's memory accesses of the DB
+  // draws issued together).  DB = 1: two draws per thread need about 190
+  // registers, which halves the waves in flight and measured slower.
+  constexpr int DB = 1;
   const int dper = (N + DS - 1) / DS;
   const int n0 = ds * dper, n1 = min(N, n0 + dper);
   int32_t* ancL = sd.anc + (size_t)(c - 1) * 2 * N;
   int32_t* ancR = ancL + N;
   const bool star = sd.star != nullptr;
-  for (int n = n0 + threadIdx.x; n < n1; n += nthr) {
-    const Words4 w = philox4x64_10((uint64_t)n, (uint64_t)c, kPurposeCombine, 0ull, sd.seed, kKey1);
-    const double u1 = unif53(w.w0), u2 = unif53(w.w1);
-    int l, r;
-    if (degenerate) {
-      l = min((int)(u1 * N), N - 1);
-      r = min((int)(u2 * N), N - 1);
-    } else {
-      const double target = u1 * T;
-      int lo = 0, hi = N;
-      while (lo < hi) {
-        const int mid = (lo + hi) >> 1;
-        if (cdf[mid] > target) hi = mid; else lo = mid + 1;
+  for (int nbase = n0 + threadIdx.x; nbase < n1; nbase += DB * nthr) {
+    int nn[DB], l[DB], r[DB];
+    double u2[DB];
+#pragma unroll
+    for (int b = 0; b < DB; ++b) {
+      nn[b] = nbase + b * nthr;
+      const int n = nn[b] < n1 ? nn[b] : nbase;  // idle slots redo draw nbase, unrecorded
+      const Words4 w =
+          philox4x64_10((uint64_t)n, (uint64_t)c, kPurposeCombine, 0ull, sd.seed, kKey1);
+      const double u1 = unif53(w.w0);
+      u2[b] = unif53(w.w1);
+      if (degenerate) {
+        l[b] = min((int)(u1 * N), N - 1);
+        r[b] = min((int)(u2[b] * N), N - 1);
+      } else {
+        const double target = u1 * T;
+        int lo = 0, hi = N;
+        while (lo < hi) {
+          const int mid = (lo + hi) >> 1;
+          if (cdf[mid] > target) hi = mid; else lo = mid + 1;
+        }
+        l[b] = lo < N ? lo : (lastpos >= 0 ? lastpos : 0);
       }
-      l = lo < N ? lo : (lastpos >= 0 ? lastpos : 0);
-      R v[DX];
+    }
+    if (!degenerate) {
+      // row l's coordinates, its first 16 chunk sums and its row sum R_l
+      // (rescued rows: the sum of their chunk sums in Pr)
+      R v[DB][DX], q[DB][16];
+      double Rl[DB];
+      bool lres[DB];
 #pragma unroll
-      for (int i = 0; i < DX; ++i) v[i] = rowp[(size_t)l * DX + i];
-      const float sh = shift[l];
-      const bool lres = (resc[l >> 5] >> (l & 31)) & 1u;
-      const R* Pl = (lres ? Prn : Pn) + (size_t)l * NcP;
-      // the first 16 chunk sums of row l, loaded together with R_l (the row sum
-      // of the row phase; rescued rows: the sum of their chunk sums in Pr)
-      R q[16];
+      for (int b = 0; b < DB; ++b) {
 #pragma unroll
-      for (int g4 = 0; g4 < 4; ++g4) {
-        R t4[4];
-        if (4 * g4 < NcP) load4<R>(Pl + 4 * g4, t4);
+        for (int i = 0; i < DX; ++i) v[b][i] = rowp[(size_t)l[b] * DX + i];
+        lres[b] = (resc[l[b] >> 5] >> (l[b] & 31)) & 1u;
+        const R* Pl = (lres[b] ? Prn : Pn) + (size_t)l[b] * NcP;
 #pragma unroll
-        for (int i = 0; i < 4; ++i) q[4 * g4 + i] = (4 * g4 < NcP) ? t4[i] : (R)0;
+        for (int g4 = 0; g4 < 4; ++g4) {
+          R t4[4];
+          if (4 * g4 < NcP) load4<R>(Pl + 4 * g4, t4);
+#pragma unroll
+          for (int i = 0; i < 4; ++i) q[b][4 * g4 + i] = (4 * g4 < NcP) ? t4[i] : (R)0;
+        }
+        Rl[b] = Rn[l[b]];
       }
-      const double target2 = u2 * (lres ? row_sum<R>(Pl, Nc, NcP) : Rn[l]);
-      // chunk: first k whose prefix of chunk sums exceeds u2 R_l (16 at a time)
-      double pref = 0.0, pref_last = 0.0, pk = 0.0, plast = 0.0;
-      int k = -1, klast = 0;
-      for (int kb = 0; kb < Nc && k < 0; kb += 16) {
-        if (kb > 0) {
 #pragma unroll
-          for (int g4 = 0; g4 < 4; ++g4) {
-            R t4[4];
-            if (kb + 4 * g4 < NcP) load4<R>(Pl + kb + 4 * g4, t4);
+      for (int b = 0; b < DB; ++b) {
+        asm volatile("" ::: "memory");  // one draw after the other from here (registers)
+        const R* Pl = (lres[b] ? Prn : Pn) + (size_t)l[b] * NcP;
+        const float sh = shift[l[b]];
+        const double target2 = u2[b] * (lres[b] ? row_sum<R>(Pl, Nc, NcP) : Rl[b]);
+        // chunk: first k whose prefix of chunk sums exceeds u2 R_l (16 at a time)
+        double pref = 0.0, pref_last = 0.0, pk = 0.0, plast = 0.0;
+        int k = -1, klast = 0;
+        for (int kb = 0; kb < Nc && k < 0; kb += 16) {
+          R qq[16];
+          if (kb > 0) {
 #pragma unroll
-            for (int i = 0; i < 4; ++i) q[4 * g4 + i] = (kb + 4 * g4 < NcP) ? t4[i] : (R)0;
+            for (int g4 = 0; g4 < 4; ++g4) {
+              R t4[4];
+              if (kb + 4 * g4 < NcP) load4<R>(Pl + kb + 4 * g4, t4);
+#pragma unroll
+              for (int i = 0; i < 4; ++i) qq[4 * g4 + i] = (kb + 4 * g4 < NcP) ? t4[i] : (R)0;
+            }
+          } else {
+#pragma unroll
+            for (int i = 0; i < 16; ++i) qq[i] = q[b][i];
+          }
+#pragma unroll
+          for (int i = 0; i < 16; ++i) {
+            const int kk = kb + i;
+            if (k < 0 && kk < Nc) {
+              const double pp = (double)qq[i];
+              if (pp > 0.0) { klast = kk; pref_last = pref; plast = pp; }
+              if (target2 < pref + pp) { k = kk; pk = pp; } else pref += pp;
+            }
           }
         }
+        if (k < 0) { k = klast; pref = pref_last; pk = plast; }
+        double rem = target2 - pref;
+        // recompute chunk k of row l in the rows kernel's order
+        const R* cp = colp + (size_t)k * cstr;
+        R acc = (R)0;
+        int lastj = 0, rr = -1;
+        bool done = false;
+        if constexpr (sizeof(R) == 4 && DX >= 16) {
+          if (rescale_chunk) {
+            // bf16 plans: the stored chunk sums come from the matrix cores'
+            // expanded form; the recompute here is the direct form, so the
+            // search is rescaled to the recomputed chunk total
+            R ev[kChunk];
+            R tot = (R)0;
 #pragma unroll
-        for (int i = 0; i < 16; ++i) {
-          const int kk = kb + i;
-          if (k < 0 && kk < Nc) {
-            const double p = (double)q[i];
-            if (p > 0.0) { klast = kk; pref_last = pref; plast = p; }
-            if (target2 < pref + p) { k = kk; pk = p; } else pref += p;
+            for (int jj = 0; jj < kChunk; ++jj) {
+              R u[DX];
+#pragma unroll
+              for (int i = 0; i < DX; ++i) u[i] = cp[jj * (DX + 1) + i];
+              ev[jj] = Real<R>::exp2(pair_log2w<R, DX>(u, cp[jj * (DX + 1) + DX], v[b]) - (R)sh);
+              tot += ev[jj];
+            }
+            if (pk > 0.0 && tot > (R)0) rem *= (double)tot / pk;
+#pragma unroll
+            for (int jj = 0; jj < kChunk; ++jj) {
+              acc += ev[jj];
+              if (ev[jj] > (R)0) lastj = jj;
+              if (rr < 0 && rem < (double)acc) rr = jj;
+            }
+            done = true;
           }
         }
-      }
-      if (k < 0) { k = klast; pref = pref_last; pk = plast; }
-      double rem = target2 - pref;
-      // recompute chunk k of row l in the rows kernel's order
-      const R* cp = colp + (size_t)k * cstr;
-      R acc = (R)0;
-      int lastj = 0;
-      r = -1;
-      bool done = false;
-      if constexpr (sizeof(R) == 4 && DX >= 16) {
-        if (rescale_chunk) {
-          // bf16 plans: the stored chunk sums come from the matrix cores'
-          // expanded form; the recompute here is the direct form, so the
-          // search is rescaled to the recomputed chunk total
-          R ev[kChunk];
-          R tot = (R)0;
+        if (!done) {
 #pragma unroll
           for (int jj = 0; jj < kChunk; ++jj) {
             R u[DX];
 #pragma unroll
             for (int i = 0; i < DX; ++i) u[i] = cp[jj * (DX + 1) + i];
-            ev[jj] = Real<R>::exp2(pair_log2w<R, DX>(u, cp[jj * (DX + 1) + DX], v) - (R)sh);
-            tot += ev[jj];
+            const R e = Real<R>::exp2(pair_log2w<R, DX>(u, cp[jj * (DX + 1) + DX], v[b]) - (R)sh);
+            acc += e;
+            if (e > (R)0) lastj = jj;
+            if (rr < 0 && rem < (double)acc) rr = jj;
           }
-          if (pk > 0.0 && tot > (R)0) rem *= (double)tot / pk;
-#pragma unroll
-          for (int jj = 0; jj < kChunk; ++jj) {
-            acc += ev[jj];
-            if (ev[jj] > (R)0) lastj = jj;
-            if (r < 0 && rem < (double)acc) r = jj;
-          }
-          done = true;
         }
+        if (rr < 0) rr = lastj;
+        rr += k * kChunk;
+        r[b] = rr < N ? rr : N - 1;  // N - 1 only reachable through NaN weights
       }
-      if (!done) {
+    }
+    int sf[DB], sl[DB];
 #pragma unroll
-        for (int jj = 0; jj < kChunk; ++jj) {
-          R u[DX];
-#pragma unroll
-          for (int i = 0; i < DX; ++i) u[i] = cp[jj * (DX + 1) + i];
-          const R e = Real<R>::exp2(pair_log2w<R, DX>(u, cp[jj * (DX + 1) + DX], v) - (R)sh);
-          acc += e;
-          if (e > (R)0) lastj = jj;
-          if (r < 0 && rem < (double)acc) r = jj;
-        }
+    for (int b = 0; b < DB; ++b) {
+      if (nn[b] == 0 && star) {  // conditional combine: slot 0 keeps the star, (0, 0)
+        l[b] = 0;
+        r[b] = 0;
       }
-      if (r < 0) r = lastj;
-      r += k * kChunk;
-      if (r >= N) r = N - 1;  // only reachable through NaN weights
+      draw_sources(nb, nd, N, l[b], r[b], sf[b], sl[b]);
     }
-    if (n == 0 && star) {  // conditional combine: slot 0 keeps the star, (0, 0)
-      l = 0;
-      r = 0;
-    }
-    record_draw<R, DX>(nb, nd, nodeid, N, Npad, n, l, r, ancL, ancR, gA, gB, logN, bmerged);
+#pragma unroll
+    for (int b = 0; b < DB; ++b)
+      if (nn[b] < n1)
+        record_draw<R, DX>(nb, nd, nodeid, N, Npad, nn[b], l[b], r[b], sf[b], sl[b], ancL, ancR,
+                           gA, gB, logN, bmerged);
   }
 }
 
@@ -1461,7 +1565,9 @@ __global__ __launch_bounds__(kBlock) void k_sample_lazy(
       l = 0;
       r = 0;
     }
-    record_draw<R, DX>(nb, nd, nodeid, N, Npad, n, l, r, ancL, ancR, gA, gB, logN, bmerged);
+    int sf, sl;
+    draw_sources(nb, nd, N, l, r, sf, sl);
+    record_draw<R, DX>(nb, nd, nodeid, N, Npad, n, l, r, sf, sl, ancL, ancR, gA, gB, logN, bmerged);
   }
   if (capped || bad) atomicOr(sd.status, (capped ? kFlagLazyCap : 0) | (bad ? kFlagNumeric : 0));
 }
@@ -1473,6 +1579,15 @@ static void launch_rows_mfma(const LevelLaunch& L, hipStream_t st, unsigned grid
                                               (float*)L.P, L.Rsum, L.Rshift, L.node_list, L.node0,
                                               L.N, L.Npad, L.Nc, L.NcP, L.RB, L.CS, L.KC,
                                               L.force_rescue ? 1 : 0);
+}
+
+template <typename R, int DX, int RPL>
+static void launch_rows_valu(const LevelLaunch& L, hipStream_t st, unsigned grid, unsigned block) {
+  k_rows<R, DX, RPL><<<grid, block, 0, st>>>((const R*)L.nb.col, (const R*)L.nb.row, (R*)L.P,
+                                             L.Rsum, L.Rshift, L.Gs, L.node_list,
+                                             L.node0, L.N, L.Npad, L.Nc, L.NcP, group_stride(L.NcP),
+                                             L.RB, L.CS, L.KC,
+                                             L.force_rescue ? 1 : 0);
 }
 
 template <typename R, int DX>
@@ -1491,24 +1606,9 @@ static int launch_rows_t(const LevelLaunch& L, hipStream_t st) {
   }
   if (L.bf16) return -1;
   switch (L.RPL) {
-    case 1:
-      k_rows<R, DX, 1><<<grid, block, 0, st>>>((const R*)L.nb.col, (const R*)L.nb.row, (R*)L.P,
-                                               L.Rsum, L.Rshift, L.node_list, L.node0, L.N, L.Npad, L.Nc,
-                                               L.NcP, L.RB, L.CS, L.KC,
-                                               L.force_rescue ? 1 : 0);
-      return 0;
-    case 2:
-      k_rows<R, DX, 2><<<grid, block, 0, st>>>((const R*)L.nb.col, (const R*)L.nb.row, (R*)L.P,
-                                               L.Rsum, L.Rshift, L.node_list, L.node0, L.N, L.Npad, L.Nc,
-                                               L.NcP, L.RB, L.CS, L.KC,
-                                               L.force_rescue ? 1 : 0);
-      return 0;
-    case 4:
-      k_rows<R, DX, 4><<<grid, block, 0, st>>>((const R*)L.nb.col, (const R*)L.nb.row, (R*)L.P,
-                                               L.Rsum, L.Rshift, L.node_list, L.node0, L.N, L.Npad, L.Nc,
-                                               L.NcP, L.RB, L.CS, L.KC,
-                                               L.force_rescue ? 1 : 0);
-      return 0;
+    case 1: launch_rows_valu<R, DX, 1>(L, st, grid, block); return 0;
+    case 2: launch_rows_valu<R, DX, 2>(L, st, grid, block); return 0;
+    case 4: launch_rows_valu<R, DX, 4>(L, st, grid, block); return 0;
   }
   return -1;
 }
@@ -1526,15 +1626,15 @@ static int launch_level_t(const LevelLaunch& L, hipStream_t st, Timer* tm) {
   tm->begin(1, st);
   if (launch_rows_t<R, DX>(L, st)) return -1;
   tm->end(1, st);
-  size_t lds_samp = (size_t)L.Npad * (sizeof(double) + sizeof(float));
+  size_t lds_samp = (size_t)L.Npad * (sizeof(double) + sizeof(float) + sizeof(R));
   const size_t lds_col = (size_t)(L.Npad / kChunk) * col_chunk_lds_stride<R, DX>() * sizeof(R);
   const int col_in_lds = (lds_samp + lds_col <= 96 * 1024) ? 1 : 0;
   if (col_in_lds) lds_samp += lds_col;
   tm->begin(2, st);
   k_sample<R, DX><<<(unsigned)L.nodes * L.DS, (unsigned)L.SB, lds_samp, st>>>(
       L.d_nodes, L.d_series, L.node_list, L.node0, L.DS, L.N, L.Npad, L.Nc, L.NcP,
-      L.CS == 1 ? 1 : 0, col_in_lds, L.force_rescue ? 1 : 0, L.bf16 ? 1 : 0, L.bmerged,
-      (const R*)L.P, (R*)L.Pr, L.Rsum, L.Rshift, L.rescue_count, L.nb);
+      L.CS == 1 ? 1 : 0, group_stride(L.NcP), col_in_lds, L.force_rescue ? 1 : 0, L.bf16 ? 1 : 0, L.bmerged,
+      (const R*)L.P, (R*)L.Pr, L.Rsum, L.Gs, L.Rshift, L.rescue_count, L.nb);
   tm->end(2, st);
   return 0;
 }
@@ -1543,7 +1643,17 @@ template <typename R, int DX>
 static void launch_leaves_t(const LeafLaunch& L, hipStream_t st, Timer* tm) {
   tm->begin(0, st);
   if constexpr (DX >= 8) {
-    k_leaves_mat<R, DX><<<L.rows, kBlock, (size_t)L.N * sizeof(double), st>>>(
+    const size_t lds = (size_t)L.N * sizeof(double);
+    if constexpr (sizeof(R) == 4 && DX >= 16) {
+      if (L.nb.colh) {  // bf16 plan: split operands too
+        k_leaves_mat<R, DX, true><<<L.rows, kBlock, lds, st>>>(
+            L.d_series, L.d_series_of_t, L.d_leaf_cons, L.row0, L.totalK, L.N, L.Npad,
+            (R*)L.leafX, (R*)L.leafW, L.leafL, L.bmerged, L.nb);
+        tm->end(0, st);
+        return;
+      }
+    }
+    k_leaves_mat<R, DX, false><<<L.rows, kBlock, lds, st>>>(
         L.d_series, L.d_series_of_t, L.d_leaf_cons, L.row0, L.totalK, L.N, L.Npad, (R*)L.leafX,
         (R*)L.leafW, L.leafL, L.bmerged, L.nb);
   } else {

@@ -73,6 +73,8 @@ struct LevelLaunch {
   void* Pr;             // chunk sums of rescued rows (same layout as P)
   double* Rsum;
   float* Rshift;        // per-row shifts of the row sums (DX >= 8), like Rsum
+  double* Gs;           // per row of the slice: sums of its groups of kGroup chunks
+                        // (group_stride(NcP) per row), written with column splits
   bool force_rescue;    // testing aid: every row takes the rescue path
   unsigned long long* rescue_count;  // rescued rows are added here when non-null
   NodeBufs nb;
@@ -98,6 +100,12 @@ struct LeafLaunch {
 // per workgroup (the exact sampler's fp64 CDF is summed in an order fixed by
 // the workgroup size, so every path uses the same one), and several
 // workgroups per combine when a level has few combines.
+// Row stride of the chunk-group sums (NcP / kGroup groups, at least 4, even).
+inline int group_stride(int NcP) {
+  const int g = NcP / kGroup;
+  return g <= 4 ? 4 : (g + 1) / 2 * 2;
+}
+
 inline void set_sample_shape(LevelLaunch& L) {
   const int nodes = L.nodes < 1 ? 1 : L.nodes;
   L.SB = kBlock;

@@ -75,6 +75,7 @@ struct Class {
   void* Pr = nullptr;
   double* Rsum = nullptr;
   float* Rshift = nullptr;
+  double* Gs = nullptr;  // chunk-group sums of rows under column splits
   NodeDesc* d_nodes = nullptr;
   int32_t* d_series_of_t = nullptr;
   int32_t* d_leaf_cons = nullptr;
@@ -134,7 +135,7 @@ int make_class(dsmc_server_impl* s, int N, int DX, std::unique_ptr<Class>* out) 
   c->rsz = c->fp64 ? 8 : 4;
   c->Npad = (N + kChunk - 1) / kChunk * kChunk;
   c->Nc = c->Npad / kChunk;
-  c->NcP = (c->Nc + 3) / 4 * 4;
+  c->NcP = (c->Nc + kGroup - 1) / kGroup * kGroup;
   const size_t budget = s->d.mem_budget / (size_t)s->d.max_classes;
   const PoolSizes ps = pool_sizes(N, DX, DX, c->rsz);
   const size_t p_budget = std::min<size_t>(budget / 4, (size_t)2 << 30);  // chunk sums + rescued copies
@@ -164,6 +165,7 @@ int make_class(dsmc_server_impl* s, int N, int DX, std::unique_ptr<Class>* out) 
       (rc = dalloc(c.get(), &c->Pr, nc * N * c->NcP * R)) ||
       (rc = dalloc(c.get(), &c->Rsum, nc * N * sizeof(double))) ||
       (rc = dalloc(c.get(), &c->Rshift, nc * N * sizeof(float))) ||
+      (rc = dalloc(c.get(), &c->Gs, nc * N * group_stride(c->NcP) * sizeof(double))) ||
       (rc = dalloc(c.get(), &c->d_nodes, TK * sizeof(NodeDesc))) ||
       (rc = dalloc(c.get(), &c->d_series_of_t, TK * sizeof(int32_t))) ||
       (rc = dalloc(c.get(), &c->d_leaf_cons, TK * sizeof(int32_t))) ||
@@ -324,6 +326,7 @@ int tick(dsmc_server_impl* s, Class* c) {
     L.Pr = c->Pr;
     L.Rsum = c->Rsum;
     L.Rshift = c->Rshift;
+    L.Gs = c->Gs;
     L.nb = c->nb;
     set_sample_shape(L);
     set_tile(L, heuristic_tile(nodes, N, c->Nc, c->DX < 8));

@@ -145,7 +145,7 @@ extern "C" int dsmc_smooth_static(const dsmc_model_t* model, int N, int precisio
   const int DX = padded_dx(dx);
   const bool fp64 = precision == DSMC_FP64;
   const size_t R = fp64 ? 8 : 4;
-  const int Npad = (N + kChunk - 1) / kChunk * kChunk, Nc = Npad / kChunk, NcP = (Nc + 3) / 4 * 4;
+  const int Npad = (N + kChunk - 1) / kChunk * kChunk, Nc = Npad / kChunk, NcP = (Nc + kGroup - 1) / kGroup * kGroup;
   const Levels lv = levels_of(K);
   const size_t TK = (size_t)K, Ns = (size_t)N;
 
@@ -171,8 +171,9 @@ extern "C" int dsmc_smooth_static(const dsmc_model_t* model, int N, int precisio
   const size_t o_tgq = cv.take(TK * Ns * sizeof(double));
   const size_t o_trow = cv.take(TK * Ns * DX * R);
   const size_t fixed = cv.used;
+  const size_t NGS = (size_t)group_stride(NcP);
   const size_t per_node = 2 * (((Ns * NcP * R) + 255) & ~size_t(255)) + Ns * sizeof(double) +
-                          Ns * sizeof(float) + 512;
+                          Ns * sizeof(float) + Ns * NGS * sizeof(double) + 768;
   const int want_nodes = std::max(1, lv.cnt[0]);
   if (fixed + per_node > kScratchBytes)
     return fail(DSMC_EUNSUPPORTED,
@@ -183,6 +184,7 @@ extern "C" int dsmc_smooth_static(const dsmc_model_t* model, int N, int precisio
   const size_t o_Pr = cv.take((size_t)node_cap * Ns * NcP * R);
   const size_t o_Rsum = cv.take((size_t)node_cap * Ns * sizeof(double));
   const size_t o_Rshift = cv.take((size_t)node_cap * Ns * sizeof(float));
+  const size_t o_Gs = cv.take((size_t)node_cap * Ns * NGS * sizeof(double));
   if (cv.used > kScratchBytes) return fail(DSMC_EUNSUPPORTED, "static workspace layout overflow");
 
   void* base = nullptr;
@@ -273,6 +275,7 @@ extern "C" int dsmc_smooth_static(const dsmc_model_t* model, int N, int precisio
       L.Pr = at(o_Pr);
       L.Rsum = (double*)at(o_Rsum);
       L.Rshift = (float*)at(o_Rshift);
+      L.Gs = (double*)at(o_Gs);
       L.force_rescue = false;
       L.rescue_count = nullptr;
       L.nb = nb;
