@@ -987,37 +987,11 @@ __device__ __forceinline__ int col_chunk_stride(int col_in_lds) {
   return col_in_lds ? col_chunk_lds_stride<R, DX>() : kChunk * (DX + 1);
 }
 
-// Chunk sums P[m][0..Nc) of one row into q (NcP <= 32: the whole row, every
-// load issued before any is used).
-template <typename R>
-__device__ __forceinline__ void load_row32(const R* __restrict__ Pm, int NcP, R (&q)[32]) {
-#pragma unroll
-  for (int g4 = 0; g4 < 8; ++g4) {
-    if (4 * g4 < NcP) {
-      R t4[4];
-      load4<R>(Pm + 4 * g4, t4);
-#pragma unroll
-      for (int i = 0; i < 4; ++i) q[4 * g4 + i] = t4[i];
-    } else {
-#pragma unroll
-      for (int i = 0; i < 4; ++i) q[4 * g4 + i] = (R)0;
-    }
-  }
-}
-
 // fp64 sum of a rescued row's chunk sums (in Pr) in chunk order: the sum the
 // rescue forms for the row's CDF weight
 template <typename R>
 __device__ __forceinline__ double row_sum(const R* __restrict__ Pm, int Nc, int NcP) {
   double s = 0.0;
-  if (NcP <= 32) {
-    R q[32];
-    load_row32<R>(Pm, NcP, q);
-#pragma unroll
-    for (int i = 0; i < 32; ++i)
-      if (i < Nc) s += (double)q[i];
-    return s;
-  }
   for (int kb = 0; kb < NcP; kb += 16) {
     R q[16];
 #pragma unroll
@@ -1335,9 +1309,10 @@ __global__ __launch_bounds__(kBlock) void k_sample(
       }
     }
     if (!degenerate) {
-      // row l's coordinates, its first 16 chunk sums and its row sum R_l
-      // (rescued rows: the sum of their chunk sums in Pr)
-      R v[DB][DX], q[DB][16];
+      // row l's coordinates and its row sum R_l (rescued rows: the sum of
+      // their chunk sums in Pr).  The chunk sums are not loaded with them:
+      // the registers that takes cost more waves in flight than it saves.
+      R v[DB][DX];
       double Rl[DB];
       bool lres[DB];
 #pragma unroll
@@ -1345,14 +1320,6 @@ __global__ __launch_bounds__(kBlock) void k_sample(
 #pragma unroll
         for (int i = 0; i < DX; ++i) v[b][i] = rowp[(size_t)l[b] * DX + i];
         lres[b] = (resc[l[b] >> 5] >> (l[b] & 31)) & 1u;
-        const R* Pl = (lres[b] ? Prn : Pn) + (size_t)l[b] * NcP;
-#pragma unroll
-        for (int g4 = 0; g4 < 4; ++g4) {
-          R t4[4];
-          if (4 * g4 < NcP) load4<R>(Pl + 4 * g4, t4);
-#pragma unroll
-          for (int i = 0; i < 4; ++i) q[b][4 * g4 + i] = (4 * g4 < NcP) ? t4[i] : (R)0;
-        }
         Rl[b] = Rn[l[b]];
       }
 #pragma unroll
@@ -1366,17 +1333,12 @@ __global__ __launch_bounds__(kBlock) void k_sample(
         int k = -1, klast = 0;
         for (int kb = 0; kb < Nc && k < 0; kb += 16) {
           R qq[16];
-          if (kb > 0) {
 #pragma unroll
-            for (int g4 = 0; g4 < 4; ++g4) {
-              R t4[4];
-              if (kb + 4 * g4 < NcP) load4<R>(Pl + kb + 4 * g4, t4);
+          for (int g4 = 0; g4 < 4; ++g4) {
+            R t4[4];
+            if (kb + 4 * g4 < NcP) load4<R>(Pl + kb + 4 * g4, t4);
 #pragma unroll
-              for (int i = 0; i < 4; ++i) qq[4 * g4 + i] = (kb + 4 * g4 < NcP) ? t4[i] : (R)0;
-            }
-          } else {
-#pragma unroll
-            for (int i = 0; i < 16; ++i) qq[i] = q[b][i];
+            for (int i = 0; i < 4; ++i) qq[4 * g4 + i] = (kb + 4 * g4 < NcP) ? t4[i] : (R)0;
           }
 #pragma unroll
           for (int i = 0; i < 16; ++i) {
