@@ -287,19 +287,19 @@ __device__ __forceinline__ double leaf_normalise(double* ell, const double* gq, 
   const double logN = log((double)N);
   __syncthreads();
   double mx = -INFINITY, gmx = -INFINITY;
-  for (int n = threadIdx.x; n < N; n += kBlock) {
+  for (int n = threadIdx.x; n < N; n += blockDim.x) {
     mx = fmax(mx, ell[n]);
     gmx = fmax(gmx, gq[n]);
   }
   block_max2(mx, gmx, red);
   double s = 0.0;
   if (mx > -INFINITY)
-    for (int n = threadIdx.x; n < N; n += kBlock) s += exp(ell[n] - mx);
+    for (int n = threadIdx.x; n < N; n += blockDim.x) s += exp(ell[n] - mx);
   s = block_sum(s, red);
   const bool degenerate = !(mx > -INFINITY);
   const double lse = mx + log(s);
   double bmax = -INFINITY;  // max_n (lbar_n + gq_n): shift of a leaf right block
-  for (int n = threadIdx.x; n < N; n += kBlock) {
+  for (int n = threadIdx.x; n < N; n += blockDim.x) {
     const double lbar = degenerate ? -logN : ell[n] - lse;
     const R lr = (R)lbar;
     leafW[(size_t)g * N + n] = lr;
@@ -354,7 +354,7 @@ __global__ __launch_bounds__(kBlock, 3) void k_leaves(
   const double* qm = M.q_mean + (size_t)t * dx;
   const double* qc = M.q_chol + (size_t)t * dx * dx;
   const bool unif = uniform(M.prop_kind) == 1;  // uniform proposal: uniforms, not normals
-  for (int n = threadIdx.x; n < N; n += kBlock) {
+  for (int n = threadIdx.x; n < N; n += blockDim.x) {
     // standard normals (or uniforms), four per Philox block, then
     // x = q_mean + L z in place from the last coordinate down (x_i needs z_0 .. z_i)
     double x[DX];
@@ -423,7 +423,7 @@ __global__ __launch_bounds__(kBlock, 3) void k_leaves(
   // block (c == t + 1).
   const int cons = leaf_cons[g];
   const int P = cons >> 1, role = cons & 1;
-  for (int n = threadIdx.x; n < N; n += kBlock) {
+  for (int n = threadIdx.x; n < N; n += blockDim.x) {
     double x[DX];
     load_particle<R, DX>(leafX, totalK, N, g, n, dx, x);
     nb.tgq[(size_t)g * N + n] = gq[n];
@@ -447,7 +447,7 @@ __global__ __launch_bounds__(kBlock, 3) void k_leaves(
     }
   }
   if (cons >= 0 && role == 1) {
-    for (int n = N + threadIdx.x; n < Npad; n += kBlock) put_col_pad<R, DX>(nb, (size_t)P, Npad, n);
+    for (int n = N + threadIdx.x; n < Npad; n += blockDim.x) put_col_pad<R, DX>(nb, (size_t)P, Npad, n);
     if (threadIdx.x == 0) nb.bcol[P] = bmax;
   }
 }
@@ -487,7 +487,7 @@ __global__ __launch_bounds__(kBlock, 3) void k_leaves_mat(
   const bool row_direct = cons >= 0 && role == 0;  // boundary t + 1 belongs to combine P
   int bad = 0;
   auto reload = [&](int n, double (&x)[DX]) { load_particle<R, DX>(leafX, totalK, N, g, n, dx, x); };
-  for (int n = threadIdx.x; n < N; n += kBlock) {
+  for (int n = threadIdx.x; n < N; n += blockDim.x) {
     cdouble* rec = opaque(rec0);
     cdouble* Lc = rec;                // q_chol[t]
     cdouble* Li = rec + DX * DX;      // q_chol[t]^{-1}
@@ -590,17 +590,17 @@ __global__ __launch_bounds__(kBlock, 3) void k_leaves_mat(
   const double* gq = nb.tgq + (size_t)g * N;  // this thread's own entries, read back
   const double bmax = leaf_normalise<R>(ell, gq, g, N, bad, sd, leafW, leafL, bmerged);
   if (col_direct) {
-    for (int n = threadIdx.x; n < N; n += kBlock) {
+    for (int n = threadIdx.x; n < N; n += blockDim.x) {
       const double beta = (bmax > -INFINITY) ? (ell[n] + gq[n] - bmax) * kLog2e : -INFINITY;
       const size_t e = (size_t)P * Npad + n;
       ((R*)nb.col)[e * (DX + 1) + DX] = (R)beta;
       if constexpr (kSplit) nb.colb[e] = (float)beta - nb.tcoln[(size_t)g * N + n];
     }
-    for (int n = N + threadIdx.x; n < Npad; n += kBlock) put_col_pad<R, DX>(nb, (size_t)P, Npad, n);
+    for (int n = N + threadIdx.x; n < Npad; n += blockDim.x) put_col_pad<R, DX>(nb, (size_t)P, Npad, n);
     if (threadIdx.x == 0) nb.bcol[P] = bmax;
   }
   if (row_direct)
-    for (int n = threadIdx.x; n < N; n += kBlock) ((R*)nb.alpha)[(size_t)P * N + n] = (R)ell[n];
+    for (int n = threadIdx.x; n < N; n += blockDim.x) ((R*)nb.alpha)[(size_t)P * N + n] = (R)ell[n];
 }
 
 // ================================================================= rows
@@ -1619,7 +1619,7 @@ static void launch_leaves_t(const LeafLaunch& L, hipStream_t st, Timer* tm) {
         L.d_series, L.d_series_of_t, L.d_leaf_cons, L.row0, L.totalK, L.N, L.Npad, (R*)L.leafX,
         (R*)L.leafW, L.leafL, L.bmerged, L.nb);
   } else {
-    k_leaves<R, DX><<<L.rows, kBlock, 2 * (size_t)L.N * sizeof(double), st>>>(
+    k_leaves<R, DX><<<L.rows, leaf_block(L.N), 2 * (size_t)L.N * sizeof(double), st>>>(
         L.d_series, L.d_series_of_t, L.d_leaf_cons, L.row0, L.totalK, L.N, L.Npad, (R*)L.leafX,
         (R*)L.leafW, L.leafL, L.bmerged, L.nb);
   }

@@ -96,19 +96,25 @@ struct LeafLaunch {
   NodeBufs nb;
 };
 
-// Shape of a level's sampling launch (needs L.N and L.nodes): kBlock threads
-// per workgroup (the exact sampler's fp64 CDF is summed in an order fixed by
-// the workgroup size, so every path uses the same one), and several
-// workgroups per combine when a level has few combines.
 // Row stride of the chunk-group sums (NcP / kGroup groups, at least 4, even).
 inline int group_stride(int NcP) {
   const int g = NcP / kGroup;
   return g <= 4 ? 4 : (g + 1) / 2 * 2;
 }
 
+// Threads per workgroup of the sampling kernel and of the small-d_x leaf kernel
+// for N particles: one wave for N <= 256, two for N <= 512, else kBlock.  A
+// function of N alone, so that every path (plan, batch, server, static) sums
+// the fp64 CDFs and the leaf normalisers in the same order.
+inline int sample_block(int N) { return N <= 256 ? 64 : (N <= 512 ? 128 : kBlock); }
+inline int leaf_block(int N) { return sample_block(N); }
+
+// Shape of a level's sampling launch (needs L.N and L.nodes): sample_block(N)
+// threads per workgroup, and several workgroups per combine when a level has
+// few combines.
 inline void set_sample_shape(LevelLaunch& L) {
   const int nodes = L.nodes < 1 ? 1 : L.nodes;
-  L.SB = kBlock;
+  L.SB = sample_block(L.N);
   const int ds_max = (L.N + 127) / 128 < 1 ? 1 : (L.N + 127) / 128;
   const int spread = (512 + nodes - 1) / nodes;
   L.DS = nodes >= 256 ? 1 : (ds_max < spread ? ds_max : spread);
