@@ -31,10 +31,17 @@ FLAGS = ["-O3", "-std=c++17", "-fPIC", "--offload-arch=gfx950",
          "-I", INCLUDE, "-I", CSRC]
 
 
+# Per-source additions: the Kalman scan's in-register Gauss-Jordan inverse is
+# a 32-step loop whose steps index a register array; it must unroll fully
+# (else the array goes to scratch memory), past the default size limit.
+EXTRA_FLAGS = {"dsmc_pit_kalman.hip": ["-mllvm", "-pragma-unroll-threshold=1000000"]}
+
+
 def _compile(src: str, objdir: str) -> str:
     obj = os.path.join(objdir, os.path.basename(src) + ".o")
     lang = ["-x", "hip"] if src.endswith((".hip", ".cpp")) else []
-    cmd = [HIPCC, *lang, *FLAGS, "-c", os.path.join(CSRC, src), "-o", obj]
+    cmd = [HIPCC, *lang, *FLAGS, *EXTRA_FLAGS.get(src, []), "-c", os.path.join(CSRC, src),
+           "-o", obj]
     r = subprocess.run(cmd, capture_output=True, text=True)
     if r.returncode != 0:
         raise RuntimeError(f"compile failed: {' '.join(cmd)}\n{r.stdout}\n{r.stderr}")

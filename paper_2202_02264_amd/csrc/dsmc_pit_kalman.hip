@@ -44,7 +44,7 @@ using namespace dsmc;
 
 namespace {
 
-constexpr int kScanBlock = 16;
+constexpr int kScanBlock = 4;
 constexpr int kPitThreads = 256;
 
 // ----------------------------------------------------- LDS linear algebra
@@ -115,67 +115,63 @@ __device__ void symmetrize(double* A, int n) {
   __syncthreads();
 }
 
-// Inverse of the n x n matrix in aug[:, 0:n] by Gauss-Jordan elimination with
-// partial pivoting; aug is n x 2n, the inverse ends in aug[:, n:2n].
-// `col` holds n values of scratch.
-__device__ void invert(double* aug, int n, double* col) {
-  const int w = 2 * n;
-  for (int e = threadIdx.x; e < n * n; e += blockDim.x) {
-    const int i = e / n, j = e - (e / n) * n;
-    aug[i * w + n + j] = (i == j) ? 1.0 : 0.0;
-  }
-  __shared__ int piv;
-  __syncthreads();
-  for (int c = 0; c < n; ++c) {
-    if (threadIdx.x < 64) {  // pivot: the first row of largest |entry| in column c (n <= 64)
-      const int r = c + (int)threadIdx.x;
-      double v = r < n ? fabs(aug[r * w + c]) : -1.0;
-      int idx = r;
-#pragma unroll
-      for (int o = 32; o > 0; o >>= 1) {
-        const double ov = __shfl_xor(v, o, 64);
-        const int oi = __shfl_xor(idx, o, 64);
-        if (ov > v || (ov == v && oi < idx)) {
-          v = ov;
-          idx = oi;
-        }
-      }
-      if (threadIdx.x == 0) piv = idx;
-    }
-    __syncthreads();
-    const int p = piv;
-    if (p != c)
-      for (int j = threadIdx.x; j < w; j += blockDim.x) {
-        const double t = aug[c * w + j];
-        aug[c * w + j] = aug[p * w + j];
-        aug[p * w + j] = t;
-      }
-    __syncthreads();
-    const double inv_p = 1.0 / aug[c * w + c];
-    __syncthreads();
-    for (int j = threadIdx.x; j < w; j += blockDim.x) aug[c * w + j] *= inv_p;
-    for (int r = threadIdx.x; r < n; r += blockDim.x) col[r] = aug[r * w + c];
-    __syncthreads();
-    for (int e = threadIdx.x; e < n * w; e += blockDim.x) {
-      const int r = e / w, j = e - (e / w) * w;
-      if (r != c) aug[e] = fma(-col[r], aug[c * w + j], aug[e]);
-    }
-    __syncthreads();
-  }
+// out = M^{-1} (n x n, n <= 32, row-major; out may alias M) by Gauss-Jordan
+// elimination with partial pivoting, in registers of the first wave: lane j
+// holds column j of the augmented matrix [M | I] (2n <= 64 columns).  Pivot:
+// the first row of largest |entry| in the column, chosen by the lane that owns
+// it; row swaps are selects; the elimination factors reach the other lanes by
+// cross-lane reads, so no step needs a barrier.
+// Value of x in lane `lane` (wave-uniform), as a scalar.
+__device__ __forceinline__ double lane_value(double x, int lane) {
+  const uint64_t b = (uint64_t)__double_as_longlong(x);
+  const uint32_t lo = (uint32_t)__builtin_amdgcn_readlane((int)(uint32_t)b, lane);
+  const uint32_t hi = (uint32_t)__builtin_amdgcn_readlane((int)(uint32_t)(b >> 32), lane);
+  return __longlong_as_double((long long)(((uint64_t)hi << 32) | lo));
 }
 
-// inverse (n x n) of aug's left block into out (row-major n x n)
-__device__ void inverse_of(double* out, double* aug, const double* M, int n, double* col) {
-  const int w = 2 * n;
-  for (int e = threadIdx.x; e < n * n; e += blockDim.x) {
-    const int i = e / n, j = e - (e / n) * n;
-    aug[i * w + j] = M[e];
-  }
-  __syncthreads();
-  invert(aug, n, col);
-  for (int e = threadIdx.x; e < n * n; e += blockDim.x) {
-    const int i = e / n, j = e - (e / n) * n;
-    out[e] = aug[i * w + n + j];
+__device__ __forceinline__ void inverse_of(double* out, const double* M, int n) {
+  if (threadIdx.x < 64) {
+    const int j = threadIdx.x;
+    double a[32];
+#pragma unroll
+    for (int r = 0; r < 32; ++r)
+      a[r] = (r >= n) ? 0.0 : (j < n ? M[r * n + j] : (j - n == r ? 1.0 : 0.0));
+#pragma unroll
+    for (int c = 0; c < 32; ++c) {
+      if (c < n) {  // uniform
+        double best = -1.0;
+        int p = c;
+#pragma unroll
+        for (int r = c; r < 32; ++r) {
+          const double v = fabs(a[r]);
+          if (r < n && v > best) {
+            best = v;
+            p = r;
+          }
+        }
+        p = __builtin_amdgcn_readlane(p, c);
+#pragma unroll
+        for (int r = c + 1; r < 32; ++r) {
+          const bool sw = r == p;
+          const double ar = a[r];
+          a[r] = sw ? a[c] : ar;
+          a[c] = sw ? ar : a[c];
+        }
+        const double ip = 1.0 / lane_value(a[c], c);
+        a[c] *= ip;
+#pragma unroll
+        for (int r = 0; r < 32; ++r) {
+          if (r != c && r < n) {
+            const double f = lane_value(a[r], c);  // column c before this step's update
+            a[r] = fma(-f, a[c], a[r]);
+          }
+        }
+      }
+    }
+    if (j >= n && j < 2 * n)
+#pragma unroll
+      for (int r = 0; r < 32; ++r)
+        if (r < n) out[r * n + (j - n)] = a[r];
   }
   __syncthreads();
 }
@@ -205,7 +201,7 @@ struct FilterOp {
     mm(M, Cx, false, Jy, false, d, d, d);
     for (int i = threadIdx.x; i < d; i += blockDim.x) M[i * d + i] += 1.0;
     __syncthreads();
-    inverse_of(M, aug, M, d, col);                      // M = (I + Cx Jy)^{-1}
+    inverse_of(M, M, d);                                // M = (I + Cx Jy)^{-1}
     mm(T1, Ay, false, M, false, d, d, d);               // T1 = Ay M^{-1}
     mm(Ao, T1, false, Ax, false, d, d, d);
     mv(v, Cx, false, ey, d, d, bx);                     // v = bx + Cx ey
@@ -293,7 +289,7 @@ __global__ __launch_bounds__(kPitThreads) void k_filter_elements(const DevModel*
   mm(S, HP, false, L.H, true, dy, d, dy);                    // H P H^T
   for (int i = threadIdx.x; i < dy; i += blockDim.x) S[i * dy + i] += 1.0;
   __syncthreads();
-  inverse_of(S, aug, S, dy, col);                            // S^{-1}
+  inverse_of(S, S, dy);                                      // S^{-1}
   mm(G, HP, true, S, false, d, dy, dy);                      // G = P H^T S^{-1}
   mm(IGH, G, false, L.H, false, d, dy, d);                   // G H
   for (int e = threadIdx.x; e < dd; e += blockDim.x) {
@@ -363,7 +359,7 @@ __global__ __launch_bounds__(kPitThreads) void k_smooth_elements(const DevModel*
   mm(FP, L.F, false, P, false, d, d, d);                      // F P
   mm(Pp, FP, false, L.F, true, d, d, d, L.Q);                 // F P F^T + Q
   symmetrize(Pp, d);
-  inverse_of(Pp, aug, Pp, d, col);
+  inverse_of(Pp, Pp, d);
   mm(E, FP, true, Pp, false, d, d, d);                        // P F^T Pp^{-1}
   copy(Eo, E, dd);
   mv(v, L.F, false, m, d, d, L.f);                            // F m + f
