@@ -779,9 +779,9 @@ void dsmc::set_tile(LevelLaunch& L, TileChoice tc) {
 
 // Time every (rows per lane, waves per workgroup) candidate, each with the
 // column splits that fill the chip, on this launch's real inputs, and keep
-// the fastest.  A trial runs the whole level (pair rows and sampling): with
-// column splits the rows kernel leaves the row sums to every sampling
-// workgroup, which can cost more than the splits save.  Re-running a level
+// the fastest.  A trial runs the whole level (pair rows and sampling): the
+// sampler's cost also depends on the tile (with column splits it adds the
+// group sums of every row).  Re-running a level
 // rewrites the same values (its kernels never modify their own inputs), and
 // the tile does not change any result.
 static TileChoice autotune_tile(dsmc_plan_t* p, LevelLaunch L) {

@@ -459,6 +459,8 @@ __global__ __launch_bounds__(kBlock, 3) void k_leaves(
 // (the model's leaf records).  A boundary consumed by this leaf's level-0
 // combine is written straight into that combine's buffers (no table entry:
 // no other combine reads it); the other boundary goes to its table.
+// Launched with kBlock threads (the loops stride by the constant: with
+// blockDim.x the compiler spilled several times more scalar registers).
 template <typename R, int DX, bool kSplit>
 __global__ __launch_bounds__(kBlock, 3) void k_leaves_mat(
     const SeriesDesc* __restrict__ series, const int32_t* __restrict__ series_of_t,
@@ -487,7 +489,7 @@ __global__ __launch_bounds__(kBlock, 3) void k_leaves_mat(
   const bool row_direct = cons >= 0 && role == 0;  // boundary t + 1 belongs to combine P
   int bad = 0;
   auto reload = [&](int n, double (&x)[DX]) { load_particle<R, DX>(leafX, totalK, N, g, n, dx, x); };
-  for (int n = threadIdx.x; n < N; n += blockDim.x) {
+  for (int n = threadIdx.x; n < N; n += kBlock) {
     cdouble* rec = opaque(rec0);
     cdouble* Lc = rec;                // q_chol[t]
     cdouble* Li = rec + DX * DX;      // q_chol[t]^{-1}
@@ -590,17 +592,17 @@ __global__ __launch_bounds__(kBlock, 3) void k_leaves_mat(
   const double* gq = nb.tgq + (size_t)g * N;  // this thread's own entries, read back
   const double bmax = leaf_normalise<R>(ell, gq, g, N, bad, sd, leafW, leafL, bmerged);
   if (col_direct) {
-    for (int n = threadIdx.x; n < N; n += blockDim.x) {
+    for (int n = threadIdx.x; n < N; n += kBlock) {
       const double beta = (bmax > -INFINITY) ? (ell[n] + gq[n] - bmax) * kLog2e : -INFINITY;
       const size_t e = (size_t)P * Npad + n;
       ((R*)nb.col)[e * (DX + 1) + DX] = (R)beta;
       if constexpr (kSplit) nb.colb[e] = (float)beta - nb.tcoln[(size_t)g * N + n];
     }
-    for (int n = N + threadIdx.x; n < Npad; n += blockDim.x) put_col_pad<R, DX>(nb, (size_t)P, Npad, n);
+    for (int n = N + threadIdx.x; n < Npad; n += kBlock) put_col_pad<R, DX>(nb, (size_t)P, Npad, n);
     if (threadIdx.x == 0) nb.bcol[P] = bmax;
   }
   if (row_direct)
-    for (int n = threadIdx.x; n < N; n += blockDim.x) ((R*)nb.alpha)[(size_t)P * N + n] = (R)ell[n];
+    for (int n = threadIdx.x; n < N; n += kBlock) ((R*)nb.alpha)[(size_t)P * N + n] = (R)ell[n];
 }
 
 // ================================================================= rows
