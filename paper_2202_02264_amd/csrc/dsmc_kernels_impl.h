@@ -548,7 +548,7 @@ __global__ __launch_bounds__(kBlock, 3) void k_leaves_mat(
       qq = fma(zi, zi, qq);
     }
     const double lq = -0.5 * qq + qln;
-    double lh, lprior = 0.0;
+    double lh = 0.0;  // other potentials: in the pass below
     if (lg_obs) {  // whitened residual y_t - H x = yo - H d
       double qh = 0.0;
 #pragma unroll 1
@@ -559,21 +559,9 @@ __global__ __launch_bounds__(kBlock, 3) void k_leaves_mat(
         qh = fma(r, r, qh);
       }
       lh = -0.5 * qh + M.obs_lognorm;
-    } else {
-      double x[DX];
-      reload(n, x);
-      lh = log_potential<DX>(M, t, x);
     }
-    if (t == 0) {
-      double x[DX];
-      reload(n, x);
-      lprior = log_prior<DX>(M, x);
-    }
-    double l, gg;
-    leaf_logw(t, weighting, lq, lh, lprior, l, gg);
-    if (isnan(l) || isnan(gg)) bad = kFlagNumeric;
-    ell[n] = l;
-    nb.tgq[(size_t)g * N + n] = gg;
+    ell[n] = lh;
+    nb.tgq[(size_t)g * N + n] = -lq;
     if (t >= 1) {  // u for boundary t
       const size_t e = col_direct ? (size_t)P * Npad + n : (size_t)g * N + n;
       R* dst = col_direct ? (R*)nb.col + e * (DX + 1) : (R*)nb.tcol + e * DX;
@@ -589,7 +577,24 @@ __global__ __launch_bounds__(kBlock, 3) void k_leaves_mat(
       emit_coords<R, DX, true, kSplit>(Wr, ro, d, dst, true, dh, dn);
     }
   }
-  const double* gq = nb.tgq + (size_t)g * N;  // this thread's own entries, read back
+  // The weights, from log q and (linear-Gaussian) log h kept above; other
+  // potentials and the prior at t = 0 re-read the stored particle.  Kept out
+  // of the loop above, whose registers these rare paths would crowd.
+  double* gq = nb.tgq + (size_t)g * N;  // this thread's own entries, read back
+  for (int n = threadIdx.x; n < N; n += kBlock) {
+    double lh = ell[n], lprior = 0.0;
+    if (!lg_obs || t == 0) {
+      double x[DX];
+      reload(n, x);
+      if (!lg_obs) lh = log_potential<DX>(M, t, x);
+      if (t == 0) lprior = log_prior<DX>(M, x);
+    }
+    double l, gg;
+    leaf_logw(t, weighting, -gq[n], lh, lprior, l, gg);
+    if (isnan(l) || isnan(gg)) bad = kFlagNumeric;
+    ell[n] = l;
+    gq[n] = gg;
+  }
   const double bmax = leaf_normalise<R>(ell, gq, g, N, bad, sd, leafW, leafL, bmerged);
   if (col_direct) {
     for (int n = threadIdx.x; n < N; n += kBlock) {
