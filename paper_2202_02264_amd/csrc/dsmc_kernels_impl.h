@@ -1022,15 +1022,25 @@ __global__ __launch_bounds__(kBlock) void k_sample(
     int N, int Npad, int Nc, int NcP, int rows_summed, int NGS, int col_in_lds,
     int force_rescue, int rescale_chunk, const double* __restrict__ bmerged,
     const R* __restrict__ P, R* __restrict__ Pr, double* __restrict__ Rsum,
-    const double* __restrict__ Gs, const float* __restrict__ Rshift,
+    const double* __restrict__ Gs, float* __restrict__ Rshift,
     unsigned long long* __restrict__ rescue_count, NodeBufs nb) {
   extern __shared__ double smem[];
   const int nthr = blockDim.x;
   const int cstr = col_chunk_stride<R, DX>(col_in_lds);
-  double* cdf = smem;                        // [Npad]: row sums R_m, then the row CDF
-  float* shift = (float*)(smem + Npad);      // [Npad]
-  R* aw = (R*)(shift + Npad);                // [Npad]: row weights alpha_m (left leaf)
-  R* lcol = aw + Npad;                       // [Nc][cstr] when col_in_lds
+  // LDS (sample_lds): cdf [Npad] fp64: row sums R_m, then the row CDF; csum
+  // [Nc] fp64: chunk sums of the row being rescued; shift [Npad] (DX >= 8
+  // only: the rows' fp32 shifts; below, only rescued rows have one, kept in
+  // Rshift); aw [Npad]: row weights alpha_m (left leaf); need, resc
+  // [Npad / 32]: rows still to rescue, rescued rows (their chunk sums are in
+  // Pr); rescue_list [nthr]; lcol [Nc][cstr] when col_in_lds.
+  double* cdf = smem;
+  double* csum = cdf + Npad;
+  float* shift = (float*)(csum + Nc);
+  R* aw = (R*)(shift + (kRowShift<DX> ? Npad : 0));
+  unsigned* need = (unsigned*)(aw + Npad);
+  unsigned* resc = need + Npad / 32;
+  int* rescue_list = (int*)(resc + Npad / 32);
+  R* lcol = (R*)(rescue_list + nthr);
   __shared__ double red[2 * kMaxWaves];
   __shared__ int redi[2 * kMaxWaves];
   const int node_local = blockIdx.x / DS;
@@ -1048,6 +1058,12 @@ __global__ __launch_bounds__(kBlock) void k_sample(
   R* __restrict__ Prn = Pr + (size_t)node_local * N * NcP;
   double* __restrict__ Rn = Rsum + (size_t)node_local * N;
   const R* __restrict__ alp = (const R*)nb.alpha + (size_t)nodeid * N;
+  // the shift of row m (fp32): DX >= 8 every row's; below, rescued rows only
+  float* rsh = Rshift + (size_t)node_local * N;
+  auto row_shift = [&](int m) -> float {
+    if constexpr (kRowShift<DX>) return shift[m];
+    return ((resc[m >> 5] >> (m & 31)) & 1u) ? rsh[m] : 0.0f;
+  };
   if (col_in_lds) {  // four loads in flight per thread
     constexpr int CW = kChunk * (DX + 1);
     const int tot = Npad * (DX + 1);
@@ -1071,12 +1087,8 @@ __global__ __launch_bounds__(kBlock) void k_sample(
   __syncthreads();
 
   // ---- row sums (thread owns a contiguous segment of rows)
-  __shared__ unsigned need[DSMC_MAX_N / 32];  // rows still to rescue
-  __shared__ unsigned resc[DSMC_MAX_N / 32];  // rescued rows: their chunk sums are in Pr
-  __shared__ double csum[DSMC_MAX_N / kChunk];  // chunk sums of the row being rescued
-  __shared__ int rescue_list[kBlock];
   __shared__ int n_rescue;
-  for (int i = threadIdx.x; i < DSMC_MAX_N / 32; i += nthr) {
+  for (int i = threadIdx.x; i < Npad / 32; i += nthr) {
     need[i] = 0u;
     resc[i] = 0u;
   }
@@ -1132,7 +1144,7 @@ __global__ __launch_bounds__(kBlock) void k_sample(
         }
         if (isnan(Rm)) row_nan = 1;
         cdf[m] = Rm;
-        shift[m] = sv[i];
+        if constexpr (kRowShift<DX>) shift[m] = sv[i];
         aw[m] = av[i];
       }
     }
@@ -1204,7 +1216,9 @@ __global__ __launch_bounds__(kBlock) void k_sample(
         double tot = 0.0;
         for (int k = 0; k < Nc; ++k) tot += csum[k];
         cdf[m] = (smax > -INFINITY) ? tot : 0.0;
-        shift[m] = (smax > -INFINITY) ? (float)sh : 0.0f;
+        const float fs = (smax > -INFINITY) ? (float)sh : 0.0f;
+        if constexpr (kRowShift<DX>) shift[m] = fs;
+        else rsh[m] = fs;  // every workgroup of the combine writes the same value
       }
       __syncthreads();
     }
@@ -1215,7 +1229,7 @@ __global__ __launch_bounds__(kBlock) void k_sample(
     double* rl = sd.row_lse + (size_t)(c - 1) * N;
     for (int m = m0; m < m1; ++m) {
       const double a = left_leaf ? (double)aw[m] : -logN;
-      rl[m] = a + Bc + M.trans_lognorm + log(cdf[m]) + (double)shift[m] * kLn2;
+      rl[m] = a + Bc + M.trans_lognorm + log(cdf[m]) + (double)row_shift(m) * kLn2;
     }
   }
 
@@ -1227,7 +1241,7 @@ __global__ __launch_bounds__(kBlock) void k_sample(
     for (int m = m0; m < m1; ++m) {
       const double a = left_leaf ? (double)aw[m] : -logN;
       double rho = -INFINITY;
-      if (Astar > -INFINITY && cdf[m] > 0.0) rho = a - Astar + (double)shift[m] * kLn2 + log(cdf[m]);
+      if (Astar > -INFINITY && cdf[m] > 0.0) rho = a - Astar + (double)row_shift(m) * kLn2 + log(cdf[m]);
       cdf[m] = rho;
       gmax = fmax(gmax, rho);
     }
@@ -1333,7 +1347,7 @@ __global__ __launch_bounds__(kBlock) void k_sample(
       for (int b = 0; b < DB; ++b) {
         asm volatile("" ::: "memory");  // one draw after the other from here (registers)
         const R* Pl = (lres[b] ? Prn : Pn) + (size_t)l[b] * NcP;
-        const float sh = shift[l[b]];
+        const float sh = row_shift(l[b]);
         const double target2 = u2[b] * (lres[b] ? row_sum<R>(Pl, Nc, NcP) : Rl[b]);
         // chunk: first k whose prefix of chunk sums exceeds u2 R_l (16 at a time)
         double pref = 0.0, pref_last = 0.0, pk = 0.0, plast = 0.0;
@@ -1595,7 +1609,7 @@ static int launch_level_t(const LevelLaunch& L, hipStream_t st, Timer* tm) {
   tm->begin(1, st);
   if (launch_rows_t<R, DX>(L, st)) return -1;
   tm->end(1, st);
-  size_t lds_samp = (size_t)L.Npad * (sizeof(double) + sizeof(float) + sizeof(R));
+  size_t lds_samp = sample_lds(L.Npad, L.Nc, (size_t)L.SB, kRowShift<DX>, sizeof(R));
   const size_t lds_col = (size_t)(L.Npad / kChunk) * col_chunk_lds_stride<R, DX>() * sizeof(R);
   const int col_in_lds = (lds_samp + lds_col <= 96 * 1024) ? 1 : 0;
   if (col_in_lds) lds_samp += lds_col;

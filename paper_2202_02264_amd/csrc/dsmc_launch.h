@@ -109,6 +109,14 @@ inline int group_stride(int NcP) {
 inline int sample_block(int N) { return N <= 256 ? 64 : (N <= 512 ? 128 : kBlock); }
 inline int leaf_block(int N) { return sample_block(N); }
 
+// LDS of the sampling kernel before its optional column data (layout in
+// k_sample): the fp64 row CDF and rescue chunk sums, the fp32 row shifts (with
+// row shifts), the row weights, two row bit masks and the rescue list.
+inline size_t sample_lds(int Npad, int Nc, size_t threads, bool row_shift, size_t real) {
+  return (size_t)Npad * 8 + (size_t)Nc * 8 + (row_shift ? (size_t)Npad * 4 : 0) +
+         (size_t)Npad * real + 2 * (size_t)(Npad / 32) * 4 + threads * 4;
+}
+
 // Shape of a level's sampling launch (needs L.N and L.nodes): sample_block(N)
 // threads per workgroup, and several workgroups per combine when a level has
 // few combines.
