@@ -673,7 +673,7 @@ __global__ __launch_bounds__(kBlock) void k_rows(const R* __restrict__ col,
   double Rm[RPL];
   R* __restrict__ Pn = P + (size_t)node_local * N * NcP;
   const int k0 = cs * KC, k1 = min(Nc, k0 + KC);
-  auto pass = [&]() {
+  auto pass = [&]() __attribute__((always_inline)) {
 #pragma unroll
     for (int r = 0; r < RPL; ++r) Rm[r] = 0.0;
     for (int kg = k0; kg < k1; kg += kGroup) {
@@ -817,7 +817,7 @@ __global__ __launch_bounds__(kBlock) void k_rows_mfma(
 #pragma unroll
   for (int b = 0; b < MB; ++b) vv0[b] = vv[b];
   // log2 weights of chunk k for block b, into acc (row-norm term vv[b])
-  auto block = [&](int k, int b, f32x16_t& acc) {
+  auto block = [&](int k, int b, f32x16_t& acc) __attribute__((always_inline)) {
     const int n0 = k * kChunk;
     bf16x8_t uf[KS], ul[KS];
     const uint16_t* up = ch + (size_t)(n0 + j32) * 2 * DX + 8 * h;
@@ -869,7 +869,7 @@ __global__ __launch_bounds__(kBlock) void k_rows_mfma(
   double Rm[MB];
   float* __restrict__ Pn = P + (size_t)node_local * N * NcP;
   const int k0 = cs * KC, k1 = min(Nc, k0 + KC);
-  auto pass = [&]() {
+  auto pass = [&]() __attribute__((always_inline)) {
 #pragma unroll
     for (int b = 0; b < MB; ++b) Rm[b] = 0.0;
     for (int kg = k0; kg < k1; kg += kGroup) {
@@ -1060,7 +1060,7 @@ __global__ __launch_bounds__(kBlock) void k_sample(
   const R* __restrict__ alp = (const R*)nb.alpha + (size_t)nodeid * N;
   // the shift of row m (fp32): DX >= 8 every row's; below, rescued rows only
   float* rsh = Rshift + (size_t)node_local * N;
-  auto row_shift = [&](int m) -> float {
+  auto row_shift = [&](int m) __attribute__((always_inline)) -> float {
     if constexpr (kRowShift<DX>) return shift[m];
     return ((resc[m >> 5] >> (m & 31)) & 1u) ? rsh[m] : 0.0f;
   };
@@ -1083,7 +1083,7 @@ __global__ __launch_bounds__(kBlock) void k_sample(
   }
   const R* colp = col_in_lds ? lcol : gcol;
   // column j, coordinate d of the combine (padded layout in LDS)
-  auto colv = [&](int j, int d) -> R { return colp[(j >> 5) * cstr + (j & 31) * (DX + 1) + d]; };
+  auto colv = [&](int j, int d) __attribute__((always_inline)) -> R { return colp[(j >> 5) * cstr + (j & 31) * (DX + 1) + d]; };
   __syncthreads();
 
   // ---- row sums (thread owns a contiguous segment of rows)
@@ -1486,7 +1486,7 @@ __global__ __launch_bounds__(kBlock) void k_sample_lazy(
     }
   }
   // natural log of pair (i, j)'s weight relative to the rejection bound
-  auto logw = [&](int i, int j) -> double {
+  auto logw = [&](int i, int j) __attribute__((always_inline)) -> double {
     R v[DX], u[DX];
 #pragma unroll
     for (int d = 0; d < DX; ++d) {
@@ -1510,7 +1510,7 @@ __global__ __launch_bounds__(kBlock) void k_sample_lazy(
     int l = n, r = n;
     if (lazy == 1) {
       double cur = logw(l, r);
-      auto step = [&](uint64_t wi, uint64_t wu) {
+      auto step = [&](uint64_t wi, uint64_t wu) __attribute__((always_inline)) {
         const int ip = index_lo(wi), jp = index_hi(wi);
         const double prop = logw(ip, jp);
         if (unif53(wu) < exp(prop - cur)) {
@@ -1529,7 +1529,7 @@ __global__ __launch_bounds__(kBlock) void k_sample_lazy(
       if (isnan(cur)) bad = 1;
     } else {
       bool done = false;
-      auto trial = [&](uint64_t wi, uint64_t wu) {
+      auto trial = [&](uint64_t wi, uint64_t wu) __attribute__((always_inline)) {
         l = index_lo(wi);
         r = index_hi(wi);
         const double lw = logw(l, r);
