@@ -1404,16 +1404,22 @@ __global__ __launch_bounds__(kBlock) void k_sample(
           }
         }
         if (!done) {
-#pragma unroll
-          for (int jj = 0; jj < kChunk; ++jj) {
+          auto col_w = [&](int jj) __attribute__((always_inline)) -> R {
             R u[DX];
 #pragma unroll
             for (int i = 0; i < DX; ++i) u[i] = cp[jj * (DX + 1) + i];
-            const R e = Real<R>::exp2(pair_log2w<R, DX>(u, cp[jj * (DX + 1) + DX], v[b]) - (R)sh);
-            acc += e;
-            if (e > (R)0) lastj = jj;
+            return Real<R>::exp2(pair_log2w<R, DX>(u, cp[jj * (DX + 1) + DX], v[b]) - (R)sh);
+          };
+#pragma unroll
+          for (int jj = 0; jj < kChunk; ++jj) {
+            acc += col_w(jj);
             if (rr < 0 && rem < (double)acc) rr = jj;
           }
+          // rounding left u2 R_l at or past the chunk's total: the last column
+          // of positive weight, found again only in this rare case
+          if (rr < 0)
+            for (int jj = kChunk - 1; jj > 0 && lastj == 0; --jj)
+              if (col_w(jj) > (R)0) lastj = jj;
         }
         if (rr < 0) rr = lastj;
         rr += k * kChunk;
