@@ -29,9 +29,13 @@
  *
  * Randomness: the library owns it.  Every draw comes from Philox4x64-10
  * (Salmon et al., SC'11) with key (seed, 0x64534D43) and counter
- * (n, t or c, purpose, j): purpose 2 = leaf normals (Box-Muller in fp64),
- * purpose 3 = the two uniforms (u1, u2) of draw n of the combine at c.  Results
- * therefore depend only on (model, N, seed), not on batching or launch order.
+ * (block, t or c, purpose, j).  Purpose 2 = leaf normals, four per block
+ * (Box-Muller on the word pairs): for d_x dividing 4 the normals of time t are
+ * one flat stream (block q, j = 0: normals 4q..4q+3; coordinate i of particle
+ * n is normal n d_x + i), otherwise block (n, t, 2, j) gives normals 4j..4j+3
+ * of particle n.  Purpose 3 = the two uniforms (u1, u2) of draw n of the
+ * combine at c: block (n, c, 3, 0), words 0 and 1.  Results therefore depend
+ * only on (model, N, seed), not on batching or launch order.
  *
  * Multinomial draws are taken in two stages: the left index from the row
  * marginal with u1, then the right index from that row with u2, each by the
@@ -97,7 +101,7 @@ enum { DSMC_OBS_NONE = -1,           /* no parametric form: h_t is given by the
 
 /* Proposal family: GAUSSIAN q_t = N(q_mean[t], q_chol[t] q_chol[t]^T);
  * UNIFORM q_t uniform on the box q_mean[t] +- diag(q_chol[t]) (d_x <= 4; the
- * uniform of coordinate i is word i % 4 of the leaf Philox block i / 4). */
+ * uniforms are the leaf Philox words, in the places of the normals). */
 enum { DSMC_PROPOSAL_GAUSSIAN = 0, DSMC_PROPOSAL_UNIFORM = 1 };
 
 /* Choice of the auxiliary measures nu_t of Definition 2.1 (Section 2.1):

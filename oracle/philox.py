@@ -11,12 +11,19 @@ Stream layout (shared contract with the GPU side, each side implementing it
 from the generator's published definition):
 
 * key     = (seed, 0x64534D43)
-* counter = (w0 = particle index n, w1 = time t or boundary c,
+* counter = (w0 = block index (particle or draw), w1 = time t or boundary c,
              w2 = purpose, w3 = sub-block j)
-* purpose 2 (LEAF):    block (n, t, 2, j) gives the standard normals
-                       z[4j .. 4j+3] of particle n at time t (Box-Muller).
+* purpose 2 (LEAF):    four standard normals per block (Box-Muller on its
+                       word pairs (w0, w1) and (w2, w3)).  d_x dividing 4
+                       (1, 2, 4): the normals of time t form one flat stream,
+                       block (q, t, 2, 0) giving normals 4q .. 4q+3, and
+                       coordinate i of particle n is normal n d_x + i.  Other
+                       d_x: block (n, t, 2, j) gives z[4j .. 4j+3] of particle
+                       n.  Uniform proposals take the words themselves, in the
+                       same places.
 * purpose 3 (COMBINE): block (n, c, 3, 0) gives the two uniforms (u1, u2) of
-                       the n-th draw of the combine at boundary c.
+                       the n-th draw of the combine at boundary c (words w0,
+                       w1).
 
 Uniform from a 64-bit word w: (w >> 11) * 2^-53 in [0, 1).
 Box-Muller from words (wa, wb): ua = ((wa >> 11) + 1) * 2^-53 in (0, 1],
@@ -81,34 +88,52 @@ def to_uniform_open0(w: np.ndarray) -> np.ndarray:
     return ((w >> np.uint64(11)).astype(np.float64) + 1.0) * 2.0 ** -53
 
 
+def _leaf_blocks(seed: int, t: int, N: int, d: int):
+    """The leaf Philox words of time t, shape (N, 4 * blocks per particle):
+    row n holds the four words of each block particle n draws from, in the
+    positions of its coordinates (flat stream for d dividing 4: row n holds
+    the words of block floor(n d / 4) rotated so that its coordinates come
+    first)."""
+    if 4 % d == 0:
+        ppb = 4 // d                                   # particles per block
+        q = np.arange((N + ppb - 1) // ppb, dtype=np.uint64)
+        w = philox4x64_10((q, np.uint64(t), np.uint64(PURPOSE_LEAF), np.uint64(0)), key_of(seed))
+        return np.stack(w, axis=1)                     # (blocks, 4): words of block q
+    n = np.arange(N, dtype=np.uint64)
+    out = []
+    for j in range((d + 3) // 4):
+        w = philox4x64_10((n, np.uint64(t), np.uint64(PURPOSE_LEAF), np.uint64(j)), key_of(seed))
+        out.append(np.stack(w, axis=1))
+    return np.concatenate(out, axis=1)                 # (N, 4 * blocks)
+
+
+def _box_muller(w: np.ndarray) -> np.ndarray:
+    """Four normals from each row of four words (pairs (w0, w1), (w2, w3))."""
+    z = np.empty(w.shape)
+    for p in range(w.shape[1] // 2):
+        ua = to_uniform_open0(w[:, 2 * p])
+        ub = to_uniform(w[:, 2 * p + 1])
+        rad = np.sqrt(-2.0 * np.log(ua))
+        z[:, 2 * p] = rad * np.cos(2.0 * np.pi * ub)
+        z[:, 2 * p + 1] = rad * np.sin(2.0 * np.pi * ub)
+    return z
+
+
 def leaf_normals(seed: int, t: int, N: int, d: int) -> np.ndarray:
     """Standard normals z[n, 0:d] of the N particles drawn at time t, shape (N, d)."""
-    n = np.arange(N, dtype=np.uint64)
-    nblk = (d + 3) // 4
-    z = np.empty((N, 4 * nblk))
-    for j in range(nblk):
-        w = philox4x64_10((n, np.uint64(t), np.uint64(PURPOSE_LEAF), np.uint64(j)), key_of(seed))
-        for p in range(2):
-            ua = to_uniform_open0(w[2 * p])
-            ub = to_uniform(w[2 * p + 1])
-            rad = np.sqrt(-2.0 * np.log(ua))
-            z[:, 4 * j + 2 * p] = rad * np.cos(2.0 * np.pi * ub)
-            z[:, 4 * j + 2 * p + 1] = rad * np.sin(2.0 * np.pi * ub)
+    z = _box_muller(_leaf_blocks(seed, t, N, d))
+    if 4 % d == 0:
+        return z.reshape(-1)[:N * d].reshape(N, d)   # normal n d + i
     return z[:, :d]
 
 
 def leaf_uniforms(seed: int, t: int, N: int, d: int) -> np.ndarray:
     """Uniforms in [0, 1) of the N particles drawn at time t, shape (N, d):
-    coordinate i from word i % 4 of block (n, t, 2, i // 4) (the blocks that
-    give a Gaussian proposal its normals)."""
-    n = np.arange(N, dtype=np.uint64)
-    u = np.empty((N, d))
-    for j in range((d + 3) // 4):
-        w = philox4x64_10((n, np.uint64(t), np.uint64(PURPOSE_LEAF), np.uint64(j)), key_of(seed))
-        for k in range(4):
-            if 4 * j + k < d:
-                u[:, 4 * j + k] = to_uniform(w[k])
-    return u
+    the words that give a Gaussian proposal its normals, in the same places."""
+    u = to_uniform(_leaf_blocks(seed, t, N, d))
+    if 4 % d == 0:
+        return u.reshape(-1)[:N * d].reshape(N, d)
+    return u[:, :d]
 
 
 def combine_uniforms(seed: int, c: int, N: int):

@@ -354,28 +354,10 @@ __global__ __launch_bounds__(kBlock, 3) void k_leaves(
   const double* qm = M.q_mean + (size_t)t * dx;
   const double* qc = M.q_chol + (size_t)t * dx * dx;
   const bool unif = uniform(M.prop_kind) == 1;  // uniform proposal: uniforms, not normals
-  for (int n = threadIdx.x; n < N; n += blockDim.x) {
-    // standard normals (or uniforms), four per Philox block, then
-    // x = q_mean + L z in place from the last coordinate down (x_i needs z_0 .. z_i)
-    double x[DX];
-#pragma unroll
-    for (int j = 0; j < (DX + 3) / 4; ++j) {
-      const Words4 w = philox4x64_10((uint64_t)n, (uint64_t)t, kPurposeLeaf, (uint64_t)j,
-                                     sd.seed, kKey1);
-      double z0, z1, z2, z3;
-      if (unif) {
-        z0 = unif53(w.w0);
-        z1 = unif53(w.w1);
-        z2 = unif53(w.w2);
-        z3 = unif53(w.w3);
-      } else {
-        leaf_normals<R>(w, z0, z1, z2, z3);
-      }
-      if (4 * j < DX) x[4 * j] = z0;
-      if (4 * j + 1 < DX) x[4 * j + 1] = z1;
-      if (4 * j + 2 < DX) x[4 * j + 2] = z2;
-      if (4 * j + 3 < DX) x[4 * j + 3] = z3;
-    }
+  // particle n from its standard variates v (normals, or uniforms): x =
+  // q_mean + L v in place from the last coordinate down (x_i needs v_0 .. v_i),
+  // stored, then its weights
+  auto particle = [&](int n, double (&x)[DX]) __attribute__((always_inline)) {
 #pragma unroll
     for (int i = DX - 1; i >= 0; --i) {
       double xi = 0.0;
@@ -415,6 +397,54 @@ __global__ __launch_bounds__(kBlock, 3) void k_leaves(
     if (isnan(l) || isnan(gg)) bad = kFlagNumeric;
     ell[n] = l;
     gq[n] = gg;
+  };
+  auto variates = [&](const Words4& w, double& z0, double& z1, double& z2, double& z3)
+      __attribute__((always_inline)) {
+    if (unif) {
+      z0 = unif53(w.w0);
+      z1 = unif53(w.w1);
+      z2 = unif53(w.w2);
+      z3 = unif53(w.w3);
+    } else {
+      leaf_normals<R>(w, z0, z1, z2, z3);
+    }
+  };
+  if constexpr (DX <= 2) {
+    // d_x dividing 4: one flat stream of variates per time, block q giving
+    // variates 4q .. 4q+3, coordinate i of particle n being variate n d_x + i
+    constexpr int PPB = 4 / DX;  // particles per block
+    for (int q = threadIdx.x; q * PPB < N; q += blockDim.x) {
+      const Words4 w = philox4x64_10((uint64_t)q, (uint64_t)t, kPurposeLeaf, 0ull, sd.seed, kKey1);
+      double z[4];
+      variates(w, z[0], z[1], z[2], z[3]);
+#pragma unroll
+      for (int k = 0; k < PPB; ++k) {
+        const int n = q * PPB + k;
+        if (n < N) {
+          double x[DX];
+#pragma unroll
+          for (int i = 0; i < DX; ++i) x[i] = z[k * DX + i];
+          particle(n, x);
+        }
+      }
+    }
+  } else {
+    // otherwise ceil(d_x / 4) blocks (n, t, 2, j) per particle, variates 4j .. 4j+3
+    for (int n = threadIdx.x; n < N; n += blockDim.x) {
+      double x[DX];
+#pragma unroll
+      for (int j = 0; j < (DX + 3) / 4; ++j) {
+        const Words4 w = philox4x64_10((uint64_t)n, (uint64_t)t, kPurposeLeaf, (uint64_t)j,
+                                       sd.seed, kKey1);
+        double z0, z1, z2, z3;
+        variates(w, z0, z1, z2, z3);
+        if (4 * j < DX) x[4 * j] = z0;
+        if (4 * j + 1 < DX) x[4 * j + 1] = z1;
+        if (4 * j + 2 < DX) x[4 * j + 2] = z2;
+        if (4 * j + 3 < DX) x[4 * j + 3] = z3;
+      }
+      particle(n, x);
+    }
   }
   const double bmax = leaf_normalise<R>(ell, gq, g, N, bad, sd, leafW, leafL, bmerged);
   // Every particle's data for the combines at both boundaries of t (the
@@ -1296,150 +1326,123 @@ __global__ __launch_bounds__(kBlock) void k_sample(
     for (int n = N + threadIdx.x; n < Npad; n += nthr) put_col_pad<R, DX>(nb, (size_t)cons, Npad, n);
     if (threadIdx.x == 0) nb.bcol[cons] = bmerged[gA];
   }
-  // ---- draws, DB per thread at a time (each step's memory accesses of the DB
-  // draws issued together).  DB = 1: two draws per thread need about 190
-  // registers, which halves the waves in flight and measured slower.
-  constexpr int DB = 1;
+  // ---- draws, one per thread at a time (consecutive draws in consecutive
+  // lanes, so that their records are coalesced).  Per draw: the left index by
+  // the CDF search in LDS, then row l's coordinates and row sum R_l (rescued
+  // rows: the sum of their chunk sums in Pr), its chunk sums 16 at a time, the
+  // recomputed chunk, the sources.  (Two draws in lockstep took about 190
+  // registers and measured slower.)
   const int dper = (N + DS - 1) / DS;
   const int n0 = ds * dper, n1 = min(N, n0 + dper);
   int32_t* ancL = sd.anc + (size_t)(c - 1) * 2 * N;
   int32_t* ancR = ancL + N;
   const bool star = sd.star != nullptr;
-  for (int nbase = n0 + threadIdx.x; nbase < n1; nbase += DB * nthr) {
-    int nn[DB], l[DB], r[DB];
-    double u2[DB];
-#pragma unroll
-    for (int b = 0; b < DB; ++b) {
-      nn[b] = nbase + b * nthr;
-      const int n = nn[b] < n1 ? nn[b] : nbase;  // idle slots redo draw nbase, unrecorded
-      const Words4 w =
-          philox4x64_10((uint64_t)n, (uint64_t)c, kPurposeCombine, 0ull, sd.seed, kKey1);
-      const double u1 = unif53(w.w0);
-      u2[b] = unif53(w.w1);
-      if (degenerate) {
-        l[b] = min((int)(u1 * N), N - 1);
-        r[b] = min((int)(u2[b] * N), N - 1);
-      } else {
-        const double target = u1 * T;
-        int lo = 0, hi = N;
-        while (lo < hi) {
-          const int mid = (lo + hi) >> 1;
-          if (cdf[mid] > target) hi = mid; else lo = mid + 1;
-        }
-        l[b] = lo < N ? lo : (lastpos >= 0 ? lastpos : 0);
+  auto draw = [&](int n, double u1, double u2) __attribute__((always_inline)) {
+    int l, r;
+    if (degenerate) {
+      l = min((int)(u1 * N), N - 1);
+      r = min((int)(u2 * N), N - 1);
+    } else {
+      const double target = u1 * T;
+      int lo = 0, hi = N;
+      while (lo < hi) {
+        const int mid = (lo + hi) >> 1;
+        if (cdf[mid] > target) hi = mid; else lo = mid + 1;
       }
-    }
-    if (!degenerate) {
-      // row l's coordinates and its row sum R_l (rescued rows: the sum of
-      // their chunk sums in Pr).  The chunk sums are not loaded with them:
-      // the registers that takes cost more waves in flight than it saves.
-      R v[DB][DX];
-      double Rl[DB];
-      bool lres[DB];
+      l = lo < N ? lo : (lastpos >= 0 ? lastpos : 0);
+      R v[DX];
 #pragma unroll
-      for (int b = 0; b < DB; ++b) {
+      for (int i = 0; i < DX; ++i) v[i] = rowp[(size_t)l * DX + i];
+      const bool lres = (resc[l >> 5] >> (l & 31)) & 1u;
+      const double Rl = Rn[l];
+      const R* Pl = (lres ? Prn : Pn) + (size_t)l * NcP;
+      const float sh = row_shift(l);
+      const double target2 = u2 * (lres ? row_sum<R>(Pl, Nc, NcP) : Rl);
+      // chunk: first k whose prefix of chunk sums exceeds u2 R_l (16 at a time)
+      double pref = 0.0, pref_last = 0.0, pk = 0.0, plast = 0.0;
+      int k = -1, klast = 0;
+      for (int kb = 0; kb < Nc && k < 0; kb += 16) {
+        R qq[16];
 #pragma unroll
-        for (int i = 0; i < DX; ++i) v[b][i] = rowp[(size_t)l[b] * DX + i];
-        lres[b] = (resc[l[b] >> 5] >> (l[b] & 31)) & 1u;
-        Rl[b] = Rn[l[b]];
+        for (int g4 = 0; g4 < 4; ++g4) {
+          R t4[4];
+          if (kb + 4 * g4 < NcP) load4<R>(Pl + kb + 4 * g4, t4);
+#pragma unroll
+          for (int i = 0; i < 4; ++i) qq[4 * g4 + i] = (kb + 4 * g4 < NcP) ? t4[i] : (R)0;
+        }
+#pragma unroll
+        for (int i = 0; i < 16; ++i) {
+          const int kk = kb + i;
+          if (k < 0 && kk < Nc) {
+            const double pp = (double)qq[i];
+            if (pp > 0.0) { klast = kk; pref_last = pref; plast = pp; }
+            if (target2 < pref + pp) { k = kk; pk = pp; } else pref += pp;
+          }
+        }
       }
+      if (k < 0) { k = klast; pref = pref_last; pk = plast; }
+      double rem = target2 - pref;
+      // recompute chunk k of row l in the rows kernel's order
+      const R* cp = colp + (size_t)k * cstr;
+      auto col_w = [&](int jj) __attribute__((always_inline)) -> R {
+        R u[DX];
 #pragma unroll
-      for (int b = 0; b < DB; ++b) {
-        asm volatile("" ::: "memory");  // one draw after the other from here (registers)
-        const R* Pl = (lres[b] ? Prn : Pn) + (size_t)l[b] * NcP;
-        const float sh = row_shift(l[b]);
-        const double target2 = u2[b] * (lres[b] ? row_sum<R>(Pl, Nc, NcP) : Rl[b]);
-        // chunk: first k whose prefix of chunk sums exceeds u2 R_l (16 at a time)
-        double pref = 0.0, pref_last = 0.0, pk = 0.0, plast = 0.0;
-        int k = -1, klast = 0;
-        for (int kb = 0; kb < Nc && k < 0; kb += 16) {
-          R qq[16];
-#pragma unroll
-          for (int g4 = 0; g4 < 4; ++g4) {
-            R t4[4];
-            if (kb + 4 * g4 < NcP) load4<R>(Pl + kb + 4 * g4, t4);
-#pragma unroll
-            for (int i = 0; i < 4; ++i) qq[4 * g4 + i] = (kb + 4 * g4 < NcP) ? t4[i] : (R)0;
-          }
-#pragma unroll
-          for (int i = 0; i < 16; ++i) {
-            const int kk = kb + i;
-            if (k < 0 && kk < Nc) {
-              const double pp = (double)qq[i];
-              if (pp > 0.0) { klast = kk; pref_last = pref; plast = pp; }
-              if (target2 < pref + pp) { k = kk; pk = pp; } else pref += pp;
-            }
-          }
-        }
-        if (k < 0) { k = klast; pref = pref_last; pk = plast; }
-        double rem = target2 - pref;
-        // recompute chunk k of row l in the rows kernel's order
-        const R* cp = colp + (size_t)k * cstr;
-        R acc = (R)0;
-        int lastj = 0, rr = -1;
-        bool done = false;
-        if constexpr (sizeof(R) == 4 && DX >= 16) {
-          if (rescale_chunk) {
-            // bf16 plans: the stored chunk sums come from the matrix cores'
-            // expanded form; the recompute here is the direct form, so the
-            // search is rescaled to the recomputed chunk total
-            R ev[kChunk];
-            R tot = (R)0;
-#pragma unroll
-            for (int jj = 0; jj < kChunk; ++jj) {
-              R u[DX];
-#pragma unroll
-              for (int i = 0; i < DX; ++i) u[i] = cp[jj * (DX + 1) + i];
-              ev[jj] = Real<R>::exp2(pair_log2w<R, DX>(u, cp[jj * (DX + 1) + DX], v[b]) - (R)sh);
-              tot += ev[jj];
-            }
-            if (pk > 0.0 && tot > (R)0) rem *= (double)tot / pk;
-#pragma unroll
-            for (int jj = 0; jj < kChunk; ++jj) {
-              acc += ev[jj];
-              if (ev[jj] > (R)0) lastj = jj;
-              if (rr < 0 && rem < (double)acc) rr = jj;
-            }
-            done = true;
-          }
-        }
-        if (!done) {
-          auto col_w = [&](int jj) __attribute__((always_inline)) -> R {
-            R u[DX];
-#pragma unroll
-            for (int i = 0; i < DX; ++i) u[i] = cp[jj * (DX + 1) + i];
-            return Real<R>::exp2(pair_log2w<R, DX>(u, cp[jj * (DX + 1) + DX], v[b]) - (R)sh);
-          };
+        for (int i = 0; i < DX; ++i) u[i] = cp[jj * (DX + 1) + i];
+        return Real<R>::exp2(pair_log2w<R, DX>(u, cp[jj * (DX + 1) + DX], v) - (R)sh);
+      };
+      R acc = (R)0;
+      int lastj = 0, rr = -1;
+      bool done = false;
+      if constexpr (sizeof(R) == 4 && DX >= 16) {
+        if (rescale_chunk) {
+          // bf16 plans: the stored chunk sums come from the matrix cores'
+          // expanded form; the recompute here is the direct form, so the
+          // search is rescaled to the recomputed chunk total
+          R ev[kChunk];
+          R tot = (R)0;
 #pragma unroll
           for (int jj = 0; jj < kChunk; ++jj) {
-            acc += col_w(jj);
+            ev[jj] = col_w(jj);
+            tot += ev[jj];
+          }
+          if (pk > 0.0 && tot > (R)0) rem *= (double)tot / pk;
+#pragma unroll
+          for (int jj = 0; jj < kChunk; ++jj) {
+            acc += ev[jj];
+            if (ev[jj] > (R)0) lastj = jj;
             if (rr < 0 && rem < (double)acc) rr = jj;
           }
-          // rounding left u2 R_l at or past the chunk's total: the last column
-          // of positive weight, found again only in this rare case
-          if (rr < 0)
-            for (int jj = kChunk - 1; jj > 0 && lastj == 0; --jj)
-              if (col_w(jj) > (R)0) lastj = jj;
+          done = true;
         }
-        if (rr < 0) rr = lastj;
-        rr += k * kChunk;
-        r[b] = rr < N ? rr : N - 1;  // N - 1 only reachable through NaN weights
       }
-    }
-    int sf[DB], sl[DB];
+      if (!done) {
 #pragma unroll
-    for (int b = 0; b < DB; ++b) {
-      if (nn[b] == 0 && star) {  // conditional combine: slot 0 keeps the star, (0, 0)
-        l[b] = 0;
-        r[b] = 0;
+        for (int jj = 0; jj < kChunk; ++jj) {
+          acc += col_w(jj);
+          if (rr < 0 && rem < (double)acc) rr = jj;
+        }
+        // rounding left u2 R_l at or past the chunk's total: the last column
+        // of positive weight, found again only in this rare case
+        if (rr < 0)
+          for (int jj = kChunk - 1; jj > 0 && lastj == 0; --jj)
+            if (col_w(jj) > (R)0) lastj = jj;
       }
-      draw_sources(nb, nd, N, l[b], r[b], sf[b], sl[b]);
+      if (rr < 0) rr = lastj;
+      rr += k * kChunk;
+      r = rr < N ? rr : N - 1;  // N - 1 only reachable through NaN weights
     }
-#pragma unroll
-    for (int b = 0; b < DB; ++b)
-      if (nn[b] < n1)
-        record_draw<R, DX>(nb, nd, nodeid, N, Npad, nn[b], l[b], r[b], sf[b], sl[b], ancL, ancR,
-                           gA, gB, logN, bmerged);
+    if (n == 0 && star) {  // conditional combine: slot 0 keeps the star, (0, 0)
+      l = 0;
+      r = 0;
+    }
+    int sf, sl;
+    draw_sources(nb, nd, N, l, r, sf, sl);
+    record_draw<R, DX>(nb, nd, nodeid, N, Npad, n, l, r, sf, sl, ancL, ancR, gA, gB, logN,
+                       bmerged);
+  };
+  for (int n = n0 + threadIdx.x; n < n1; n += nthr) {
+    const Words4 w = philox4x64_10((uint64_t)n, (uint64_t)c, kPurposeCombine, 0ull, sd.seed, kKey1);
+    draw(n, unif53(w.w0), unif53(w.w1));
   }
 }
 
