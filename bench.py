@@ -57,7 +57,7 @@ BF16_MFMA_PEAK = 2.5e15
 # (profiles/k_rows_sv_K4096_N1024.md).  `src` is the sha256 prefix of the
 # kernel source the counters were taken on; when the source differs the
 # figure is reported as null.
-K_ROWS_SV_TRAFFIC = {"src": "dea7d712112fdf52", "read_MiB": 10.01, "write_MiB": 56.28}
+K_ROWS_SV_TRAFFIC = {"src": "ab4d91511ce3b5d6", "read_MiB": 10.01, "write_MiB": 57.04}
 # Lazy resampling kernel (k_sample_lazy<float, 1>): VALU instructions per
 # proposal in its Metropolis-Hastings loop, counted in the gfx950 assembly of
 # this source (half a Philox4x64-10 block, pair weight, fp64 exponential: 395
