@@ -1092,7 +1092,8 @@ static int enqueue_batch(dsmc_plan_t* p, int B, int totalK, hipStream_t st) {
       HIP_TRY(hipGetLastError());
     }
   }
-  launch_output(LL, 0, B, p->d.d_x, st, &p->timer);
+  launch_output_levels(LL, p->level_off.data(), p->level_cnt.data(), (int)p->level_cnt.size(),
+                       p->nb.sfirst, B, p->d.d_x, st, &p->timer);
   HIP_TRY(hipGetLastError());
   return DSMC_OK;
 }

@@ -131,6 +131,11 @@ inline void set_sample_shape(LevelLaunch& L) {
 int launch_leaves(const LeafLaunch& L, hipStream_t st, Timer* tm);
 int launch_level(const LevelLaunch& L, hipStream_t st, Timer* tm);
 void launch_output(const LeafLaunch& L, int s0, int B, int dx, hipStream_t st, Timer* tm);
+// The output by tree levels from the roots down (schedules whose combines are
+// numbered level by level, level l at [level_off[l], + level_cnt[l])); map is
+// N int32 per combine of scratch, which the levels' sampling no longer needs.
+void launch_output_levels(const LeafLaunch& L, const int* level_off, const int* level_cnt,
+                          int levels, int32_t* map, int B, int dx, hipStream_t st, Timer* tm);
 void launch_clear_status(const SeriesDesc* d_series, int s0, int B, hipStream_t st);
 // Fills a model's leaf records (rec = its leafrec array, padded dimension DX).
 void launch_leaf_records(const DevModel* dev, double* rec, int K, int DX, hipStream_t st);
