@@ -480,6 +480,16 @@ int dsmc_schedule(int K, int cap, int32_t *a, int32_t *c, int32_t *b, int32_t *l
 /* Message describing the last error on this thread ("" if none). */
 const char *dsmc_last_error(void);
 
+/* Failure-injection hook for tests of the error paths (not part of the
+ * method): from this call on, the k-th (0-based) device allocation that
+ * dsmc_plan makes for its workspace fails as an out-of-memory hipMalloc
+ * would.  That dsmc_plan then returns DSMC_ENOMEM with *out = NULL, having
+ * freed every allocation it had made.  The hook fires once and then turns
+ * itself off; k < 0 turns it off without firing.  Process-wide (one counter
+ * for all threads and devices); calls of dsmc_plan that overlap with it on
+ * several threads may see the failure at any one of them.  Returns DSMC_OK. */
+int dsmc_debug_fail_allocation(int k);
+
 #ifdef __cplusplus
 }
 #endif

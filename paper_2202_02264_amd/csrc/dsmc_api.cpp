@@ -4,6 +4,7 @@
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
+#include <atomic>
 #include <cmath>
 #include <cstdarg>
 #include <cstdio>
@@ -526,6 +527,23 @@ int dsmc::padded_dx(int dx) {
   return q;
 }
 
+// Failure injection (dsmc_debug_fail_allocation): workspace allocations left
+// before the one that fails; -1 when off.
+static std::atomic<int> g_fail_alloc{-1};
+
+static bool take_injected_failure() {
+  int k = g_fail_alloc.load();
+  while (k >= 0) {
+    if (g_fail_alloc.compare_exchange_weak(k, k - 1)) return k == 0;
+  }
+  return false;
+}
+
+extern "C" int dsmc_debug_fail_allocation(int k) {
+  g_fail_alloc.store(k < 0 ? -1 : k);
+  return DSMC_OK;
+}
+
 extern "C" int dsmc_plan(const dsmc_plan_desc* d, dsmc_plan_t** out) {
   if (!d || !out) return fail(DSMC_EINVAL, "null argument");
   *out = nullptr;
@@ -611,7 +629,8 @@ extern "C" int dsmc_plan(const dsmc_plan_desc* d, dsmc_plan_t** out) {
     all.push_back({(void**)&p->nb.trown, TK * N * sizeof(float), "row table norms"});
   }
   for (auto& a : all) {
-    hipError_t e = hipMalloc(a.ptr, std::max<size_t>(a.bytes, 256));
+    hipError_t e = take_injected_failure() ? hipErrorOutOfMemory
+                                           : hipMalloc(a.ptr, std::max<size_t>(a.bytes, 256));
     if (e != hipSuccess) {
       rc = fail(DSMC_ENOMEM, "hipMalloc(%s, %zu B): %s", a.what, a.bytes, hipGetErrorString(e));
       plan_free(p);

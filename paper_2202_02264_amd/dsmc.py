@@ -127,6 +127,7 @@ def _load() -> C.CDLL:
         "dsmc_schedule": (i, [i, i, C.POINTER(C.c_int32), C.POINTER(C.c_int32),
                               C.POINTER(C.c_int32), C.POINTER(C.c_int32)]),
         "dsmc_last_error": (C.c_char_p, []),
+        "dsmc_debug_fail_allocation": (i, [i]),
         "dsmc_device_count": (i, [C.POINTER(i)]),
     }
     for name, (res, args) in sig.items():
@@ -201,6 +202,11 @@ def dsmc_model_check(spec, callbacks: Optional[dsmc_model_callbacks] = None) -> 
 
 def last_error() -> str:
     return _lib.dsmc_last_error().decode()
+
+
+def dsmc_debug_fail_allocation(k: int) -> None:
+    """Make the k-th device allocation of the next dsmc_plan fail (k < 0: off)."""
+    _check(_lib.dsmc_debug_fail_allocation(int(k)), "dsmc_debug_fail_allocation")
 
 
 class Model:
