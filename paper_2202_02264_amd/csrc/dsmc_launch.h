@@ -117,15 +117,25 @@ inline size_t sample_lds(int Npad, int Nc, size_t threads, bool row_shift, size_
          (size_t)Npad * real + 2 * (size_t)(Npad / 32) * 4 + threads * 4;
 }
 
-// Shape of a level's sampling launch (needs L.N and L.nodes): sample_block(N)
-// threads per workgroup, and several workgroups per combine when a level has
-// few combines.
+// Shape of a level's sampling launch (needs L.N, L.DX, L.nodes and L.lazy):
+// sample_block(N) threads per workgroup, and several workgroups per combine
+// (each computes the combine's CDF and takes a share of its draws) when a level
+// has few combines.  Where a draw is dear against that repeated CDF pass
+// (N <= 1024, or padded d_x >= 8 with its d_x-dimensional chunk recompute),
+// exact draws aim at about 1024 workgroups, four per compute unit, to hide
+// their dependent loads: one workgroup per combine at 256 combines (N = 1024)
+// took 42 us, against 25 us for 128 combines in 512 workgroups.  Elsewhere
+// (exact draws at N = 4096, d_x = 1: 8 % slower with the wider split; the
+// lazy chains) the target is 512.  Results do not depend on the split.
 inline void set_sample_shape(LevelLaunch& L) {
   const int nodes = L.nodes < 1 ? 1 : L.nodes;
   L.SB = sample_block(L.N);
+  const bool wide = !L.lazy && (L.N <= 1024 || L.DX >= 8);
+  const int target = wide ? 1024 : 512;      // workgroups per launch
+  const int one_each = wide ? 1024 : 256;    // combines from which one workgroup each
   const int ds_max = (L.N + 127) / 128 < 1 ? 1 : (L.N + 127) / 128;
-  const int spread = (512 + nodes - 1) / nodes;
-  L.DS = nodes >= 256 ? 1 : (ds_max < spread ? ds_max : spread);
+  const int spread = (target + nodes - 1) / nodes;
+  L.DS = nodes >= one_each ? 1 : (ds_max < spread ? ds_max : spread);
 }
 
 int launch_leaves(const LeafLaunch& L, hipStream_t st, Timer* tm);
